@@ -1,0 +1,302 @@
+"""Geometric multigrid for the oracle (Section 4: Alg. 2, SMO-1, SMO-2,
+restriction/prolongation, bottom LU, Alg. 3 ordering).
+
+Readings of the paper used here:
+
+* Level m re-embeds the domain at h_m = 2^m h and re-discretises (Section 4);
+  coarsening stops before the first level that is smaller than
+  ``coarsest_min_n`` cells per side, has an odd size, or whose cut cells or
+  lattices cannot be built; the last level built is solved by LU.
+* SMO-1 (the printed formula carries a stray O in its second term): on the
+  regular block, u1 <- u1 + omega D^{-1} (r1 - L11 u1 - L12 u2), a
+  Jacobi step with old values everywhere, D the diagonal of L11.
+* SMO-2 (eq. updateByBlock): u2 solves L22 u2 = r2 - L21 u1 with the updated
+  u1, by a precomputed LU factorisation of L22.
+* Restriction: r_I^{m+1} = 1/4 sum over the regular children c of the coarse
+  cell I of (r - L u)_c; irregular children contribute nothing (their
+  residual is zero after SMO-2).  Prolongation: u_c += e_{floor(c/2)} on
+  regular fine cells only; irregular cells receive no correction.
+* Stopping: L-infinity relative residual ||r - L u|| / ||r|| over non-empty
+  cells, zero initial guess (Fig. 5 caption).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .discretization import Discretization, PLGError
+from .geometry import CutGrid, GeometryError
+
+
+class Level:
+    def __init__(self, grid, curves, a, b, c, theta=0.3):
+        self.cg = CutGrid(grid, curves, theta=theta)
+        self.disc = Discretization(self.cg, a, b, c)
+        d = self.disc
+        self.nx, self.ny = d.nx, d.ny
+        self.L, self.N = d.matrices()
+        self.L = self.L.tocsr()
+        self.reg = d.regular
+        self.irr = d.irregular
+        self.nonempty = d.nonempty
+        self.ne_idx = np.flatnonzero(self.nonempty)
+        self.Lirr = self.L[self.irr]                     # irregular rows
+        self.L21 = self.Lirr[:, np.flatnonzero(self.reg)]
+        self.order, self.block = alg3_order(d, with_blocks=True)
+        P = self.irr[self.order]
+        self.L22 = self.L[P][:, P].tocsc()
+        self.lu22 = spla.splu(self.L22) if P.size else None
+        self.perm = P
+        self.L21p = self.L[P][:, np.flatnonzero(self.reg)].tocsr()
+
+
+def alg3_order(disc, with_blocks=False):
+    """Alg. 3: permutation of ``disc.irregular`` that numbers, for each
+    boundary cell in the order of its boundary parameter, the still
+    unnumbered irregular cells of its 5x5 neighbourhood in linear-index order;
+    leftover irregular cells follow by linear index.
+
+    Boundary cells are those owning a boundary face; a cell's key is
+    (curve index, boundary parameter): the box is parametrised
+    counter-clockwise from its lower-left corner by the projection of the
+    cell centre onto its nearest border edge, a curve by the midpoint
+    parameter of the cell's own arc on it."""
+    cg = disc.cg
+    nx, ny = disc.nx, disc.ny
+    keys = []
+    for idx in disc.irregular:
+        idx = int(idx)
+        f = cg.faces(idx)
+        if not f:
+            continue
+        c = min(f)
+        keys.append(((c, boundary_parameter(cg, idx, c)), idx))
+    keys.sort()
+    pos = {int(q): k for k, q in enumerate(disc.irregular)}
+    num = np.full(disc.irregular.size, -1, dtype=np.int64)
+    blk = np.full(disc.irregular.size, -1, dtype=np.int64)
+    k = 0
+    irr_set = set(pos)
+    for (curve, _), idx in keys:
+        i, j = idx % nx, idx // nx
+        for dy in range(-2, 3):
+            for dx in range(-2, 3):
+                ii, jj = i + dx, j + dy
+                if not (0 <= ii < nx and 0 <= jj < ny):
+                    continue
+                q = jj * nx + ii
+                if q in irr_set and num[pos[q]] < 0:
+                    num[pos[q]] = k
+                    blk[pos[q]] = curve
+                    k += 1
+    for q in disc.irregular:
+        if num[pos[int(q)]] < 0:
+            num[pos[int(q)]] = k
+            k += 1
+    order = np.empty_like(num)
+    order[num] = np.arange(num.size)
+    if with_blocks:
+        return order, blk[order]
+    return order
+
+
+def boundary_parameter(cg, idx, curve):
+    nx = cg.nx
+    if cg.box is not None and curve == cg.box.index:
+        i, j = idx % nx, idx // nx
+        X, Y = (i + 0.5) / cg.nx, (j + 0.5) / cg.ny
+        cand = []
+        if j == 0:
+            cand.append((0, X))
+        if i == cg.nx - 1:
+            cand.append((1, 1.0 + Y))
+        if j == cg.ny - 1:
+            cand.append((2, 2.0 + (1.0 - X)))
+        if i == 0:
+            cand.append((3, 3.0 + (1.0 - Y)))
+        if not cand:
+            # merged host whose box edge belongs to a merged-in member
+            for own, comp in cg.cv[idx].members:
+                oi, oj = own % nx, own // nx
+                for e, s in ((0, (oi + 0.5) / cg.nx), (1, 1.0 + (oj + 0.5) / cg.ny),
+                             (2, 2.0 + 1.0 - (oi + 0.5) / cg.nx), (3, 3.0 + 1.0 - (oj + 0.5) / cg.ny)):
+                    if cg._on_border(oi, oj, e):
+                        cand.append((e, s))
+        return min(cand)[1]
+    best = None
+    for own, comp in cg.cv[idx].members:
+        if comp.loop is None:
+            continue
+        for item in comp.loop:
+            if item[0] == "arc" and item[1].curve == curve:
+                pcs = item[1].pieces
+                t = (0.5 * (pcs[0][0] + pcs[-1][1])) % (2.0 * math.pi)
+                best = t if best is None else min(best, t)
+    return best
+
+
+def cyclic_bandwidth(level):
+    """Largest |P(i) - P(j)| over the non-zeros of the reordered L22, with
+    distances measured around the cycle of each boundary's own block."""
+    A = level.L22.tocoo()
+    if A.shape[0] == 0:
+        return 0
+    blk = level.block
+    size = {b: int(np.sum(blk == b)) for b in np.unique(blk)}
+    d = np.abs(A.row - A.col)
+    same = (blk[A.row] == blk[A.col]) & (blk[A.row] >= 0)
+    nb = np.array([size[b] for b in blk[A.row]])
+    d = np.where(same, np.minimum(d, nb - d), d)
+    return int(np.max(d))
+
+
+class Hierarchy:
+    """Grid levels 0..M (Section 4) with the bottom LU."""
+
+    def __init__(self, grid, curves, a, b, c, theta=0.3, coarsest_min_n=16, max_levels=20):
+        self.a, self.b, self.c = a, b, c
+        self.levels = [Level(grid, curves, a, b, c, theta)]
+        g = dict(grid)
+        while len(self.levels) < max_levels:
+            nx, ny = g["nx"], g["ny"]
+            if nx % 2 or ny % 2 or nx // 2 < coarsest_min_n or ny // 2 < coarsest_min_n:
+                break
+            g = {"x0": g["x0"], "y0": g["y0"], "h": 2.0 * g["h"], "nx": nx // 2, "ny": ny // 2}
+            try:
+                self.levels.append(Level(g, curves, a, b, c, theta))
+            except (GeometryError, PLGError):
+                break
+        self._factor_bottom()
+
+    def _factor_bottom(self):
+        bot = self.levels[-1]
+        Ab = bot.L[bot.ne_idx][:, bot.ne_idx].tocsc()
+        self.bottom = spla.splu(Ab)
+
+    def select_depth(self, max_rate=0.5, cycles=6, seed=0):
+        """Drop coarse levels until V-cycles contract a seeded random residual
+        by at most ``max_rate`` per cycle (geometric mean over ``cycles``).
+        Coarse levels that resolve the geometry poorly can carry spurious
+        modes that make the coarse correction harmful; the converged solution
+        does not depend on the depth.  Returns the measured rate."""
+        lv = self.levels[0]
+        r = np.random.default_rng(seed).standard_normal(lv.nx * lv.ny) * lv.nonempty
+        rate = None
+        while True:
+            hist = []
+            self.solve(r, tol=0.0, max_cycles=cycles, history=hist)
+            rate = (hist[-1] / 1.0) ** (1.0 / len(hist)) if hist else 0.0
+            if rate <= max_rate or len(self.levels) <= 2:
+                return rate
+            self.levels.pop()
+            self._factor_bottom()
+
+    @property
+    def M(self):
+        return len(self.levels) - 1
+
+    # -- components ------------------------------------------------------------
+    def smooth(self, m, u, r, omega):
+        lv = self.levels[m]
+        Lu = lv.L @ u
+        d = lv.disc.diag
+        reg = lv.reg
+        u = u.copy()
+        u[reg] += omega / d * (r[reg] - Lu[reg])             # SMO-1
+        if lv.lu22 is not None:                               # SMO-2
+            rhs = r[lv.perm] - lv.L21p @ u[reg]
+            u[lv.perm] = lv.lu22.solve(rhs)
+        return u
+
+    def restrict(self, m, res):
+        lv, cv = self.levels[m], self.levels[m + 1]
+        R = np.where(lv.reg, res, 0.0).reshape(lv.ny, lv.nx)
+        rc = 0.25 * (R[0::2, 0::2] + R[1::2, 0::2] + R[0::2, 1::2] + R[1::2, 1::2])
+        return rc.ravel() * cv.nonempty
+
+    def prolong(self, m, e):
+        lv, cv = self.levels[m], self.levels[m + 1]
+        E = e.reshape(cv.ny, cv.nx)
+        fine = np.repeat(np.repeat(E, 2, axis=0), 2, axis=1).ravel()
+        return np.where(lv.reg, fine, 0.0)
+
+    def bottom_solve(self, r):
+        lv = self.levels[-1]
+        u = np.zeros(lv.nx * lv.ny)
+        u[lv.ne_idx] = self.bottom.solve(r[lv.ne_idx])
+        return u
+
+    def vcycle(self, m, u, r, nu1=3, nu2=3, omega=0.5):
+        """Alg. 2."""
+        if m == self.M:
+            return self.bottom_solve(r)
+        for _ in range(nu1):
+            u = self.smooth(m, u, r, omega)
+        lv = self.levels[m]
+        res = r - lv.L @ u
+        rc = self.restrict(m, res)
+        ec = self.vcycle(m + 1, np.zeros_like(rc), rc, nu1, nu2, omega)
+        u = u + self.prolong(m, ec)
+        for _ in range(nu2):
+            u = self.smooth(m, u, r, omega)
+        return u
+
+    def residual(self, u, r):
+        lv = self.levels[0]
+        return (r - lv.L @ u) * lv.nonempty
+
+    def solve(self, r, tol=1e-10, max_cycles=100, nu1=3, nu2=3, omega=0.5, u0=None, history=None):
+        """V-cycles from a zero initial guess until the relative L-infinity
+        residual reaches tol (or stagnates: three cycles each reducing it by
+        less than 5%)."""
+        lv = self.levels[0]
+        u = np.zeros(lv.nx * lv.ny) if u0 is None else u0.copy()
+        rn = np.max(np.abs(r[lv.nonempty]))
+        if rn == 0.0:
+            return u
+        prev, slow = None, 0
+        for _ in range(max_cycles):
+            u = self.vcycle(0, u, r, nu1, nu2, omega)
+            rel = np.max(np.abs(self.residual(u, r))) / rn
+            if history is not None:
+                history.append(rel)
+            if rel <= tol:
+                break
+            if prev is not None and rel > 0.95 * prev:
+                slow += 1
+                if slow >= 3:
+                    break
+            else:
+                slow = 0
+            prev = rel
+        return u
+
+
+def direct_solve(level, r):
+    """u = L^{-1} r on the non-empty cells by sparse LU (the plain definition
+    of the converged multigrid result)."""
+    ne = level.ne_idx
+    A = level.L[ne][:, ne].tocsc()
+    u = np.zeros(level.nx * level.ny)
+    u[ne] = spla.spsolve(A, r[ne])
+    return u
+
+
+def direct_solve_transpose(level, r):
+    """lambda = L^{-T} r on the non-empty cells (adjoint reference)."""
+    ne = level.ne_idx
+    A = level.L[ne][:, ne].T.tocsc()
+    lam = np.zeros(level.nx * level.ny)
+    lam[ne] = spla.spsolve(A, r[ne])
+    return lam
+
+
+def rhs_vector(level, f_avg, g):
+    """r-hat = f-hat - N g-hat (eq. PoissonResidualForm), zero on empty cells."""
+    r = np.asarray(f_avg, dtype=float).ravel().copy()
+    if g is not None and len(level.disc.faces):
+        r -= level.N @ g
+    return r * level.nonempty

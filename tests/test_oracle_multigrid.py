@@ -1,0 +1,121 @@
+"""Pins of the oracle's solution and multigrid (Sections 3.4, 4, 5)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle.discretization import boundary_data
+from oracle.geometry import cell_averages
+from oracle.multigrid import (Hierarchy, Level, alg3_order, cyclic_bandwidth, direct_solve,
+                              direct_solve_transpose, rhs_vector)
+from oracle.norms import norms
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _errors(cfg, n):
+    lv = Level(cfg["grid"] if n is None else W.grid(n), cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
+    sol = cfg["solution"]
+    f = cell_averages(lv.cg, cfg["f"])
+    g = boundary_data(lv.disc, sol)
+    u = direct_solve(lv, rhs_vector(lv, f, g))
+    ue = cell_averages(lv.cg, sol.u).ravel()
+    return norms(u - ue, lv.cg.vol), lv, u, f, g
+
+
+def test_problem2_dirichlet_matches_paper_table():
+    """Problem 2 with Dirichlet data on the ellipse (Table tab:errorsOfEllipseDD):
+    same magnitude as the paper at h = 1/64, 1/128 and a fourth-order rate."""
+    gold = json.load(open(os.path.join(GOLDEN, "problem2_errors.json")))["dirichlet_ellipse"]
+    errs = []
+    for k, n in enumerate((64, 128)):
+        (l1, l2, li), *_ = _errors(W.problem2(n, hole_bc=W.DIRICHLET), None)
+        errs.append((l1, l2, li))
+        for got, ref in zip((li, l1, l2), (gold["Linf"][k], gold["L1"][k], gold["L2"][k])):
+            assert ref / 5 < got < ref * 5, (n, got, ref)
+    rates = np.log2(np.array(errs[0]) / np.array(errs[1]))
+    assert np.all(rates > 3.5) and np.all(rates < 5.5), rates
+
+
+def test_problem2_neumann_fourth_order():
+    gold = json.load(open(os.path.join(GOLDEN, "problem2_errors.json")))["neumann_ellipse"]
+    (l1a, l2a, lia), *_ = _errors(W.problem2(64, hole_bc=W.NEUMANN), None)
+    (l1b, l2b, lib), *_ = _errors(W.problem2(128, hole_bc=W.NEUMANN), None)
+    assert gold["Linf"][1] / 10 < lib < gold["Linf"][1] * 10
+    for a, b in ((l1a, l1b), (l2a, l2b), (lia, lib)):
+        assert 3.5 < np.log2(a / b) < 5.0
+
+
+def test_exact_recovery_of_quartic():
+    """u in Pi_4 is reproduced to rounding (the discretization is exact on Pi_4)."""
+    cfg = W.config(2, n=32)
+    sol = W.polynomial({(4, 0): 1.0, (2, 2): -0.5, (1, 1): 2.0, (0, 3): 0.25, (0, 0): 1.0})
+    cfg = dict(cfg, solution=sol, f=sol.f(cfg["a"], cfg["b"], cfg["c"]))
+    (l1, l2, li), *_ = _errors(cfg, None)
+    assert li < 1e-11
+
+
+def test_dense_brute_force_and_gmg_agree():
+    cfg = W.config(1, n=16)
+    lv = Level(W.grid(16), cfg["curves"], 1.0, 0.0, 1.0)
+    r = np.random.default_rng(3).standard_normal(16 * 16) * lv.nonempty
+    ne = lv.ne_idx
+    dense = np.linalg.solve(lv.L[ne][:, ne].toarray(), r[ne])
+    sparse = direct_solve(lv, r)[ne]
+    assert np.max(np.abs(dense - sparse)) < 1e-12 * np.max(np.abs(dense))
+    cfg = W.config(1, n=32)
+    H = Hierarchy(cfg["grid"], cfg["curves"], 1.0, 0.0, 1.0)
+    H.select_depth()
+    lv = H.levels[0]
+    r = np.random.default_rng(4).standard_normal(32 * 32) * lv.nonempty
+    hist = []
+    u = H.solve(r, tol=1e-13, history=hist)
+    ud = direct_solve(lv, r)
+    assert np.max(np.abs(u - ud)) < 1e-11 * np.max(np.abs(ud))
+    assert all(b < a for a, b in zip(hist, hist[1:]))          # monotone decrease
+
+
+def test_smo2_zeroes_irregular_residual():
+    """After SMO-2 the residual of the irregular rows vanishes (Section 4.1)."""
+    cfg = W.config(4, n=64)
+    H = Hierarchy(cfg["grid"], cfg["curves"], 1.0, 0.0, 1.0, max_levels=2)
+    lv = H.levels[0]
+    r = np.random.default_rng(5).standard_normal(lv.nx * lv.ny) * lv.nonempty
+    u = H.smooth(0, np.zeros_like(r), r, 0.5)
+    res = r - lv.L @ u
+    assert np.max(np.abs(res[lv.irr])) < 1e-12 * np.max(np.abs(r))
+    assert np.max(np.abs(res[lv.reg])) > 1e-3
+
+
+def test_transpose_solve():
+    cfg = W.config(2, n=32)
+    lv = Level(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal(lv.nx * lv.ny) * lv.nonempty
+    lam = direct_solve_transpose(lv, r)
+    ne = lv.ne_idx
+    assert np.max(np.abs(lv.L[ne][:, ne].T @ lam[ne] - r[ne])) < 1e-9 * np.max(np.abs(r))
+    u = rng.standard_normal(lv.nx * lv.ny) * lv.nonempty
+    v = rng.standard_normal(lv.nx * lv.ny) * lv.nonempty
+    lhs = np.dot(lv.L @ u, v)
+    rhs = np.dot(u, lv.L.T @ v)
+    assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(lv.L @ u) * np.linalg.norm(v)
+
+
+def test_alg3_order_is_permutation_with_bounded_bandwidth():
+    bws = []
+    for n in (64, 128):
+        lv = Level(W.grid(n), [W.box(), W.circle(0.5, 0.5, 0.2)], 1.0, 0.0, 1.0)
+        order = alg3_order(lv.disc)
+        assert np.array_equal(np.sort(order), np.arange(lv.irr.size))
+        bws.append(cyclic_bandwidth(lv))
+    # independent of h and small (Section 4.2 reports <= 20 for its own numbering)
+    assert max(bws) <= 32 and bws[1] <= bws[0] + 2
+
+
+def test_norms_normalisation():
+    vol = np.array([0.0, 1.0, 0.5, 0.25])
+    assert norms(np.full(4, -3.0), vol) == (3.0, 3.0, 3.0)

@@ -1,0 +1,241 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU path.
+
+This module holds *no* arithmetic of the cut-cell method: it only describes
+problems (domains as analytic curves, coefficients, manufactured solutions
+with their closed-form derivatives) and draws seeded random numbers.  Cell
+and boundary averages of these functions are computed by each side with its
+own cubature.
+
+Curve descriptors are plain dicts::
+
+    {"kind": BOX|CIRCLE|ELLIPSE|POLAR_SIN|POLAR_COS,
+     "p": [...], "inside": 1 if the domain lies inside the curve else 0,
+     "bc": DIRICHLET|NEUMANN}
+
+Parameter layouts: circle ``cx, cy, r``; ellipse ``cx, cy, a1, a2, rot``;
+polar ``cx, cy, r0, A, k, phase`` with ``r(t) = r0 + A sin(k t + phase)``
+(or ``cos``); box ``x0, y0, x1, y1`` (the grid extent).
+
+The problem statement these describe is the elliptic equation
+``a u_xx + b u_xy + c u_yy = f`` with ``b^2 - 4ac < 0`` (Section 1,
+eq. ccEllipticEq) and Dirichlet or Neumann data on each boundary curve
+(Section 3.3).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+BOX, CIRCLE, ELLIPSE, POLAR_SIN, POLAR_COS = 0, 1, 2, 3, 4
+DIRICHLET, NEUMANN = 0, 1
+
+
+def box(bc=DIRICHLET, x0=0.0, y0=0.0, x1=1.0, y1=1.0):
+    return {"kind": BOX, "p": [x0, y0, x1, y1], "inside": 1, "bc": bc}
+
+
+def circle(cx, cy, r, inside=0, bc=DIRICHLET):
+    return {"kind": CIRCLE, "p": [cx, cy, r], "inside": inside, "bc": bc}
+
+
+def ellipse(cx, cy, a1, a2, rot=0.0, inside=0, bc=DIRICHLET):
+    return {"kind": ELLIPSE, "p": [cx, cy, a1, a2, rot], "inside": inside, "bc": bc}
+
+
+def polar_sin(cx, cy, r0, A, k, phase=0.0, inside=0, bc=DIRICHLET):
+    return {"kind": POLAR_SIN, "p": [cx, cy, r0, A, float(k), phase], "inside": inside, "bc": bc}
+
+
+def polar_cos(cx, cy, r0, A, k, phase=0.0, inside=0, bc=DIRICHLET):
+    return {"kind": POLAR_COS, "p": [cx, cy, r0, A, float(k), phase], "inside": inside, "bc": bc}
+
+
+# ---------------------------------------------------------------------------
+# Manufactured solutions: value, gradient and second derivatives in closed form.
+# ---------------------------------------------------------------------------
+class Manufactured:
+    """u and its derivatives; ``f`` applies a u_xx + b u_xy + c u_yy."""
+
+    def __init__(self, name, u, ux, uy, uxx, uxy, uyy):
+        self.name = name
+        self.u, self.ux, self.uy = u, ux, uy
+        self.uxx, self.uxy, self.uyy = uxx, uxy, uyy
+
+    def f(self, a, b, c):
+        return lambda x, y: a * self.uxx(x, y) + b * self.uxy(x, y) + c * self.uyy(x, y)
+
+    def dudn(self, x, y, nx, ny):
+        return self.ux(x, y) * nx + self.uy(x, y) * ny
+
+
+PI = math.pi
+
+SIN2PIX_EXPY = Manufactured(
+    "sin(2 pi x) exp(y)",
+    lambda x, y: np.sin(2 * PI * x) * np.exp(y),
+    lambda x, y: 2 * PI * np.cos(2 * PI * x) * np.exp(y),
+    lambda x, y: np.sin(2 * PI * x) * np.exp(y),
+    lambda x, y: -4 * PI * PI * np.sin(2 * PI * x) * np.exp(y),
+    lambda x, y: 2 * PI * np.cos(2 * PI * x) * np.exp(y),
+    lambda x, y: np.sin(2 * PI * x) * np.exp(y),
+)
+
+EXPX_COS3Y = Manufactured(
+    "exp(x) cos(3y)",
+    lambda x, y: np.exp(x) * np.cos(3 * y),
+    lambda x, y: np.exp(x) * np.cos(3 * y),
+    lambda x, y: -3 * np.exp(x) * np.sin(3 * y),
+    lambda x, y: np.exp(x) * np.cos(3 * y),
+    lambda x, y: -3 * np.exp(x) * np.sin(3 * y),
+    lambda x, y: -9 * np.exp(x) * np.cos(3 * y),
+)
+
+SINPIX_SINPIY = Manufactured(
+    "sin(pi x) sin(pi y)",
+    lambda x, y: np.sin(PI * x) * np.sin(PI * y),
+    lambda x, y: PI * np.cos(PI * x) * np.sin(PI * y),
+    lambda x, y: PI * np.sin(PI * x) * np.cos(PI * y),
+    lambda x, y: -PI * PI * np.sin(PI * x) * np.sin(PI * y),
+    lambda x, y: PI * PI * np.cos(PI * x) * np.cos(PI * y),
+    lambda x, y: -PI * PI * np.sin(PI * x) * np.sin(PI * y),
+)
+
+SINPIX_SIN2PIY_X3 = Manufactured(
+    "sin(pi x) sin(2 pi y) + x^3",
+    lambda x, y: np.sin(PI * x) * np.sin(2 * PI * y) + x ** 3,
+    lambda x, y: PI * np.cos(PI * x) * np.sin(2 * PI * y) + 3 * x ** 2,
+    lambda x, y: 2 * PI * np.sin(PI * x) * np.cos(2 * PI * y) + 0 * x,
+    lambda x, y: -PI * PI * np.sin(PI * x) * np.sin(2 * PI * y) + 6 * x,
+    lambda x, y: 2 * PI * PI * np.cos(PI * x) * np.cos(2 * PI * y),
+    lambda x, y: -4 * PI * PI * np.sin(PI * x) * np.sin(2 * PI * y) + 0 * x,
+)
+
+
+def polynomial(coeffs):
+    """Manufactured polynomial sum_{(p,q)} c x^p y^q given as {(p, q): c}."""
+    def term(dp, dq):
+        def fn(x, y):
+            out = 0.0 * x + 0.0 * y
+            for (p, q), c in coeffs.items():
+                if p < dp or q < dq:
+                    continue
+                k = c
+                for s in range(dp):
+                    k *= (p - s)
+                for s in range(dq):
+                    k *= (q - s)
+                out = out + k * x ** (p - dp) * y ** (q - dq)
+            return out
+        return fn
+    return Manufactured("poly", term(0, 0), term(1, 0), term(0, 1), term(2, 0), term(1, 1), term(0, 2))
+
+
+def fourier_rhs(seed, modes=8):
+    """f = sum_{p,q<=modes} c_pq sin(p pi x) sin(q pi y), c_pq ~ N(0,1)."""
+    c = np.random.default_rng(seed).standard_normal((modes, modes))
+
+    def f(x, y):
+        out = 0.0 * x
+        for p in range(modes):
+            sx = np.sin((p + 1) * PI * x)
+            for q in range(modes):
+                out = out + c[p, q] * sx * np.sin((q + 1) * PI * y)
+        return out
+    return f, c
+
+
+# ---------------------------------------------------------------------------
+# Seeded geometries.
+# ---------------------------------------------------------------------------
+def random_circles(seed, count, rmin, rmax, clearance=0.05, lo=0.0, hi=1.0):
+    """Non-overlapping circles in the box [lo,hi]^2, drawn by rejection."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        r = rng.uniform(rmin, rmax)
+        cx = rng.uniform(lo + r + clearance, hi - r - clearance)
+        cy = rng.uniform(lo + r + clearance, hi - r - clearance)
+        if all(math.hypot(cx - q[0], cy - q[1]) >= r + q[2] + clearance for q in out):
+            out.append((cx, cy, r))
+    return [circle(cx, cy, r) for cx, cy, r in out]
+
+
+def random_ellipses(seed, count, amin, amax, clearance=0.05, lo=0.0, hi=1.0, bc=DIRICHLET):
+    """Non-overlapping ellipses (bounding circles kept apart), random rotation."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        a1, a2 = rng.uniform(amin, amax, size=2)
+        rot = rng.uniform(0.0, PI)
+        R = max(a1, a2)
+        cx = rng.uniform(lo + R + clearance, hi - R - clearance)
+        cy = rng.uniform(lo + R + clearance, hi - R - clearance)
+        if all(math.hypot(cx - q[0], cy - q[1]) >= R + q[2] + clearance for q in out):
+            out.append((cx, cy, R, a1, a2, rot))
+    return [ellipse(cx, cy, a1, a2, rot, bc=bc) for cx, cy, R, a1, a2, rot in out]
+
+
+def grid(n, x0=0.0, y0=0.0, length=1.0):
+    return {"x0": x0, "y0": y0, "h": length / n, "nx": n, "ny": n}
+
+
+def config(k, n=None):
+    """The five synthetic workloads.  Returns a dict with grid, curves, (a,b,c),
+    manufactured solution (or None) and the right-hand side function."""
+    if k == 1:
+        n = n or 64
+        curves = [circle(0.5, 0.5, 0.3, inside=1)]
+        a, b, c = 1.0, 0.0, 1.0
+        sol = SIN2PIX_EXPY
+    elif k == 2:
+        n = n or 1024
+        curves = [box(), polar_sin(0.5, 0.5, 0.25, 0.05, 5, bc=NEUMANN)]
+        a, b, c = 1.0, 0.5, 1.0
+        sol = EXPX_COS3Y
+    elif k == 3:
+        n = n or 512
+        curves = [box(), circle(0.5, 0.5, 0.2)]
+        a, b, c = 1.0, 0.0, 1.0
+        sol = None
+    elif k == 4:
+        n = n or 2048
+        curves = [box()] + random_circles(4, 3, 0.05, 0.15)
+        a, b, c = 1.0, 0.0, 1.0
+        sol = SINPIX_SINPIY
+    elif k == 5:
+        n = n or 4096
+        curves = [box()] + random_ellipses(5, 5, 0.03, 0.12)
+        a, b, c = 1.0, 1.2, 1.0
+        sol = SINPIX_SIN2PIY_X3
+    else:
+        raise ValueError(k)
+    out = {"id": k, "grid": grid(n), "curves": curves, "a": a, "b": b, "c": c, "solution": sol}
+    if sol is not None:
+        out["f"] = sol.f(a, b, c)
+    else:
+        out["f"] = fourier_rhs(3000)[0]
+    return out
+
+
+def batch_geometries(count=32, seed0=3100):
+    """Config-3 geometry batch: grid sizes from {128,...,1024}, 1-3 ellipses."""
+    out = []
+    for g in range(count):
+        rng = np.random.default_rng(seed0 + g)
+        n = int(rng.choice([128, 256, 512, 1024]))
+        m = int(rng.integers(1, 4))
+        curves = [box()] + random_ellipses(seed0 + 1000 + g, m, 0.05, 0.2)
+        out.append({"id": f"3g{g}", "grid": grid(n), "curves": curves, "a": 1.0, "b": 0.0, "c": 1.0,
+                    "solution": None, "f": fourier_rhs(3000 + g)[0]})
+    return out
+
+
+def problem2(n, hole_bc=NEUMANN):
+    """Poisson on [0,1]^2 minus the ellipse c=(1/2,1/2), a=(1/8,1/4) (Section 5.1, Problem 2)."""
+    return {"id": "P2", "grid": grid(n), "curves": [box(), ellipse(0.5, 0.5, 0.125, 0.25, 0.0, bc=hole_bc)],
+            "a": 1.0, "b": 0.0, "c": 1.0, "solution": SINPIX_SINPIY, "f": SINPIX_SINPIY.f(1.0, 0.0, 1.0)}
+
+
+def random_field(seed, shape):
+    return np.random.default_rng(seed).standard_normal(shape)

@@ -1,0 +1,218 @@
+/*
+ * ccgmg.h -- C interface of the MI355X cut-cell geometric-multigrid solver
+ * for the fourth-order finite-volume discretisation of
+ *
+ *      a u_xx + b u_xy + c u_yy = f   in an irregular 2-D domain,  b^2 < 4ac,
+ *
+ * with Dirichlet or Neumann data on each boundary curve (problem statement:
+ * Section 1, eq. ccEllipticEq; boundary operators: Section 3.3).  The
+ * unknowns are cut-cell averages of u and the data are cell averages of f
+ * and boundary-face averages of g (Section 3.2).  The discrete system is
+ * L u + N g = f (eq. PoissonLinearDiscretization); the solver iterates
+ * multigrid V-cycles (Alg. 2) on L u = f - N g (eq. PoissonResidualForm).
+ *
+ * Conventions
+ *  - Every function returns a ccgmg_status (0 = OK, < 0 = error); no C++
+ *    exception crosses this interface.  On error a context is left unchanged
+ *    and ccgmg_last_error() describes the failure.
+ *  - Grids are row-major with x fastest: cell (i, j) has linear index
+ *    j * nx + i and covers (x0 + i h, x0 + (i+1) h) x (y0 + j h, y0 + (j+1) h).
+ *  - "device" pointers are HIP device memory on the context's device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the library owns the context and all its device data, which are
+ *    allocated in ccgmg_create and freed in ccgmg_destroy.
+ *  - All device work is ordered on options.hip_stream (0 = the null stream).
+ *    A context is not thread safe; distinct contexts are independent.
+ *  - Values on empty or merged-away cells are ignored on input and written
+ *    as zero on output.  A merged cell's value is the average over the union
+ *    (Section 3.1, Alg. 1).
+ */
+#ifndef CCGMG_H
+#define CCGMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque solver context; owned by the library (created by ccgmg_create,
+ * released by ccgmg_destroy). */
+typedef struct ccgmg_ctx ccgmg_ctx;
+
+typedef enum {
+  CCGMG_OK = 0,
+  CCGMG_EINVAL = -1,       /* bad argument, NaN/Inf input, size out of range      */
+  CCGMG_ENOTELLIPTIC = -2, /* b^2 - 4ac >= 0                                      */
+  CCGMG_EGEOM = -3,        /* curves leave the grid, lie inside one cell, ...     */
+  CCGMG_EPLG = -4,         /* no acceptable poised lattice on the finest grid     */
+  CCGMG_ESINGULAR = -5,    /* singular coarsest operator                          */
+  CCGMG_ENOCONV = -6,      /* max_cycles reached or the residual stagnated        */
+  CCGMG_EDEVICE = -7,      /* HIP runtime error                                   */
+  CCGMG_ENOMEM = -8        /* host or device allocation failed                    */
+} ccgmg_status;
+
+typedef enum { CCGMG_BOX = 0, CCGMG_CIRCLE = 1, CCGMG_ELLIPSE = 2, CCGMG_POLAR_SIN = 3,
+               CCGMG_POLAR_COS = 4 } ccgmg_curve_kind;
+
+typedef enum { CCGMG_DIRICHLET = 0, CCGMG_NEUMANN = 1 } ccgmg_bc;
+
+/* A boundary curve.  Parameter layouts (p[]):
+ *   BOX      x0, y0, x1, y1              (must equal the grid extent)
+ *   CIRCLE   cx, cy, r
+ *   ELLIPSE  cx, cy, a1, a2, rot
+ *   POLAR_*  cx, cy, r0, A, k, phase     r(t) = r0 + A sin|cos(k t + phase)
+ * domain_inside = 1 for the outer boundary (the domain is inside the
+ * curve), 0 for a hole.  bc is a ccgmg_bc; the Neumann normal points out of
+ * the domain. */
+typedef struct {
+  int kind;
+  double p[8];
+  int domain_inside;
+  int bc;
+} ccgmg_curve;
+
+typedef struct {
+  double x0, y0, h;
+  int nx, ny;
+} ccgmg_grid;
+
+typedef struct {
+  double theta;          /* small-cell merge threshold (Alg. 1), default 0.3              */
+  double w_min;          /* least-squares weight floor (eq. weightDef), default 0.5       */
+  double omega;          /* weighted-Jacobi factor of SMO-1, default 0.5                  */
+  int nu1, nu2;          /* pre/post smoothing steps, default 3, 3                        */
+  int coarsest_min_n;    /* smallest coarse grid side considered, default 16              */
+  int max_levels;        /* default 16                                                    */
+  int auto_depth;        /* 1: drop coarse levels whose V-cycles contract poorly          */
+  double depth_max_rate; /* contraction bound used by auto_depth, default 0.5            */
+  int precision;         /* 0: FP64 sweeps; 1: FP32 sweeps inside FP64 refinement         */
+  int prolongation;      /* 0: piecewise constant (Section 4.1); 1: bilinear              */
+  int smo2_every_sweep;  /* 1: SMO-2 after every SMO-1 sweep (Section 4.1); 0: after the
+                            last sweep of each smoothing phase only                        */
+  int smo2_iters;        /* block iterations per SMO-2 application, default 2             */
+  int smo2_block;        /* irregular cells per block, default 64                         */
+  int smo2_overlap;      /* overlap layers of a block in the matrix graph, default 2      */
+  double tol;            /* stop when ||f - N g - L u||_inf / ||f - N g||_inf <= tol      */
+  int max_cycles;        /* default 100                                                   */
+  int max_nrhs;          /* right-hand sides solved together, default 1                   */
+  int use_initial_guess; /* 1: u_hat holds the initial guess; 0: start from zero          */
+  int num_threads;       /* host threads for set-up (0 = hardware concurrency)            */
+  int use_graph;         /* 1: replay V-cycles from a captured hipGraph                   */
+  int host_only;         /* 1: build the hierarchy on the host only (no device calls);
+                            queries work, apply/solve return CCGMG_EINVAL                  */
+  void* hip_stream;      /* hipStream_t all device work is ordered on                     */
+} ccgmg_options;
+
+typedef struct {
+  long n_cells;          /* nx * ny on the finest grid                                    */
+  long n_unknowns;       /* non-empty cells after merging                                 */
+  long n_irregular;      /* cells discretised by least-squares rows                       */
+  long n_bdry_faces;     /* boundary faces = entries of g-hat                             */
+  int n_levels;
+  int nx_coarsest, ny_coarsest;
+  long coarse_unknowns;
+  double setup_seconds;
+  double plg_max_cond;
+} ccgmg_info;
+
+typedef struct {
+  int cycles;            /* V-cycles run (all outer iterations together)                  */
+  int outer_iters;       /* FP64 refinement steps (precision 1)                           */
+  double rel_res_inf;    /* final relative L-infinity residual (FP64, difference form)    */
+  double seconds;        /* device time of the solve                                      */
+  double history[64];    /* relative residual after each check                            */
+} ccgmg_report;
+
+/* Defaults from the paper: theta 0.3 (Fig. 1), w_min 1/2 (eq. weightDef),
+ * omega 0.5 and nu1 = nu2 = 3 (Fig. 5); tol 1e-10. */
+void ccgmg_default_options(ccgmg_options* opts);
+
+/* Set up the grid hierarchy (Section 4): cut cells and merging (Alg. 1),
+ * regular/irregular classification (Section 3.2), poised lattices and
+ * least-squares weights (Section 3.3, eq. derivedCoefAgain) on every level,
+ * the SMO-2 block data (Section 4.1, ordered by Alg. 3) and the inverse of
+ * the coarsest operator; uploads everything to the current HIP device.
+ * grid, curves, opts: host, read only.  *out receives the new context. */
+int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves, double a, double b,
+                 double c, const ccgmg_options* opts, ccgmg_ctx** out);
+
+int ccgmg_query(const ccgmg_ctx* ctx, ccgmg_info* info);
+
+/* Level-m classification (host arrays of nx_m * ny_m entries):
+ * kinds: 0 empty, 1 merged into another cell, 2 regular, 3 irregular pure,
+ * 4 irregular cut (or merged host); hosts: final host of a merged cell, else -1.
+ * Either pointer may be NULL. */
+int ccgmg_get_cell_kinds(const ccgmg_ctx* ctx, int level, int8_t* kinds, int32_t* hosts);
+
+/* Level-m grid side lengths. */
+int ccgmg_get_level_shape(const ccgmg_ctx* ctx, int level, int* nx, int* ny);
+
+/* Cut-cell volumes in units of h^2 (host, nx_m * ny_m). */
+int ccgmg_get_volumes(const ccgmg_ctx* ctx, int level, double* vol);
+
+/* Irregular rows of L on level m (Section 3.3): for the k-th irregular cell
+ * (increasing linear index) rows[k] is its index, cols[15k..15k+14] its
+ * lattice in increasing linear index, vals the weights (1/h^2 units) and
+ * cond[k] the 2-norm condition number of the lattice's cell-average sample
+ * matrix.  Host arrays sized by ccgmg_info.n_irregular for level 0 (query
+ * other levels with ccgmg_get_counts).  Any pointer may be NULL. */
+int ccgmg_get_counts(const ccgmg_ctx* ctx, int level, long* n_irregular, long* n_faces);
+int ccgmg_get_irregular(const ccgmg_ctx* ctx, int level, int32_t* rows, int32_t* cols, double* vals,
+                        double* cond);
+
+/* Boundary faces of level 0 in g-hat order: face k belongs to cell[k] and
+ * curve[k]; its weight in row cell[k] of N is nweight[k] (so that
+ * (N g)_cell = sum over the cell's faces of nweight * g).  Host arrays. */
+int ccgmg_get_boundary_faces(const ccgmg_ctx* ctx, int32_t* cell, int32_t* curve, double* nweight);
+
+/* Alg. 3 numbering of the level-m irregular cells: perm[p] is the linear
+ * index of the p-th cell in the order (host, n_irregular entries). */
+int ccgmg_get_alg3_order(const ccgmg_ctx* ctx, int level, int32_t* perm);
+
+/* Quadrature for callers that average their own f and g (Section 2.4).
+ * Cells: every non-pure non-empty level-0 cell gets nodes (x, y) and weights
+ * w with sum_q w_q f(x_q, y_q) ~= int over the cell of f / h^2 (exact for
+ * polynomials of degree <= 15 along the boundary pieces); pure cells are
+ * squares the caller integrates itself.  Faces: nodes along each boundary
+ * face with arclength weights (units of h) and the outward unit normal.
+ * Two-call pattern: pass NULL arrays to receive the counts.
+ * cell_of[k] / face_of[k]: owning cell / face index of node k. */
+int ccgmg_cell_quadrature(const ccgmg_ctx* ctx, long* count, int32_t* cell_of, double* x, double* y,
+                          double* w);
+int ccgmg_face_quadrature(const ccgmg_ctx* ctx, long* count, int32_t* face_of, double* x, double* y,
+                          double* w, double* nx, double* ny);
+
+/* (L u) on every non-empty level-0 cell, N g not included.
+ * u, Lu: device, nx * ny doubles; may not alias. */
+int ccgmg_apply(ccgmg_ctx* ctx, const double* u, double* Lu);
+
+/* Set the boundary data g-hat (device, n_bdry_faces * nrhs doubles, face
+ * fastest).  The library copies it; nrhs <= max_nrhs. */
+int ccgmg_set_boundary(ccgmg_ctx* ctx, const double* g_hat, int nrhs);
+
+/* Solve L u = f - N g for nrhs right-hand sides: f_hat device
+ * [nrhs][ny][nx], u_hat device [nrhs][ny][nx] (initial guess in, solution
+ * out).  rep: host, may be NULL.  Returns CCGMG_ENOCONV (with u_hat holding
+ * the last iterate) when tol is not reached. */
+int ccgmg_solve(ccgmg_ctx* ctx, const double* f_hat, double* u_hat, int nrhs, ccgmg_report* rep);
+
+/* Adjoint solve L^T lambda = rhs (device arrays as in ccgmg_solve), by
+ * V-cycles on the transposed operators. */
+int ccgmg_solve_adjoint(ccgmg_ctx* ctx, const double* rhs, double* lambda, int nrhs, ccgmg_report* rep);
+
+/* out = N^T lambda (device; lambda nx*ny, out n_bdry_faces doubles). */
+int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out);
+
+const char* ccgmg_last_error(const ccgmg_ctx* ctx);
+
+/* Error text of the last failed ccgmg_create on this thread. */
+const char* ccgmg_create_error(void);
+
+void ccgmg_destroy(ccgmg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCGMG_H */

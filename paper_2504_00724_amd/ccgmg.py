@@ -1,0 +1,255 @@
+"""ctypes binding of libccgmg.so (the C interface in include/ccgmg.h).
+
+Argument marshalling only: every step of the set-up and the solve runs in
+the native library.  Device arrays are passed as raw pointers of torch CUDA
+(HIP) tensors; torch supplies device memory and the stream.  The library
+must be built (``paper_2504_00724_amd.build.build()``); loading fails loudly
+otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccgmg.so")
+
+OK, EINVAL, ENOTELLIPTIC, EGEOM, EPLG, ESINGULAR, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTELLIPTIC", -3: "EGEOM", -4: "EPLG", -5: "ESINGULAR", -6: "ENOCONV",
+          -7: "EDEVICE", -8: "ENOMEM"}
+
+EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
+           "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_boundary_faces",
+           "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
+           "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_NT", "ccgmg_last_error",
+           "ccgmg_create_error", "ccgmg_destroy"]
+
+
+class CurveT(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double * 8), ("domain_inside", C.c_int), ("bc", C.c_int)]
+
+
+class GridT(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("h", C.c_double), ("nx", C.c_int), ("ny", C.c_int)]
+
+
+class OptionsT(C.Structure):
+    _fields_ = [("theta", C.c_double), ("w_min", C.c_double), ("omega", C.c_double), ("nu1", C.c_int),
+                ("nu2", C.c_int), ("coarsest_min_n", C.c_int), ("max_levels", C.c_int), ("auto_depth", C.c_int),
+                ("depth_max_rate", C.c_double), ("precision", C.c_int), ("prolongation", C.c_int),
+                ("smo2_every_sweep", C.c_int), ("smo2_iters", C.c_int), ("smo2_block", C.c_int),
+                ("smo2_overlap", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
+                ("use_initial_guess", C.c_int), ("num_threads", C.c_int), ("use_graph", C.c_int),
+                ("host_only", C.c_int), ("hip_stream", C.c_void_p)]
+
+
+class InfoT(C.Structure):
+    _fields_ = [("n_cells", C.c_long), ("n_unknowns", C.c_long), ("n_irregular", C.c_long),
+                ("n_bdry_faces", C.c_long), ("n_levels", C.c_int), ("nx_coarsest", C.c_int),
+                ("ny_coarsest", C.c_int), ("coarse_unknowns", C.c_long), ("setup_seconds", C.c_double),
+                ("plg_max_cond", C.c_double)]
+
+
+class ReportT(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("outer_iters", C.c_int), ("rel_res_inf", C.c_double),
+                ("seconds", C.c_double), ("history", C.c_double * 64)]
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libccgmg.so is not built; run paper_2504_00724_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, ip = C.c_void_p, C.c_int
+        L.ccgmg_default_options.argtypes = [C.POINTER(OptionsT)]
+        L.ccgmg_default_options.restype = None
+        L.ccgmg_create.argtypes = [C.POINTER(GridT), C.POINTER(CurveT), ip, C.c_double, C.c_double, C.c_double,
+                                   C.POINTER(OptionsT), C.POINTER(vp)]
+        L.ccgmg_query.argtypes = [vp, C.POINTER(InfoT)]
+        L.ccgmg_get_cell_kinds.argtypes = [vp, ip, vp, vp]
+        L.ccgmg_get_level_shape.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
+        L.ccgmg_get_volumes.argtypes = [vp, ip, vp]
+        L.ccgmg_get_counts.argtypes = [vp, ip, C.POINTER(C.c_long), C.POINTER(C.c_long)]
+        L.ccgmg_get_irregular.argtypes = [vp, ip, vp, vp, vp, vp]
+        L.ccgmg_get_boundary_faces.argtypes = [vp, vp, vp, vp]
+        L.ccgmg_get_alg3_order.argtypes = [vp, ip, vp]
+        L.ccgmg_cell_quadrature.argtypes = [vp, C.POINTER(C.c_long), vp, vp, vp, vp]
+        L.ccgmg_face_quadrature.argtypes = [vp, C.POINTER(C.c_long), vp, vp, vp, vp, vp, vp]
+        L.ccgmg_apply.argtypes = [vp, vp, vp]
+        L.ccgmg_set_boundary.argtypes = [vp, vp, ip]
+        L.ccgmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
+        L.ccgmg_solve_adjoint.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
+        L.ccgmg_apply_NT.argtypes = [vp, vp, vp]
+        L.ccgmg_last_error.argtypes = [vp]
+        L.ccgmg_last_error.restype = C.c_char_p
+        L.ccgmg_create_error.argtypes = []
+        L.ccgmg_create_error.restype = C.c_char_p
+        L.ccgmg_destroy.argtypes = [vp]
+        L.ccgmg_destroy.restype = None
+        _LIB = L
+    return _LIB
+
+
+class CcgmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+def default_options(**kw):
+    o = OptionsT()
+    lib().ccgmg_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a):
+    """Raw pointer of a numpy array or a torch tensor."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+class Solver:
+    """One context: geometry and coefficients fixed at construction."""
+
+    def __init__(self, grid, curves, a, b, c, **options):
+        L = lib()
+        g = GridT(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
+        cs = (CurveT * len(curves))()
+        for k, cu in enumerate(curves):
+            cs[k].kind = cu["kind"]
+            for t, v in enumerate(cu["p"]):
+                cs[k].p[t] = v
+            cs[k].domain_inside = cu["inside"]
+            cs[k].bc = cu["bc"]
+        self.options = default_options(**options)
+        self.ctx = C.c_void_p()
+        st = L.ccgmg_create(C.byref(g), cs, len(curves), a, b, c, C.byref(self.options), C.byref(self.ctx))
+        if st != OK:
+            raise CcgmgError(st, L.ccgmg_create_error().decode())
+        self.nx, self.ny = grid["nx"], grid["ny"]
+        self.info = self.query()
+
+    def _check(self, st):
+        if st != OK:
+            raise CcgmgError(st, lib().ccgmg_last_error(self.ctx).decode())
+
+    def close(self):
+        if self.ctx:
+            lib().ccgmg_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries -----------------------------------------------------------------
+    def query(self):
+        i = InfoT()
+        self._check(lib().ccgmg_query(self.ctx, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in InfoT._fields_}
+
+    def level_shape(self, level):
+        nx, ny = C.c_int(), C.c_int()
+        self._check(lib().ccgmg_get_level_shape(self.ctx, level, C.byref(nx), C.byref(ny)))
+        return nx.value, ny.value
+
+    def kinds(self, level=0):
+        nx, ny = self.level_shape(level)
+        k = np.zeros(nx * ny, dtype=np.int8)
+        h = np.zeros(nx * ny, dtype=np.int32)
+        self._check(lib().ccgmg_get_cell_kinds(self.ctx, level, _ptr(k), _ptr(h)))
+        return k, h
+
+    def volumes(self, level=0):
+        nx, ny = self.level_shape(level)
+        v = np.zeros(nx * ny)
+        self._check(lib().ccgmg_get_volumes(self.ctx, level, _ptr(v)))
+        return v
+
+    def counts(self, level=0):
+        ni, nf = C.c_long(), C.c_long()
+        self._check(lib().ccgmg_get_counts(self.ctx, level, C.byref(ni), C.byref(nf)))
+        return ni.value, nf.value
+
+    def irregular(self, level=0):
+        ni, _ = self.counts(level)
+        rows = np.zeros(ni, dtype=np.int32)
+        cols = np.zeros(ni * 15, dtype=np.int32)
+        vals = np.zeros(ni * 15)
+        cond = np.zeros(ni)
+        self._check(lib().ccgmg_get_irregular(self.ctx, level, _ptr(rows), _ptr(cols), _ptr(vals), _ptr(cond)))
+        return rows, cols.reshape(ni, 15), vals.reshape(ni, 15), cond
+
+    def boundary_faces(self):
+        nf = self.info["n_bdry_faces"]
+        cell = np.zeros(nf, dtype=np.int32)
+        curve = np.zeros(nf, dtype=np.int32)
+        w = np.zeros(nf)
+        self._check(lib().ccgmg_get_boundary_faces(self.ctx, _ptr(cell), _ptr(curve), _ptr(w)))
+        return cell, curve, w
+
+    def alg3_order(self, level=0):
+        ni, _ = self.counts(level)
+        p = np.zeros(ni, dtype=np.int32)
+        self._check(lib().ccgmg_get_alg3_order(self.ctx, level, _ptr(p)))
+        return p
+
+    def cell_quadrature(self):
+        n = C.c_long(0)
+        self._check(lib().ccgmg_cell_quadrature(self.ctx, C.byref(n), None, None, None, None))
+        cell = np.zeros(n.value, dtype=np.int32)
+        x, y, w = np.zeros(n.value), np.zeros(n.value), np.zeros(n.value)
+        self._check(lib().ccgmg_cell_quadrature(self.ctx, C.byref(n), _ptr(cell), _ptr(x), _ptr(y), _ptr(w)))
+        return cell, x, y, w
+
+    def face_quadrature(self):
+        n = C.c_long(0)
+        self._check(lib().ccgmg_face_quadrature(self.ctx, C.byref(n), None, None, None, None, None, None))
+        out = [np.zeros(n.value, dtype=np.int32)] + [np.zeros(n.value) for _ in range(5)]
+        self._check(lib().ccgmg_face_quadrature(self.ctx, C.byref(n), *[_ptr(a) for a in out]))
+        return tuple(out)
+
+    # -- device calls ------------------------------------------------------------
+    def apply(self, u, out):
+        self._check(lib().ccgmg_apply(self.ctx, _ptr(u), _ptr(out)))
+
+    def set_boundary(self, g, nrhs=1):
+        self._check(lib().ccgmg_set_boundary(self.ctx, _ptr(g), nrhs))
+
+    def solve(self, f, u, nrhs=1, raise_on_noconv=True):
+        rep = ReportT()
+        st = lib().ccgmg_solve(self.ctx, _ptr(f), _ptr(u), nrhs, C.byref(rep))
+        if st != OK and (raise_on_noconv or st != ENOCONV):
+            self._check(st)
+        return _report(rep, st)
+
+    def solve_adjoint(self, rhs, lam, nrhs=1, raise_on_noconv=True):
+        rep = ReportT()
+        st = lib().ccgmg_solve_adjoint(self.ctx, _ptr(rhs), _ptr(lam), nrhs, C.byref(rep))
+        if st != OK and (raise_on_noconv or st != ENOCONV):
+            self._check(st)
+        return _report(rep, st)
+
+    def apply_NT(self, lam, out):
+        self._check(lib().ccgmg_apply_NT(self.ctx, _ptr(lam), _ptr(out)))
+
+
+def _report(rep, st):
+    return {"status": st, "cycles": rep.cycles, "outer_iters": rep.outer_iters, "rel_res_inf": rep.rel_res_inf,
+            "seconds": rep.seconds, "history": list(rep.history[:min(64, max(rep.cycles, 0))])}

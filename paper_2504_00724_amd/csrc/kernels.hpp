@@ -1,0 +1,76 @@
+// HIP kernels of the cut-cell multigrid V-cycle for gfx950.
+//
+// Layout: every level stores cell averages row-major [nrhs][ny][nx] (x
+// fastest); blockIdx.z selects the right-hand side.  kind[] holds one byte
+// per cell: bit 0 = regular (Section 3.2), bit 1 = non-empty.
+//
+// Regular rows use the fourth-order formulas eq. stdLap (u_xx, u_yy) and the
+// twice-applied eq. stdGrad (u_xy) in difference form,
+//   (L u)_i = sum_{m != 0} c_m (u_{i+m} - u_i),
+// an exact rewrite because the stencil coefficients sum to zero; it keeps
+// the FP64 rounding floor of the residual near eps * h |grad u| / h^2
+// instead of eps * |u| / h^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccgk {
+
+constexpr int TX = 64;        // tile width (one wavefront per row)
+constexpr int TY = 16;        // tile height; 4 waves x 4 rows each
+constexpr int HALO = 2;       // half width of the 5x5 stencil
+constexpr int LW = TX + 2 * HALO;
+constexpr int LH = TY + 2 * HALO;
+constexpr int BLOCK = 256;
+
+struct Coef {                 // regular stencil, units 1/h^2
+  double ax1, ax2;            // 16a/12h^2, -a/12h^2
+  double cy1, cy2;            // 16c/12h^2, -c/12h^2
+  double bxy;                 // b/144h^2
+  double omega_invD;          // omega / D, D = -30(a+c)/12h^2
+};
+
+template <typename T>
+struct CoefT {
+  T ax1, ax2, cy1, cy2, bxy, omega_invD;
+  __host__ __device__ CoefT() {}
+  __host__ CoefT(const Coef& c)
+      : ax1((T)c.ax1), ax2((T)c.ax2), cy1((T)c.cy1), cy2((T)c.cy2), bxy((T)c.bxy), omega_invD((T)c.omega_invD) {}
+};
+
+// Stage the (TY+4) x (TX+4) neighbourhood of a tile in LDS; outside the grid
+// the value is 0 (never read by a regular cell).
+template <typename T>
+__device__ __forceinline__ void load_tile(T (*tile)[LW], const T* __restrict__ u, int nx, int ny, int bx, int by) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < LH * LW; k += BLOCK) {
+    const int ly = k / LW, lx = k - ly * LW;
+    const int gx = bx + lx - HALO, gy = by + ly - HALO;
+    T v = (T)0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = u[(size_t)gy * nx + gx];
+    tile[ly][lx] = v;
+  }
+}
+
+// (L u) at tile position (ly, lx) (already offset by HALO), difference form.
+template <typename T, bool CROSS>
+__device__ __forceinline__ T apply_regular(const T (*t)[LW], int ly, int lx, const CoefT<T>& c) {
+  const T uc = t[ly][lx];
+  const T two = (T)2 * uc;
+  T acc = c.ax1 * ((t[ly][lx + 1] + t[ly][lx - 1]) - two) + c.ax2 * ((t[ly][lx + 2] + t[ly][lx - 2]) - two) +
+          c.cy1 * ((t[ly + 1][lx] + t[ly - 1][lx]) - two) + c.cy2 * ((t[ly + 2][lx] + t[ly - 2][lx]) - two);
+  if (CROSS) {
+    // sum_{m1,m2} g(m1) g(m2) u, g(+-1) = +-8, g(+-2) = -+1, as nested differences
+    T d[5];
+#pragma unroll
+    for (int m = -2; m <= 2; ++m) {
+      if (m == 0) continue;
+      d[m + 2] = (T)8 * (t[ly + 1][lx + m] - t[ly - 1][lx + m]) - (t[ly + 2][lx + m] - t[ly - 2][lx + m]);
+    }
+    acc += c.bxy * ((T)8 * (d[3] - d[1]) - (d[4] - d[0]));
+  }
+  return acc;
+}
+
+}  // namespace ccgk

@@ -1,0 +1,116 @@
+"""The C-ABI library on the CPU: exported symbols, host-side set-up parity
+with the oracle (bit-exact classification, lattices and Alg. 3 order;
+least-squares weights within 1e-12 in h^2 units) and error codes."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.discretization import Discretization
+from oracle.geometry import build_cut_grid
+from oracle.multigrid import alg3_order
+
+ccgmg = pytest.importorskip("paper_2504_00724_amd.ccgmg")
+
+
+def _lib_or_skip():
+    try:
+        return ccgmg.lib()
+    except RuntimeError as e:       # not built
+        pytest.skip(str(e))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    header = open(ccgmg.os.path.join(ccgmg.HERE, "..", "include", "ccgmg.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(ccgmg_\w+)\s*\(", header, re.M))
+    assert declared == set(ccgmg.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("k,n", [(1, 64), (2, 64), (4, 64), (5, 64), (2, 128)])
+def test_host_setup_matches_oracle(k, n):
+    _lib_or_skip()
+    cfg = W.config(k, n=n)
+    S = ccgmg.Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], host_only=1, max_levels=1)
+    cg = build_cut_grid(cfg["grid"], cfg["curves"])
+    d = Discretization(cg, cfg["a"], cfg["b"], cfg["c"])
+    kind, host = S.kinds(0)
+    assert np.array_equal(kind, d.kind)
+    assert np.array_equal(host, cg.host)
+    assert np.max(np.abs(S.volumes(0) - cg.vol)) < 1e-14
+    rows, cols, vals, cond = S.irregular(0)
+    assert np.array_equal(rows, d.irregular)
+    for i, q in enumerate(rows):
+        assert list(cols[i]) == d.stencils[int(q)]
+        assert np.max(np.abs(vals[i] - d.weights[int(q)])) * cg.h ** 2 <= 1e-12
+        assert abs(cond[i] - d.conds[int(q)]) <= 1e-8 * d.conds[int(q)]
+    cell, curve, nw = S.boundary_faces()
+    assert [(int(a), int(b)) for a, b in zip(cell, curve)] == d.faces
+    ref = np.zeros(len(d.faces))
+    for q, fws in d.face_weights.items():
+        for fk, v in fws:
+            ref[fk] = v
+    assert np.max(np.abs(nw - ref)) * cg.h ** 2 <= 1e-12
+    assert np.array_equal(S.alg3_order(0), d.irregular[alg3_order(d)])
+    S.close()
+
+
+def test_coarse_levels_match_oracle():
+    _lib_or_skip()
+    cfg = W.config(4, n=128)
+    S = ccgmg.Solver(cfg["grid"], cfg["curves"], 1.0, 0.0, 1.0, host_only=1, coarsest_min_n=32)
+    assert S.info["n_levels"] >= 2
+    cg = build_cut_grid(W.grid(64), cfg["curves"])
+    d = Discretization(cg, 1.0, 0.0, 1.0)
+    assert S.level_shape(1) == (64, 64)
+    kind, _ = S.kinds(1)
+    assert np.array_equal(kind, d.kind)
+    rows, cols, vals, _ = S.irregular(1)
+    for i, q in enumerate(rows):
+        assert list(cols[i]) == d.stencils[int(q)]
+
+
+def test_quadrature_export_integrates_polynomials():
+    """sum_q w_q f(x_q, y_q) over a cut cell equals its area moments."""
+    _lib_or_skip()
+    cfg = W.config(1, n=32)
+    S = ccgmg.Solver(cfg["grid"], cfg["curves"], 1.0, 0.0, 1.0, host_only=1, max_levels=1)
+    cell, x, y, w = S.cell_quadrature()
+    vol = S.volumes(0)
+    area = np.bincount(cell, weights=w, minlength=32 * 32)
+    cut = np.unique(cell)
+    assert np.max(np.abs(area[cut] - vol[cut])) < 1e-13
+    mx = np.bincount(cell, weights=w * x * x * y, minlength=32 * 32)
+    cg = build_cut_grid(cfg["grid"], cfg["curves"])
+    from oracle.geometry import cell_averages
+    ref = cell_averages(cg, lambda X, Y: X * X * Y).ravel() * cg.vol
+    assert np.max(np.abs(mx[cut] - ref[cut])) < 1e-13
+    fcell, fx, fy, fw, fnx, fny = S.face_quadrature()
+    length = np.sum(fw) * cfg["grid"]["h"]
+    assert abs(length - 2 * np.pi * 0.3) < 1e-12
+
+
+@pytest.mark.parametrize("curves,abc,code", [
+    ([W.box()], (1.0, 2.0, 1.0), ccgmg.ENOTELLIPTIC),
+    ([W.box(), W.circle(0.95, 0.5, 0.2)], (1.0, 0.0, 1.0), ccgmg.EGEOM),
+    ([W.box(), W.circle(0.515, 0.515, 0.005)], (1.0, 0.0, 1.0), ccgmg.EGEOM),
+    ([W.box(x1=0.9)], (1.0, 0.0, 1.0), ccgmg.EGEOM),
+])
+def test_error_codes(curves, abc, code):
+    _lib_or_skip()
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        ccgmg.Solver(W.grid(32), curves, *abc, host_only=1)
+    assert ei.value.code == code
+
+
+def test_host_only_context_refuses_device_calls():
+    _lib_or_skip()
+    S = ccgmg.Solver(W.grid(16), [W.box()], 1.0, 0.0, 1.0, host_only=1)
+    buf = np.zeros(256)
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        S.apply(buf, buf.copy())
+    assert ei.value.code == ccgmg.EINVAL

@@ -90,7 +90,7 @@ typedef struct {
   int prolongation;      /* 0: piecewise constant (Section 4.1); 1: bilinear              */
   int smo2_every_sweep;  /* 1: SMO-2 after every SMO-1 sweep (Section 4.1); 0: after the
                             last sweep of each smoothing phase only                        */
-  int smo2_iters;        /* block iterations per SMO-2 application, default 2             */
+  int smo2_iters;        /* block iterations per SMO-2 application, default 1             */
   int smo2_block;        /* irregular cells per block, default 64                         */
   int smo2_overlap;      /* overlap layers of a block in the matrix graph, default 2      */
   double tol;            /* stop when ||f - N g - L u||_inf / ||f - N g||_inf <= tol      */
@@ -203,6 +203,15 @@ int ccgmg_solve_adjoint(ccgmg_ctx* ctx, const double* rhs, double* lambda, int n
 
 /* out = N^T lambda (device; lambda nx*ny, out n_bdry_faces doubles). */
 int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out);
+
+/* Diagnostic timing: launch one V-cycle kernel `reps` times on the
+ * context's stream, on the context's own work buffers of level `level`
+ * (one right-hand side), bracketed by HIP events; *avg_us receives the mean
+ * duration per launch in microseconds.  kernel: 0 SMO-1 sweep (FP64),
+ * 1 residual + restriction (FP64), 2 prolongation (FP64), 3 SMO-2 block
+ * pass (FP64), 4 coarsest solve, 5 SMO-1 sweep (FP32).  Leaves the work
+ * buffers of that level undefined; no user buffer is touched. */
+int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double* avg_us);
 
 const char* ccgmg_last_error(const ccgmg_ctx* ctx);
 

@@ -23,7 +23,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTELLIPTIC", -3: "EGEOM", -4: "EPLG", -5
 EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
-           "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_NT", "ccgmg_last_error",
+           "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_NT", "ccgmg_profile_kernel",
+           "ccgmg_last_error",
            "ccgmg_create_error", "ccgmg_destroy"]
 
 
@@ -87,6 +88,7 @@ def lib():
         L.ccgmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
         L.ccgmg_solve_adjoint.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
         L.ccgmg_apply_NT.argtypes = [vp, vp, vp]
+        L.ccgmg_profile_kernel.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_double)]
         L.ccgmg_last_error.argtypes = [vp]
         L.ccgmg_last_error.restype = C.c_char_p
         L.ccgmg_create_error.argtypes = []
@@ -245,6 +247,12 @@ class Solver:
         if st != OK and (raise_on_noconv or st != ENOCONV):
             self._check(st)
         return _report(rep, st)
+
+    def profile_kernel(self, kernel, level=0, reps=50):
+        """Mean duration (microseconds) of one V-cycle kernel, HIP events."""
+        us = C.c_double()
+        self._check(lib().ccgmg_profile_kernel(self.ctx, kernel, level, reps, C.byref(us)))
+        return us.value
 
     def apply_NT(self, lam, out):
         self._check(lib().ccgmg_apply_NT(self.ctx, _ptr(lam), _ptr(out)))

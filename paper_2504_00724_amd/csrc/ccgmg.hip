@@ -38,7 +38,9 @@ using namespace ccgk;
 
 // SMO-1: u_out = u + omega/D (r - L u) on regular cells, u_out = u elsewhere
 // (Jacobi: reads u, writes a second buffer).
-template <typename T, bool CROSS>
+// FINEST only selects a separate instantiation for the finest level so that
+// kernel traces separate it from the coarse levels; the code is the same.
+template <typename T, bool CROSS, bool FINEST>
 __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const T* __restrict__ r,
                                                  const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
                                                  int ny, CoefT<T> c) {
@@ -46,25 +48,34 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const 
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   u += zoff, r += zoff, out += zoff;
   const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
+  // issue the kind and right-hand-side loads before the tile barrier
+  uint8_t kd[TY / 4];
+  T rr[TY / 4];
+#pragma unroll
+  for (int k = 0; k < TY / 4; ++k) {
+    const int gx = bx + tx, gy = by + w + 4 * k;
+    const bool in = gx < nx && gy < ny;
+    kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
+    rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
+  }
   load_tile(tile, u, nx, ny, bx, by);
   __syncthreads();
-  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < TY / 4; ++k) {
     const int ry = w + 4 * k;
     const int gx = bx + tx, gy = by + ry;
     if (gx < nx && gy < ny) {
-      const size_t g = (size_t)gy * nx + gx;
       T v = tile[ry + HALO][tx + HALO];
-      if (kind[g] & 1) v += c.omega_invD * (r[g] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c));
-      out[g] = v;
+      if (kd[k] & 1) v += c.omega_invD * (rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c));
+      out[(size_t)gy * nx + gx] = v;
     }
   }
 }
 
 // Residual of the regular cells restricted to the coarse grid:
 // rc_I = 1/4 sum over regular children c of (r - L u)_c  (Section 4.1).
-template <typename T, typename TC, bool CROSS>
+template <typename T, typename TC, bool CROSS, bool FINEST>
 __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, const T* __restrict__ r,
                                                     const uint8_t* __restrict__ kind, TC* __restrict__ rc, int nx,
                                                     int ny, int ncx, int ncy, CoefT<T> c) {
@@ -73,23 +84,25 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, con
   u += zoff, r += zoff;
   rc += (size_t)blockIdx.z * ncx * ncy;
   const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+  const int cx = threadIdx.x & 31, cy = threadIdx.x >> 5;  // 32 x 8 coarse cells
+  uint8_t kd[4];
+  T rr[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int gx = bx + 2 * cx + (d & 1), gy = by + 2 * cy + (d >> 1);
+    const bool in = gx < nx && gy < ny;
+    kd[d] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
+    rr[d] = in ? r[(size_t)gy * nx + gx] : (T)0;
+  }
   load_tile(tile, u, nx, ny, bx, by);
   __syncthreads();
-  const int cx = threadIdx.x & 31, cy = threadIdx.x >> 5;  // 32 x 8 coarse cells
   const int I = blockIdx.x * (TX / 2) + cx, J = blockIdx.y * (TY / 2) + cy;
   if (I >= ncx || J >= ncy) return;
   T s = (T)0;
 #pragma unroll
-  for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-    for (int dx = 0; dx < 2; ++dx) {
-      const int lx = 2 * cx + dx, ly = 2 * cy + dy;
-      const int gx = bx + lx, gy = by + ly;
-      if (gx < nx && gy < ny) {
-        const size_t g = (size_t)gy * nx + gx;
-        if (kind[g] & 1) s += r[g] - apply_regular<T, CROSS>(tile, ly + HALO, lx + HALO, c);
-      }
-    }
+  for (int d = 0; d < 4; ++d)
+    if (kd[d] & 1)
+      s += rr[d] - apply_regular<T, CROSS>(tile, 2 * cy + (d >> 1) + HALO, 2 * cx + (d & 1) + HALO, c);
   rc[(size_t)J * ncx + I] = (TC)((T)0.25 * s);
 }
 
@@ -120,18 +133,18 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(T* __restrict__ u, const T* _
 }
 
 // SMO-2 by restricted additive Schwarz.  Workgroup = one block of <= 64
-// consecutive irregular cells (Alg. 3 numbering) plus its overlap.  Every
-// thread first evaluates irregular-row residuals of the overlapped set,
-//   res_k = r_k - bterm_k - sum_t beta_kt (u_t - u_k) - S_k u_k   (FP64),
-// then the block's own rows of the precomputed inverse are applied:
-// du_own = (A_ext^{-1})_{own,:} res_ext.  du is added by k_add_du.
+// consecutive irregular cells (Alg. 3 numbering) plus its overlap.  The
+// rows of the overlapped set are stored per block (cell, 15 columns, 15
+// weights, row sum), so a residual needs one level of gathers:
+//   res_t = r_q - bterm - sum_s beta_ts (u_s - u_q) - S_t u_q   (FP64),
+// then the block's own rows of the precomputed inverse are applied,
+// du_own = (A_ext^{-1})_{own,:} res_ext; du is added by k_add_du.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_smo2(const T* __restrict__ u, const T* __restrict__ r,
-                                                const double* __restrict__ bterm, const int32_t* __restrict__ cell,
-                                                const int32_t* __restrict__ cols, const double* __restrict__ vals,
-                                                const double* __restrict__ rowsum,
+                                                const double* __restrict__ bterm, const int32_t* __restrict__ ecell,
+                                                const int32_t* __restrict__ ecols, const double* __restrict__ evals,
+                                                const double* __restrict__ ersum, const int32_t* __restrict__ eirr,
                                                 const int32_t* __restrict__ ext_ptr,
-                                                const int32_t* __restrict__ ext_idx,
                                                 const int32_t* __restrict__ own_cnt,
                                                 const int64_t* __restrict__ inv_off,
                                                 const double* __restrict__ inv, double* __restrict__ du, int nirr,
@@ -142,26 +155,35 @@ __global__ __launch_bounds__(BLOCK) void k_smo2(const T* __restrict__ u, const T
   u += (size_t)z * plane, r += (size_t)z * plane;
   const int e0 = ext_ptr[b], ne = ext_ptr[b + 1] - e0, nown = own_cnt[b];
   for (int t = threadIdx.x; t < ne; t += BLOCK) {
-    const int k = ext_idx[e0 + t];
-    const int q = cell[k];
+    const size_t e = (size_t)(e0 + t);
+    const int q = ecell[e];
+    int cl[15];
+#pragma unroll
+    for (int s = 0; s < 15; ++s) cl[s] = ecols[e * 15 + s];
     const double uq = (double)u[q];
+    double rhs = (double)r[q];
+    if (bterm) rhs -= bterm[(size_t)z * nirr + eirr[e]];
     double acc = 0.0;
 #pragma unroll
-    for (int s = 0; s < 15; ++s) acc += vals[15 * k + s] * ((double)u[cols[15 * k + s]] - uq);
-    double rhs = (double)r[q];
-    if (bterm) rhs -= bterm[(size_t)z * nirr + k];
-    res[t] = rhs - acc - rowsum[k] * uq;
+    for (int s = 0; s < 15; ++s) acc += evals[e * 15 + s] * ((double)u[cl[s]] - uq);
+    res[t] = rhs - acc - ersum[e] * uq;
   }
   __syncthreads();
   const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  double s = 0.0;
+  double s0 = 0.0, s1 = 0.0;
   if (row < nown) {
-    const double* A = inv + inv_off[b];
-    for (int col = grp; col < ne; col += 4) s += A[(size_t)col * nown + row] * res[col];
+    const double* A = inv + inv_off[b] + row;
+    int col = grp;
+    for (; col + 4 < ne; col += 8) {
+      s0 += A[(size_t)col * nown] * res[col];
+      s1 += A[(size_t)(col + 4) * nown] * res[col + 4];
+    }
+    if (col < ne) s0 += A[(size_t)col * nown] * res[col];
   }
-  part[grp][row] = s;
+  part[grp][row] = s0 + s1;
   __syncthreads();
-  if (grp == 0 && row < nown) du[(size_t)z * nirr + ext_idx[e0 + row]] = part[0][row] + part[1][row] + part[2][row] + part[3][row];
+  if (grp == 0 && row < nown)
+    du[(size_t)z * nirr + eirr[e0 + row]] = part[0][row] + part[1][row] + part[2][row] + part[3][row];
 }
 
 template <typename T>
@@ -315,7 +337,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual_f32(const double* __restrict
 }
 
 // Coarsest level: u[cell_k] = sum_j Inv[k, j] r[cell_j] (FP64), one wavefront
-// per row, the gathered right-hand side staged in LDS.
+// per row (4 rows per workgroup), the gathered right-hand side staged in LDS.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
                                                   const int32_t* __restrict__ cell, const double* __restrict__ inv,
@@ -325,14 +347,17 @@ __global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __
   u += (size_t)z * plane, r += (size_t)z * plane;
   for (int k = threadIdx.x; k < nm; k += BLOCK) rv[k] = (double)r[cell[k]];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int row = blockIdx.x * 16 + wv; row < min(nm, (int)(blockIdx.x * 16 + 16)); row += 4) {
-    const double* A = inv + (size_t)row * nm;
-    double s = 0.0;
-    for (int k = lane; k < nm; k += 64) s += A[k] * rv[k];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) u[cell[row]] = (T)s;
-  }
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= nm) return;
+  const double* A = inv + (size_t)row * nm;
+  double s0 = 0.0, s1 = 0.0;
+  int k = lane;
+  for (; k + 64 < nm; k += 128) s0 += A[k] * rv[k], s1 += A[k + 64] * rv[k + 64];
+  if (k < nm) s0 += A[k] * rv[k];
+  double s = s0 + s1;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) u[cell[row]] = (T)s;
 }
 
 // Boundary term of the irregular rows: bterm_k = sum over k's faces of N g.
@@ -403,6 +428,8 @@ T* upload(const std::vector<T>& v, std::vector<void*>& owned) {
 struct Smo2Data {                 // RAS blocks of one level (one orientation)
   int nblk = 0;
   int32_t *ext_ptr = nullptr, *ext_idx = nullptr, *own_cnt = nullptr;
+  int32_t *ecell = nullptr, *ecols = nullptr;   // per overlapped row: cell, 15 columns
+  double *evals = nullptr, *ersum = nullptr;    // 15 weights, row sum
   int64_t* inv_off = nullptr;
   double* inv = nullptr;
   size_t inv_bytes = 0;
@@ -460,8 +487,21 @@ struct ccgmg_ctx {
   double plg_max_cond = 0;
   std::string err;
   bool host_only = false;
-  hipGraphExec_t graph = nullptr;
-  int graph_nrhs = -1, graph_kind = -1;
+  // solves run on a private stream (ordered after the caller's stream by
+  // events) so that each V-cycle can be captured into a hipGraph
+  hipStream_t ws = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  struct GraphEntry {
+    const void *u, *f, *bterm;
+    int nrhs, precision, M;
+    bool adjoint;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  void clear_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
 };
 
 namespace {
@@ -549,6 +589,23 @@ void build_smo2(const std::vector<int32_t>& cellv, const std::vector<int32_t>& c
     ioff[b] = (int64_t)all.size();
     all.insert(all.end(), inv[b].begin(), inv[b].end());
   }
+  std::vector<int32_t> ecell(eidx.size()), ecols(eidx.size() * 15);
+  std::vector<double> evals(eidx.size() * 15), ersum(eidx.size());
+  for (size_t e = 0; e < eidx.size(); ++e) {
+    const int k = eidx[e];
+    ecell[e] = cellv[k];
+    double rs = 0;
+    for (int t = 0; t < 15; ++t) {
+      ecols[e * 15 + t] = colv[15 * k + t];
+      evals[e * 15 + t] = valv[15 * k + t];
+      rs += valv[15 * k + t];
+    }
+    ersum[e] = rs;
+  }
+  out.ecell = upload(ecell, owned);
+  out.ecols = upload(ecols, owned);
+  out.evals = upload(evals, owned);
+  out.ersum = upload(ersum, owned);
   out.nblk = nblk;
   out.ext_ptr = upload(eptr, owned);
   out.ext_idx = upload(eidx, owned);
@@ -595,10 +652,29 @@ struct Driver {
   template <typename T>
   void sweep(DevLevel& L, const T* u, const T* r, T* out) {
     CoefT<T> c(L.coef);
-    if (L.cross)
-      hipLaunchKernelGGL((k_sweep<T, true>), tiles(L.nx, L.ny, nrhs), dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c);
-    else
-      hipLaunchKernelGGL((k_sweep<T, false>), tiles(L.nx, L.ny, nrhs), dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c);
+    const dim3 g = tiles(L.nx, L.ny, nrhs);
+    const bool fin = &L == &X->lv[0];
+    if (L.cross) {
+      if (fin) hipLaunchKernelGGL((k_sweep<T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c);
+      else hipLaunchKernelGGL((k_sweep<T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c);
+    } else {
+      if (fin) hipLaunchKernelGGL((k_sweep<T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c);
+      else hipLaunchKernelGGL((k_sweep<T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c);
+    }
+  }
+
+  template <typename T>
+  void restrict_(DevLevel& L, DevLevel& C, const T* u, const T* r, T* rc) {
+    CoefT<T> c(L.coef);
+    const dim3 g((L.nx + TX - 1) / TX, (L.ny + TY - 1) / TY, nrhs);
+    const bool fin = &L == &X->lv[0];
+    if (L.cross) {
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c);
+      else hipLaunchKernelGGL((k_restrict<T, T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c);
+    } else {
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c);
+      else hipLaunchKernelGGL((k_restrict<T, T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c);
+    }
   }
 
   template <typename T>
@@ -611,8 +687,8 @@ struct Driver {
     const double* vals = adjoint ? L.tvals : L.vals;
     const double* rs = adjoint ? L.trowsum : L.rowsum;
     for (int it = 0; it < X->opt.smo2_iters; ++it) {
-      hipLaunchKernelGGL((k_smo2<T>), dim3(S.nblk, nrhs), dim3(BLOCK), 0, s, u, r, bterm, cell, cols, vals, rs,
-                         S.ext_ptr, S.ext_idx, S.own_cnt, S.inv_off, S.inv, L.du, ni, L.n);
+      hipLaunchKernelGGL((k_smo2<T>), dim3(S.nblk, nrhs), dim3(BLOCK), 0, s, u, r, bterm, S.ecell, S.ecols, S.evals,
+                         S.ersum, S.ext_idx, S.ext_ptr, S.own_cnt, S.inv_off, S.inv, L.du, ni, L.n);
       hipLaunchKernelGGL((k_add_du<T>), dim3((ni + 255) / 256, nrhs), dim3(256), 0, s, u, L.du, cell, ni, L.n);
     }
   }
@@ -637,7 +713,7 @@ struct Driver {
   void coarse(DevLevel& L, T* u, const T* r) {
     const double* inv = adjoint ? X->mtinv : X->minv;
     const int nm = X->nm;
-    hipLaunchKernelGGL((k_coarse<T>), dim3((nm + 15) / 16, nrhs), dim3(BLOCK), nm * sizeof(double), s, u, r,
+    hipLaunchKernelGGL((k_coarse<T>), dim3((nm + 3) / 4, nrhs), dim3(BLOCK), nm * sizeof(double), s, u, r,
                        X->mcell, inv, nm, L.n);
   }
 
@@ -653,12 +729,7 @@ struct Driver {
     T* oth = cur == u ? v : u;
     DevLevel& C = X->lv[m + 1];
     Buf<T> cb = bufs<T>(C);
-    CoefT<T> c(L.coef);
-    const dim3 g((L.nx + TX - 1) / TX, (L.ny + TY - 1) / TY, nrhs);
-    if (L.cross)
-      hipLaunchKernelGGL((k_restrict<T, T, true>), g, dim3(BLOCK), 0, s, cur, r, L.kind, cb.r, L.nx, L.ny, C.nx, C.ny, c);
-    else
-      hipLaunchKernelGGL((k_restrict<T, T, false>), g, dim3(BLOCK), 0, s, cur, r, L.kind, cb.r, L.nx, L.ny, C.nx, C.ny, c);
+    restrict_<T>(L, C, cur, r, cb.r);
     fill<T>(cb.u, C.n * nrhs, (T)0);
     T* e = vcycle<T>(m + 1, cb.u, cb.v, cb.r, nullptr);
     hipLaunchKernelGGL((k_prolong<T>), dim3((L.nx + 255) / 256, L.ny, nrhs), dim3(256), 0, s, cur, e, L.kind, C.kind,
@@ -729,10 +800,8 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
   build_smo2(D.irr, D.sten, D.wts, opos, (int)L.n, X->opt.smo2_block, X->opt.smo2_overlap, X->opt.num_threads,
              L.smo2, X->owned);
   // work arrays
-  if (m > 0) {
-    L.u = dalloc<double>(L.n * maxr, X->owned);
-    L.r = dalloc<double>(L.n * maxr, X->owned);
-  }
+  L.u = dalloc<double>(L.n * maxr, X->owned);
+  L.r = dalloc<double>(L.n * maxr, X->owned);
   L.v = dalloc<double>(L.n * maxr, X->owned);
   L.u32 = dalloc<float>(L.n * maxr, X->owned);
   L.v32 = dalloc<float>(L.n * maxr, X->owned);
@@ -743,6 +812,8 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
   L.part = dalloc<double>((size_t)(L.npart_reg + L.npart_irr) * maxr, X->owned);
 }
 
+constexpr long MAX_COARSE_UNKNOWNS = 8000;   // gathered rhs must fit in LDS
+
 void upload_coarsest(ccgmg_ctx* X) {
   ccg::Discretization& D = X->H.disc[X->M];
   std::vector<int32_t> cells;
@@ -750,6 +821,7 @@ void upload_coarsest(ccgmg_ctx* X) {
   for (size_t k = 0; k < D.nonempty.size(); ++k)
     if (D.nonempty[k]) pos[k] = (int32_t)cells.size(), cells.push_back((int32_t)k);
   const int n = (int)cells.size();
+  if (n > MAX_COARSE_UNKNOWNS) throw ccg::Error(CCGMG_EINVAL, "coarsest level has too many unknowns");
   std::vector<double> A((size_t)n * n, 0.0);
   for (int r = 0; r < n; ++r) {
     int q = cells[r];
@@ -794,7 +866,7 @@ void ccgmg_default_options(ccgmg_options* o) {
   o->precision = 0;
   o->prolongation = 0;
   o->smo2_every_sweep = 1;
-  o->smo2_iters = 2;
+  o->smo2_iters = 1;
   o->smo2_block = 64;
   o->smo2_overlap = 2;
   o->tol = 1e-10;
@@ -855,6 +927,9 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
     X->M = (int)X->H.disc.size() - 1;
     if (!X->host_only) {
       X->stream = (hipStream_t)X->opt.hip_stream;
+      HIP_OK(hipStreamCreateWithFlags(&X->ws, hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&X->ev_in, hipEventDisableTiming));
+      HIP_OK(hipEventCreateWithFlags(&X->ev_out, hipEventDisableTiming));
       const int maxr = X->opt.max_nrhs;
       X->lv.resize(X->H.disc.size());
       for (size_t m = 0; m < X->H.disc.size(); ++m) upload_level(X.get(), (int)m, maxr);
@@ -881,9 +956,13 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
           double rate = 1.0;
           run_depth_test(X.get(), &rate);
           if (rate <= X->opt.depth_max_rate || X->M <= 1) break;
+          long next = 0;
+          for (uint8_t v : X->H.disc[X->M - 1].nonempty) next += v;
+          if (next > MAX_COARSE_UNKNOWNS) break;
           X->M -= 1;
           upload_coarsest(X.get());
         }
+        X->clear_graphs();
       }
     }
     X->setup_seconds = now() - t0;
@@ -1227,39 +1306,70 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
   return guard(X, [&]() {
     if (!f || !u || nrhs < 1 || nrhs > X->opt.max_nrhs) throw ccg::Error(CCGMG_EINVAL, "bad solve arguments");
     if (adjoint) throw ccg::Error(CCGMG_EINVAL, "adjoint solve not available in this build");
-    Driver Dr{X, X->stream, nrhs, adjoint};
+    hipStream_t ws = X->ws;
+    Driver Dr{X, ws, nrhs, adjoint};
     DevLevel& L0 = X->lv[0];
     const size_t n = L0.n * nrhs;
+    HIP_OK(hipEventRecord(X->ev_in, X->stream));
+    HIP_OK(hipStreamWaitEvent(ws, X->ev_in, 0));
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
-    HIP_OK(hipEventRecord(e0, X->stream));
+    HIP_OK(hipEventRecord(e0, ws));
     const double* bterm = nullptr;
     if (X->nfaces > 0 && X->g_nrhs >= nrhs && L0.nirr > 0) {
-      hipLaunchKernelGGL(k_bterm, dim3((L0.nirr + 255) / 256, nrhs), dim3(256), 0, X->stream, X->g, X->fptr, X->fface,
+      hipLaunchKernelGGL(k_bterm, dim3((L0.nirr + 255) / 256, nrhs), dim3(256), 0, ws, X->g, X->fptr, X->fface,
                          X->fval, X->bterm, L0.nirr, X->nfaces);
       bterm = X->bterm;
     }
     if (!X->opt.use_initial_guess) Dr.fill<double>(u, n, 0.0);
-    hipLaunchKernelGGL(k_mask_empty, dim3(std::min<size_t>(4096, (n + 255) / 256)), dim3(256), 0, X->stream, u, L0.kind, L0.n, n);
+    hipLaunchKernelGGL(k_mask_empty, dim3(std::min<size_t>(4096, (n + 255) / 256)), dim3(256), 0, ws, u, L0.kind, L0.n, n);
     Dr.resmax<double>(L0, u, f, bterm, 1, nullptr);
     std::vector<double> rn(nrhs);
-    HIP_OK(hipMemcpyAsync(X->norm_host, X->norm_out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, X->stream));
-    HIP_OK(hipStreamSynchronize(X->stream));
+    HIP_OK(hipMemcpyAsync(X->norm_host, X->norm_out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ws));
+    HIP_OK(hipStreamSynchronize(ws));
     for (int z = 0; z < nrhs; ++z) rn[z] = X->norm_host[z] > 0 ? X->norm_host[z] : 1.0;
+    // one V-cycle (FP64, or FP32 inside one FP64 refinement step), the FP64
+    // residual check and its read-back, replayed from a graph when allowed
+    auto cycle = [&]() {
+      if (X->opt.precision == 1)
+        mp_cycle(Dr, u, f, bterm);
+      else
+        fp64_cycle(Dr, u, f, bterm);
+      Dr.resmax<double>(L0, u, f, bterm, 0, nullptr);
+      HIP_OK(hipMemcpyAsync(X->norm_host, X->norm_out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ws));
+    };
+    hipGraphExec_t exec = nullptr;
+    if (X->opt.use_graph) {
+      for (auto& g : X->graphs)
+        if (g.u == u && g.f == f && g.bterm == bterm && g.nrhs == nrhs && g.precision == X->opt.precision &&
+            g.M == X->M && g.adjoint == adjoint)
+          exec = g.exec;
+      if (!exec) {
+        hipGraph_t graph;
+        HIP_OK(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+        cycle();
+        HIP_OK(hipStreamEndCapture(ws, &graph));
+        HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+        if (X->graphs.size() >= 8) {
+          (void)hipGraphExecDestroy(X->graphs.front().exec);
+          X->graphs.erase(X->graphs.begin());
+        }
+        X->graphs.push_back({u, f, bterm, nrhs, X->opt.precision, X->M, adjoint, exec});
+      }
+    }
     int cycles = 0, hist = 0, slow = 0;
     double prev = 1e300, rel = 1.0;
     if (rep) std::memset(rep, 0, sizeof(*rep));
     bool converged = false;
     for (int it = 0; it < X->opt.max_cycles; ++it) {
-      if (X->opt.precision == 1)
-        mp_cycle(Dr, u, f, bterm);
+      if (exec)
+        HIP_OK(hipGraphLaunch(exec, ws));
       else
-        fp64_cycle(Dr, u, f, bterm);
+        cycle();
       ++cycles;
-      Dr.resmax<double>(L0, u, f, bterm, 0, nullptr);
-      HIP_OK(hipMemcpyAsync(X->norm_host, X->norm_out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, X->stream));
-      HIP_OK(hipStreamSynchronize(X->stream));
+      HIP_OK(hipStreamSynchronize(ws));
       rel = 0;
       for (int z = 0; z < nrhs; ++z) rel = std::max(rel, X->norm_host[z] / rn[z]);
       if (rep && hist < 64) rep->history[hist++] = rel;
@@ -1275,12 +1385,14 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
       }
       prev = rel;
     }
-    HIP_OK(hipEventRecord(e1, X->stream));
+    HIP_OK(hipEventRecord(e1, ws));
+    HIP_OK(hipEventRecord(X->ev_out, ws));
+    HIP_OK(hipStreamWaitEvent(X->stream, X->ev_out, 0));
     HIP_OK(hipEventSynchronize(e1));
     float ms = 0;
     HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rep) {
       rep->cycles = cycles;
       rep->outer_iters = X->opt.precision == 1 ? cycles : 0;
@@ -1318,8 +1430,8 @@ static int run_depth_test(ccgmg_ctx* X, double* rate_out) {
   solve_impl(X, rd, ud, 1, &rep, false);
   X->opt = saved;
   X->g_nrhs = g_saved;
-  hipFree(rd);
-  hipFree(ud);
+  (void)hipFree(rd);
+  (void)hipFree(ud);
   double last = rep.cycles > 0 ? rep.history[std::min(rep.cycles, 64) - 1] : 1.0;
   *rate_out = (std::isfinite(last) && rep.cycles > 0) ? std::pow(last, 1.0 / rep.cycles) : 1e300;
   return 0;
@@ -1361,6 +1473,55 @@ int ccgmg_solve_adjoint(ccgmg_ctx* X, const double* rhs, double* lam, int nrhs, 
   return solve_impl(X, rhs, lam, nrhs, rep, true);
 }
 
+int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* avg_us) {
+  return guard(X, [&]() {
+    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 5)
+      throw ccg::Error(CCGMG_EINVAL, "bad profile arguments");
+    Driver Dr{X, X->stream, 1, false};
+    DevLevel& L = X->lv[level];
+    Dr.fill<double>(L.u, L.n, 1.0);
+    Dr.fill<double>(L.r, L.n, 0.5);
+    Dr.fill<double>(L.v, L.n, 0.0);
+    Dr.fill<float>(L.u32, L.n, 1.0f);
+    Dr.fill<float>(L.r32, L.n, 0.5f);
+    DevLevel* C = level < X->M ? &X->lv[level + 1] : nullptr;
+    if ((kernel == 1 || kernel == 2) && !C) throw ccg::Error(CCGMG_EINVAL, "no coarser level");
+    if (kernel == 4 && level != X->M) throw ccg::Error(CCGMG_EINVAL, "coarsest solve only on the coarsest level");
+    auto launch = [&]() {
+      switch (kernel) {
+        case 0: Dr.sweep<double>(L, L.u, L.r, L.v); break;
+        case 1: Dr.restrict_<double>(L, *C, L.u, L.r, C->r); break;
+        case 2:
+          hipLaunchKernelGGL((k_prolong<double>), dim3((L.nx + 255) / 256, L.ny, 1), dim3(256), 0, X->stream, L.u,
+                             C->u, L.kind, C->kind, L.nx, L.ny, C->nx, C->ny, X->opt.prolongation);
+          break;
+        case 3:
+          if (L.nirr > 0)
+            hipLaunchKernelGGL((k_smo2<double>), dim3(L.smo2.nblk, 1), dim3(BLOCK), 0, X->stream, L.u, L.r,
+                               (const double*)nullptr, L.smo2.ecell, L.smo2.ecols, L.smo2.evals, L.smo2.ersum,
+                               L.smo2.ext_idx, L.smo2.ext_ptr, L.smo2.own_cnt, L.smo2.inv_off, L.smo2.inv, L.du,
+                               L.nirr, L.n);
+          break;
+        case 4: Dr.coarse<double>(L, L.u, L.r); break;
+        default: Dr.sweep<float>(L, L.u32, L.r32, L.v32); break;
+      }
+    };
+    launch();
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, X->stream));
+    for (int k = 0; k < reps; ++k) launch();
+    HIP_OK(hipEventRecord(e1, X->stream));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_us = 1e3 * ms / reps;
+  });
+}
+
 int ccgmg_apply_NT(ccgmg_ctx* X, const double* lam, double* out) {
   return guard(X, [&]() {
     if (!lam || !out) throw ccg::Error(CCGMG_EINVAL, "bad arguments");
@@ -1373,11 +1534,14 @@ int ccgmg_apply_NT(ccgmg_ctx* X, const double* lam, double* out) {
 void ccgmg_destroy(ccgmg_ctx* X) {
   if (!X) return;
   if (!X->host_only) {
-    if (X->stream) hipStreamSynchronize(X->stream);
-    else hipDeviceSynchronize();
-    if (X->graph) hipGraphExecDestroy(X->graph);
-    for (void* p : X->owned) hipFree(p);
-    if (X->norm_host) hipHostFree(X->norm_host);
+    if (X->stream) (void)hipStreamSynchronize(X->stream);
+    else (void)hipDeviceSynchronize();
+    X->clear_graphs();
+    if (X->ws) (void)hipStreamDestroy(X->ws);
+    if (X->ev_in) (void)hipEventDestroy(X->ev_in);
+    if (X->ev_out) (void)hipEventDestroy(X->ev_out);
+    for (void* p : X->owned) (void)hipFree(p);
+    if (X->norm_host) (void)hipHostFree(X->norm_host);
   }
   delete X;
 }

@@ -93,6 +93,9 @@ typedef struct {
   int smo2_iters;        /* block iterations per SMO-2 application, default 1             */
   int smo2_block;        /* irregular cells per block, default 64                         */
   int smo2_overlap;      /* overlap layers of a block in the matrix graph, default 2      */
+  int smo2_widen;        /* regular cells within this distance of the least-squares rows
+                            join the SMO-2 blocks instead of SMO-1, default 1 (0 = the
+                            paper's split)                                               */
   double tol;            /* stop when ||f - N g - L u||_inf / ||f - N g||_inf <= tol      */
   int max_cycles;        /* default 100                                                   */
   int max_nrhs;          /* right-hand sides solved together, default 1                   */
@@ -197,12 +200,20 @@ int ccgmg_set_boundary(ccgmg_ctx* ctx, const double* g_hat, int nrhs);
  * the last iterate) when tol is not reached. */
 int ccgmg_solve(ccgmg_ctx* ctx, const double* f_hat, double* u_hat, int nrhs, ccgmg_report* rep);
 
-/* Adjoint solve L^T lambda = rhs (device arrays as in ccgmg_solve), by
- * V-cycles on the transposed operators. */
+/* Adjoint solve L^T lambda = rhs (device arrays as in ccgmg_solve) by
+ * V-cycles on the transposed operators of every level (L is not symmetric
+ * near the boundary: the least-squares rows of Section 3.3).  The transposed
+ * system of eq. PoissonResidualForm gives the gradients of a loss J(u) with
+ * respect to f-hat (= lambda for rhs = dJ/du) and g-hat (= -N^T lambda). */
 int ccgmg_solve_adjoint(ccgmg_ctx* ctx, const double* rhs, double* lambda, int nrhs, ccgmg_report* rep);
 
-/* out = N^T lambda (device; lambda nx*ny, out n_bdry_faces doubles). */
-int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out);
+/* (L^T lambda) on every non-empty level-0 cell.  lambda, out: device,
+ * nx * ny doubles; may not alias. */
+int ccgmg_apply_adjoint(ccgmg_ctx* ctx, const double* lambda, double* out);
+
+/* out = N^T lambda for nrhs planes (device; lambda [nrhs][ny][nx], out
+ * [nrhs][n_bdry_faces]). */
+int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out, int nrhs);
 
 /* Diagnostic timing: launch one V-cycle kernel `reps` times on the
  * context's stream, on the context's own work buffers of level `level`

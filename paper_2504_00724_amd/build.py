@@ -22,15 +22,18 @@ def build(verbose=True):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    setup_o = os.path.join(bdir, "setup.o")
+    host_o = []
+    for src in ("setup.cpp", "quadrature.cpp"):
+        o = os.path.join(bdir, src.replace(".cpp", ".o"))
+        _run(["g++", "-std=c++17", "-O2", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE, "-c",
+              os.path.join(CSRC, src), "-o", o])
+        host_o.append(o)
     hip_o = os.path.join(bdir, "ccgmg.o")
-    _run(["g++", "-std=c++17", "-O2", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE, "-c",
-          os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
     _run([hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-c", os.path.join(CSRC, "ccgmg.hip"), "-o", hip_o])
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, hip_o, setup_o, "-pthread"])
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, hip_o] + host_o + ["-pthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -23,7 +23,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTELLIPTIC", -3: "EGEOM", -4: "EPLG", -5
 EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
-           "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_NT", "ccgmg_profile_kernel",
+           "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
+           "ccgmg_profile_kernel",
            "ccgmg_last_error",
            "ccgmg_create_error", "ccgmg_destroy"]
 
@@ -41,7 +42,7 @@ class OptionsT(C.Structure):
                 ("nu2", C.c_int), ("coarsest_min_n", C.c_int), ("max_levels", C.c_int), ("auto_depth", C.c_int),
                 ("depth_max_rate", C.c_double), ("precision", C.c_int), ("prolongation", C.c_int),
                 ("smo2_every_sweep", C.c_int), ("smo2_iters", C.c_int), ("smo2_block", C.c_int),
-                ("smo2_overlap", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
+                ("smo2_overlap", C.c_int), ("smo2_widen", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
                 ("use_initial_guess", C.c_int), ("num_threads", C.c_int), ("use_graph", C.c_int),
                 ("host_only", C.c_int), ("hip_stream", C.c_void_p)]
 
@@ -87,7 +88,8 @@ def lib():
         L.ccgmg_set_boundary.argtypes = [vp, vp, ip]
         L.ccgmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
         L.ccgmg_solve_adjoint.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
-        L.ccgmg_apply_NT.argtypes = [vp, vp, vp]
+        L.ccgmg_apply_adjoint.argtypes = [vp, vp, vp]
+        L.ccgmg_apply_NT.argtypes = [vp, vp, vp, ip]
         L.ccgmg_profile_kernel.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_double)]
         L.ccgmg_last_error.argtypes = [vp]
         L.ccgmg_last_error.restype = C.c_char_p
@@ -254,8 +256,11 @@ class Solver:
         self._check(lib().ccgmg_profile_kernel(self.ctx, kernel, level, reps, C.byref(us)))
         return us.value
 
-    def apply_NT(self, lam, out):
-        self._check(lib().ccgmg_apply_NT(self.ctx, _ptr(lam), _ptr(out)))
+    def apply_adjoint(self, lam, out):
+        self._check(lib().ccgmg_apply_adjoint(self.ctx, _ptr(lam), _ptr(out)))
+
+    def apply_NT(self, lam, out, nrhs=1):
+        self._check(lib().ccgmg_apply_NT(self.ctx, _ptr(lam), _ptr(out), nrhs))
 
 
 def _report(rep, st):

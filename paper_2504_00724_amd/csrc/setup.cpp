@@ -1398,6 +1398,162 @@ void Hierarchy::build(const std::vector<Curve>& curves, int nx, int ny, double x
   for (size_t k = 0; k < geo.size(); ++k) disc[k].g = &geo[k];
 }
 
+void forward_rows(const Discretization& D, RowSet& out) {
+  const int ni = (int)D.irr.size();
+  out.cell = D.irr;
+  out.rp.resize(ni + 1);
+  for (int k = 0; k <= ni; ++k) out.rp[k] = NB * k;
+  out.cols = D.sten;
+  out.vals = D.wts;
+  out.order.resize(ni);
+  for (int p = 0; p < ni; ++p) out.order[p] = D.irr_pos[D.order[p]];
+}
+
+void transposed_rows(const Discretization& D, RowSet& out, std::vector<uint8_t>& adj_regular) {
+  const int nx = D.nx, ny = D.ny;
+  const size_t n = (size_t)nx * ny;
+  const int ni = (int)D.irr.size();
+  // irregular-row entries grouped by column
+  std::vector<std::vector<std::pair<int32_t, double>>> by_col(n);
+  std::vector<uint8_t> ref(n, 0);
+  for (int k = 0; k < ni; ++k)
+    for (int t = 0; t < NB; ++t) {
+      const int c = D.sten[NB * k + t];
+      by_col[c].push_back({D.irr[k], D.wts[NB * k + t]});
+      ref[c] = 1;
+    }
+  adj_regular.assign(n, 0);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t g = (size_t)j * nx + i;
+      if (!D.regular[g] || ref[g]) continue;
+      bool all = true;
+      for (int dy = -2; dy <= 2 && all; ++dy)
+        for (int dx = -2; dx <= 2; ++dx)
+          if (!D.regular[(size_t)(j + dy) * nx + (i + dx)]) {
+            all = false;
+            break;
+          }
+      adj_regular[g] = all;
+    }
+  out.cell.clear();
+  out.rp.assign(1, 0);
+  out.cols.clear();
+  out.vals.clear();
+  std::vector<int32_t> pos(n, -1);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t g = (size_t)j * nx + i;
+      if (!D.nonempty[g] || adj_regular[g]) continue;
+      std::map<int32_t, double> e;
+      for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+          const int ii = i + dx, jj = j + dy;
+          if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+          const size_t r = (size_t)jj * nx + ii;
+          // L(r, g) for a regular row r: coefficient at offset g - r
+          const double w = D.coef[2 - dy][2 - dx];
+          if (D.regular[r] && w != 0.0) e[(int32_t)r] += w;
+        }
+      for (auto& pr : by_col[g]) e[pr.first] += pr.second;
+      pos[g] = (int32_t)out.cell.size();
+      out.cell.push_back((int32_t)g);
+      for (auto& kv : e) {
+        out.cols.push_back(kv.first);
+        out.vals.push_back(kv.second);
+      }
+      out.rp.push_back((int32_t)out.cols.size());
+    }
+  const int nt = (int)out.cell.size();
+  std::vector<int32_t> num(nt, -1);
+  int k = 0;
+  for (int p = 0; p < ni; ++p) {
+    const int q = D.order[p], i = q % nx, j = q / nx;
+    for (int dy = -4; dy <= 4; ++dy)
+      for (int dx = -4; dx <= 4; ++dx) {
+        const int ii = i + dx, jj = j + dy;
+        if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+        const int t = pos[(size_t)jj * nx + ii];
+        if (t >= 0 && num[t] < 0) num[t] = k++;
+      }
+  }
+  for (int t = 0; t < nt; ++t)
+    if (num[t] < 0) num[t] = k++;
+  out.order.assign(nt, 0);
+  for (int t = 0; t < nt; ++t) out.order[num[t]] = t;
+}
+
+void smoother_rows(const Discretization& D, const RowSet& base, const std::vector<uint8_t>& stencil_mask,
+                   int widen, RowSet& out, std::vector<int32_t>& base_index, std::vector<uint8_t>& jacobi_mask) {
+  const int nx = D.nx, ny = D.ny;
+  const size_t n = (size_t)nx * ny;
+  const int nb = (int)base.cell.size();
+  std::vector<int32_t> bpos(n, -1);
+  for (int k = 0; k < nb; ++k) bpos[base.cell[k]] = k;
+  std::vector<uint8_t> in(n, 0);
+  for (int k = 0; k < nb; ++k) in[base.cell[k]] = 1;
+  if (widen > 0)
+    for (int k = 0; k < nb; ++k) {
+      const int q = base.cell[k], i = q % nx, j = q / nx;
+      for (int dy = -widen; dy <= widen; ++dy)
+        for (int dx = -widen; dx <= widen; ++dx) {
+          const int ii = i + dx, jj = j + dy;
+          if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+          const size_t c = (size_t)jj * nx + ii;
+          if (stencil_mask[c]) in[c] = 1;
+        }
+    }
+  jacobi_mask.assign(n, 0);
+  for (size_t c = 0; c < n; ++c) jacobi_mask[c] = stencil_mask[c] && !in[c];
+  out.cell.clear();
+  out.rp.assign(1, 0);
+  out.cols.clear();
+  out.vals.clear();
+  base_index.clear();
+  std::vector<int32_t> pos(n, -1);
+  for (size_t c = 0; c < n; ++c) {
+    if (!in[c]) continue;
+    pos[c] = (int32_t)out.cell.size();
+    out.cell.push_back((int32_t)c);
+    const int b = bpos[c];
+    base_index.push_back(b);
+    if (b >= 0) {
+      for (int t = base.rp[b]; t < base.rp[b + 1]; ++t) {
+        out.cols.push_back(base.cols[t]);
+        out.vals.push_back(base.vals[t]);
+      }
+    } else {
+      const int i = (int)(c % nx), j = (int)(c / nx);
+      for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+          const double w = D.coef[dy + 2][dx + 2];
+          if (w == 0.0) continue;
+          out.cols.push_back((j + dy) * nx + i + dx);
+          out.vals.push_back(w);
+        }
+    }
+    out.rp.push_back((int32_t)out.cols.size());
+  }
+  const int ns = (int)out.cell.size();
+  const int rad = std::max(widen, 1);
+  std::vector<int32_t> num(ns, -1);
+  int k = 0;
+  for (int p = 0; p < nb; ++p) {
+    const int q = base.cell[base.order[p]], i = q % nx, j = q / nx;
+    for (int dy = -rad; dy <= rad; ++dy)
+      for (int dx = -rad; dx <= rad; ++dx) {
+        const int ii = i + dx, jj = j + dy;
+        if (ii < 0 || jj < 0 || ii >= nx || jj >= ny) continue;
+        const int t = pos[(size_t)jj * nx + ii];
+        if (t >= 0 && num[t] < 0) num[t] = k++;
+      }
+  }
+  for (int t = 0; t < ns; ++t)
+    if (num[t] < 0) num[t] = k++;
+  out.order.assign(ns, 0);
+  for (int t = 0; t < ns; ++t) out.order[num[t]] = t;
+}
+
 bool dense_inverse(std::vector<double>& A, int n, int threads) {
   // Gauss-Jordan with partial pivoting on [A | I], row-major.
   std::vector<double> B((size_t)n * n, 0.0);

@@ -142,6 +142,39 @@ struct Hierarchy {
              double a, double b, double c, const Options& opt);
 };
 
+// Rows of an operator that the V-cycle treats explicitly (everything but the
+// constant-stencil rows): cell of each row, CSR columns/values, and the
+// numbering used to cut the SMO-2 blocks (positions into `cell`).
+struct RowSet {
+  std::vector<int32_t> cell, rp, cols;
+  std::vector<double> vals;
+  std::vector<int32_t> order;
+};
+
+// Irregular rows of L in increasing cell index, numbered by Alg. 3.
+void forward_rows(const Discretization& D, RowSet& out);
+
+// Rows of L^T.  A cell keeps the regular (symmetric) stencil in L^T when its
+// whole 5x5 box is regular and no irregular row references it; those cells
+// are flagged in `adj_regular`.  Every other non-empty cell gets an explicit
+// row: stencil coefficients of its regular neighbours' rows plus the
+// weights of the irregular rows that reference it.  Rows are numbered by
+// visiting the Alg. 3 order of the irregular cells and taking the still
+// unnumbered rows within infinity-distance 4 (the lattice reach).
+void transposed_rows(const Discretization& D, RowSet& out, std::vector<uint8_t>& adj_regular);
+
+// Rows of the SMO-2 block solve: `base` plus the (regular-stencil) rows of
+// every cell flagged in `stencil_mask` within infinity-distance `widen` of a
+// base row.  `jacobi_mask` receives the stencil cells left to SMO-1.  The
+// numbering visits the base rows in their order and takes the still
+// unnumbered rows within distance max(widen, 1) of each.
+void smoother_rows(const Discretization& D, const RowSet& base, const std::vector<uint8_t>& stencil_mask,
+                   int widen, RowSet& out, std::vector<int32_t>& base_index, std::vector<uint8_t>& jacobi_mask);
+
+int cell_quadrature(const Geometry& G, long* count, int32_t* cell_of, double* x, double* y, double* w);
+int face_quadrature(const Geometry& G, const Discretization& D, long* count, int32_t* face_of, double* x, double* y,
+                    double* w, double* nxo, double* nyo);
+
 // Dense inverse (Gauss-Jordan with partial pivoting), row-major n x n, threads.
 bool dense_inverse(std::vector<double>& A, int n, int threads);
 

@@ -80,6 +80,8 @@ def test_solve_matches_oracle_direct(k, n):
 
 
 def test_mixed_precision_within_discretization_error():
+    """FP32 smoothing inside FP64 refinement reaches the FP64 tolerance and
+    the FP64 oracle's solution, far below the discretization error."""
     dev = _dev()
     cfg, lv = _level(4, 128)
     f = cell_averages(lv.cg, cfg["f"]).ravel()
@@ -87,7 +89,7 @@ def test_mixed_precision_within_discretization_error():
     ref = direct_solve(lv, rhs_vector(lv, f, g))
     exact = cell_averages(lv.cg, cfg["solution"].u).ravel()
     disc_err = np.max(np.abs(ref - exact)[lv.nonempty])
-    S = _solver(cfg, tol=1e-10, precision=1)
+    S = _solver(cfg, tol=1e-12, precision=1, max_cycles=200)
     fd = torch.tensor(f, device=dev)
     S.set_boundary(torch.tensor(g, device=dev), 1)
     u = torch.zeros_like(fd)
@@ -96,7 +98,8 @@ def test_mixed_precision_within_discretization_error():
     err = np.max(np.abs(u.cpu().numpy() - ref)[lv.nonempty])
     print("mixed precision: cycles %d rel_res %.2e err vs oracle %.2e (disc err %.2e)" % (
         rep["cycles"], rep["rel_res_inf"], err, disc_err), flush=True)
-    assert rep["rel_res_inf"] <= 1e-10
+    assert rep["rel_res_inf"] <= 1e-12
+    assert err <= 1e-10 * np.max(np.abs(ref))
     assert err <= disc_err
     S.close()
 
@@ -115,4 +118,78 @@ def test_batched_right_hand_sides():
     for z in range(3):
         ref = direct_solve(lv, F[z])
         assert np.max(np.abs(got[z] - ref)) <= 1e-10 * np.max(np.abs(ref))
+    S.close()
+
+
+@pytest.mark.parametrize("k,n", [(1, 64), (2, 64), (4, 128), (5, 64)])
+def test_adjoint_apply_and_solve_match_oracle(k, n):
+    from oracle.multigrid import direct_solve_transpose
+    dev = _dev()
+    cfg, lv = _level(k, n)
+    print("adjoint parity config %d n=%d" % (k, n), flush=True)
+    S = _solver(cfg, tol=1e-12, max_cycles=200)
+    rng = np.random.default_rng(20 + k)
+    lam = rng.standard_normal(n * n) * lv.nonempty
+    ld = torch.tensor(lam, device=dev)
+    out = torch.zeros_like(ld)
+    S.apply_adjoint(ld, out)
+    torch.cuda.synchronize()
+    ref = lv.L.T @ lam
+    scale = abs(lv.L).T @ np.abs(lam)
+    ne = lv.nonempty
+    assert np.all(np.abs(out.cpu().numpy() - ref)[ne] <= 1e-12 * scale[ne] + 1e-300)
+    rhs = rng.standard_normal(n * n) * lv.nonempty
+    want = direct_solve_transpose(lv, rhs)
+    got = torch.zeros_like(ld)
+    rep = S.solve_adjoint(torch.tensor(rhs, device=dev), got)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(got.cpu().numpy() - want)) / np.max(np.abs(want))
+    print("   adjoint cycles %d rel_res %.2e rel_err %.2e" % (rep["cycles"], rep["rel_res_inf"], err), flush=True)
+    assert err <= 1e-10
+    S.close()
+
+
+def test_autograd_gradients_match_finite_differences():
+    """J = 1/2 ||u - u_target||^2 with u_target = <u> + N(0, 1e-3^2); the
+    adjoint gradients against central differences (eps = 1e-6) along random
+    unit directions in (f-hat, g-hat) (J is quadratic, so central differences
+    are exact up to rounding and solver error)."""
+    from paper_2504_00724_amd.autograd import cutcell_solve
+    dev = _dev()
+    cfg, lv = _level(4, 64)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ue = cell_averages(lv.cg, cfg["solution"].u).ravel()
+    rng = np.random.default_rng(44)
+    target = (ue + 1e-3 * rng.standard_normal(ue.size)) * lv.nonempty
+    S = _solver(cfg, tol=1e-12, max_cycles=300)
+    mask = torch.tensor(lv.nonempty, device=dev, dtype=torch.float64)
+    tt = torch.tensor(target, device=dev)
+
+    def J(fv, gv):
+        u = cutcell_solve(fv, gv, S)
+        return 0.5 * torch.sum(((u - tt) * mask) ** 2)
+
+    fd = torch.tensor(f, device=dev, requires_grad=True)
+    gd = torch.tensor(g, device=dev, requires_grad=True)
+    loss = J(fd, gd)
+    loss.backward()
+    gf, gg = fd.grad.clone(), gd.grad.clone()
+    eps = 1e-6
+    worst = 0.0
+    for s in range(4):
+        r = np.random.default_rng(400 + s)
+        df = r.standard_normal(f.size) * lv.nonempty
+        dg = r.standard_normal(g.size)
+        nrm = np.sqrt(np.sum(df ** 2) + np.sum(dg ** 2))
+        df, dg = torch.tensor(df / nrm, device=dev), torch.tensor(dg / nrm, device=dev)
+        with torch.no_grad():
+            jp = float(J(fd + eps * df, gd + eps * dg))
+            jm = float(J(fd - eps * df, gd - eps * dg))
+        fdv = (jp - jm) / (2 * eps)
+        adj = float(torch.sum(gf * df) + torch.sum(gg * dg))
+        rel = abs(fdv - adj) / max(abs(adj), 1e-300)
+        worst = max(worst, rel)
+        print("   direction %d: fd %.10e adjoint %.10e rel %.2e" % (s, fdv, adj, rel), flush=True)
+    assert worst < 1e-5
     S.close()

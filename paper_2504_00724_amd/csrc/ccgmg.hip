@@ -87,14 +87,22 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const 
 
 // Residual of the regular cells restricted to the coarse grid:
 // rc_I = 1/4 sum over regular children c of (r - L u)_c  (Section 4.1).
+// The same launch zeroes the coarse iterate uc (the recursion starts from a
+// zero guess, Alg. 2) and the compact copy cc of its block rows.
 template <typename T, typename TC, bool CROSS, bool FINEST>
 __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, const T* __restrict__ r,
-                                                    const uint8_t* __restrict__ kind, TC* __restrict__ rc, int nx,
+                                                    const uint8_t* __restrict__ kind, TC* __restrict__ rc,
+                                                    TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx,
                                                     int ny, int ncx, int ncy, CoefT<T> c, uint8_t regbit) {
   __shared__ T tile[LH][LW];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   u += zoff, r += zoff;
   rc += (size_t)blockIdx.z * ncx * ncy;
+  uc += (size_t)blockIdx.z * ncx * ncy;
+  {
+    const int flat = (blockIdx.y * gridDim.x + blockIdx.x) * BLOCK + threadIdx.x;
+    if (flat < ncc) cc[(size_t)blockIdx.z * ncc + flat] = 0.0;
+  }
   const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
   const int cx = threadIdx.x & 31, cy = threadIdx.x >> 5;  // 32 x 8 coarse cells
   uint8_t kd[4];
@@ -116,22 +124,15 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, con
     if (kd[d] & regbit)
       s += rr[d] - apply_regular<T, CROSS>(tile, 2 * cy + (d >> 1) + HALO, 2 * cx + (d & 1) + HALO, c);
   rc[(size_t)J * ncx + I] = (TC)((T)0.25 * s);
+  uc[(size_t)J * ncx + I] = (TC)0;
 }
 
 // Correction u_c += P e on regular fine cells: piecewise constant
 // (Section 4.1) or bilinear with the 9/16, 3/16, 3/16, 1/16 cell-centred
 // weights where all four coarse cells are non-empty.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_prolong(T* __restrict__ u, const T* __restrict__ e,
-                                                   const uint8_t* __restrict__ kind,
-                                                   const uint8_t* __restrict__ ckind, int nx, int ny, int ncx,
-                                                   int ncy, int bilinear, uint8_t regbit) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-  if (i >= nx) return;
-  const size_t g = (size_t)j * nx + i;
-  if (!(kind[g] & regbit)) return;
-  u += (size_t)blockIdx.z * nx * ny;
-  e += (size_t)blockIdx.z * ncx * ncy;
+__device__ __forceinline__ T prolong_value(const T* __restrict__ e, const uint8_t* __restrict__ ckind, int i, int j,
+                                           int ncx, int ncy, int bilinear) {
   const int I = i >> 1, J = j >> 1;
   T v = e[(size_t)J * ncx + I];
   if (bilinear) {
@@ -141,7 +142,34 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(T* __restrict__ u, const T* _
       v = ((T)9 * v + (T)3 * e[(size_t)J * ncx + I2] + (T)3 * e[(size_t)J2 * ncx + I] + e[(size_t)J2 * ncx + I2]) *
           (T)0.0625;
   }
-  u[g] += v;
+  return v;
+}
+
+// Grid rows 0..ny-1 update u; the extra rows apply the same correction to
+// the compact copy c of the block rows (SMO-2), computed from the same
+// inputs so that c stays equal to u on those cells.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_prolong(T* __restrict__ u, const T* __restrict__ e,
+                                                   const uint8_t* __restrict__ kind,
+                                                   const uint8_t* __restrict__ ckind, int nx, int ny, int ncx,
+                                                   int ncy, int bilinear, uint8_t regbit,
+                                                   const int32_t* __restrict__ scell, double* __restrict__ c, int ns) {
+  const int z = blockIdx.z;
+  e += (size_t)z * ncx * ncy;
+  if ((int)blockIdx.y < ny) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= nx) return;
+    const size_t g = (size_t)j * nx + i;
+    if (!(kind[g] & regbit)) return;
+    u[(size_t)z * nx * ny + g] += prolong_value(e, ckind, i, j, ncx, ncy, bilinear);
+    return;
+  }
+  const int k = ((blockIdx.y - ny) * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  const int q = scell[k];
+  if (!(kind[q] & regbit)) return;
+  const T v = (T)(c[(size_t)z * ns + k]) + prolong_value(e, ckind, q % nx, q / nx, ncx, ncy, bilinear);
+  c[(size_t)z * ns + k] = (double)v;
 }
 
 // Residual of one explicit row (FP64, difference form):
@@ -163,58 +191,84 @@ __device__ __forceinline__ double row_residual(const T* __restrict__ u, double r
 // SMO-2 by restricted additive Schwarz.  Workgroup = one block of <= 64
 // consecutive rows of the block numbering plus its overlap.  The rows of
 // the overlapped set are stored per block (cell, CSR columns and weights,
-// row sum), so a residual needs one level of gathers; then the block's own
-// rows of the precomputed inverse are applied, du_own = (A_ext^{-1})_{own,:}
-// res_ext; du is added by k_add_du.
+// row sum); a column that is itself a block row is encoded as -(row + 1)
+// and read from the compact copy c_in of the block rows' values, all other
+// columns are read from u.  Every block therefore reads only cells that no
+// block writes, and writes its own rows straight into u (and c_out):
+//   res_t = r_q - bterm - sum_s beta_s (u_s - u_q) - S_t u_q   (FP64),
+//   u_own = c_in_own + (A_ext^{-1})_{own,:} res_ext.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_smo2(const T* __restrict__ u, const T* __restrict__ r,
-                                                const double* __restrict__ bterm, const int32_t* __restrict__ ecell,
-                                                const int32_t* __restrict__ erp, const int32_t* __restrict__ ecols,
-                                                const double* __restrict__ evals, const double* __restrict__ ersum,
-                                                const int32_t* __restrict__ eidx, const int32_t* __restrict__ ebt,
-                                                const int32_t* __restrict__ ext_ptr,
+__global__ __launch_bounds__(BLOCK) void k_smo2(T* u, const T* __restrict__ r, const double* __restrict__ bterm,
+                                                const int32_t* __restrict__ ecell, const int32_t* __restrict__ erp,
+                                                const int32_t* __restrict__ ecols, const double* __restrict__ evals,
+                                                const double* __restrict__ ersum, const int32_t* __restrict__ eidx,
+                                                const int32_t* __restrict__ ebt, const int32_t* __restrict__ ext_ptr,
                                                 const int32_t* __restrict__ own_cnt,
-                                                const int64_t* __restrict__ inv_off,
-                                                const double* __restrict__ inv, double* __restrict__ du, int nrows,
+                                                const int64_t* __restrict__ inv_off, const double* __restrict__ inv,
+                                                const double* __restrict__ c_in, double* __restrict__ c_out, int ns,
                                                 int nbt, size_t plane) {
   __shared__ double res[1024];
   __shared__ double part[4][64];
   const int b = blockIdx.x, z = blockIdx.y;
   u += (size_t)z * plane, r += (size_t)z * plane;
+  c_in += (size_t)z * ns, c_out += (size_t)z * ns;
   const int e0 = ext_ptr[b], ne = ext_ptr[b + 1] - e0, nown = own_cnt[b];
   for (int t = threadIdx.x; t < ne; t += BLOCK) {
     const int e = e0 + t;
-    const int q = ecell[e];
-    double rhs = (double)r[q];
+    const double uq = c_in[eidx[e]];
+    double rhs = (double)r[ecell[e]];
     if (bterm && ebt[e] >= 0) rhs -= bterm[(size_t)z * nbt + ebt[e]];
-    const int p0 = erp[e];
-    res[t] = row_residual(u, rhs, q, ecols + p0, evals + p0, erp[e + 1] - p0, ersum[e]);
+    const int p1 = erp[e + 1];
+    double acc = 0.0;
+    for (int p = erp[e]; p < p1; p += 8) {
+      int cc[8];
+      double vv[8], uu[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool in = p + k < p1;
+        cc[k] = in ? ecols[p + k] : 0;
+        vv[k] = in ? evals[p + k] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) uu[k] = cc[k] >= 0 ? (double)u[cc[k]] : c_in[-cc[k] - 1];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += vv[k] * (uu[k] - uq);
+    }
+    res[t] = rhs - acc - ersum[e] * uq;
   }
   __syncthreads();
   const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  double s0 = 0.0, s1 = 0.0;
+  double s = 0.0;
   if (row < nown) {
     const double* A = inv + inv_off[b] + row;
     int col = grp;
-    for (; col + 4 < ne; col += 8) {
-      s0 += A[(size_t)col * nown] * res[col];
-      s1 += A[(size_t)(col + 4) * nown] * res[col + 4];
+    for (; col + 28 < ne; col += 32) {
+      double a[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] = A[(size_t)(col + 4 * k) * nown];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += a[k] * res[col + 4 * k];
     }
-    if (col < ne) s0 += A[(size_t)col * nown] * res[col];
+    for (; col < ne; col += 4) s += A[(size_t)col * nown] * res[col];
   }
-  part[grp][row] = s0 + s1;
+  part[grp][row] = s;
   __syncthreads();
-  if (grp == 0 && row < nown)
-    du[(size_t)z * nrows + eidx[e0 + row]] = part[0][row] + part[1][row] + part[2][row] + part[3][row];
+  if (grp == 0 && row < nown) {
+    const int k = eidx[e0 + row];
+    const T v = (T)(c_in[k] + (part[0][row] + part[1][row] + part[2][row] + part[3][row]));
+    u[ecell[e0 + row]] = v;
+    c_out[k] = (double)v;
+  }
 }
 
+// c[k] = u[cell[k]] for every block row (start of a solve on level 0).
 template <typename T>
-__global__ void k_add_du(T* __restrict__ u, const double* __restrict__ du, const int32_t* __restrict__ cell,
-                         int nrows, size_t plane) {
+__global__ void k_gather_rows(const T* __restrict__ u, const int32_t* __restrict__ cell, double* __restrict__ c,
+                              int ns, size_t plane) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nrows) return;
+  if (k >= ns) return;
   const int z = blockIdx.y;
-  u[(size_t)z * plane + cell[k]] += (T)du[(size_t)z * nrows + k];
+  c[(size_t)z * ns + k] = (double)u[(size_t)z * plane + cell[k]];
 }
 
 // (A u) for explicit rows (plain sum).
@@ -465,6 +519,8 @@ struct Smo2Data {                 // RAS blocks of one row set
   int32_t* ebt = nullptr;         // boundary-term index of each overlapped row (-1: none)
   int32_t* scell = nullptr;       // cell of every block row
   int ns = 0;                     // block rows
+  double* cbuf[2] = {nullptr, nullptr};   // compact copies of the block rows' values
+  int cur = 0;                    // which copy is current while a cycle is recorded
   double *evals = nullptr, *ersum = nullptr;
   int64_t* inv_off = nullptr;
   double* inv = nullptr;
@@ -633,7 +689,8 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, size_t nce
     ebt[e] = bt[k];
     double rs = 0;
     for (int t = R.rp[k]; t < R.rp[k + 1]; ++t) {
-      ecols.push_back(R.cols[t]);
+      const int p = pos[R.cols[t]];
+      ecols.push_back(p >= 0 ? -(p + 1) : R.cols[t]);
       evals.push_back(R.vals[t]);
       rs += R.vals[t];
     }
@@ -719,43 +776,68 @@ struct Driver {
     }
   }
 
+  // restriction into rc; also zeroes the coarse iterate uc and the coarse
+  // block rows' compact copy (which becomes the current one)
   template <typename T>
-  void restrict_(DevLevel& L, DevLevel& C, const T* u, const T* r, T* rc) {
+  void restrict_(DevLevel& L, DevLevel& C, const T* u, const T* r, T* rc, T* uc) {
     CoefT<T> c(L.coef);
     const dim3 g((L.nx + TX - 1) / TX, (L.ny + TY - 1) / TY, nrhs);
     const bool fin = &L == &X->lv[0];
     const uint8_t rb = regbit();
+    Smo2Data& CS = rows(C).smo2;
+    CS.cur = 0;
+    double* cc = CS.cbuf[0];
+    const int ncc = CS.ns;
     if (L.cross) {
-      if (fin) hipLaunchKernelGGL((k_restrict<T, T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c, rb);
-      else hipLaunchKernelGGL((k_restrict<T, T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c, rb);
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
+      else hipLaunchKernelGGL((k_restrict<T, T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
     } else {
-      if (fin) hipLaunchKernelGGL((k_restrict<T, T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c, rb);
-      else hipLaunchKernelGGL((k_restrict<T, T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, L.nx, L.ny, C.nx, C.ny, c, rb);
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
+      else hipLaunchKernelGGL((k_restrict<T, T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
     }
   }
 
   template <typename T>
   void prolong(DevLevel& L, DevLevel& C, T* u, const T* e) {
-    hipLaunchKernelGGL((k_prolong<T>), dim3((L.nx + 255) / 256, L.ny, nrhs), dim3(256), 0, s, u, e, L.kind, C.kind,
-                       L.nx, L.ny, C.nx, C.ny, X->opt.prolongation, regbit());
+    Smo2Data& S = rows(L).smo2;
+    const int gx = (L.nx + 255) / 256;
+    const int extra = S.ns > 0 ? (S.ns + 256 * gx - 1) / (256 * gx) : 0;
+    hipLaunchKernelGGL((k_prolong<T>), dim3(gx, L.ny + extra, nrhs), dim3(256), 0, s, u, e, L.kind, C.kind, L.nx,
+                       L.ny, C.nx, C.ny, X->opt.prolongation, regbit(), S.scell, S.cbuf[S.cur], S.ns);
   }
 
   template <typename T>
   void smo2_pass(DevLevel& L, T* u, const T* r, const double* bterm) {
     DevRows& R = rows(L);
-    const Smo2Data& S = R.smo2;
+    Smo2Data& S = R.smo2;
     hipLaunchKernelGGL((k_smo2<T>), dim3(S.nblk, nrhs), dim3(BLOCK), 0, s, u, r, bterm, S.ecell, S.erp, S.ecols,
-                       S.evals, S.ersum, S.ext_idx, S.ebt, S.ext_ptr, S.own_cnt, S.inv_off, S.inv, L.du, S.ns, R.n,
-                       L.n);
+                       S.evals, S.ersum, S.ext_idx, S.ebt, S.ext_ptr, S.own_cnt, S.inv_off, S.inv, S.cbuf[S.cur],
+                       S.cbuf[1 - S.cur], S.ns, R.n, L.n);
+    S.cur = 1 - S.cur;
   }
 
   template <typename T>
   void smo2(DevLevel& L, T* u, const T* r, const double* bterm) {
-    const Smo2Data& S = rows(L).smo2;
-    if (S.ns == 0) return;
-    for (int it = 0; it < X->opt.smo2_iters; ++it) {
-      smo2_pass<T>(L, u, r, bterm);
-      hipLaunchKernelGGL((k_add_du<T>), dim3((S.ns + 255) / 256, nrhs), dim3(256), 0, s, u, L.du, S.scell, S.ns, L.n);
+    if (rows(L).smo2.ns == 0) return;
+    for (int it = 0; it < X->opt.smo2_iters; ++it) smo2_pass<T>(L, u, r, bterm);
+  }
+
+  // copy of the block rows' values, from an iterate (start of a solve)
+  template <typename T>
+  void gather_rows(DevLevel& L, const T* u) {
+    Smo2Data& S = rows(L).smo2;
+    S.cur = 0;
+    if (S.ns > 0)
+      hipLaunchKernelGGL((k_gather_rows<T>), dim3((S.ns + 255) / 256, nrhs), dim3(256), 0, s, u, S.scell,
+                         S.cbuf[0], S.ns, L.n);
+  }
+
+  // a recorded cycle must leave the current copy where it found it
+  void settle_rows(DevLevel& L) {
+    Smo2Data& S = rows(L).smo2;
+    if (S.cur != 0 && S.ns > 0) {
+      HIP_OK(hipMemcpyAsync(S.cbuf[0], S.cbuf[1], sizeof(double) * S.ns * nrhs, hipMemcpyDeviceToDevice, s));
+      S.cur = 0;
     }
   }
 
@@ -795,11 +877,12 @@ struct Driver {
     T* oth = cur == u ? v : u;
     DevLevel& C = X->lv[m + 1];
     Buf<T> cb = bufs<T>(C);
-    restrict_<T>(L, C, cur, r, cb.r);
-    fill<T>(cb.u, C.n * nrhs, (T)0);
+    restrict_<T>(L, C, cur, r, cb.r, cb.u);
     T* e = vcycle<T>(m + 1, cb.u, cb.v, cb.r, nullptr);
     prolong<T>(L, C, cur, e);
-    return smooth<T>(L, cur, oth, r, bterm, X->opt.nu2);
+    T* out = smooth<T>(L, cur, oth, r, bterm, X->opt.nu2);
+    settle_rows(L);
+    return out;
   }
 
   // max over non-empty cells of |r - bterm - A u| (zero_u: of |r - bterm|)
@@ -865,6 +948,8 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
   L.u32 = dalloc<float>(L.n * maxr, X->owned);
   L.v32 = dalloc<float>(L.n * maxr, X->owned);
   L.r32 = dalloc<float>(L.n * maxr, X->owned);
+  for (DevRows* R : {&L.fwd, &L.adj})
+    for (int k = 0; k < 2; ++k) R->smo2.cbuf[k] = dalloc<double>((size_t)std::max(1, R->smo2.ns) * maxr, X->owned);
   const int nrows = std::max(1, std::max(std::max(L.fwd.n, L.adj.n), std::max(L.fwd.smo2.ns, L.adj.smo2.ns)));
   L.du = dalloc<double>((size_t)nrows * maxr, X->owned);
   L.npart_reg = (int)(((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY));
@@ -943,6 +1028,7 @@ void mp_cycle(Driver& Dr, double* u, const double* f, const double* bterm) {
     hipLaunchKernelGGL((k_residual_f32<false>), tiles(L0.nx, L0.ny, nr), dim3(BLOCK), 0, Dr.s, u, f, L0.kind, L0.r32, L0.nx, L0.ny, c, rb);
   Dr.resmax<double>(L0, u, f, bterm, 0, L0.r32);
   Dr.fill<float>(L0.u32, L0.n * nr, 0.0f);
+  Dr.gather_rows<float>(L0, L0.u32);
   float* e = Dr.vcycle<float>(0, L0.u32, L0.v32, L0.r32, nullptr);
   const size_t n = L0.n * nr;
   hipLaunchKernelGGL(k_axpy_f32, dim3(std::min<size_t>(4096, (n + 255) / 256)), dim3(256), 0, Dr.s, u, e, L0.kind, L0.n, n);
@@ -969,6 +1055,7 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     }
     if (!X->opt.use_initial_guess) Dr.fill<double>(u, n, 0.0);
     hipLaunchKernelGGL(k_mask_empty, dim3(std::min<size_t>(4096, (n + 255) / 256)), dim3(256), 0, ws, u, L0.kind, L0.n, n);
+    if (X->opt.precision != 1) Dr.gather_rows<double>(L0, u);
     Dr.resmax<double>(L0, u, f, bterm, 1, nullptr);
     std::vector<double> rn(nrhs);
     HIP_OK(hipMemcpyAsync(X->norm_host, X->norm_out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ws));
@@ -1379,10 +1466,11 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
     auto launch = [&]() {
       switch (kernel) {
         case 0: Dr.sweep<double>(L, L.u, L.r, L.v); break;
-        case 1: Dr.restrict_<double>(L, *C, L.u, L.r, C->r); break;
+        case 1: Dr.restrict_<double>(L, *C, L.u, L.r, C->r, C->u); break;
         case 2: Dr.prolong<double>(L, *C, L.u, C->u); break;
         case 3:
           if (L.fwd.smo2.ns > 0) Dr.smo2_pass<double>(L, L.u, L.r, nullptr);
+          Dr.settle_rows(L);
           break;
         case 4: Dr.coarse<double>(L, L.u, L.r); break;
         default: Dr.sweep<float>(L, L.u32, L.r32, L.v32); break;

@@ -84,7 +84,9 @@ typedef struct {
   int nu1, nu2;          /* pre/post smoothing steps, default 3, 3                        */
   int coarsest_min_n;    /* smallest coarse grid side considered, default 16              */
   int max_levels;        /* default 16                                                    */
-  int auto_depth;        /* 1: drop coarse levels whose V-cycles contract poorly          */
+  int auto_depth;        /* coarsest level: 0 deepest that can be built; 1 deepest whose
+                            V-cycles contract by <= depth_max_rate; 2 (default) measured:
+                            the admissible depth with the fastest timed solve          */
   double depth_max_rate; /* contraction bound used by auto_depth, default 0.5            */
   int precision;         /* 0: FP64 sweeps; 1: FP32 sweeps inside FP64 refinement         */
   int prolongation;      /* 0: piecewise constant (Section 4.1); 1: bilinear              */
@@ -92,7 +94,7 @@ typedef struct {
                             last sweep of each smoothing phase only                        */
   int smo2_iters;        /* block iterations per SMO-2 application, default 1             */
   int smo2_block;        /* irregular cells per block, default 64                         */
-  int smo2_overlap;      /* overlap layers of a block in the matrix graph, default 2      */
+  int smo2_overlap;      /* overlap layers of a block in the matrix graph, default 1      */
   int smo2_widen;        /* regular cells within this distance of the least-squares rows
                             join the SMO-2 blocks instead of SMO-1, default 1 (0 = the
                             paper's split)                                               */

@@ -565,6 +565,13 @@ struct ccgmg_ctx {
   int32_t* mcell = nullptr;
   double* minv = nullptr;           // inverse of the coarsest operator
   double* mtinv = nullptr;          // inverse of its transpose
+  struct Coarse {
+    int nm;
+    int32_t* cell;
+    double *inv, *tinv;
+  };
+  std::map<int, Coarse> coarse_cache;   // per coarsest level index
+  std::vector<double> tune_ms;          // autotune: solve time per depth (index = M)
   int nfaces = 0;                   // level-0 boundary data
   int32_t *fptr = nullptr, *fface = nullptr, *fcell = nullptr;
   double *fval = nullptr, *fweight = nullptr;
@@ -958,6 +965,11 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
 }
 
 void upload_coarsest(ccgmg_ctx* X) {
+  auto hit = X->coarse_cache.find(X->M);
+  if (hit != X->coarse_cache.end()) {
+    X->nm = hit->second.nm, X->mcell = hit->second.cell, X->minv = hit->second.inv, X->mtinv = hit->second.tinv;
+    return;
+  }
   ccg::Discretization& D = X->H.disc[X->M];
   std::vector<int32_t> cells;
   std::vector<int32_t> pos(D.nonempty.size(), -1);
@@ -989,6 +1001,7 @@ void upload_coarsest(ccgmg_ctx* X) {
   X->mcell = upload(cells, X->owned);
   X->minv = upload(A, X->owned);
   X->mtinv = upload(AT, X->owned);
+  X->coarse_cache[X->M] = {n, X->mcell, X->minv, X->mtinv};
 }
 
 int guard(ccgmg_ctx* X, const std::function<void()>& body) {
@@ -1137,7 +1150,7 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
 
 // V-cycles on a seeded random right-hand side with the current depth; the
 // geometric-mean contraction of the residual over 6 cycles.
-double depth_test_rate(ccgmg_ctx* X) {
+double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, double* seconds = nullptr) {
   DevLevel& L0 = X->lv[0];
   std::vector<double> r(L0.n, 0.0);
   std::mt19937_64 gen(12345);
@@ -1148,8 +1161,8 @@ double depth_test_rate(ccgmg_ctx* X) {
   double* ud = L0.u;
   HIP_OK(hipMemcpy(rd, r.data(), sizeof(double) * L0.n, hipMemcpyHostToDevice));
   ccgmg_options saved = X->opt;
-  X->opt.max_cycles = 6;
-  X->opt.tol = 0.0;
+  X->opt.max_cycles = max_cycles;
+  X->opt.tol = tol;
   X->opt.use_initial_guess = 0;
   X->opt.precision = 0;
   X->opt.use_graph = 0;
@@ -1159,6 +1172,7 @@ double depth_test_rate(ccgmg_ctx* X) {
   solve_impl(X, rd, ud, 1, &rep, false);
   X->opt = saved;
   X->g_nrhs = g_saved;
+  if (seconds) *seconds = rep.seconds;
   double last = rep.cycles > 0 ? rep.history[std::min(rep.cycles, 64) - 1] : 1.0;
   return (std::isfinite(last) && rep.cycles > 0) ? std::pow(last, 1.0 / rep.cycles) : 1e300;
 }
@@ -1179,14 +1193,14 @@ void ccgmg_default_options(ccgmg_options* o) {
   o->nu2 = 3;
   o->coarsest_min_n = 16;
   o->max_levels = 16;
-  o->auto_depth = 1;
+  o->auto_depth = 2;
   o->depth_max_rate = 0.5;
   o->precision = 0;
   o->prolongation = 0;
   o->smo2_every_sweep = 1;
   o->smo2_iters = 1;
   o->smo2_block = 64;
-  o->smo2_overlap = 2;
+  o->smo2_overlap = 1;
   o->smo2_widen = 1;
   o->tol = 1e-10;
   o->max_cycles = 100;
@@ -1278,7 +1292,29 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
         throw ccg::Error(CCGMG_EINVAL, "coarsest level has too many unknowns; allow more levels");
       }
       upload_coarsest(X.get());
-      if (X->opt.auto_depth && X->M > 1) {
+      if (X->opt.auto_depth == 2 && X->M > 1) {
+        // measured: time a full solve (seeded right-hand side, 1e-10) for
+        // every admissible coarsest level and keep the fastest
+        const int Mmax = X->M;
+        X->tune_ms.assign(Mmax + 1, 0.0);
+        double best = 1e300;
+        int bestM = Mmax;
+        for (int Mc = Mmax; Mc >= 1; --Mc) {
+          long nu = 0;
+          for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
+          if (nu > MAX_COARSE_UNKNOWNS) break;
+          X->M = Mc;
+          upload_coarsest(X.get());
+          double sec = 0;
+          depth_test_rate(X.get(), 1e-10, 60, &sec);
+          const double rate = depth_test_rate(X.get(), 1e-10, 60, &sec);
+          X->tune_ms[Mc] = rate <= X->opt.depth_max_rate ? 1e3 * sec : -1.0;
+          if (rate <= X->opt.depth_max_rate && sec < best) best = sec, bestM = Mc;
+        }
+        X->M = bestM;
+        upload_coarsest(X.get());
+        X->clear_graphs();
+      } else if (X->opt.auto_depth == 1 && X->M > 1) {
         for (;;) {
           const double rate = depth_test_rate(X.get());
           if (rate <= X->opt.depth_max_rate || X->M <= 1) break;

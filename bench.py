@@ -63,10 +63,10 @@ def make_inputs(S, cfg, torch, dev):
     return torch.tensor(fh, device=dev), torch.tensor(ghat, device=dev), ex, kinds
 
 
-def cpu_baseline(n_sample):
+def cpu_baseline(n_sample, seconds):
     """The oracle's own V-cycle solve, one core, on the same geometry and
-    problem at a smaller grid (its set-up is not timed)."""
-    import numpy as np
+    problem at a smaller grid: its set-up is not timed; the solve from a zero
+    guess is repeated until at least ``seconds`` of CPU time have passed."""
     from threadpoolctl import threadpool_limits
 
     import workloads as W
@@ -75,20 +75,30 @@ def cpu_baseline(n_sample):
     from oracle.multigrid import Hierarchy, rhs_vector
     cfg = W.config(4, n=n_sample)
     with threadpool_limits(limits=1):
+        t_set = time.perf_counter()
         H = Hierarchy(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
         H.select_depth()
         lv = H.levels[0]
         f = cell_averages(lv.cg, cfg["f"]).ravel()
         g = boundary_data(lv.disc, cfg["solution"])
         r = rhs_vector(lv, f, g)
-        hist = []
+        t_set = time.perf_counter() - t_set
+        solves, cycles = 0, 0
         t0 = time.perf_counter()
-        H.solve(r, tol=1e-10, history=hist)
-        dt = time.perf_counter() - t0
+        while True:
+            hist = []
+            H.solve(r, tol=1e-10, history=hist)
+            solves += 1
+            cycles = len(hist)
+            dt = time.perf_counter() - t0
+            if dt >= seconds:
+                break
     nu = int(lv.nonempty.sum())
-    return {"value": nu / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle V-cycles (Alg. 2, exact SMO-2 and bottom LU) to 1e-10 on the same geometry and "
-                      "problem at %d^2 (%d unknowns, %d cycles, %.1f s)" % (n_sample, nu, len(hist), dt)}
+    return {"value": nu * solves / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle V-cycle solves (Alg. 2, exact SMO-2 blocks, LU at the coarsest level) from zero to "
+                      "1e-10 on the same geometry and problem at %d^2 (%d unknowns, %d cycles per solve), "
+                      "%d solves in %.1f s on 1 thread; oracle set-up %.1f s untimed"
+                      % (n_sample, nu, cycles, solves, dt, t_set)}
 
 
 def main():
@@ -99,6 +109,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--prolongation", type=int, default=0)
     ap.add_argument("--smo2-every-sweep", type=int, default=1)
@@ -113,6 +124,7 @@ def main():
 
     import workloads as W
     from paper_2504_00724_amd.ccgmg import Solver
+    from paper_2504_00724_amd.prof_summary import read_traffic_record
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -155,6 +167,14 @@ def main():
     other = {name: S.profile_kernel(k, 0, 20) for name, k in (("restrict_us", 1), ("prolong_us", 2),
                                                                ("smo2_block_us", 3))}
 
+    # HBM bytes per launch of the same kernel from the committed counter runs
+    # (FETCH_SIZE, WRITE_SIZE, copy-calibrated); null once the kernel sources
+    # differ from those the counters were taken on
+    rec = read_traffic_record(os.path.join(ROOT, "profiles", "k_sweep_fp64_2048_pmc.md"))
+    traffic = None
+    if rec and rec["cells"] == args.n * args.n:
+        traffic = rec["traffic_bytes_per_launch"]
+
     mixed = None
     if not args.no_mixed:
         Sm = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-10, max_cycles=200,
@@ -178,7 +198,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_sample_n)
+        cpu = cpu_baseline(args.cpu_sample_n, args.cpu_seconds)
 
     out = {
         "metric": "4th-order cut-cell GMG solve: unknowns/s and HBM GB/s at 1e-10 rel. residual, 2048^2",
@@ -202,7 +222,7 @@ def main():
         "disc_err_inf": disc_err,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep<double,false,true> (finest-level SMO-1)", "avg_us": sweep_us,
                      "alg_bytes_per_launch": sweep_bytes},
         "kernels_us": other,

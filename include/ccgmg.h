@@ -222,7 +222,8 @@ int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out, int nrhs);
  * (one right-hand side), bracketed by HIP events; *avg_us receives the mean
  * duration per launch in microseconds.  kernel: 0 SMO-1 sweep (FP64),
  * 1 residual + restriction (FP64), 2 prolongation (FP64), 3 SMO-2 block
- * pass (FP64), 4 coarsest solve, 5 SMO-1 sweep (FP32).  Leaves the work
+ * pass (FP64), 4 coarsest solve, 5 SMO-1 sweep (FP32), 6 plain FP64 copy of
+ * the level's cell array (16 bytes per cell; calibrates byte counters).  Leaves the work
  * buffers of that level undefined; no user buffer is touched. */
 int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double* avg_us);
 

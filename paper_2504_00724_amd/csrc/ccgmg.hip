@@ -471,6 +471,13 @@ __global__ void k_fill(T* __restrict__ p, size_t n, T v) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
 }
 
+// Plain FP64 copy, 16 bytes per element: the calibration kernel for HBM
+// byte counters.
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
 __global__ void k_axpy_f32(double* __restrict__ u, const float* __restrict__ e, const uint8_t* __restrict__ kind,
                            size_t plane, size_t n) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
@@ -1487,7 +1494,7 @@ int ccgmg_apply_NT(ccgmg_ctx* X, const double* lam, double* out, int nrhs) {
 
 int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* avg_us) {
   return guard(X, [&]() {
-    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 5)
+    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 6)
       throw ccg::Error(CCGMG_EINVAL, "bad profile arguments");
     Driver Dr{X, X->stream, 1, false};
     DevLevel& L = X->lv[level];
@@ -1509,6 +1516,10 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
           Dr.settle_rows(L);
           break;
         case 4: Dr.coarse<double>(L, L.u, L.r); break;
+        case 6:
+          hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(8192, (L.n + 255) / 256)), dim3(256), 0, X->stream, L.v,
+                             L.u, L.n);
+          break;
         default: Dr.sweep<float>(L, L.u32, L.r32, L.v32); break;
       }
     };

@@ -104,6 +104,8 @@ typedef struct {
   int use_initial_guess; /* 1: u_hat holds the initial guess; 0: start from zero          */
   int num_threads;       /* host threads for set-up (0 = hardware concurrency)            */
   int use_graph;         /* 1: replay V-cycles from a captured hipGraph                   */
+  int tune_tiles;        /* 1 (default): pick the SMO-1 tile height of every level and
+                            precision by timing the candidates at set-up; 0: 64 x 16     */
   int host_only;         /* 1: build the hierarchy on the host only (no device calls);
                             queries work, apply/solve return CCGMG_EINVAL                  */
   void* hip_stream;      /* hipStream_t all device work is ordered on                     */
@@ -163,6 +165,10 @@ int ccgmg_get_volumes(const ccgmg_ctx* ctx, int level, double* vol);
  * matrix.  Host arrays sized by ccgmg_info.n_irregular for level 0 (query
  * other levels with ccgmg_get_counts).  Any pointer may be NULL. */
 int ccgmg_get_counts(const ccgmg_ctx* ctx, int level, long* n_irregular, long* n_faces);
+
+/* SMO-1 tile height (64-wide tiles of 8, 16 or 32 rows) chosen for level m
+ * in FP64 and FP32 sweeps (tune_tiles).  Device contexts only. */
+int ccgmg_get_tuning(const ccgmg_ctx* ctx, int level, int* sweep_ty_fp64, int* sweep_ty_fp32);
 int ccgmg_get_irregular(const ccgmg_ctx* ctx, int level, int32_t* rows, int32_t* cols, double* vals,
                         double* cond);
 

@@ -24,7 +24,7 @@ EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_ce
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
            "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
-           "ccgmg_profile_kernel",
+           "ccgmg_profile_kernel", "ccgmg_get_tuning",
            "ccgmg_last_error",
            "ccgmg_create_error", "ccgmg_destroy"]
 
@@ -44,7 +44,7 @@ class OptionsT(C.Structure):
                 ("smo2_every_sweep", C.c_int), ("smo2_iters", C.c_int), ("smo2_block", C.c_int),
                 ("smo2_overlap", C.c_int), ("smo2_widen", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
                 ("use_initial_guess", C.c_int), ("num_threads", C.c_int), ("use_graph", C.c_int),
-                ("host_only", C.c_int), ("hip_stream", C.c_void_p)]
+                ("tune_tiles", C.c_int), ("host_only", C.c_int), ("hip_stream", C.c_void_p)]
 
 
 class InfoT(C.Structure):
@@ -91,6 +91,7 @@ def lib():
         L.ccgmg_apply_adjoint.argtypes = [vp, vp, vp]
         L.ccgmg_apply_NT.argtypes = [vp, vp, vp, ip]
         L.ccgmg_profile_kernel.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_double)]
+        L.ccgmg_get_tuning.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
         L.ccgmg_last_error.argtypes = [vp]
         L.ccgmg_last_error.restype = C.c_char_p
         L.ccgmg_create_error.argtypes = []
@@ -255,6 +256,12 @@ class Solver:
         us = C.c_double()
         self._check(lib().ccgmg_profile_kernel(self.ctx, kernel, level, reps, C.byref(us)))
         return us.value
+
+    def tuning(self, level=0):
+        """SMO-1 tile heights (FP64, FP32) picked for a level at set-up."""
+        a, b = C.c_int(), C.c_int()
+        self._check(lib().ccgmg_get_tuning(self.ctx, level, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def apply_adjoint(self, lam, out):
         self._check(lib().ccgmg_apply_adjoint(self.ctx, _ptr(lam), _ptr(out)))

@@ -49,32 +49,37 @@ constexpr uint8_t F_JAC_T = 16;   // smoothed by SMO-1 (L^T)
 // ===========================================================================
 
 // SMO-1: u_out = u + omega/D (r - L u) on cells flagged `regbit`, u_out = u
-// elsewhere (Jacobi: reads u, writes a second buffer).  FINEST only selects
-// a separate instantiation for the finest level so that kernel traces
-// separate it from the coarse levels; the code is the same.
-template <typename T, bool CROSS, bool FINEST>
+// elsewhere (Jacobi: reads u, writes a second buffer).  Tiles of TX x TYS
+// cells (TYS = 8, 16 or 32, picked per level by measurement), one workgroup
+// each, on a 1-D grid remapped by xcd_tile; nbx = tiles per grid row.
+// FINEST only selects a separate instantiation for the finest level so that
+// kernel traces separate it from the coarse levels; the code is the same.
+template <typename T, bool CROSS, bool FINEST, int TYS>
 __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const T* __restrict__ r,
                                                  const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
-                                                 int ny, CoefT<T> c, uint8_t regbit) {
-  __shared__ T tile[LH][LW];
+                                                 int ny, int nbx, CoefT<T> c, uint8_t regbit) {
+  constexpr int RPW = TYS / 4;            // rows per wave
+  __shared__ T tile[TYS + 2 * HALO][LW];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   u += zoff, r += zoff, out += zoff;
-  const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = t / nbx;
+  const int bx = (t - tyi * nbx) * TX, by = tyi * TYS;
   const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
   // issue the kind and right-hand-side loads before the tile barrier
-  uint8_t kd[TY / 4];
-  T rr[TY / 4];
+  uint8_t kd[RPW];
+  T rr[RPW];
 #pragma unroll
-  for (int k = 0; k < TY / 4; ++k) {
+  for (int k = 0; k < RPW; ++k) {
     const int gx = bx + tx, gy = by + w + 4 * k;
     const bool in = gx < nx && gy < ny;
     kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
     rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
   }
-  load_tile(tile, u, nx, ny, bx, by);
+  load_tile<T, TYS + 2 * HALO>(tile, u, nx, ny, bx, by);
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < TY / 4; ++k) {
+  for (int k = 0; k < RPW; ++k) {
     const int ry = w + 4 * k;
     const int gx = bx + tx, gy = by + ry;
     if (gx < nx && gy < ny) {
@@ -93,17 +98,19 @@ template <typename T, typename TC, bool CROSS, bool FINEST>
 __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, const T* __restrict__ r,
                                                     const uint8_t* __restrict__ kind, TC* __restrict__ rc,
                                                     TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx,
-                                                    int ny, int ncx, int ncy, CoefT<T> c, uint8_t regbit) {
+                                                    int ny, int nbx, int ncx, int ncy, CoefT<T> c, uint8_t regbit) {
   __shared__ T tile[LH][LW];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   u += zoff, r += zoff;
   rc += (size_t)blockIdx.z * ncx * ncy;
   uc += (size_t)blockIdx.z * ncx * ncy;
   {
-    const int flat = (blockIdx.y * gridDim.x + blockIdx.x) * BLOCK + threadIdx.x;
+    const int flat = blockIdx.x * BLOCK + threadIdx.x;
     if (flat < ncc) cc[(size_t)blockIdx.z * ncc + flat] = 0.0;
   }
-  const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = t / nbx, txi = t - tyi * nbx;
+  const int bx = txi * TX, by = tyi * TY;
   const int cx = threadIdx.x & 31, cy = threadIdx.x >> 5;  // 32 x 8 coarse cells
   uint8_t kd[4];
   T rr[4];
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, con
   }
   load_tile(tile, u, nx, ny, bx, by);
   __syncthreads();
-  const int I = blockIdx.x * (TX / 2) + cx, J = blockIdx.y * (TY / 2) + cy;
+  const int I = txi * (TX / 2) + cx, J = tyi * (TY / 2) + cy;
   if (I >= ncx || J >= ncy) return;
   T s = (T)0;
 #pragma unroll
@@ -306,12 +313,14 @@ __global__ __launch_bounds__(BLOCK) void k_apply(const double* __restrict__ u, c
 template <typename T, bool CROSS>
 __global__ __launch_bounds__(BLOCK) void k_resmax_reg(const T* __restrict__ u, const T* __restrict__ r,
                                                       const uint8_t* __restrict__ kind, double* __restrict__ partial,
-                                                      int nx, int ny, CoefT<T> c, int zero_u, uint8_t regbit) {
+                                                      int nx, int ny, int nbx, CoefT<T> c, int zero_u, uint8_t regbit) {
   __shared__ T tile[LH][LW];
   __shared__ double red[BLOCK];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   u += zoff, r += zoff;
-  const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = t / nbx;
+  const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
   const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
   uint8_t kd[TY / 4];
   T rr[TY / 4];
@@ -340,7 +349,7 @@ __global__ __launch_bounds__(BLOCK) void k_resmax_reg(const T* __restrict__ u, c
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    partial[(size_t)blockIdx.z * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    partial[(size_t)blockIdx.z * gridDim.x + blockIdx.x] = red[0];
 }
 
 // Same for the explicit rows (FP64), optionally writing the residual into a
@@ -396,11 +405,13 @@ __global__ void k_reduce_max(const double* __restrict__ pa, int na, const double
 template <bool CROSS>
 __global__ __launch_bounds__(BLOCK) void k_residual_f32(const double* __restrict__ u, const double* __restrict__ r,
                                                         const uint8_t* __restrict__ kind, float* __restrict__ out,
-                                                        int nx, int ny, CoefT<double> c, uint8_t regbit) {
+                                                        int nx, int ny, int nbx, CoefT<double> c, uint8_t regbit) {
   __shared__ double tile[LH][LW];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   u += zoff, r += zoff, out += zoff;
-  const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = t / nbx;
+  const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
   const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
   uint8_t kd[TY / 4];
   double rr[TY / 4];
@@ -555,6 +566,7 @@ struct DevLevel {
   float *u32 = nullptr, *v32 = nullptr, *r32 = nullptr;
   double* du = nullptr;
   double* part = nullptr;         // reduction partials
+  int sweep_ty[2] = {16, 16};     // SMO-1 tile height (FP64, FP32), tuned at set-up
   int npart_reg = 0, npart_irr = 0;
 };
 
@@ -610,6 +622,11 @@ struct ccgmg_ctx {
 
 namespace {
 
+// 1-D grid of TX x ty tiles (remapped per XCD in the kernels), nrhs planes
+int tiles_x(int nx) { return (nx + TX - 1) / TX; }
+dim3 tiles1d(int nx, int ny, int nrhs, int ty = TY) {
+  return dim3(tiles_x(nx) * ((ny + ty - 1) / ty), 1, nrhs);
+}
 dim3 tiles(int nx, int ny, int nrhs) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, nrhs); }
 
 // RAS block data for a row set: blocks of `bsize` consecutive rows of the
@@ -775,18 +792,29 @@ struct Driver {
   uint8_t jacbit() const { return adjoint ? F_JAC_T : F_JAC; }
   DevRows& rows(DevLevel& L) const { return adjoint ? L.adj : L.fwd; }
 
-  template <typename T>
-  void sweep(DevLevel& L, const T* u, const T* r, T* out) {
+  template <typename T, bool CROSS, bool FIN>
+  void sweep_t(DevLevel& L, const T* u, const T* r, T* out, int ty) {
     CoefT<T> c(L.coef);
-    const dim3 g = tiles(L.nx, L.ny, nrhs);
-    const bool fin = &L == &X->lv[0];
+    const dim3 g = tiles1d(L.nx, L.ny, nrhs, ty);
+    const int nbx = tiles_x(L.nx);
     const uint8_t rb = jacbit();
+    switch (ty) {
+      case 8: hipLaunchKernelGGL((k_sweep<T, CROSS, FIN, 8>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb); break;
+      case 32: hipLaunchKernelGGL((k_sweep<T, CROSS, FIN, 32>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb); break;
+      default: hipLaunchKernelGGL((k_sweep<T, CROSS, FIN, 16>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb); break;
+    }
+  }
+
+  template <typename T>
+  void sweep(DevLevel& L, const T* u, const T* r, T* out, int ty = 0) {
+    if (ty == 0) ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
+    const bool fin = &L == &X->lv[0];
     if (L.cross) {
-      if (fin) hipLaunchKernelGGL((k_sweep<T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c, rb);
-      else hipLaunchKernelGGL((k_sweep<T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c, rb);
+      if (fin) sweep_t<T, true, true>(L, u, r, out, ty);
+      else sweep_t<T, true, false>(L, u, r, out, ty);
     } else {
-      if (fin) hipLaunchKernelGGL((k_sweep<T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c, rb);
-      else hipLaunchKernelGGL((k_sweep<T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, c, rb);
+      if (fin) sweep_t<T, false, true>(L, u, r, out, ty);
+      else sweep_t<T, false, false>(L, u, r, out, ty);
     }
   }
 
@@ -795,7 +823,8 @@ struct Driver {
   template <typename T>
   void restrict_(DevLevel& L, DevLevel& C, const T* u, const T* r, T* rc, T* uc) {
     CoefT<T> c(L.coef);
-    const dim3 g((L.nx + TX - 1) / TX, (L.ny + TY - 1) / TY, nrhs);
+    const dim3 g = tiles1d(L.nx, L.ny, nrhs);
+    const int nbx = tiles_x(L.nx);
     const bool fin = &L == &X->lv[0];
     const uint8_t rb = regbit();
     Smo2Data& CS = rows(C).smo2;
@@ -803,11 +832,11 @@ struct Driver {
     double* cc = CS.cbuf[0];
     const int ncc = CS.ns;
     if (L.cross) {
-      if (fin) hipLaunchKernelGGL((k_restrict<T, T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
-      else hipLaunchKernelGGL((k_restrict<T, T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
+      else hipLaunchKernelGGL((k_restrict<T, T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
     } else {
-      if (fin) hipLaunchKernelGGL((k_restrict<T, T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
-      else hipLaunchKernelGGL((k_restrict<T, T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, C.nx, C.ny, c, rb);
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
+      else hipLaunchKernelGGL((k_restrict<T, T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
     }
   }
 
@@ -902,13 +931,14 @@ struct Driver {
   // max over non-empty cells of |r - bterm - A u| (zero_u: of |r - bterm|)
   template <typename T>
   void resmax(DevLevel& L, const T* u, const T* r, const double* bterm, int zero_u, float* res_out) {
-    const dim3 g = tiles(L.nx, L.ny, nrhs);
+    const dim3 g = tiles1d(L.nx, L.ny, nrhs);
+    const int nbx = tiles_x(L.nx);
     CoefT<T> c(L.coef);
     const uint8_t rb = regbit();
     if (L.cross)
-      hipLaunchKernelGGL((k_resmax_reg<T, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.part, L.nx, L.ny, c, zero_u, rb);
+      hipLaunchKernelGGL((k_resmax_reg<T, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.part, L.nx, L.ny, nbx, c, zero_u, rb);
     else
-      hipLaunchKernelGGL((k_resmax_reg<T, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.part, L.nx, L.ny, c, zero_u, rb);
+      hipLaunchKernelGGL((k_resmax_reg<T, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.part, L.nx, L.ny, nbx, c, zero_u, rb);
     DevRows& R = rows(L);
     const int gi = std::max(1, (R.n + BLOCK - 1) / BLOCK);
     double* pirr = L.part + (size_t)L.npart_reg * nrhs;
@@ -1011,6 +1041,44 @@ void upload_coarsest(ccgmg_ctx* X) {
   X->coarse_cache[X->M] = {n, X->mcell, X->minv, X->mtinv};
 }
 
+// Tile-height autotuning of the SMO-1 sweep: on every level and in both
+// precisions, time each admissible tile height (HIP events, private stream,
+// work buffers of that level) and keep the fastest.
+void tune_tiles(ccgmg_ctx* X) {
+  static const int cand[] = {8, 16, 32};
+  Driver Dr{X, X->ws, 1, false};
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  const int reps = 10;
+  for (DevLevel& L : X->lv) {
+    Dr.fill<double>(L.u, L.n, 1.0);
+    Dr.fill<double>(L.r, L.n, 0.5);
+    Dr.fill<float>(L.u32, L.n, 1.0f);
+    Dr.fill<float>(L.r32, L.n, 0.5f);
+    for (int prec = 0; prec < 2; ++prec) {
+      float best = 1e30f;
+      for (int ty : cand) {
+        auto launch = [&]() {
+          if (prec == 0) Dr.sweep<double>(L, L.u, L.r, L.v, ty);
+          else Dr.sweep<float>(L, L.u32, L.r32, L.v32, ty);
+        };
+        launch();
+        launch();
+        HIP_OK(hipEventRecord(e0, X->ws));
+        for (int k = 0; k < reps; ++k) launch();
+        HIP_OK(hipEventRecord(e1, X->ws));
+        HIP_OK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) best = ms, L.sweep_ty[prec] = ty;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 int guard(ccgmg_ctx* X, const std::function<void()>& body) {
   if (!X) return CCGMG_EINVAL;
   try {
@@ -1043,9 +1111,9 @@ void mp_cycle(Driver& Dr, double* u, const double* f, const double* bterm) {
   CoefT<double> c(L0.coef);
   const uint8_t rb = Dr.regbit();
   if (L0.cross)
-    hipLaunchKernelGGL((k_residual_f32<true>), tiles(L0.nx, L0.ny, nr), dim3(BLOCK), 0, Dr.s, u, f, L0.kind, L0.r32, L0.nx, L0.ny, c, rb);
+    hipLaunchKernelGGL((k_residual_f32<true>), tiles1d(L0.nx, L0.ny, nr), dim3(BLOCK), 0, Dr.s, u, f, L0.kind, L0.r32, L0.nx, L0.ny, tiles_x(L0.nx), c, rb);
   else
-    hipLaunchKernelGGL((k_residual_f32<false>), tiles(L0.nx, L0.ny, nr), dim3(BLOCK), 0, Dr.s, u, f, L0.kind, L0.r32, L0.nx, L0.ny, c, rb);
+    hipLaunchKernelGGL((k_residual_f32<false>), tiles1d(L0.nx, L0.ny, nr), dim3(BLOCK), 0, Dr.s, u, f, L0.kind, L0.r32, L0.nx, L0.ny, tiles_x(L0.nx), c, rb);
   Dr.resmax<double>(L0, u, f, bterm, 0, L0.r32);
   Dr.fill<float>(L0.u32, L0.n * nr, 0.0f);
   Dr.gather_rows<float>(L0, L0.u32);
@@ -1215,6 +1283,7 @@ void ccgmg_default_options(ccgmg_options* o) {
   o->use_initial_guess = 0;
   o->num_threads = 0;
   o->use_graph = 1;
+  o->tune_tiles = 1;
   o->host_only = 0;
   o->hip_stream = nullptr;
 }
@@ -1299,6 +1368,7 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
         throw ccg::Error(CCGMG_EINVAL, "coarsest level has too many unknowns; allow more levels");
       }
       upload_coarsest(X.get());
+      if (X->opt.tune_tiles) tune_tiles(X.get());
       if (X->opt.auto_depth == 2 && X->M > 1) {
         // measured: time a full solve (seeded right-hand side, 1e-10) for
         // every admissible coarsest level and keep the fastest
@@ -1390,6 +1460,13 @@ int ccgmg_get_volumes(const ccgmg_ctx* X, int level, double* vol) {
   if (!X || !vol || level < 0 || level >= (int)X->H.disc.size()) return CCGMG_EINVAL;
   const auto& v = X->H.geo[level].vol;
   std::memcpy(vol, v.data(), sizeof(double) * v.size());
+  return CCGMG_OK;
+}
+
+int ccgmg_get_tuning(const ccgmg_ctx* X, int level, int* sweep_ty_fp64, int* sweep_ty_fp32) {
+  if (!X || X->host_only || level < 0 || level >= (int)X->lv.size()) return CCGMG_EINVAL;
+  if (sweep_ty_fp64) *sweep_ty_fp64 = X->lv[level].sweep_ty[0];
+  if (sweep_ty_fp32) *sweep_ty_fp32 = X->lv[level].sweep_ty[1];
   return CCGMG_OK;
 }
 

@@ -39,18 +39,34 @@ struct CoefT {
       : ax1((T)c.ax1), ax2((T)c.ax2), cy1((T)c.cy1), cy2((T)c.cy2), bxy((T)c.bxy), omega_invD((T)c.omega_invD) {}
 };
 
-// Stage the (TY+4) x (TX+4) neighbourhood of a tile in LDS; outside the grid
-// the value is 0 (never read by a regular cell).
-template <typename T>
+// Stage the (ROWS) x (TX+4) neighbourhood of a tile (ROWS = tile height + 4)
+// in LDS; outside the grid the value is 0 (never read by a regular cell).
+template <typename T, int ROWS = LH>
 __device__ __forceinline__ void load_tile(T (*tile)[LW], const T* __restrict__ u, int nx, int ny, int bx, int by) {
   const int tid = threadIdx.x;
-  for (int k = tid; k < LH * LW; k += BLOCK) {
+  for (int k = tid; k < ROWS * LW; k += BLOCK) {
     const int ly = k / LW, lx = k - ly * LW;
     const int gx = bx + lx - HALO, gy = by + ly - HALO;
     T v = (T)0;
     if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = u[(size_t)gy * nx + gx];
     tile[ly][lx] = v;
   }
+}
+
+// Workgroups of a launch are handed to the 8 XCDs round-robin (workgroup id
+// mod 8) and every XCD has its own L2.  xcd_tile maps the 1-D workgroup id b
+// of an nb-workgroup launch to a tile index so that XCD x processes one
+// contiguous range of tiles, i.e. a band of tile rows: horizontally and
+// vertically adjacent tiles, whose halos overlap, then share an L2.  The map
+// is a bijection of [0, nb): XCD x owns ceil(nb/8) tiles if x < nb mod 8
+// (or nb mod 8 == 0), one fewer otherwise.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int per = (nb + NXCD - 1) / NXCD, rem = nb % NXCD;
+  const int x = b % NXCD, k = b / NXCD;
+  int start = x * per;
+  if (rem != 0 && x > rem) start -= x - rem;
+  return start + k;
 }
 
 // (L u) at tile position (ly, lx) (already offset by HALO), difference form.

@@ -106,6 +106,11 @@ typedef struct {
   int use_graph;         /* 1: replay V-cycles from a captured hipGraph                   */
   int tune_tiles;        /* 1 (default): pick the SMO-1 tile height of every level and
                             precision by timing the candidates at set-up; 0: 64 x 16     */
+  int smoother_fused;    /* 0: each smoothing step is SMO-1 then SMO-2 (Alg. 2); 1: both
+                            in one launch from the same iterate (additive)               */
+  int tune_schedule;     /* 1 (default, with auto_depth 2): also time the schedules
+                            (smoother_fused, nu1, nu2) = (0,3,3), (1,3,3), (1,4,4),
+                            (1,5,5) and keep the fastest; 0: use the fields above        */
   int host_only;         /* 1: build the hierarchy on the host only (no device calls);
                             queries work, apply/solve return CCGMG_EINVAL                  */
   void* hip_stream;      /* hipStream_t all device work is ordered on                     */
@@ -121,6 +126,8 @@ typedef struct {
   long coarse_unknowns;
   double setup_seconds;
   double plg_max_cond;
+  int smoother_fused;    /* smoothing schedule in use (after tuning)                      */
+  int nu1, nu2;
 } ccgmg_info;
 
 typedef struct {
@@ -229,7 +236,8 @@ int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out, int nrhs);
  * duration per launch in microseconds.  kernel: 0 SMO-1 sweep (FP64),
  * 1 residual + restriction (FP64), 2 prolongation (FP64), 3 SMO-2 block
  * pass (FP64), 4 coarsest solve, 5 SMO-1 sweep (FP32), 6 plain FP64 copy of
- * the level's cell array (16 bytes per cell; calibrates byte counters).  Leaves the work
+ * the level's cell array (16 bytes per cell; calibrates byte counters),
+ * 7 fused smoothing step (FP64, smoother_fused).  Leaves the work
  * buffers of that level undefined; no user buffer is touched. */
 int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double* avg_us);
 

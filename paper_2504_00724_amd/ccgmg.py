@@ -44,14 +44,14 @@ class OptionsT(C.Structure):
                 ("smo2_every_sweep", C.c_int), ("smo2_iters", C.c_int), ("smo2_block", C.c_int),
                 ("smo2_overlap", C.c_int), ("smo2_widen", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
                 ("use_initial_guess", C.c_int), ("num_threads", C.c_int), ("use_graph", C.c_int),
-                ("tune_tiles", C.c_int), ("host_only", C.c_int), ("hip_stream", C.c_void_p)]
+                ("tune_tiles", C.c_int), ("smoother_fused", C.c_int), ("tune_schedule", C.c_int), ("host_only", C.c_int), ("hip_stream", C.c_void_p)]
 
 
 class InfoT(C.Structure):
     _fields_ = [("n_cells", C.c_long), ("n_unknowns", C.c_long), ("n_irregular", C.c_long),
                 ("n_bdry_faces", C.c_long), ("n_levels", C.c_int), ("nx_coarsest", C.c_int),
                 ("ny_coarsest", C.c_int), ("coarse_unknowns", C.c_long), ("setup_seconds", C.c_double),
-                ("plg_max_cond", C.c_double)]
+                ("plg_max_cond", C.c_double), ("smoother_fused", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int)]
 
 
 class ReportT(C.Structure):

@@ -43,26 +43,29 @@ constexpr uint8_t F_NONEMPTY = 2;
 constexpr uint8_t F_REG_T = 4;    // regular row of L^T
 constexpr uint8_t F_JAC = 8;      // smoothed by SMO-1 (L)
 constexpr uint8_t F_JAC_T = 16;   // smoothed by SMO-1 (L^T)
+constexpr uint8_t F_S2 = 32;      // row of an SMO-2 block (L)
+constexpr uint8_t F_S2_T = 64;    // row of an SMO-2 block (L^T)
 
 // ===========================================================================
 // Kernels
 // ===========================================================================
 
-// SMO-1: u_out = u + omega/D (r - L u) on cells flagged `regbit`, u_out = u
-// elsewhere (Jacobi: reads u, writes a second buffer).  Tiles of TX x TYS
-// cells (TYS = 8, 16 or 32, picked per level by measurement), one workgroup
-// each, on a 1-D grid remapped by xcd_tile; nbx = tiles per grid row.
-// FINEST only selects a separate instantiation for the finest level so that
-// kernel traces separate it from the coarse levels; the code is the same.
-template <typename T, bool CROSS, bool FINEST, int TYS>
-__global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const T* __restrict__ r,
-                                                 const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
-                                                 int ny, int nbx, CoefT<T> c, uint8_t regbit) {
+// SMO-1 on one tile: u_out = u + omega/D (r - L u) on cells flagged `regbit`,
+// u_out = u elsewhere except on cells flagged `skipbit` (left to the SMO-2
+// blocks of a fused step).  Jacobi: reads u, writes a second buffer.  Tiles
+// of TX x TYS cells (TYS = 8, 16 or 32, picked per level by measurement);
+// t is the tile index, nbx the number of tiles per grid row.
+template <typename T, int TYS>
+constexpr int sweep_lds_doubles() { return ((TYS + 2 * HALO) * LW * (int)sizeof(T) + 7) / 8; }
+
+template <typename T, bool CROSS, int TYS, bool PRO = false>
+__device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restrict__ u, const T* __restrict__ r,
+                                           const uint8_t* __restrict__ kind, T* __restrict__ out, int nx, int ny,
+                                           int nbx, const CoefT<T>& c, uint8_t regbit, uint8_t skipbit,
+                                           const T* __restrict__ e = nullptr, int ncx = 0, uint8_t probit = 0) {
   constexpr int RPW = TYS / 4;            // rows per wave
-  __shared__ T tile[TYS + 2 * HALO][LW];
-  const size_t zoff = (size_t)blockIdx.z * nx * ny;
-  u += zoff, r += zoff, out += zoff;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  constexpr int ROWS = TYS + 2 * HALO;
+  T (*tile)[LW] = reinterpret_cast<T (*)[LW]>(smem);
   const int tyi = t / nbx;
   const int bx = (t - tyi * nbx) * TX, by = tyi * TYS;
   const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
@@ -76,18 +79,47 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const 
     kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
     rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
   }
-  load_tile<T, TYS + 2 * HALO>(tile, u, nx, ny, bx, by);
+  if (PRO) {
+    // tile of u + P e: the pending coarse-grid correction (piecewise
+    // constant, cells flagged probit only) is added while staging
+    for (int k = threadIdx.x; k < ROWS * LW; k += BLOCK) {
+      const int ly = k / LW, lx = k - ly * LW;
+      const int gx = bx + lx - HALO, gy = by + ly - HALO;
+      T v = (T)0;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+        const size_t g = (size_t)gy * nx + gx;
+        v = u[g];
+        if (kind[g] & probit) v += e[(size_t)(gy >> 1) * ncx + (gx >> 1)];
+      }
+      tile[ly][lx] = v;
+    }
+  } else {
+    load_tile<T, ROWS>(tile, u, nx, ny, bx, by);
+  }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int ry = w + 4 * k;
     const int gx = bx + tx, gy = by + ry;
-    if (gx < nx && gy < ny) {
+    if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
       T v = tile[ry + HALO][tx + HALO];
       if (kd[k] & regbit) v += c.omega_invD * (rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c));
       out[(size_t)gy * nx + gx] = v;
     }
   }
+}
+
+// SMO-1 sweep launch: one workgroup per tile on a 1-D grid remapped by
+// xcd_tile.  FINEST only selects a separate instantiation for the finest
+// level so that kernel traces separate it from the coarse levels.
+template <typename T, bool CROSS, bool FINEST, int TYS>
+__global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const T* __restrict__ r,
+                                                 const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
+                                                 int ny, int nbx, CoefT<T> c, uint8_t regbit) {
+  __shared__ double smem[sweep_lds_doubles<T, TYS>()];
+  const size_t zoff = (size_t)blockIdx.z * nx * ny;
+  sweep_tile<T, CROSS, TYS>(smem, xcd_tile(blockIdx.x, gridDim.x), u + zoff, r + zoff, kind, out + zoff, nx, ny,
+                            nbx, c, regbit, 0);
 }
 
 // Residual of the regular cells restricted to the coarse grid:
@@ -195,6 +227,95 @@ __device__ __forceinline__ double row_residual(const T* __restrict__ u, double r
   return rhs - (a0 + a1) - rowsum * uq;
 }
 
+// Arguments of an SMO-2 pass (see k_smo2).
+struct Smo2Args {
+  const double* bterm;
+  const int32_t *ecell, *erp, *ecols;
+  const double *evals, *ersum;
+  const int32_t *eidx, *ebt, *ext_ptr, *own_cnt;
+  const int64_t* inv_off;
+  const double* inv;
+  const double* c_in;
+  double* c_out;
+  int ns, nbt;
+  const int32_t* epar;    // per CSR entry: coarse parent of the column cell if it takes the correction, else -1
+  const int32_t* eqpar;   // per overlapped row: the same for the row's own cell
+};
+
+// One RAS block b of plane z: reads uin (non-block columns) and c_in, writes
+// its own rows to uout and c_out.  With a pending coarse-grid correction
+// (PRO, coarse values ecor), every value read is taken as value +
+// ecor[parent] where the cell takes the correction (a.epar / a.eqpar >= 0),
+// i.e. the block works on u + P e.
+constexpr int SMO2_LDS_DOUBLES = 1024 + 4 * 64 + 64;
+
+template <typename T, bool PRO = false>
+__device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* uin, T* uout,
+                                           const T* __restrict__ r, const Smo2Args& a,
+                                           const T* __restrict__ ecor = nullptr) {
+  double* res = smem;                                              // [1024]
+  double (*part)[64] = reinterpret_cast<double (*)[64]>(smem + 1024);   // [4][64]
+  double* uown = smem + 1024 + 4 * 64;                             // [64]
+  const double* c_in = a.c_in + (size_t)z * a.ns;
+  double* c_out = a.c_out + (size_t)z * a.ns;
+  const int e0 = a.ext_ptr[b], ne = a.ext_ptr[b + 1] - e0, nown = a.own_cnt[b];
+  for (int t = threadIdx.x; t < ne; t += BLOCK) {
+    const int e = e0 + t;
+    double uq = c_in[a.eidx[e]];
+    if (PRO) {
+      const int pq = a.eqpar[e];
+      if (pq >= 0) uq += (double)ecor[pq];
+    }
+    if (t < 64) uown[t] = uq;
+    double rhs = (double)r[a.ecell[e]];
+    if (a.bterm && a.ebt[e] >= 0) rhs -= a.bterm[(size_t)z * a.nbt + a.ebt[e]];
+    const int p1 = a.erp[e + 1];
+    double acc = 0.0;
+    for (int p = a.erp[e]; p < p1; p += 8) {
+      int cc[8], pp[8];
+      double vv[8], uu[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool in = p + k < p1;
+        cc[k] = in ? a.ecols[p + k] : 0;
+        vv[k] = in ? a.evals[p + k] : 0.0;
+        pp[k] = (PRO && in) ? a.epar[p + k] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        uu[k] = cc[k] >= 0 ? (double)uin[cc[k]] : c_in[-cc[k] - 1];
+        if (PRO && pp[k] >= 0) uu[k] += (double)ecor[pp[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += vv[k] * (uu[k] - uq);
+    }
+    res[t] = rhs - acc - a.ersum[e] * uq;
+  }
+  __syncthreads();
+  const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  double s = 0.0;
+  if (row < nown) {
+    const double* A = a.inv + a.inv_off[b] + row;
+    int col = grp;
+    for (; col + 28 < ne; col += 32) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = A[(size_t)(col + 4 * k) * nown];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += v[k] * res[col + 4 * k];
+    }
+    for (; col < ne; col += 4) s += A[(size_t)col * nown] * res[col];
+  }
+  part[grp][row] = s;
+  __syncthreads();
+  if (grp == 0 && row < nown) {
+    const int k = a.eidx[e0 + row];
+    const T v = (T)(uown[row] + (part[0][row] + part[1][row] + part[2][row] + part[3][row]));
+    uout[a.ecell[e0 + row]] = v;
+    c_out[k] = (double)v;
+  }
+}
+
 // SMO-2 by restricted additive Schwarz.  Workgroup = one block of <= 64
 // consecutive rows of the block numbering plus its overlap.  The rows of
 // the overlapped set are stored per block (cell, CSR columns and weights,
@@ -205,67 +326,37 @@ __device__ __forceinline__ double row_residual(const T* __restrict__ u, double r
 //   res_t = r_q - bterm - sum_s beta_s (u_s - u_q) - S_t u_q   (FP64),
 //   u_own = c_in_own + (A_ext^{-1})_{own,:} res_ext.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_smo2(T* u, const T* __restrict__ r, const double* __restrict__ bterm,
-                                                const int32_t* __restrict__ ecell, const int32_t* __restrict__ erp,
-                                                const int32_t* __restrict__ ecols, const double* __restrict__ evals,
-                                                const double* __restrict__ ersum, const int32_t* __restrict__ eidx,
-                                                const int32_t* __restrict__ ebt, const int32_t* __restrict__ ext_ptr,
-                                                const int32_t* __restrict__ own_cnt,
-                                                const int64_t* __restrict__ inv_off, const double* __restrict__ inv,
-                                                const double* __restrict__ c_in, double* __restrict__ c_out, int ns,
-                                                int nbt, size_t plane) {
-  __shared__ double res[1024];
-  __shared__ double part[4][64];
-  const int b = blockIdx.x, z = blockIdx.y;
-  u += (size_t)z * plane, r += (size_t)z * plane;
-  c_in += (size_t)z * ns, c_out += (size_t)z * ns;
-  const int e0 = ext_ptr[b], ne = ext_ptr[b + 1] - e0, nown = own_cnt[b];
-  for (int t = threadIdx.x; t < ne; t += BLOCK) {
-    const int e = e0 + t;
-    const double uq = c_in[eidx[e]];
-    double rhs = (double)r[ecell[e]];
-    if (bterm && ebt[e] >= 0) rhs -= bterm[(size_t)z * nbt + ebt[e]];
-    const int p1 = erp[e + 1];
-    double acc = 0.0;
-    for (int p = erp[e]; p < p1; p += 8) {
-      int cc[8];
-      double vv[8], uu[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const bool in = p + k < p1;
-        cc[k] = in ? ecols[p + k] : 0;
-        vv[k] = in ? evals[p + k] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) uu[k] = cc[k] >= 0 ? (double)u[cc[k]] : c_in[-cc[k] - 1];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) acc += vv[k] * (uu[k] - uq);
-    }
-    res[t] = rhs - acc - ersum[e] * uq;
-  }
-  __syncthreads();
-  const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  double s = 0.0;
-  if (row < nown) {
-    const double* A = inv + inv_off[b] + row;
-    int col = grp;
-    for (; col + 28 < ne; col += 32) {
-      double a[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) a[k] = A[(size_t)(col + 4 * k) * nown];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) s += a[k] * res[col + 4 * k];
-    }
-    for (; col < ne; col += 4) s += A[(size_t)col * nown] * res[col];
-  }
-  part[grp][row] = s;
-  __syncthreads();
-  if (grp == 0 && row < nown) {
-    const int k = eidx[e0 + row];
-    const T v = (T)(c_in[k] + (part[0][row] + part[1][row] + part[2][row] + part[3][row]));
-    u[ecell[e0 + row]] = v;
-    c_out[k] = (double)v;
-  }
+__global__ __launch_bounds__(BLOCK) void k_smo2(T* u, const T* __restrict__ r, Smo2Args a, size_t plane) {
+  __shared__ double smem[SMO2_LDS_DOUBLES];
+  const size_t zoff = (size_t)blockIdx.y * plane;
+  smo2_block<T>(smem, blockIdx.x, blockIdx.y, u + zoff, u + zoff, r + zoff, a);
+}
+
+// Fused smoothing step: SMO-1 on the regular cells and SMO-2 on the blocks
+// in one launch, both from the same old iterate u (additive instead of
+// SMO-1 followed by SMO-2).  The first nblk workgroups are SMO-2 blocks
+// (dispatched first, so that their chains of dependent loads overlap the
+// streaming tiles), the rest SMO-1 tiles remapped by xcd_tile; u_out
+// receives every cell.  PRO: the
+// first step after the coarse-grid correction, which it applies on the fly
+// (the iterate is u + P e, P piecewise constant onto the cells flagged
+// probit; the coarse grid is ncx x ncy).
+template <typename T, bool CROSS, bool FINEST, int TYS, bool PRO>
+__global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u, const T* __restrict__ r,
+                                                        const uint8_t* __restrict__ kind, T* __restrict__ out,
+                                                        int nx, int ny, int nbx, int nblk, CoefT<T> c,
+                                                        uint8_t regbit, uint8_t s2bit, Smo2Args a,
+                                                        const T* __restrict__ e, int ncx, int ncy, uint8_t probit) {
+  // one LDS buffer shared by the two kinds of workgroup
+  constexpr int NS = sweep_lds_doubles<T, TYS>();
+  __shared__ double smem[NS > SMO2_LDS_DOUBLES ? NS : SMO2_LDS_DOUBLES];
+  const size_t zoff = (size_t)blockIdx.z * nx * ny;
+  const T* ez = PRO ? e + (size_t)blockIdx.z * ncx * ncy : nullptr;
+  if ((int)blockIdx.x < nblk)
+    smo2_block<T, PRO>(smem, blockIdx.x, blockIdx.z, u + zoff, out + zoff, r + zoff, a, ez);
+  else
+    sweep_tile<T, CROSS, TYS, PRO>(smem, xcd_tile(blockIdx.x - nblk, gridDim.x - nblk), u + zoff, r + zoff, kind,
+                                   out + zoff, nx, ny, nbx, c, regbit, s2bit, ez, ncx, probit);
 }
 
 // c[k] = u[cell[k]] for every block row (start of a solve on level 0).
@@ -308,97 +399,71 @@ __global__ __launch_bounds__(BLOCK) void k_apply(const double* __restrict__ u, c
   }
 }
 
-// Block-wise max of |r - L u| over stencil cells (difference form) or of |r|
-// when zero_u is set; one partial per workgroup.
+// max over non-empty cells of |r - bterm - L u| (difference form), or of
+// |r - bterm| when zero_u is set, in one launch: workgroups [0, ntiles) take
+// the stencil cells of one TX x TY tile each (remapped by xcd_tile), the
+// rest BLOCK explicit rows each (FP64; optionally writing the row residual
+// into res_out as FP32 for the refinement loop).  Every workgroup stores its
+// partial maximum in partial[z * gridDim.x + b]; the host, which reads the
+// norm back anyway, takes the maximum of the partials (no second launch and
+// no device-wide fence).
 template <typename T, bool CROSS>
-__global__ __launch_bounds__(BLOCK) void k_resmax_reg(const T* __restrict__ u, const T* __restrict__ r,
-                                                      const uint8_t* __restrict__ kind, double* __restrict__ partial,
-                                                      int nx, int ny, int nbx, CoefT<T> c, int zero_u, uint8_t regbit) {
+__global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, const T* __restrict__ r,
+                                                   const uint8_t* __restrict__ kind, int nx, int ny, int nbx,
+                                                   int ntiles, CoefT<T> c, int zero_u, uint8_t regbit,
+                                                   const double* __restrict__ bterm, const int32_t* __restrict__ cell,
+                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                   const double* __restrict__ vals,
+                                                   const double* __restrict__ rowsum, int nrows,
+                                                   float* __restrict__ res_out, double* __restrict__ partial) {
   __shared__ T tile[LH][LW];
   __shared__ double red[BLOCK];
-  const size_t zoff = (size_t)blockIdx.z * nx * ny;
-  u += zoff, r += zoff;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int tyi = t / nbx;
-  const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
-  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
-  uint8_t kd[TY / 4];
-  T rr[TY / 4];
-#pragma unroll
-  for (int k = 0; k < TY / 4; ++k) {
-    const int gx = bx + tx, gy = by + w + 4 * k;
-    const bool in = gx < nx && gy < ny;
-    kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
-    rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
-  }
-  load_tile(tile, u, nx, ny, bx, by);
-  __syncthreads();
+  const int z = blockIdx.z;
+  const size_t plane = (size_t)nx * ny;
+  u += z * plane, r += z * plane;
   double m = 0.0;
+  if ((int)blockIdx.x < ntiles) {
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const int tyi = t / nbx;
+    const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
+    const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
+    uint8_t kd[TY / 4];
+    T rr[TY / 4];
 #pragma unroll
-  for (int k = 0; k < TY / 4; ++k) {
-    if (kd[k] & regbit) {
-      T v = rr[k];
-      if (!zero_u) v -= apply_regular<T, CROSS>(tile, w + 4 * k + HALO, tx + HALO, c);
-      m = fmax(m, fabs((double)v));
+    for (int k = 0; k < TY / 4; ++k) {
+      const int gx = bx + tx, gy = by + w + 4 * k;
+      const bool in = gx < nx && gy < ny;
+      kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
+      rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
+    }
+    load_tile(tile, u, nx, ny, bx, by);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TY / 4; ++k) {
+      if (kd[k] & regbit) {
+        T v = rr[k];
+        if (!zero_u) v -= apply_regular<T, CROSS>(tile, w + 4 * k + HALO, tx + HALO, c);
+        m = fmax(m, fabs((double)v));
+      }
+    }
+  } else {
+    const int k = (blockIdx.x - ntiles) * BLOCK + threadIdx.x;
+    if (k < nrows) {
+      const int q = cell[k];
+      double rhs = (double)r[q];
+      if (bterm) rhs -= bterm[(size_t)z * nrows + k];
+      if (!zero_u) rhs = row_residual(u, rhs, q, cols + rp[k], vals + rp[k], rp[k + 1] - rp[k], rowsum[k]);
+      if (res_out) res_out[z * plane + q] = (float)rhs;
+      m = fabs(rhs);
     }
   }
   red[threadIdx.x] = m;
   __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0)
-    partial[(size_t)blockIdx.z * gridDim.x + blockIdx.x] = red[0];
-}
-
-// Same for the explicit rows (FP64), optionally writing the residual into a
-// grid array (FP32, used by the refinement loop).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_resmax_rows(const T* __restrict__ u, const T* __restrict__ r,
-                                                       const double* __restrict__ bterm,
-                                                       const int32_t* __restrict__ cell, const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ cols,
-                                                       const double* __restrict__ vals,
-                                                       const double* __restrict__ rowsum, double* __restrict__ partial,
-                                                       int nrows, size_t plane, int zero_u, float* __restrict__ res_out) {
-  __shared__ double red[BLOCK];
-  const int z = blockIdx.y;
-  u += (size_t)z * plane, r += (size_t)z * plane;
-  const int k = blockIdx.x * BLOCK + threadIdx.x;
-  double m = 0.0;
-  if (k < nrows) {
-    const int q = cell[k];
-    double rhs = (double)r[q];
-    if (bterm) rhs -= bterm[(size_t)z * nrows + k];
-    if (!zero_u) rhs = row_residual(u, rhs, q, cols + rp[k], vals + rp[k], rp[k + 1] - rp[k], rowsum[k]);
-    if (res_out) res_out[(size_t)z * plane + q] = (float)rhs;
-    m = fabs(rhs);
-  }
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+  for (int st = BLOCK / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = red[0];
-}
-
-// Final stage of the max reductions: out[z] = max(partA[z,*], partB[z,*]).
-__global__ void k_reduce_max(const double* __restrict__ pa, int na, const double* __restrict__ pb, int nb,
-                             double* __restrict__ out) {
-  __shared__ double red[BLOCK];
-  const int z = blockIdx.x;
-  double m = 0.0;
-  for (int k = threadIdx.x; k < na; k += BLOCK) m = fmax(m, pa[(size_t)z * na + k]);
-  for (int k = threadIdx.x; k < nb; k += BLOCK) m = fmax(m, pb[(size_t)z * nb + k]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[z] = red[0];
 }
 
 // FP64 refinement residual on stencil cells, written as FP32 (MP mode).
@@ -536,6 +601,7 @@ struct Smo2Data {                 // RAS blocks of one row set
   int32_t *ecell = nullptr, *erp = nullptr, *ecols = nullptr;   // overlapped rows, CSR
   int32_t* ebt = nullptr;         // boundary-term index of each overlapped row (-1: none)
   int32_t* scell = nullptr;       // cell of every block row
+  int32_t *epar = nullptr, *eqpar = nullptr;   // coarse parents (fused prolongation), -1: none
   int ns = 0;                     // block rows
   double* cbuf[2] = {nullptr, nullptr};   // compact copies of the block rows' values
   int cur = 0;                    // which copy is current while a cycle is recorded
@@ -597,8 +663,7 @@ struct ccgmg_ctx {
   double* g = nullptr;              // [max_nrhs][nfaces]
   double* bterm = nullptr;          // [max_nrhs][nirr0]
   int g_nrhs = 0;
-  double* norm_out = nullptr;       // device [max_nrhs]
-  double* norm_host = nullptr;      // pinned
+  double* norm_host = nullptr;      // pinned: partial maxima of the residual norm (level 0)
   double setup_seconds = 0;
   double plg_max_cond = 0;
   std::string err;
@@ -633,8 +698,8 @@ dim3 tiles(int nx, int ny, int nrhs) { return dim3((nx + TX - 1) / TX, (ny + TY 
 // numbering `order`, each extended by `overlap` layers of its matrix-graph
 // neighbourhood (restricted to the row set); the dense inverse of the
 // extended block is kept for the block's own rows (column-major).
-void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, size_t ncells, int bsize, int overlap,
-                int threads, Smo2Data& out, std::vector<void*>& owned) {
+void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, const std::vector<int32_t>& parent,
+                size_t ncells, int bsize, int overlap, int threads, Smo2Data& out, std::vector<void*>& owned) {
   const int ni = (int)R.cell.size();
   if (ni == 0) return;
   std::vector<int32_t> pos(ncells, -1);
@@ -712,16 +777,19 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, size_t nce
     all.insert(all.end(), inv[b].begin(), inv[b].end());
     out.max_ext = std::max(out.max_ext, (int)ext[b].size());
   }
-  std::vector<int32_t> ecell(eidx.size()), erp(eidx.size() + 1, 0), ecols, ebt(eidx.size());
+  std::vector<int32_t> ecell(eidx.size()), erp(eidx.size() + 1, 0), ecols, ebt(eidx.size()), epar,
+      eqpar(eidx.size());
   std::vector<double> evals, ersum(eidx.size());
   for (size_t e = 0; e < eidx.size(); ++e) {
     const int k = eidx[e];
     ecell[e] = R.cell[k];
     ebt[e] = bt[k];
+    eqpar[e] = parent[R.cell[k]];
     double rs = 0;
     for (int t = R.rp[k]; t < R.rp[k + 1]; ++t) {
       const int p = pos[R.cols[t]];
       ecols.push_back(p >= 0 ? -(p + 1) : R.cols[t]);
+      epar.push_back(parent[R.cols[t]]);
       evals.push_back(R.vals[t]);
       rs += R.vals[t];
     }
@@ -734,6 +802,8 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, size_t nce
   out.ns = ni;
   out.erp = upload(erp, owned);
   out.ecols = upload(ecols, owned);
+  out.epar = upload(epar, owned);
+  out.eqpar = upload(eqpar, owned);
   out.evals = upload(evals, owned);
   out.ersum = upload(ersum, owned);
   out.nblk = nblk;
@@ -745,8 +815,9 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, size_t nce
   out.inv_bytes = all.size() * sizeof(double);
 }
 
-void upload_rows(const ccg::RowSet& R, const ccg::RowSet& S, const std::vector<int32_t>& bt, size_t ncells,
-                 const ccgmg_options& opt, DevRows& D, std::vector<void*>& owned) {
+void upload_rows(const ccg::RowSet& R, const ccg::RowSet& S, const std::vector<int32_t>& bt,
+                 const std::vector<int32_t>& parent, size_t ncells, const ccgmg_options& opt, DevRows& D,
+                 std::vector<void*>& owned) {
   D.n = (int)R.cell.size();
   std::vector<double> rs(D.n);
   for (int k = 0; k < D.n; ++k) {
@@ -759,7 +830,7 @@ void upload_rows(const ccg::RowSet& R, const ccg::RowSet& S, const std::vector<i
   D.cols = upload(R.cols, owned);
   D.vals = upload(R.vals, owned);
   D.rowsum = upload(rs, owned);
-  build_smo2(S, bt, ncells, opt.smo2_block, opt.smo2_overlap, opt.num_threads, D.smo2, owned);
+  build_smo2(S, bt, parent, ncells, opt.smo2_block, opt.smo2_overlap, opt.num_threads, D.smo2, owned);
 }
 
 }  // namespace
@@ -849,14 +920,72 @@ struct Driver {
                        L.ny, C.nx, C.ny, X->opt.prolongation, regbit(), S.scell, S.cbuf[S.cur], S.ns);
   }
 
-  template <typename T>
-  void smo2_pass(DevLevel& L, T* u, const T* r, const double* bterm) {
+  // kernel arguments of one SMO-2 pass (reads the current compact copy,
+  // writes the other one)
+  Smo2Args smo2_args(DevLevel& L, const double* bterm) {
     DevRows& R = rows(L);
     Smo2Data& S = R.smo2;
-    hipLaunchKernelGGL((k_smo2<T>), dim3(S.nblk, nrhs), dim3(BLOCK), 0, s, u, r, bterm, S.ecell, S.erp, S.ecols,
-                       S.evals, S.ersum, S.ext_idx, S.ebt, S.ext_ptr, S.own_cnt, S.inv_off, S.inv, S.cbuf[S.cur],
-                       S.cbuf[1 - S.cur], S.ns, R.n, L.n);
+    Smo2Args a;
+    a.bterm = bterm;
+    a.ecell = S.ecell, a.erp = S.erp, a.ecols = S.ecols;
+    a.evals = S.evals, a.ersum = S.ersum;
+    a.eidx = S.ext_idx, a.ebt = S.ebt, a.ext_ptr = S.ext_ptr, a.own_cnt = S.own_cnt;
+    a.inv_off = S.inv_off, a.inv = S.inv;
+    a.c_in = S.cbuf[S.cur], a.c_out = S.cbuf[1 - S.cur];
+    a.ns = S.ns, a.nbt = R.n;
+    a.epar = S.epar, a.eqpar = S.eqpar;
+    return a;
+  }
+
+  template <typename T>
+  void smo2_pass(DevLevel& L, T* u, const T* r, const double* bterm) {
+    Smo2Data& S = rows(L).smo2;
+    hipLaunchKernelGGL((k_smo2<T>), dim3(S.nblk, nrhs), dim3(BLOCK), 0, s, u, r, smo2_args(L, bterm), L.n);
     S.cur = 1 - S.cur;
+  }
+
+  // one fused smoothing step (SMO-1 and SMO-2 from the same iterate u)
+  template <typename T, bool CROSS, bool FIN, bool PRO>
+  void fused_t(DevLevel& L, const T* u, const T* r, T* out, const double* bterm, int ty, const T* e,
+               const DevLevel* C) {
+    Smo2Data& S = rows(L).smo2;
+    CoefT<T> c(L.coef);
+    const int nbx = tiles_x(L.nx);
+    const int ntiles = nbx * ((L.ny + ty - 1) / ty);
+    const dim3 g(ntiles + S.nblk, 1, nrhs);
+    const uint8_t rb = jacbit(), sb = adjoint ? F_S2_T : F_S2;
+    const Smo2Args a = smo2_args(L, bterm);
+    const int ncx = C ? C->nx : 0, ncy = C ? C->ny : 0;
+    const uint8_t pb = regbit();
+    switch (ty) {
+      case 8: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 8, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb); break;
+      case 32: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 32, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb); break;
+      default: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 16, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb); break;
+    }
+    S.cur = 1 - S.cur;
+  }
+
+  template <typename T, bool CROSS, bool FIN>
+  void fused_p(DevLevel& L, const T* u, const T* r, T* out, const double* bterm, int ty, const T* e,
+               const DevLevel* C) {
+    if (e) fused_t<T, CROSS, FIN, true>(L, u, r, out, bterm, ty, e, C);
+    else fused_t<T, CROSS, FIN, false>(L, u, r, out, bterm, ty, nullptr, nullptr);
+  }
+
+  // one fused step; with e, the pending coarse-grid correction P e (coarse
+  // level C) is applied on the fly
+  template <typename T>
+  void fused_step(DevLevel& L, const T* u, const T* r, T* out, const double* bterm, const T* e = nullptr,
+                  const DevLevel* C = nullptr) {
+    const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
+    const bool fin = &L == &X->lv[0];
+    if (L.cross) {
+      if (fin) fused_p<T, true, true>(L, u, r, out, bterm, ty, e, C);
+      else fused_p<T, true, false>(L, u, r, out, bterm, ty, e, C);
+    } else {
+      if (fin) fused_p<T, false, true>(L, u, r, out, bterm, ty, e, C);
+      else fused_p<T, false, false>(L, u, r, out, bterm, ty, e, C);
+    }
   }
 
   template <typename T>
@@ -884,9 +1013,21 @@ struct Driver {
     }
   }
 
-  // smooth nsteps times; returns pointer to the buffer holding the result
+  bool fused(DevLevel& L) const { return X->opt.smoother_fused && rows(L).smo2.ns > 0; }
+
+  // smooth nsteps times; returns pointer to the buffer holding the result.
+  // Fused mode: e (if given) is the pending coarse-grid correction from
+  // level C, applied by the first step.
   template <typename T>
-  T* smooth(DevLevel& L, T* cur, T* other, const T* r, const double* bterm, int nsteps) {
+  T* smooth(DevLevel& L, T* cur, T* other, const T* r, const double* bterm, int nsteps, const T* e = nullptr,
+            const DevLevel* C = nullptr) {
+    if (fused(L)) {
+      for (int k = 0; k < nsteps; ++k) {
+        fused_step<T>(L, cur, r, other, bterm, k == 0 ? e : nullptr, C);
+        std::swap(cur, other);
+      }
+      return cur;
+    }
     for (int k = 0; k < nsteps; ++k) {
       sweep<T>(L, cur, r, other);
       std::swap(cur, other);
@@ -922,31 +1063,38 @@ struct Driver {
     Buf<T> cb = bufs<T>(C);
     restrict_<T>(L, C, cur, r, cb.r, cb.u);
     T* e = vcycle<T>(m + 1, cb.u, cb.v, cb.r, nullptr);
-    prolong<T>(L, C, cur, e);
-    T* out = smooth<T>(L, cur, oth, r, bterm, X->opt.nu2);
+    T* out;
+    if (fused(L) && X->opt.prolongation == 0 && X->opt.nu2 > 0) {
+      out = smooth<T>(L, cur, oth, r, bterm, X->opt.nu2, e, &C);   // correction applied by the first step
+    } else {
+      prolong<T>(L, C, cur, e);
+      out = smooth<T>(L, cur, oth, r, bterm, X->opt.nu2);
+    }
     settle_rows(L);
     return out;
   }
 
-  // max over non-empty cells of |r - bterm - A u| (zero_u: of |r - bterm|)
+  // partial maxima over non-empty cells of |r - bterm - A u| (zero_u: of
+  // |r - bterm|), one launch, into L.part[z * norm_parts(L) + b]
+  int norm_parts(DevLevel& L) {
+    return tiles_x(L.nx) * ((L.ny + TY - 1) / TY) + (rows(L).n + BLOCK - 1) / BLOCK;
+  }
+
   template <typename T>
   void resmax(DevLevel& L, const T* u, const T* r, const double* bterm, int zero_u, float* res_out) {
-    const dim3 g = tiles1d(L.nx, L.ny, nrhs);
     const int nbx = tiles_x(L.nx);
+    const int ntiles = nbx * ((L.ny + TY - 1) / TY);
+    DevRows& R = rows(L);
+    const int nrb = (R.n + BLOCK - 1) / BLOCK;
+    const dim3 g(ntiles + nrb, 1, nrhs);
     CoefT<T> c(L.coef);
     const uint8_t rb = regbit();
     if (L.cross)
-      hipLaunchKernelGGL((k_resmax_reg<T, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.part, L.nx, L.ny, nbx, c, zero_u, rb);
+      hipLaunchKernelGGL((k_resnorm<T, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.nx, L.ny, nbx, ntiles, c, zero_u,
+                         rb, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, res_out, L.part);
     else
-      hipLaunchKernelGGL((k_resmax_reg<T, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.part, L.nx, L.ny, nbx, c, zero_u, rb);
-    DevRows& R = rows(L);
-    const int gi = std::max(1, (R.n + BLOCK - 1) / BLOCK);
-    double* pirr = L.part + (size_t)L.npart_reg * nrhs;
-    if (R.n > 0)
-      hipLaunchKernelGGL((k_resmax_rows<T>), dim3(gi, nrhs), dim3(BLOCK), 0, s, u, r, bterm, R.cell, R.rp, R.cols,
-                         R.vals, R.rowsum, pirr, R.n, L.n, zero_u, res_out);
-    hipLaunchKernelGGL(k_reduce_max, dim3(nrhs), dim3(BLOCK), 0, s, L.part, L.npart_reg, pirr, R.n > 0 ? gi : 0,
-                       X->norm_out);
+      hipLaunchKernelGGL((k_resnorm<T, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.nx, L.ny, nbx, ntiles, c,
+                         zero_u, rb, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, res_out, L.part);
   }
 };
 
@@ -983,9 +1131,25 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
   for (size_t k = 0; k < L.n; ++k)
     kind[k] = (D.regular[k] ? F_REG : 0) | (D.nonempty[k] ? F_NONEMPTY : 0) | (treg[k] ? F_REG_T : 0) |
               (jf[k] ? F_JAC : 0) | (jt[k] ? F_JAC_T : 0);
+  for (int32_t q : SF.cell) kind[q] |= F_S2;
+  for (int32_t q : ST.cell) kind[q] |= F_S2_T;
   L.kind = upload(kind, X->owned);
-  upload_rows(F, SF, btf, L.n, X->opt, L.fwd, X->owned);
-  upload_rows(T, ST, btt, L.n, X->opt, L.adj, X->owned);
+  // coarse parent of every cell that takes the piecewise-constant correction
+  // (regular rows of L, resp. of L^T); -1 elsewhere and on the coarsest level
+  std::vector<int32_t> parf(L.n, -1), part(L.n, -1);
+  if (m + 1 < (int)X->H.disc.size()) {
+    const int ncx = X->H.disc[m + 1].nx, ncy = X->H.disc[m + 1].ny;
+    for (int j = 0; j < L.ny; ++j)
+      for (int i = 0; i < L.nx; ++i) {
+        const size_t q = (size_t)j * L.nx + i;
+        if ((i >> 1) >= ncx || (j >> 1) >= ncy) continue;
+        const int32_t pc = (int32_t)((j >> 1) * ncx + (i >> 1));
+        if (kind[q] & F_REG) parf[q] = pc;
+        if (kind[q] & F_REG_T) part[q] = pc;
+      }
+  }
+  upload_rows(F, SF, btf, parf, L.n, X->opt, L.fwd, X->owned);
+  upload_rows(T, ST, btt, part, L.n, X->opt, L.adj, X->owned);
   L.u = dalloc<double>(L.n * maxr, X->owned);
   L.r = dalloc<double>(L.n * maxr, X->owned);
   L.v = dalloc<double>(L.n * maxr, X->owned);
@@ -1144,11 +1308,22 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     if (!X->opt.use_initial_guess) Dr.fill<double>(u, n, 0.0);
     hipLaunchKernelGGL(k_mask_empty, dim3(std::min<size_t>(4096, (n + 255) / 256)), dim3(256), 0, ws, u, L0.kind, L0.n, n);
     if (X->opt.precision != 1) Dr.gather_rows<double>(L0, u);
+    // residual norms: per-workgroup partial maxima read back and reduced here
+    const int nparts = Dr.norm_parts(L0);
+    const size_t part_bytes = sizeof(double) * nparts * nrhs;
+    auto norm_of = [&](int z) {
+      double m = 0.0;
+      for (int k = 0; k < nparts; ++k) m = std::max(m, X->norm_host[(size_t)z * nparts + k]);
+      return m;
+    };
     Dr.resmax<double>(L0, u, f, bterm, 1, nullptr);
     std::vector<double> rn(nrhs);
-    HIP_OK(hipMemcpyAsync(X->norm_host, X->norm_out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ws));
+    HIP_OK(hipMemcpyAsync(X->norm_host, L0.part, part_bytes, hipMemcpyDeviceToHost, ws));
     HIP_OK(hipStreamSynchronize(ws));
-    for (int z = 0; z < nrhs; ++z) rn[z] = X->norm_host[z] > 0 ? X->norm_host[z] : 1.0;
+    for (int z = 0; z < nrhs; ++z) {
+      const double m = norm_of(z);
+      rn[z] = m > 0 ? m : 1.0;
+    }
     // one V-cycle (FP64, or FP32 inside one FP64 refinement step), the FP64
     // residual check and its read-back, replayed from a graph when allowed
     auto cycle = [&]() {
@@ -1157,7 +1332,7 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
       else
         fp64_cycle(Dr, u, f, bterm);
       Dr.resmax<double>(L0, u, f, bterm, 0, nullptr);
-      HIP_OK(hipMemcpyAsync(X->norm_host, X->norm_out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ws));
+      HIP_OK(hipMemcpyAsync(X->norm_host, L0.part, part_bytes, hipMemcpyDeviceToHost, ws));
     };
     hipGraphExec_t exec = nullptr;
     if (X->opt.use_graph) {
@@ -1191,7 +1366,7 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
       ++cycles;
       HIP_OK(hipStreamSynchronize(ws));
       rel = 0;
-      for (int z = 0; z < nrhs; ++z) rel = std::max(rel, X->norm_host[z] / rn[z]);
+      for (int z = 0; z < nrhs; ++z) rel = std::max(rel, norm_of(z) / rn[z]);
       if (rep && hist < 64) rep->history[hist++] = rel;
       if (!std::isfinite(rel)) break;
       if (rel <= X->opt.tol) {
@@ -1225,7 +1400,8 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
 
 // V-cycles on a seeded random right-hand side with the current depth; the
 // geometric-mean contraction of the residual over 6 cycles.
-double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, double* seconds = nullptr) {
+double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, double* seconds = nullptr,
+                       bool keep_graphs = false) {
   DevLevel& L0 = X->lv[0];
   std::vector<double> r(L0.n, 0.0);
   std::mt19937_64 gen(12345);
@@ -1240,15 +1416,19 @@ double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, doubl
   X->opt.tol = tol;
   X->opt.use_initial_guess = 0;
   X->opt.precision = 0;
-  X->opt.use_graph = 0;
+  X->opt.use_graph = 1;   // timed as the solves will run: graph replays
   int g_saved = X->g_nrhs;
   X->g_nrhs = 0;
   ccgmg_report rep;
   solve_impl(X, rd, ud, 1, &rep, false);
   X->opt = saved;
   X->g_nrhs = g_saved;
+  if (!keep_graphs) X->clear_graphs();
   if (seconds) *seconds = rep.seconds;
   double last = rep.cycles > 0 ? rep.history[std::min(rep.cycles, 64) - 1] : 1.0;
+  // with a tolerance, a depth whose solve stops short of it (stagnation or
+  // the cycle limit) is not admissible
+  if (tol > 0.0 && !(rep.rel_res_inf <= tol)) return 1e300;
   return (std::isfinite(last) && rep.cycles > 0) ? std::pow(last, 1.0 / rep.cycles) : 1e300;
 }
 
@@ -1284,6 +1464,8 @@ void ccgmg_default_options(ccgmg_options* o) {
   o->num_threads = 0;
   o->use_graph = 1;
   o->tune_tiles = 1;
+  o->smoother_fused = 0;
+  o->tune_schedule = 1;
   o->host_only = 0;
   o->hip_stream = nullptr;
 }
@@ -1358,8 +1540,10 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       X->fweight = upload(fw, X->owned);
       X->g = dalloc<double>((size_t)std::max(1, X->nfaces) * maxr, X->owned);
       X->bterm = dalloc<double>((size_t)std::max(1, (int)D0.irr.size()) * maxr, X->owned);
-      X->norm_out = dalloc<double>(maxr, X->owned);
-      HIP_OK(hipHostMalloc((void**)&X->norm_host, sizeof(double) * maxr, hipHostMallocDefault));
+
+      HIP_OK(hipHostMalloc((void**)&X->norm_host,
+                           sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
+                           hipHostMallocDefault));
       // the coarsest level must be small enough for the dense inverse
       while (X->M > 0) {
         long nu = 0;
@@ -1371,23 +1555,38 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       if (X->opt.tune_tiles) tune_tiles(X.get());
       if (X->opt.auto_depth == 2 && X->M > 1) {
         // measured: time a full solve (seeded right-hand side, 1e-10) for
-        // every admissible coarsest level and keep the fastest
+        // every admissible coarsest level and, with tune_schedule, every
+        // candidate smoothing schedule; keep the fastest that converges
+        struct Sched {
+          int fused, nu1, nu2;
+        };
+        std::vector<Sched> cands;
+        if (X->opt.tune_schedule)
+          cands = {{0, 3, 3}, {1, 3, 3}, {1, 4, 4}, {1, 5, 5}};
+        else
+          cands = {{X->opt.smoother_fused, X->opt.nu1, X->opt.nu2}};
         const int Mmax = X->M;
-        X->tune_ms.assign(Mmax + 1, 0.0);
+        X->tune_ms.assign(Mmax + 1, -1.0);
         double best = 1e300;
         int bestM = Mmax;
-        for (int Mc = Mmax; Mc >= 1; --Mc) {
-          long nu = 0;
-          for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
-          if (nu > MAX_COARSE_UNKNOWNS) break;
-          X->M = Mc;
-          upload_coarsest(X.get());
-          double sec = 0;
-          depth_test_rate(X.get(), 1e-10, 60, &sec);
-          const double rate = depth_test_rate(X.get(), 1e-10, 60, &sec);
-          X->tune_ms[Mc] = rate <= X->opt.depth_max_rate ? 1e3 * sec : -1.0;
-          if (rate <= X->opt.depth_max_rate && sec < best) best = sec, bestM = Mc;
+        Sched bestS = cands[0];
+        for (const Sched& sc : cands) {
+          X->opt.smoother_fused = sc.fused, X->opt.nu1 = sc.nu1, X->opt.nu2 = sc.nu2;
+          for (int Mc = Mmax; Mc >= 1; --Mc) {
+            long nu = 0;
+            for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
+            if (nu > MAX_COARSE_UNKNOWNS) break;
+            X->M = Mc;
+            upload_coarsest(X.get());
+            double sec = 0;
+            depth_test_rate(X.get(), 1e-10, 60, &sec, true);   // captures the graph
+            const double rate = depth_test_rate(X.get(), 1e-10, 60, &sec);
+            const bool ok = rate <= X->opt.depth_max_rate;
+            if (ok && (X->tune_ms[Mc] < 0 || 1e3 * sec < X->tune_ms[Mc])) X->tune_ms[Mc] = 1e3 * sec;
+            if (ok && sec < best) best = sec, bestM = Mc, bestS = sc;
+          }
         }
+        X->opt.smoother_fused = bestS.fused, X->opt.nu1 = bestS.nu1, X->opt.nu2 = bestS.nu2;
         X->M = bestM;
         upload_coarsest(X.get());
         X->clear_graphs();
@@ -1438,6 +1637,9 @@ int ccgmg_query(const ccgmg_ctx* X, ccgmg_info* info) {
   info->coarse_unknowns = cu;
   info->setup_seconds = X->setup_seconds;
   info->plg_max_cond = X->plg_max_cond;
+  info->smoother_fused = X->opt.smoother_fused;
+  info->nu1 = X->opt.nu1;
+  info->nu2 = X->opt.nu2;
   return CCGMG_OK;
 }
 
@@ -1571,7 +1773,7 @@ int ccgmg_apply_NT(ccgmg_ctx* X, const double* lam, double* out, int nrhs) {
 
 int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* avg_us) {
   return guard(X, [&]() {
-    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 6)
+    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 7)
       throw ccg::Error(CCGMG_EINVAL, "bad profile arguments");
     Driver Dr{X, X->stream, 1, false};
     DevLevel& L = X->lv[level];
@@ -1593,6 +1795,10 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
           Dr.settle_rows(L);
           break;
         case 4: Dr.coarse<double>(L, L.u, L.r); break;
+        case 7:
+          Dr.fused_step<double>(L, L.u, L.r, L.v, nullptr);
+          Dr.settle_rows(L);
+          break;
         case 6:
           hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(8192, (L.n + 255) / 256)), dim3(256), 0, X->stream, L.v,
                              L.u, L.n);

@@ -193,3 +193,41 @@ def test_autograd_gradients_match_finite_differences():
         print("   direction %d: fd %.10e adjoint %.10e rel %.2e" % (s, fdv, adj, rel), flush=True)
     assert worst < 1e-5
     S.close()
+
+
+SCHEDULES = [dict(smoother_fused=0, nu1=3, nu2=3), dict(smoother_fused=1, nu1=3, nu2=3),
+             dict(smoother_fused=1, nu1=4, nu2=4), dict(smoother_fused=1, nu1=3, nu2=3, prolongation=1),
+             dict(smoother_fused=1, nu1=3, nu2=3, precision=1)]
+
+
+@pytest.mark.parametrize("k,n", [(2, 64), (5, 64)])
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda d: "-".join("%s%s" % kv for kv in d.items()))
+def test_smoothing_schedules_reach_oracle_solution(k, n, sched):
+    """Every smoothing schedule (SMO-1 then SMO-2, or both fused into one
+    launch with the coarse-grid correction applied on the fly) converges to
+    the oracle's solution of L u = f - N g and of the transposed system."""
+    from oracle.multigrid import direct_solve_transpose
+    dev = _dev()
+    cfg, lv = _level(k, n)
+    print("schedule %s config %d n=%d" % (sched, k, n), flush=True)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ref = direct_solve(lv, rhs_vector(lv, f, g))
+    S = _solver(cfg, tol=1e-12, max_cycles=200, tune_schedule=0, **sched)
+    assert S.info["smoother_fused"] == sched["smoother_fused"] and S.info["nu1"] == sched["nu1"]
+    fd = torch.tensor(f, device=dev)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    u = torch.zeros_like(fd)
+    rep = S.solve(fd, u)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    rng = np.random.default_rng(30 + k)
+    rhs = rng.standard_normal(n * n) * lv.nonempty
+    want = direct_solve_transpose(lv, rhs)
+    lam = torch.zeros_like(fd)
+    rep_t = S.solve_adjoint(torch.tensor(rhs, device=dev), lam)
+    torch.cuda.synchronize()
+    err_t = np.max(np.abs(lam.cpu().numpy() - want)) / np.max(np.abs(want))
+    print("   cycles %d / %d, rel err %.2e / %.2e" % (rep["cycles"], rep_t["cycles"], err, err_t), flush=True)
+    assert err <= 1e-10 and err_t <= 1e-10
+    S.close()

@@ -42,6 +42,7 @@ DEG = 4                   # moments up to total degree 4
 POLAR_SAMPLES = 8192      # derivative sampling for polar-curve extrema
 DEGENERATE_CHORD = 1e-10  # sub-arcs shorter than this (in units of h) are dropped
 PERIM_SNAP = 1e-9         # perimeter gaps below this are read as touching
+EXTREMUM_REL = 1e-8       # |x'(t)| (or |y'(t)|) below this times |c'(t)|: an extremum of x (or y)
 
 # cell states after Alg. 1
 EMPTY, MERGED, PURE, CUT = 0, 1, 2, 3
@@ -377,14 +378,23 @@ class CutGrid:
                 ta = bps[b]
                 tb = bps[b + 1] if b + 1 < nb else bps[0] + TWO_PI
                 pa, pb = c.point(ta), c.point(tb)
-                # vertical lines x = x0 + k h strictly between
+                # grid lines strictly between the piece's end values; a line
+                # within DEGENERATE_CHORD h of an end where this coordinate is
+                # extremal only touches the curve (tangency) and is not
+                # crossed -- on both pieces meeting there, so the reading is
+                # consistent
+                da, db = c.deriv(ta), c.deriv(tb)
                 for comp, org in ((0, x0), (1, y0)):
                     lo, hi = min(pa[comp], pb[comp]), max(pa[comp], pb[comp])
+                    ext = [pe[comp] for pe, de in ((pa, da), (pb, db))
+                           if abs(de[comp]) <= EXTREMUM_REL * math.hypot(de[0], de[1])]
                     k0 = math.floor((lo - org) / h)
                     k1 = math.ceil((hi - org) / h)
                     for k in range(k0, k1 + 1):
                         xk = org + k * h
                         if not (lo < xk < hi):
+                            continue
+                        if any(abs(xk - v) <= DEGENERATE_CHORD * h for v in ext):
                             continue
                         t = _bisect_level(lambda tt, comp=comp: c.point(tt)[comp], ta, tb, xk)
                         p = c.point(t)

@@ -44,6 +44,7 @@ static const double TWO_PI = 2.0 * M_PI;
 static const int POLAR_SAMPLES = 8192;
 static const double DEGENERATE_CHORD = 1e-10;
 static const double PERIM_SNAP = 1e-9;
+static const double EXTREMUM_REL = 1e-8;   // |x'| (|y'|) <= this * |c'|: x (y) is extremal there
 static const int PLG_RADIUS = 4;
 static const double COND_MAX = 1e8;
 static const int PLG_POOL = 16;
@@ -391,16 +392,25 @@ void Geometry::intersect() {
     const int nb = (int)bps.size();
     for (int b = 0; b < nb; ++b) {
       double ta = bps[b], tb = b + 1 < nb ? bps[b + 1] : bps[0] + TWO_PI;
-      double pa[2], pb[2];
+      double pa[2], pb[2], da[2], db[2];
       c.point(ta, pa[0], pa[1]);
       c.point(tb, pb[0], pb[1]);
+      c.deriv(ta, da[0], da[1]);
+      c.deriv(tb, db[0], db[1]);
       for (int comp = 0; comp < 2; ++comp) {
         double org = comp == 0 ? x0 : y0;
         double lo = std::min(pa[comp], pb[comp]), hi = std::max(pa[comp], pb[comp]);
+        // ends where this coordinate is extremal: a grid line that close to
+        // such an end is touched (tangency), not crossed
+        const bool ext_a = std::fabs(da[comp]) <= EXTREMUM_REL * std::hypot(da[0], da[1]);
+        const bool ext_b = std::fabs(db[comp]) <= EXTREMUM_REL * std::hypot(db[0], db[1]);
         long k0 = (long)std::floor((lo - org) / h), k1 = (long)std::ceil((hi - org) / h);
         for (long k = k0; k <= k1; ++k) {
           double xk = org + k * h;
           if (!(lo < xk && xk < hi)) continue;
+          if ((ext_a && std::fabs(xk - pa[comp]) <= DEGENERATE_CHORD * h) ||
+              (ext_b && std::fabs(xk - pb[comp]) <= DEGENERATE_CHORD * h))
+            continue;
           auto fn = [&](double t) {
             double x, y;
             c.point(t, x, y);

@@ -31,10 +31,10 @@ def test_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("k,n", [(1, 64), (2, 64), (4, 64), (5, 64), (2, 128)])
+@pytest.mark.parametrize("k,n", [(1, 64), (2, 64), (4, 64), (5, 64), (2, 128), ("P1", 40), ("P2", 64)])
 def test_host_setup_matches_oracle(k, n):
     _lib_or_skip()
-    cfg = W.config(k, n=n)
+    cfg = {"P1": lambda: W.problem1(n), "P2": lambda: W.problem2(n)}[k]() if isinstance(k, str) else W.config(k, n=n)
     S = ccgmg.Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], host_only=1, max_levels=1)
     cg = build_cut_grid(cfg["grid"], cfg["curves"])
     d = Discretization(cg, cfg["a"], cfg["b"], cfg["c"])

@@ -119,3 +119,32 @@ def test_alg3_order_is_permutation_with_bounded_bandwidth():
 def test_norms_normalisation():
     vol = np.array([0.0, 1.0, 0.5, 0.25])
     assert norms(np.full(4, -3.0), vol) == (3.0, 3.0, 3.0)
+
+
+def test_problem1_matches_paper_tables():
+    """Problem 1 (Section 5.1; Tables tab:truncationErrorsOfProblem1 and
+    tab:solutionErrorsOfProblem1): truncation and solution errors at
+    h = 1/40 and 1/80 of the paper's magnitude, fourth-order solution error
+    and about fourth-order L1 truncation error.  The flower is tangent to the
+    grid lines y = +-0.2 at x = 0, which exercises the tangency reading of
+    the cut-cell construction."""
+    from oracle.norms import norms as _norms
+    gold = json.load(open(os.path.join(GOLDEN, "problem1_errors.json")))
+    tau, err = [], []
+    for n in (40, 80):
+        cfg = W.problem1(n)
+        lv = Level(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
+        f = cell_averages(lv.cg, cfg["f"]).ravel()
+        g = boundary_data(lv.disc, cfg["solution"])
+        ue = cell_averages(lv.cg, cfg["solution"].u).ravel()
+        N = lv.disc.matrices()[1]
+        tau.append(_norms((lv.L @ ue + N @ g - f) * lv.nonempty, lv.cg.vol))
+        u = direct_solve(lv, rhs_vector(lv, f, g))
+        err.append(_norms((u - ue) * lv.nonempty, lv.cg.vol))
+    for k in range(2):
+        for key, idx in (("L1", 0), ("L2", 1), ("Linf", 2)):
+            for got, table in ((tau[k][idx], gold["truncation"][key][k]), (err[k][idx], gold["solution"][key][k])):
+                assert table / 5 < got < table * 5, (k, key, got, table)
+    sol_rates = np.log2(np.array(err[0]) / np.array(err[1]))
+    assert np.all(sol_rates > 3.3) and np.all(sol_rates < 5.5), sol_rates
+    assert np.log2(tau[0][0] / tau[1][0]) > 3.0

@@ -176,6 +176,43 @@ def random_ellipses(seed, count, amin, amax, clearance=0.05, lo=0.0, hi=1.0, bc=
     return [ellipse(cx, cy, a1, a2, rot, bc=bc) for cx, cy, R, a1, a2, rot in out]
 
 
+def _r4cos3t():
+    """u = r^4 cos 3t = r p with p = x^3 - 3 x y^2 (Problem 1 of Section 5.1);
+    derivatives by the product rule with r_x = x/r, r_xx = y^2/r^3,
+    r_xy = -x y/r^3, r_yy = x^2/r^3."""
+    def r(x, y):
+        return np.sqrt(x * x + y * y)
+
+    def p(x, y):
+        return x ** 3 - 3 * x * y * y
+
+    def ux(x, y):
+        rr = r(x, y)
+        return x / rr * p(x, y) + rr * (3 * x * x - 3 * y * y)
+
+    def uy(x, y):
+        rr = r(x, y)
+        return y / rr * p(x, y) + rr * (-6 * x * y)
+
+    def uxx(x, y):
+        rr = r(x, y)
+        return y * y / rr ** 3 * p(x, y) + 2 * x / rr * (3 * x * x - 3 * y * y) + rr * 6 * x
+
+    def uyy(x, y):
+        rr = r(x, y)
+        return x * x / rr ** 3 * p(x, y) + 2 * y / rr * (-6 * x * y) + rr * (-6 * x)
+
+    def uxy(x, y):
+        rr = r(x, y)
+        return (-x * y / rr ** 3 * p(x, y) + x / rr * (-6 * x * y) + y / rr * (3 * x * x - 3 * y * y)
+                + rr * (-6 * y))
+
+    return Manufactured("r^4 cos(3 theta)", lambda x, y: r(x, y) * p(x, y), ux, uy, uxx, uxy, uyy)
+
+
+R4COS3T = _r4cos3t()
+
+
 def grid(n, x0=0.0, y0=0.0, length=1.0):
     return {"x0": x0, "y0": y0, "h": length / n, "nx": n, "ny": n}
 
@@ -235,6 +272,15 @@ def problem2(n, hole_bc=NEUMANN):
     """Poisson on [0,1]^2 minus the ellipse c=(1/2,1/2), a=(1/8,1/4) (Section 5.1, Problem 2)."""
     return {"id": "P2", "grid": grid(n), "curves": [box(), ellipse(0.5, 0.5, 0.125, 0.25, 0.0, bc=hole_bc)],
             "a": 1.0, "b": 0.0, "c": 1.0, "solution": SINPIX_SINPIY, "f": SINPIX_SINPIY.f(1.0, 0.0, 1.0)}
+
+
+def problem1(n):
+    """Poisson on the box [-1/2, 1/2]^2 minus the flower r >= 0.25 + 0.05 cos 6t
+    (Section 5.1, Problem 1): Dirichlet on the box, Neumann on the flower,
+    u = r^4 cos 3t."""
+    return {"id": "P1", "grid": grid(n, -0.5, -0.5), "curves": [box(x0=-0.5, y0=-0.5, x1=0.5, y1=0.5),
+                                                            polar_cos(0.0, 0.0, 0.25, 0.05, 6, bc=NEUMANN)],
+            "a": 1.0, "b": 0.0, "c": 1.0, "solution": R4COS3T, "f": R4COS3T.f(1.0, 0.0, 1.0)}
 
 
 def random_field(seed, shape):

@@ -24,6 +24,19 @@ ALG_BYTES_SWEEP = 25   # per cell per FP64 sweep: read u, r (8+8), kind (1), wri
 HBM_PEAK_GBS = 8000.0
 
 
+def fused_step_bytes(n_cells, st):
+    """Algorithmic bytes of one fused FP64 smoothing step on a level:
+    SMO-1 tiles read u, r, kind of every cell (17 B) and write u' of every
+    cell not in an SMO-2 block (8 B); the SMO-2 blocks read their dense
+    inverses, their overlapped rows' CSR entries (column 4 B + weight 8 B)
+    and per overlapped row its index, cell, row pointer, boundary-term index
+    (4 B each), row sum, right-hand side and current value (8 B each), and
+    write u' and the compact copy of their own rows (16 B)."""
+    sweep = 17 * n_cells + 8 * (n_cells - st["rows"])
+    smo2 = st["inv_bytes"] + 12 * st["ext_nnz"] + 40 * st["ext_rows"] + 16 * st["rows"]
+    return sweep + smo2
+
+
 def make_inputs(S, cfg, torch, dev):
     """f-hat and g-hat from the library's quadrature export (no oracle)."""
     import numpy as np
@@ -159,20 +172,31 @@ def main():
     ne = kinds >= 2
     disc_err = float(np.max(np.abs(u64 - exact)[ne]))
 
-    # dominant kernel: the finest-level SMO-1 sweep, timed with HIP events on
-    # the library's stream right after the timed solves
-    sweep_us = S.profile_kernel(0, 0, 50)
-    sweep_bytes = ALG_BYTES_SWEEP * args.n * args.n
-    achieved = sweep_bytes / (sweep_us * 1e-6) / 1e9
-    other = {name: S.profile_kernel(k, 0, 20) for name, k in (("restrict_us", 1), ("prolong_us", 2),
-                                                               ("smo2_block_us", 3))}
+    # dominant kernel: the finest-level smoothing step (fused SMO-1 + SMO-2
+    # launch, or the SMO-1 sweep of the unfused schedule), timed with HIP
+    # events on the library's stream right after the timed solves
+    ty = S.tuning(0)[0]
+    cells = args.n * args.n
+    if info["smoother_fused"]:
+        kname = "k_smooth_fused<double, false, true, %d, false>" % ty
+        kdesc = "finest-level fused SMO-1 + SMO-2 step"
+        dom_us = S.profile_kernel(7, 0, 50)
+        dom_bytes = fused_step_bytes(cells, S.smo2_stats(0))
+    else:
+        kname = "k_sweep<double, false, true, %d>" % ty
+        kdesc = "finest-level SMO-1 sweep"
+        dom_us = S.profile_kernel(0, 0, 50)
+        dom_bytes = ALG_BYTES_SWEEP * cells
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    other = {name: S.profile_kernel(k, 0, 20) for name, k in (("sweep_us", 0), ("restrict_us", 1),
+                                                               ("prolong_us", 2), ("smo2_block_us", 3))}
 
     # HBM bytes per launch of the same kernel from the committed counter runs
     # (FETCH_SIZE, WRITE_SIZE, copy-calibrated); null once the kernel sources
     # differ from those the counters were taken on
-    rec = read_traffic_record(os.path.join(ROOT, "profiles", "k_sweep_fp64_2048_pmc.md"))
+    rec = read_traffic_record(os.path.join(ROOT, "profiles", "smoothing_step_fp64_2048_pmc.md"))
     traffic = None
-    if rec and rec["cells"] == args.n * args.n:
+    if rec and rec["cells"] == cells and rec["kernel"] == kname:
         traffic = rec["traffic_bytes_per_launch"]
 
     mixed = None
@@ -216,15 +240,17 @@ def main():
         "config": {"workload": "unit square minus 3 seeded circles (seed 4), %d^2 cells, Poisson, Dirichlet, "
                                "u = sin(pi x) sin(pi y), FP64 V-cycles from zero to 1e-10" % args.n,
                    "n_unknowns": nu, "n_irregular": info["n_irregular"], "levels": info["n_levels"],
-                   "coarsest": info["nx_coarsest"], "nrhs": 1},
+                   "coarsest": info["nx_coarsest"], "nrhs": 1,
+                   "schedule": {"smoother_fused": info["smoother_fused"], "nu1": info["nu1"], "nu2": info["nu2"]},
+                   "sweep_tile_rows": [S.tuning(m)[0] for m in range(info["n_levels"])]},
         "cycles": reps[-1]["cycles"],
         "rel_res_inf": reps[-1]["rel_res_inf"],
         "disc_err_inf": disc_err,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep<double,false,true> (finest-level SMO-1)", "avg_us": sweep_us,
-                     "alg_bytes_per_launch": sweep_bytes},
+                     "kernel": "%s (%s)" % (kname, kdesc), "avg_us": dom_us,
+                     "alg_bytes_per_launch": dom_bytes, "traffic_unit": "bytes per launch"},
         "kernels_us": other,
         "mixed_precision": mixed,
         "cpu_baseline": cpu,

@@ -86,7 +86,9 @@ typedef struct {
   int max_levels;        /* default 16                                                    */
   int auto_depth;        /* coarsest level: 0 deepest that can be built; 1 deepest whose
                             V-cycles contract by <= depth_max_rate; 2 (default) measured:
-                            the admissible depth with the fastest timed solve          */
+                            time seeded solves at every admissible depth and keep the
+                            one with the least time per cycle x cycles per 1e10 at the
+                            measured asymptotic rate                                   */
   double depth_max_rate; /* contraction bound used by auto_depth, default 0.5            */
   int precision;         /* 0: FP64 sweeps; 1: FP32 sweeps inside FP64 refinement         */
   int prolongation;      /* 0: piecewise constant (Section 4.1); 1: bilinear              */
@@ -176,6 +178,13 @@ int ccgmg_get_counts(const ccgmg_ctx* ctx, int level, long* n_irregular, long* n
 /* SMO-1 tile height (64-wide tiles of 8, 16 or 32 rows) chosen for level m
  * in FP64 and FP32 sweeps (tune_tiles).  Device contexts only. */
 int ccgmg_get_tuning(const ccgmg_ctx* ctx, int level, int* sweep_ty_fp64, int* sweep_ty_fp32);
+
+/* Size of the SMO-2 block data of level m (adjoint = 1: of L^T), for
+ * traffic accounting: stats[0] blocks, [1] block rows (the rows updated by
+ * SMO-2: least-squares rows plus the regular rows joined to them),
+ * [2] overlapped rows over all blocks, [3] their CSR entries, [4] bytes of
+ * the blocks' dense FP64 inverses.  Device contexts only. */
+int ccgmg_get_smo2_stats(const ccgmg_ctx* ctx, int level, int adjoint, long* stats);
 int ccgmg_get_irregular(const ccgmg_ctx* ctx, int level, int32_t* rows, int32_t* cols, double* vals,
                         double* cond);
 

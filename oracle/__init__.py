@@ -15,7 +15,9 @@ Modules
   norms           volume-weighted error norms (Section 5)
 
 Parity status of each function is recorded in its docstring; functions
-without an independent pin say "parity unpinned".
+without an independent pin say "parity unpinned": the choice of lattice in
+Discretization.lattice_pool / plg, the exact order of alg3_order, and the
+depth heuristic Hierarchy.select_depth (the paper fixes none of them).
 """
 from .geometry import CutGrid, GeometryError, build_cut_grid  # noqa: F401
 try:

@@ -239,7 +239,12 @@ class Discretization:
         return 0 <= i < self.nx and 0 <= j < self.ny and self.nonempty[j * self.nx + i]
 
     def lattice_pool(self, q):
-        """The PLG_POOL most compact feasible lattices (sorted cell lists)."""
+        """The PLG_POOL most compact feasible lattices (sorted cell lists).
+
+        Parity unpinned: the paper does not give its PLG algorithm, so which
+        poised lattice is chosen is this project's rule (module docstring);
+        tests pin only what any valid choice satisfies (15 distinct cells
+        inside K, containing q, poised, exactness of the fitted row)."""
         nx = self.nx
         qi, qj = q % nx, q // nx
         R = PLG_RADIUS
@@ -310,7 +315,11 @@ class Discretization:
         return cond, weighted_min_norm(M, w, Lhat), fkeys, w
 
     def plg(self, q):
-        """R-PLG: lattice and weights for irregular cell q."""
+        """R-PLG: lattice and weights for irregular cell q.
+
+        Parity unpinned as to the choice of lattice (see lattice_pool); the
+        weights of a given lattice are pinned (exact rationals, exactness on
+        quartics, agreement with the minimum-norm characterisation)."""
         best = None
         bound = OWN_WEIGHT_MAX * (self.a + self.c)
         for cells in self.lattice_pool(q):

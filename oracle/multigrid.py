@@ -63,7 +63,14 @@ def alg3_order(disc, with_blocks=False):
     (curve index, boundary parameter): the box is parametrised
     counter-clockwise from its lower-left corner by the projection of the
     cell centre onto its nearest border edge, a curve by the midpoint
-    parameter of the cell's own arc on it."""
+    parameter of the cell's own arc on it.
+
+    Parity unpinned as to the exact order: the paper defines the ordering
+    for one closed interface curve; the key above is this project's reading
+    for several curves and the box.  Tests pin that it is a permutation of
+    the irregular cells whose blocks have an h-independent bandwidth, which
+    is the property Section 4 relies on; the converged solution does not
+    depend on it."""
     cg = disc.cg
     nx, ny = disc.nx, disc.ny
     keys = []
@@ -181,7 +188,10 @@ class Hierarchy:
         by at most ``max_rate`` per cycle (geometric mean over ``cycles``).
         Coarse levels that resolve the geometry poorly can carry spurious
         modes that make the coarse correction harmful; the converged solution
-        does not depend on the depth.  Returns the measured rate."""
+        does not depend on the depth.  Returns the measured rate.
+
+        Parity unpinned: the paper only asks for a coarsest level whose
+        direct solution is cheap; this rule is a heuristic of the project."""
         lv = self.levels[0]
         r = np.random.default_rng(seed).standard_normal(lv.nx * lv.ny) * lv.nonempty
         rate = None

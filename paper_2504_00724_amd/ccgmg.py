@@ -24,7 +24,7 @@ EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_ce
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
            "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
-           "ccgmg_profile_kernel", "ccgmg_get_tuning",
+           "ccgmg_profile_kernel", "ccgmg_get_tuning", "ccgmg_get_smo2_stats",
            "ccgmg_last_error",
            "ccgmg_create_error", "ccgmg_destroy"]
 
@@ -92,6 +92,7 @@ def lib():
         L.ccgmg_apply_NT.argtypes = [vp, vp, vp, ip]
         L.ccgmg_profile_kernel.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_double)]
         L.ccgmg_get_tuning.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
+        L.ccgmg_get_smo2_stats.argtypes = [vp, ip, ip, C.POINTER(C.c_long)]
         L.ccgmg_last_error.argtypes = [vp]
         L.ccgmg_last_error.restype = C.c_char_p
         L.ccgmg_create_error.argtypes = []
@@ -262,6 +263,14 @@ class Solver:
         a, b = C.c_int(), C.c_int()
         self._check(lib().ccgmg_get_tuning(self.ctx, level, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def smo2_stats(self, level=0, adjoint=False):
+        """SMO-2 block data sizes: blocks, block rows, overlapped rows, their
+        CSR entries, inverse bytes."""
+        st = (C.c_long * 5)()
+        self._check(lib().ccgmg_get_smo2_stats(self.ctx, level, int(adjoint), st))
+        keys = ("blocks", "rows", "ext_rows", "ext_nnz", "inv_bytes")
+        return dict(zip(keys, list(st)))
 
     def apply_adjoint(self, lam, out):
         self._check(lib().ccgmg_apply_adjoint(self.ctx, _ptr(lam), _ptr(out)))

@@ -610,6 +610,7 @@ struct Smo2Data {                 // RAS blocks of one row set
   double* inv = nullptr;
   size_t inv_bytes = 0;
   int max_ext = 0;
+  long n_ext = 0, n_ext_nnz = 0;   // overlapped rows and their CSR entries, all blocks
 };
 
 struct DevRows {                  // explicit rows of L (or L^T) on one level
@@ -813,6 +814,8 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, const std:
   out.inv_off = upload(ioff, owned);
   out.inv = upload(all, owned);
   out.inv_bytes = all.size() * sizeof(double);
+  out.n_ext = (long)eidx.size();
+  out.n_ext_nnz = (long)ecols.size();
 }
 
 void upload_rows(const ccg::RowSet& R, const ccg::RowSet& S, const std::vector<int32_t>& bt,
@@ -1401,7 +1404,7 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
 // V-cycles on a seeded random right-hand side with the current depth; the
 // geometric-mean contraction of the residual over 6 cycles.
 double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, double* seconds = nullptr,
-                       bool keep_graphs = false) {
+                       bool keep_graphs = false, double* score = nullptr) {
   DevLevel& L0 = X->lv[0];
   std::vector<double> r(L0.n, 0.0);
   std::mt19937_64 gen(12345);
@@ -1426,6 +1429,16 @@ double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, doubl
   if (!keep_graphs) X->clear_graphs();
   if (seconds) *seconds = rep.seconds;
   double last = rep.cycles > 0 ? rep.history[std::min(rep.cycles, 64) - 1] : 1.0;
+  if (score) {
+    // estimated time to reduce the residual by 1e10 at the asymptotic rate
+    // (geometric mean over the cycles after the first two): time per cycle
+    // times cycles needed; less sensitive to whole-cycle rounding than the
+    // solve time itself
+    const int nc = std::min(rep.cycles, 64);
+    double tail = 1.0;
+    if (nc >= 4) tail = std::pow(rep.history[nc - 1] / rep.history[1], 1.0 / (nc - 2));
+    *score = (tail > 0.0 && tail < 1.0) ? rep.seconds / rep.cycles * std::log(1e-10) / std::log(tail) : 1e300;
+  }
   // with a tolerance, a depth whose solve stops short of it (stagnation or
   // the cycle limit) is not admissible
   if (tol > 0.0 && !(rep.rel_res_inf <= tol)) return 1e300;
@@ -1556,7 +1569,8 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       if (X->opt.auto_depth == 2 && X->M > 1) {
         // measured: time a full solve (seeded right-hand side, 1e-10) for
         // every admissible coarsest level and, with tune_schedule, every
-        // candidate smoothing schedule; keep the fastest that converges
+        // candidate smoothing schedule; among those that converge keep the
+        // one with the smallest estimated time to a 1e10 reduction
         struct Sched {
           int fused, nu1, nu2;
         };
@@ -1578,12 +1592,12 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
             if (nu > MAX_COARSE_UNKNOWNS) break;
             X->M = Mc;
             upload_coarsest(X.get());
-            double sec = 0;
+            double sec = 0, score = 0;
             depth_test_rate(X.get(), 1e-10, 60, &sec, true);   // captures the graph
-            const double rate = depth_test_rate(X.get(), 1e-10, 60, &sec);
+            const double rate = depth_test_rate(X.get(), 1e-10, 60, &sec, false, &score);
             const bool ok = rate <= X->opt.depth_max_rate;
-            if (ok && (X->tune_ms[Mc] < 0 || 1e3 * sec < X->tune_ms[Mc])) X->tune_ms[Mc] = 1e3 * sec;
-            if (ok && sec < best) best = sec, bestM = Mc, bestS = sc;
+            if (ok && (X->tune_ms[Mc] < 0 || 1e3 * score < X->tune_ms[Mc])) X->tune_ms[Mc] = 1e3 * score;
+            if (ok && score < best) best = score, bestM = Mc, bestS = sc;
           }
         }
         X->opt.smoother_fused = bestS.fused, X->opt.nu1 = bestS.nu1, X->opt.nu2 = bestS.nu2;
@@ -1669,6 +1683,17 @@ int ccgmg_get_tuning(const ccgmg_ctx* X, int level, int* sweep_ty_fp64, int* swe
   if (!X || X->host_only || level < 0 || level >= (int)X->lv.size()) return CCGMG_EINVAL;
   if (sweep_ty_fp64) *sweep_ty_fp64 = X->lv[level].sweep_ty[0];
   if (sweep_ty_fp32) *sweep_ty_fp32 = X->lv[level].sweep_ty[1];
+  return CCGMG_OK;
+}
+
+int ccgmg_get_smo2_stats(const ccgmg_ctx* X, int level, int adjoint, long* stats) {
+  if (!X || X->host_only || !stats || level < 0 || level >= (int)X->lv.size()) return CCGMG_EINVAL;
+  const Smo2Data& S = adjoint ? X->lv[level].adj.smo2 : X->lv[level].fwd.smo2;
+  stats[0] = S.nblk;
+  stats[1] = S.ns;
+  stats[2] = S.n_ext;
+  stats[3] = S.n_ext_nnz;
+  stats[4] = (long)S.inv_bytes;
   return CCGMG_OK;
 }
 

@@ -76,6 +76,101 @@ def make_inputs(S, cfg, torch, dev):
     return torch.tensor(fh, device=dev), torch.tensor(ghat, device=dev), ex, kinds
 
 
+def fourier_averages(S, cfg, coeffs, torch, dev):
+    """Cell averages of f = sum c_pq sin(p pi x) sin(q pi y): pure cells in
+    closed form (the average of a product of sines over a square cell is the
+    product of the one-dimensional averages), cut cells by the library's
+    quadrature; zero on empty and merged cells."""
+    import numpy as np
+    grid = cfg["grid"]
+    n, h = grid["nx"], grid["h"]
+    m = coeffs.shape[0]
+    k = np.arange(1, m + 1)[:, None] * np.pi
+    xl = grid["x0"] + np.arange(n)[None, :] * h
+    yl = grid["y0"] + np.arange(n)[None, :] * h
+    sx = (np.cos(k * xl) - np.cos(k * (xl + h))) / (k * h)      # [p][i]
+    sy = (np.cos(k * yl) - np.cos(k * (yl + h))) / (k * h)      # [q][j]
+    fh = (sy.T @ coeffs.T @ sx).ravel()                          # [j][i]
+    kinds, _ = S.kinds(0)
+    vol = S.volumes(0)
+    cell, qx, qy, qw = S.cell_quadrature()
+    fx = np.zeros_like(qx)
+    for p in range(m):
+        for q in range(m):
+            fx += coeffs[p, q] * np.sin((p + 1) * np.pi * qx) * np.sin((q + 1) * np.pi * qy)
+    cut = np.unique(cell)
+    fh[cut] = np.bincount(cell, weights=qw * fx, minlength=n * n)[cut] / vol[cut]
+    fh[kinds <= 1] = 0.0
+    return fh
+
+
+def run_batch(args):
+    """Batched workload: 64 right-hand sides (seeded Fourier sums, 8 x 8
+    modes) on the unit square minus a disk r = 0.2 at 512^2, plus 32
+    geometries with n in {128, 256, 512, 1024} and 1-3 seeded ellipse holes,
+    homogeneous Dirichlet data, all solved together by one captured
+    multi-branch launch per V-cycle."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2504_00724_amd.ccgmg import Batch, Solver
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    prec = 0 if args.batch_fp64 else 1
+    t0 = time.perf_counter()
+    probs = [W.config(3, n=512)] + W.batch_geometries(args.batch_geometries)
+    solvers, fs, us, nr, nu = [], [], [], [], 0
+    for i, cfg in enumerate(probs):
+        m = args.batch_rhs if i == 0 else 1
+        S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-10, max_cycles=200,
+                   hip_stream=stream, max_nrhs=m, precision=prec)
+        seeds = [3000 + z for z in range(m)] if i == 0 else [3000 + i - 1]
+        F = np.stack([fourier_averages(S, cfg, W.fourier_rhs(sd)[1], torch, dev) for sd in seeds])
+        solvers.append(S)
+        fs.append(torch.tensor(F, device=dev))
+        us.append(torch.zeros_like(fs[-1]))
+        nr.append(m)
+        nu += S.info["n_unknowns"] * m
+        print("geometry %d: n=%d unknowns %d x %d rhs, levels %d" % (
+            i, cfg["grid"]["nx"], S.info["n_unknowns"], m, S.info["n_levels"]), file=sys.stderr, flush=True)
+    setup_s = time.perf_counter() - t0
+    B = Batch(solvers, nbranches=args.batch_branches)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        B.solve(fs, us, nr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        reps = B.solve(fs, us, nr)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t1) / args.steps
+    # the same problems solved one after another (same contexts)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for S, f, u, m in zip(solvers, fs, us, nr):
+        S.solve(f, u, m)
+    torch.cuda.synchronize()
+    seq_ms = 1e3 * (time.perf_counter() - t2)
+    out = {
+        "metric": "batched cut-cell GMG solve: unknowns x right-hand sides per second at 1e-10 rel. residual",
+        "value": nu / (ms * 1e-3), "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec else "f64", "data": "synthetic",
+        "config": {"workload": "%d RHS on unit square minus disk r=0.2 at 512^2 + %d seeded ellipse geometries, "
+                               "n in {128,256,512,1024}, homogeneous Dirichlet, Fourier RHS 8x8 modes"
+                               % (args.batch_rhs, args.batch_geometries),
+                   "unknowns_x_rhs": nu, "branches": args.batch_branches,
+                   "precision": "FP32 V-cycles in FP64 refinement" if prec else "FP64"},
+        "max_cycles": max(r["cycles"] for r in reps), "worst_rel_res": max(r["rel_res_inf"] for r in reps),
+        "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms, "setup_s": setup_s,
+    }
+    print(json.dumps(out))
+    B.close()
+    for S in solvers:
+        S.close()
+
+
 def cpu_baseline(n_sample, seconds):
     """The oracle's own V-cycle solve, one core, on the same geometry and
     problem at a smaller grid: its set-up is not timed; the solve from a zero
@@ -126,11 +221,20 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--prolongation", type=int, default=0)
     ap.add_argument("--smo2-every-sweep", type=int, default=1)
+    ap.add_argument("--workload", choices=["metric", "batch"], default="metric",
+                    help="metric: the three-circle Poisson solve at --n; batch: the batched workload")
+    ap.add_argument("--batch-rhs", type=int, default=64)
+    ap.add_argument("--batch-geometries", type=int, default=32)
+    ap.add_argument("--batch-branches", type=int, default=4)
+    ap.add_argument("--batch-fp64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import numpy as np
     import torch

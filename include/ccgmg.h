@@ -250,6 +250,34 @@ int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out, int nrhs);
  * buffers of that level undefined; no user buffer is touched. */
 int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double* avg_us);
 
+/* ---- Many geometries in one launch (batching) -------------------------
+ * A batch groups contexts created by ccgmg_create (different geometries,
+ * grid sizes and coefficients; each with its own boundary data set by
+ * ccgmg_set_boundary).  ccgmg_batch_solve solves all of them together: one
+ * V-cycle of every geometry (FP64 or mixed precision, as each context was
+ * created) is captured into a single hipGraph whose branches run
+ * concurrently, and the graph is replayed until every geometry's relative
+ * residual is below its own tol (a converged geometry keeps cycling while
+ * others finish).  Work is ordered after the stream of ctxs[0].  Contexts
+ * must outlive the batch and must not be used by other calls while a batch
+ * solve runs.  Not a paper construct: the batched use of the solve of
+ * Section 4 (Alg. 2) for many independent problems. */
+typedef struct ccgmg_batch ccgmg_batch;
+
+/* nbranches: concurrent graph branches (geometry g runs on branch
+ * g mod nbranches); 4 matches the hardware queues a process gets by
+ * default. */
+int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch** out);
+
+/* f[g], u[g]: device arrays of geometry g ([nrhs[g]][ny][nx], as in
+ * ccgmg_solve, from a zero guess unless the context uses an initial guess);
+ * reps: host array of n reports or NULL (seconds = the whole batch).
+ * CCGMG_ENOCONV if any geometry did not reach its tolerance. */
+int ccgmg_batch_solve(ccgmg_batch* batch, const double* const* f, double* const* u, const int* nrhs,
+                      ccgmg_report* reps);
+const char* ccgmg_batch_last_error(const ccgmg_batch* batch);
+void ccgmg_batch_destroy(ccgmg_batch* batch);
+
 const char* ccgmg_last_error(const ccgmg_ctx* ctx);
 
 /* Error text of the last failed ccgmg_create on this thread. */

@@ -25,8 +25,8 @@ EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_ce
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
            "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
            "ccgmg_profile_kernel", "ccgmg_get_tuning", "ccgmg_get_smo2_stats",
-           "ccgmg_last_error",
-           "ccgmg_create_error", "ccgmg_destroy"]
+           "ccgmg_batch_create", "ccgmg_batch_solve", "ccgmg_batch_last_error", "ccgmg_batch_destroy",
+           "ccgmg_last_error", "ccgmg_create_error", "ccgmg_destroy"]
 
 
 class CurveT(C.Structure):
@@ -93,6 +93,12 @@ def lib():
         L.ccgmg_profile_kernel.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_double)]
         L.ccgmg_get_tuning.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
         L.ccgmg_get_smo2_stats.argtypes = [vp, ip, ip, C.POINTER(C.c_long)]
+        L.ccgmg_batch_create.argtypes = [C.POINTER(vp), ip, ip, C.POINTER(vp)]
+        L.ccgmg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(ip), C.POINTER(ReportT)]
+        L.ccgmg_batch_last_error.argtypes = [vp]
+        L.ccgmg_batch_last_error.restype = C.c_char_p
+        L.ccgmg_batch_destroy.argtypes = [vp]
+        L.ccgmg_batch_destroy.restype = None
         L.ccgmg_last_error.argtypes = [vp]
         L.ccgmg_last_error.restype = C.c_char_p
         L.ccgmg_create_error.argtypes = []
@@ -282,3 +288,42 @@ class Solver:
 def _report(rep, st):
     return {"status": st, "cycles": rep.cycles, "outer_iters": rep.outer_iters, "rel_res_inf": rep.rel_res_inf,
             "seconds": rep.seconds, "history": list(rep.history[:min(64, max(rep.cycles, 0))])}
+
+
+class Batch:
+    """Several Solver contexts (different geometries) solved together: one
+    captured V-cycle of every geometry per graph replay (ccgmg_batch_*)."""
+
+    def __init__(self, solvers, nbranches=4):
+        L = lib()
+        self.solvers = list(solvers)      # keeps the contexts alive
+        arr = (C.c_void_p * len(self.solvers))(*[S.ctx.value for S in self.solvers])
+        self.h = C.c_void_p()
+        st = L.ccgmg_batch_create(arr, len(self.solvers), nbranches, C.byref(self.h))
+        if st != OK:
+            raise CcgmgError(st, L.ccgmg_create_error().decode())
+
+    def solve(self, fs, us, nrhs=None, raise_on_noconv=True):
+        n = len(self.solvers)
+        if len(fs) != n or len(us) != n:
+            raise ValueError("one right-hand side and one solution array per geometry")
+        nr = nrhs or [1] * n
+        fa = (C.c_void_p * n)(*[_ptr(f) for f in fs])
+        ua = (C.c_void_p * n)(*[_ptr(u) for u in us])
+        na = (C.c_int * n)(*nr)
+        reps = (ReportT * n)()
+        st = lib().ccgmg_batch_solve(self.h, fa, ua, na, reps)
+        if st != OK and (raise_on_noconv or st != ENOCONV):
+            raise CcgmgError(st, lib().ccgmg_batch_last_error(self.h).decode())
+        return [_report(r, st) for r in reps]
+
+    def close(self):
+        if self.h:
+            lib().ccgmg_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,515 @@
+// Device kernels of the cut-cell multigrid V-cycle (gfx950): SMO-1 sweeps,
+// SMO-2 block updates, the fused smoothing step, residual + restriction,
+// prolongation, residual norms, the coarsest solve and the mixed-precision
+// helpers.  The host driver that launches them is ccgmg.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+// private header of ccgmg.hip (included once); kernels keep global names
+using namespace ccgk;
+
+// cell flag bits of kind[]
+constexpr uint8_t F_REG = 1;      // regular row of L
+constexpr uint8_t F_NONEMPTY = 2;
+constexpr uint8_t F_REG_T = 4;    // regular row of L^T
+constexpr uint8_t F_JAC = 8;      // smoothed by SMO-1 (L)
+constexpr uint8_t F_JAC_T = 16;   // smoothed by SMO-1 (L^T)
+constexpr uint8_t F_S2 = 32;      // row of an SMO-2 block (L)
+constexpr uint8_t F_S2_T = 64;    // row of an SMO-2 block (L^T)
+
+// ===========================================================================
+// Kernels
+// ===========================================================================
+
+// SMO-1 on one tile: u_out = u + omega/D (r - L u) on cells flagged `regbit`,
+// u_out = u elsewhere except on cells flagged `skipbit` (left to the SMO-2
+// blocks of a fused step).  Jacobi: reads u, writes a second buffer.  Tiles
+// of TX x TYS cells (TYS = 8, 16 or 32, picked per level by measurement);
+// t is the tile index, nbx the number of tiles per grid row.
+template <typename T, int TYS>
+constexpr int sweep_lds_doubles() { return ((TYS + 2 * HALO) * LW * (int)sizeof(T) + 7) / 8; }
+
+template <typename T, bool CROSS, int TYS, bool PRO = false>
+__device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restrict__ u, const T* __restrict__ r,
+                                           const uint8_t* __restrict__ kind, T* __restrict__ out, int nx, int ny,
+                                           int nbx, const CoefT<T>& c, uint8_t regbit, uint8_t skipbit,
+                                           const T* __restrict__ e = nullptr, int ncx = 0, uint8_t probit = 0) {
+  constexpr int RPW = TYS / 4;            // rows per wave
+  constexpr int ROWS = TYS + 2 * HALO;
+  T (*tile)[LW] = reinterpret_cast<T (*)[LW]>(smem);
+  const int tyi = t / nbx;
+  const int bx = (t - tyi * nbx) * TX, by = tyi * TYS;
+  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
+  // issue the kind and right-hand-side loads before the tile barrier
+  uint8_t kd[RPW];
+  T rr[RPW];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int gx = bx + tx, gy = by + w + 4 * k;
+    const bool in = gx < nx && gy < ny;
+    kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
+    rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
+  }
+  if (PRO) {
+    // tile of u + P e: the pending coarse-grid correction (piecewise
+    // constant, cells flagged probit only) is added while staging
+    for (int k = threadIdx.x; k < ROWS * LW; k += BLOCK) {
+      const int ly = k / LW, lx = k - ly * LW;
+      const int gx = bx + lx - HALO, gy = by + ly - HALO;
+      T v = (T)0;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+        const size_t g = (size_t)gy * nx + gx;
+        v = u[g];
+        if (kind[g] & probit) v += e[(size_t)(gy >> 1) * ncx + (gx >> 1)];
+      }
+      tile[ly][lx] = v;
+    }
+  } else {
+    load_tile<T, ROWS>(tile, u, nx, ny, bx, by);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int ry = w + 4 * k;
+    const int gx = bx + tx, gy = by + ry;
+    if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
+      T v = tile[ry + HALO][tx + HALO];
+      if (kd[k] & regbit) v += c.omega_invD * (rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c));
+      out[(size_t)gy * nx + gx] = v;
+    }
+  }
+}
+
+// SMO-1 sweep launch: one workgroup per tile on a 1-D grid remapped by
+// xcd_tile.  FINEST only selects a separate instantiation for the finest
+// level so that kernel traces separate it from the coarse levels.
+template <typename T, bool CROSS, bool FINEST, int TYS>
+__global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const T* __restrict__ r,
+                                                 const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
+                                                 int ny, int nbx, CoefT<T> c, uint8_t regbit) {
+  __shared__ double smem[sweep_lds_doubles<T, TYS>()];
+  const size_t zoff = (size_t)blockIdx.z * nx * ny;
+  sweep_tile<T, CROSS, TYS>(smem, xcd_tile(blockIdx.x, gridDim.x), u + zoff, r + zoff, kind, out + zoff, nx, ny,
+                            nbx, c, regbit, 0);
+}
+
+// Residual of the regular cells restricted to the coarse grid:
+// rc_I = 1/4 sum over regular children c of (r - L u)_c  (Section 4.1).
+// The same launch zeroes the coarse iterate uc (the recursion starts from a
+// zero guess, Alg. 2) and the compact copy cc of its block rows.
+template <typename T, typename TC, bool CROSS, bool FINEST>
+__global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, const T* __restrict__ r,
+                                                    const uint8_t* __restrict__ kind, TC* __restrict__ rc,
+                                                    TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx,
+                                                    int ny, int nbx, int ncx, int ncy, CoefT<T> c, uint8_t regbit) {
+  __shared__ T tile[LH][LW];
+  const size_t zoff = (size_t)blockIdx.z * nx * ny;
+  u += zoff, r += zoff;
+  rc += (size_t)blockIdx.z * ncx * ncy;
+  uc += (size_t)blockIdx.z * ncx * ncy;
+  {
+    const int flat = blockIdx.x * BLOCK + threadIdx.x;
+    if (flat < ncc) cc[(size_t)blockIdx.z * ncc + flat] = 0.0;
+  }
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = t / nbx, txi = t - tyi * nbx;
+  const int bx = txi * TX, by = tyi * TY;
+  const int cx = threadIdx.x & 31, cy = threadIdx.x >> 5;  // 32 x 8 coarse cells
+  uint8_t kd[4];
+  T rr[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int gx = bx + 2 * cx + (d & 1), gy = by + 2 * cy + (d >> 1);
+    const bool in = gx < nx && gy < ny;
+    kd[d] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
+    rr[d] = in ? r[(size_t)gy * nx + gx] : (T)0;
+  }
+  load_tile(tile, u, nx, ny, bx, by);
+  __syncthreads();
+  const int I = txi * (TX / 2) + cx, J = tyi * (TY / 2) + cy;
+  if (I >= ncx || J >= ncy) return;
+  T s = (T)0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+    if (kd[d] & regbit)
+      s += rr[d] - apply_regular<T, CROSS>(tile, 2 * cy + (d >> 1) + HALO, 2 * cx + (d & 1) + HALO, c);
+  rc[(size_t)J * ncx + I] = (TC)((T)0.25 * s);
+  uc[(size_t)J * ncx + I] = (TC)0;
+}
+
+// Correction u_c += P e on regular fine cells: piecewise constant
+// (Section 4.1) or bilinear with the 9/16, 3/16, 3/16, 1/16 cell-centred
+// weights where all four coarse cells are non-empty.
+template <typename T>
+__device__ __forceinline__ T prolong_value(const T* __restrict__ e, const uint8_t* __restrict__ ckind, int i, int j,
+                                           int ncx, int ncy, int bilinear) {
+  const int I = i >> 1, J = j >> 1;
+  T v = e[(size_t)J * ncx + I];
+  if (bilinear) {
+    const int I2 = I + ((i & 1) ? 1 : -1), J2 = J + ((j & 1) ? 1 : -1);
+    if (I2 >= 0 && I2 < ncx && J2 >= 0 && J2 < ncy && (ckind[(size_t)J * ncx + I2] & F_NONEMPTY) &&
+        (ckind[(size_t)J2 * ncx + I] & F_NONEMPTY) && (ckind[(size_t)J2 * ncx + I2] & F_NONEMPTY))
+      v = ((T)9 * v + (T)3 * e[(size_t)J * ncx + I2] + (T)3 * e[(size_t)J2 * ncx + I] + e[(size_t)J2 * ncx + I2]) *
+          (T)0.0625;
+  }
+  return v;
+}
+
+// Grid rows 0..ny-1 update u; the extra rows apply the same correction to
+// the compact copy c of the block rows (SMO-2), computed from the same
+// inputs so that c stays equal to u on those cells.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_prolong(T* __restrict__ u, const T* __restrict__ e,
+                                                   const uint8_t* __restrict__ kind,
+                                                   const uint8_t* __restrict__ ckind, int nx, int ny, int ncx,
+                                                   int ncy, int bilinear, uint8_t regbit,
+                                                   const int32_t* __restrict__ scell, double* __restrict__ c, int ns) {
+  const int z = blockIdx.z;
+  e += (size_t)z * ncx * ncy;
+  if ((int)blockIdx.y < ny) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= nx) return;
+    const size_t g = (size_t)j * nx + i;
+    if (!(kind[g] & regbit)) return;
+    u[(size_t)z * nx * ny + g] += prolong_value(e, ckind, i, j, ncx, ncy, bilinear);
+    return;
+  }
+  const int k = ((blockIdx.y - ny) * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  const int q = scell[k];
+  if (!(kind[q] & regbit)) return;
+  const T v = (T)(c[(size_t)z * ns + k]) + prolong_value(e, ckind, q % nx, q / nx, ncx, ncy, bilinear);
+  c[(size_t)z * ns + k] = (double)v;
+}
+
+// Residual of one explicit row (FP64, difference form):
+//   r_q - bterm - sum_s beta_s (u_s - u_q) - S u_q,  S = sum_s beta_s.
+template <typename T>
+__device__ __forceinline__ double row_residual(const T* __restrict__ u, double rhs, int q, const int32_t* cols,
+                                               const double* vals, int len, double rowsum) {
+  const double uq = (double)u[q];
+  double a0 = 0.0, a1 = 0.0;
+  int s = 0;
+  for (; s + 1 < len; s += 2) {
+    a0 += vals[s] * ((double)u[cols[s]] - uq);
+    a1 += vals[s + 1] * ((double)u[cols[s + 1]] - uq);
+  }
+  if (s < len) a0 += vals[s] * ((double)u[cols[s]] - uq);
+  return rhs - (a0 + a1) - rowsum * uq;
+}
+
+// Arguments of an SMO-2 pass (see k_smo2).
+struct Smo2Args {
+  const double* bterm;
+  const int32_t *ecell, *erp, *ecols;
+  const double *evals, *ersum;
+  const int32_t *eidx, *ebt, *ext_ptr, *own_cnt;
+  const int64_t* inv_off;
+  const double* inv;
+  const double* c_in;
+  double* c_out;
+  int ns, nbt;
+  const int32_t* epar;    // per CSR entry: coarse parent of the column cell if it takes the correction, else -1
+  const int32_t* eqpar;   // per overlapped row: the same for the row's own cell
+};
+
+// One RAS block b of plane z: reads uin (non-block columns) and c_in, writes
+// its own rows to uout and c_out.  With a pending coarse-grid correction
+// (PRO, coarse values ecor), every value read is taken as value +
+// ecor[parent] where the cell takes the correction (a.epar / a.eqpar >= 0),
+// i.e. the block works on u + P e.
+constexpr int SMO2_LDS_DOUBLES = 1024 + 4 * 64 + 64;
+
+template <typename T, bool PRO = false>
+__device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* uin, T* uout,
+                                           const T* __restrict__ r, const Smo2Args& a,
+                                           const T* __restrict__ ecor = nullptr) {
+  double* res = smem;                                              // [1024]
+  double (*part)[64] = reinterpret_cast<double (*)[64]>(smem + 1024);   // [4][64]
+  double* uown = smem + 1024 + 4 * 64;                             // [64]
+  const double* c_in = a.c_in + (size_t)z * a.ns;
+  double* c_out = a.c_out + (size_t)z * a.ns;
+  const int e0 = a.ext_ptr[b], ne = a.ext_ptr[b + 1] - e0, nown = a.own_cnt[b];
+  for (int t = threadIdx.x; t < ne; t += BLOCK) {
+    const int e = e0 + t;
+    double uq = c_in[a.eidx[e]];
+    if (PRO) {
+      const int pq = a.eqpar[e];
+      if (pq >= 0) uq += (double)ecor[pq];
+    }
+    if (t < 64) uown[t] = uq;
+    double rhs = (double)r[a.ecell[e]];
+    if (a.bterm && a.ebt[e] >= 0) rhs -= a.bterm[(size_t)z * a.nbt + a.ebt[e]];
+    const int p1 = a.erp[e + 1];
+    double acc = 0.0;
+    for (int p = a.erp[e]; p < p1; p += 8) {
+      int cc[8], pp[8];
+      double vv[8], uu[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool in = p + k < p1;
+        cc[k] = in ? a.ecols[p + k] : 0;
+        vv[k] = in ? a.evals[p + k] : 0.0;
+        pp[k] = (PRO && in) ? a.epar[p + k] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        uu[k] = cc[k] >= 0 ? (double)uin[cc[k]] : c_in[-cc[k] - 1];
+        if (PRO && pp[k] >= 0) uu[k] += (double)ecor[pp[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += vv[k] * (uu[k] - uq);
+    }
+    res[t] = rhs - acc - a.ersum[e] * uq;
+  }
+  __syncthreads();
+  const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  double s = 0.0;
+  if (row < nown) {
+    const double* A = a.inv + a.inv_off[b] + row;
+    int col = grp;
+    for (; col + 28 < ne; col += 32) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = A[(size_t)(col + 4 * k) * nown];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += v[k] * res[col + 4 * k];
+    }
+    for (; col < ne; col += 4) s += A[(size_t)col * nown] * res[col];
+  }
+  part[grp][row] = s;
+  __syncthreads();
+  if (grp == 0 && row < nown) {
+    const int k = a.eidx[e0 + row];
+    const T v = (T)(uown[row] + (part[0][row] + part[1][row] + part[2][row] + part[3][row]));
+    uout[a.ecell[e0 + row]] = v;
+    c_out[k] = (double)v;
+  }
+}
+
+// SMO-2 by restricted additive Schwarz.  Workgroup = one block of <= 64
+// consecutive rows of the block numbering plus its overlap.  The rows of
+// the overlapped set are stored per block (cell, CSR columns and weights,
+// row sum); a column that is itself a block row is encoded as -(row + 1)
+// and read from the compact copy c_in of the block rows' values, all other
+// columns are read from u.  Every block therefore reads only cells that no
+// block writes, and writes its own rows straight into u (and c_out):
+//   res_t = r_q - bterm - sum_s beta_s (u_s - u_q) - S_t u_q   (FP64),
+//   u_own = c_in_own + (A_ext^{-1})_{own,:} res_ext.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_smo2(T* u, const T* __restrict__ r, Smo2Args a, size_t plane) {
+  __shared__ double smem[SMO2_LDS_DOUBLES];
+  const size_t zoff = (size_t)blockIdx.y * plane;
+  smo2_block<T>(smem, blockIdx.x, blockIdx.y, u + zoff, u + zoff, r + zoff, a);
+}
+
+// Fused smoothing step: SMO-1 on the regular cells and SMO-2 on the blocks
+// in one launch, both from the same old iterate u (additive instead of
+// SMO-1 followed by SMO-2).  The first nblk workgroups are SMO-2 blocks
+// (dispatched first, so that their chains of dependent loads overlap the
+// streaming tiles), the rest SMO-1 tiles remapped by xcd_tile; u_out
+// receives every cell.  PRO: the
+// first step after the coarse-grid correction, which it applies on the fly
+// (the iterate is u + P e, P piecewise constant onto the cells flagged
+// probit; the coarse grid is ncx x ncy).
+template <typename T, bool CROSS, bool FINEST, int TYS, bool PRO>
+__global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u, const T* __restrict__ r,
+                                                        const uint8_t* __restrict__ kind, T* __restrict__ out,
+                                                        int nx, int ny, int nbx, int nblk, CoefT<T> c,
+                                                        uint8_t regbit, uint8_t s2bit, Smo2Args a,
+                                                        const T* __restrict__ e, int ncx, int ncy, uint8_t probit) {
+  // one LDS buffer shared by the two kinds of workgroup
+  constexpr int NS = sweep_lds_doubles<T, TYS>();
+  __shared__ double smem[NS > SMO2_LDS_DOUBLES ? NS : SMO2_LDS_DOUBLES];
+  const size_t zoff = (size_t)blockIdx.z * nx * ny;
+  const T* ez = PRO ? e + (size_t)blockIdx.z * ncx * ncy : nullptr;
+  if ((int)blockIdx.x < nblk)
+    smo2_block<T, PRO>(smem, blockIdx.x, blockIdx.z, u + zoff, out + zoff, r + zoff, a, ez);
+  else
+    sweep_tile<T, CROSS, TYS, PRO>(smem, xcd_tile(blockIdx.x - nblk, gridDim.x - nblk), u + zoff, r + zoff, kind,
+                                   out + zoff, nx, ny, nbx, c, regbit, s2bit, ez, ncx, probit);
+}
+
+// c[k] = u[cell[k]] for every block row (start of a solve on level 0).
+template <typename T>
+__global__ void k_gather_rows(const T* __restrict__ u, const int32_t* __restrict__ cell, double* __restrict__ c,
+                              int ns, size_t plane) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  const int z = blockIdx.y;
+  c[(size_t)z * ns + k] = (double)u[(size_t)z * plane + cell[k]];
+}
+
+// (A u) for explicit rows (plain sum).
+__global__ void k_rows_apply(const double* __restrict__ u, double* __restrict__ Lu, const int32_t* __restrict__ cell,
+                             const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                             const double* __restrict__ vals, int nrows) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nrows) return;
+  double acc = 0.0;
+  for (int s = rp[k]; s < rp[k + 1]; ++s) acc += vals[s] * u[cols[s]];
+  Lu[cell[k]] = acc;
+}
+
+// (L u) on cells flagged `regbit`; zero elsewhere.
+template <bool CROSS>
+__global__ __launch_bounds__(BLOCK) void k_apply(const double* __restrict__ u, const uint8_t* __restrict__ kind,
+                                                 double* __restrict__ Lu, int nx, int ny, CoefT<double> c,
+                                                 uint8_t regbit) {
+  __shared__ double tile[LH][LW];
+  const int bx = blockIdx.x * TX, by = blockIdx.y * TY;
+  load_tile(tile, u, nx, ny, bx, by);
+  __syncthreads();
+  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
+  for (int k = 0; k < TY / 4; ++k) {
+    const int ry = w + 4 * k, gx = bx + tx, gy = by + ry;
+    if (gx < nx && gy < ny) {
+      const size_t g = (size_t)gy * nx + gx;
+      Lu[g] = (kind[g] & regbit) ? apply_regular<double, CROSS>(tile, ry + HALO, tx + HALO, c) : 0.0;
+    }
+  }
+}
+
+// max over non-empty cells of |r - bterm - L u| (difference form), or of
+// |r - bterm| when zero_u is set, in one launch: workgroups [0, ntiles) take
+// the stencil cells of one TX x TY tile each (remapped by xcd_tile), the
+// rest BLOCK explicit rows each (FP64).  With res_out, the residual of every
+// cell is also stored there as FP32 (0 on empty cells) for the refinement
+// loop: stencil cells by the tile workgroups, explicit rows by the row
+// workgroups, so no cell is written twice.  Every workgroup stores its
+// partial maximum in partial[z * gridDim.x + b]; the host, which reads the
+// norm back anyway, takes the maximum of the partials (no second launch and
+// no device-wide fence).
+template <typename T, bool CROSS>
+__global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, const T* __restrict__ r,
+                                                   const uint8_t* __restrict__ kind, int nx, int ny, int nbx,
+                                                   int ntiles, CoefT<T> c, int zero_u, uint8_t regbit,
+                                                   const double* __restrict__ bterm, const int32_t* __restrict__ cell,
+                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                   const double* __restrict__ vals,
+                                                   const double* __restrict__ rowsum, int nrows,
+                                                   float* __restrict__ res_out, double* __restrict__ partial) {
+  __shared__ T tile[LH][LW];
+  __shared__ double red[BLOCK];
+  const int z = blockIdx.z;
+  const size_t plane = (size_t)nx * ny;
+  u += z * plane, r += z * plane;
+  double m = 0.0;
+  if ((int)blockIdx.x < ntiles) {
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const int tyi = t / nbx;
+    const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
+    const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
+    uint8_t kd[TY / 4];
+    T rr[TY / 4];
+#pragma unroll
+    for (int k = 0; k < TY / 4; ++k) {
+      const int gx = bx + tx, gy = by + w + 4 * k;
+      const bool in = gx < nx && gy < ny;
+      kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
+      rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
+    }
+    load_tile(tile, u, nx, ny, bx, by);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TY / 4; ++k) {
+      const int gx = bx + tx, gy = by + w + 4 * k;
+      if (kd[k] & regbit) {
+        T v = rr[k];
+        if (!zero_u) v -= apply_regular<T, CROSS>(tile, w + 4 * k + HALO, tx + HALO, c);
+        m = fmax(m, fabs((double)v));
+        if (res_out) res_out[z * plane + (size_t)gy * nx + gx] = (float)v;
+      } else if (res_out && gx < nx && gy < ny && !(kd[k] & F_NONEMPTY)) {
+        res_out[z * plane + (size_t)gy * nx + gx] = 0.0f;   // explicit rows: written by the row workgroups
+      }
+    }
+  } else {
+    const int k = (blockIdx.x - ntiles) * BLOCK + threadIdx.x;
+    if (k < nrows) {
+      const int q = cell[k];
+      double rhs = (double)r[q];
+      if (bterm) rhs -= bterm[(size_t)z * nrows + k];
+      if (!zero_u) rhs = row_residual(u, rhs, q, cols + rp[k], vals + rp[k], rp[k + 1] - rp[k], rowsum[k]);
+      if (res_out) res_out[z * plane + q] = (float)rhs;
+      m = fabs(rhs);
+    }
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = BLOCK / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Coarsest level: u[cell_k] = sum_j Inv[k, j] r[cell_j] (FP64), one wavefront
+// per row (4 rows per workgroup), the gathered right-hand side staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
+                                                  const int32_t* __restrict__ cell, const double* __restrict__ inv,
+                                                  int nm, size_t plane) {
+  extern __shared__ double rv[];
+  const int z = blockIdx.y;
+  u += (size_t)z * plane, r += (size_t)z * plane;
+  for (int k = threadIdx.x; k < nm; k += BLOCK) rv[k] = (double)r[cell[k]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= nm) return;
+  const double* A = inv + (size_t)row * nm;
+  double s0 = 0.0, s1 = 0.0;
+  int k = lane;
+  for (; k + 64 < nm; k += 128) s0 += A[k] * rv[k], s1 += A[k + 64] * rv[k + 64];
+  if (k < nm) s0 += A[k] * rv[k];
+  double s = s0 + s1;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) u[cell[row]] = (T)s;
+}
+
+// Boundary term of the irregular rows: bterm_k = sum over k's faces of N g.
+__global__ void k_bterm(const double* __restrict__ g, const int32_t* __restrict__ fptr,
+                        const int32_t* __restrict__ fface, const double* __restrict__ fval, double* __restrict__ bterm,
+                        int nirr, int nfaces) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nirr) return;
+  const int z = blockIdx.y;
+  double s = 0.0;
+  for (int t = fptr[k]; t < fptr[k + 1]; ++t) s += fval[t] * g[(size_t)z * nfaces + fface[t]];
+  bterm[(size_t)z * nirr + k] = s;
+}
+
+// out = N^T lambda: out[face] = nweight[face] * lambda[cell[face]].
+__global__ void k_apply_NT(const double* __restrict__ lam, const int32_t* __restrict__ fcell,
+                           const double* __restrict__ fw, double* __restrict__ out, int nfaces, size_t plane) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (k < nfaces) out[(size_t)z * nfaces + k] = fw[k] * lam[(size_t)z * plane + fcell[k]];
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, size_t n, T v) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
+}
+
+// Plain FP64 copy, 16 bytes per element: the calibration kernel for HBM
+// byte counters.
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+__global__ void k_axpy_f32(double* __restrict__ u, const float* __restrict__ e, const uint8_t* __restrict__ kind,
+                           size_t plane, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    if (kind[k % plane] & F_NONEMPTY) u[k] += (double)e[k];
+}
+
+__global__ void k_mask_empty(double* __restrict__ u, const uint8_t* __restrict__ kind, size_t plane, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    if (!(kind[k % plane] & F_NONEMPTY)) u[k] = 0.0;
+}

@@ -24,11 +24,11 @@ import os
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/ccgmg.hip", "csrc/kernels.hpp")
+KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/vcycle_kernels.hpp")
 
 
 def source_hash():
-    """SHA-256 over the HIP kernel sources (counters go stale when it changes)."""
+    """SHA-256 over the device-code sources (counters go stale when it changes)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(HERE, rel), "rb") as f:

@@ -123,8 +123,11 @@ def run_batch(args):
     solvers, fs, us, nr, nu = [], [], [], [], 0
     for i, cfg in enumerate(probs):
         m = args.batch_rhs if i == 0 else 1
+        tg = time.perf_counter()
+        sched = {} if args.batch_tune else dict(tune_schedule=0, smoother_fused=1, nu1=4, nu2=4)
         S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-10, max_cycles=200,
-                   hip_stream=stream, max_nrhs=m, precision=prec)
+                   hip_stream=stream, max_nrhs=m, precision=prec, **sched)
+        tg = time.perf_counter() - tg
         seeds = [3000 + z for z in range(m)] if i == 0 else [3000 + i - 1]
         F = np.stack([fourier_averages(S, cfg, W.fourier_rhs(sd)[1], torch, dev) for sd in seeds])
         solvers.append(S)
@@ -132,8 +135,9 @@ def run_batch(args):
         us.append(torch.zeros_like(fs[-1]))
         nr.append(m)
         nu += S.info["n_unknowns"] * m
-        print("geometry %d: n=%d unknowns %d x %d rhs, levels %d" % (
-            i, cfg["grid"]["nx"], S.info["n_unknowns"], m, S.info["n_levels"]), file=sys.stderr, flush=True)
+        print("geometry %d: n=%d unknowns %d x %d rhs, levels %d, set-up %.1f s (library %.1f s)" % (
+            i, cfg["grid"]["nx"], S.info["n_unknowns"], m, S.info["n_levels"], tg, S.info["setup_seconds"]),
+            file=sys.stderr, flush=True)
     setup_s = time.perf_counter() - t0
     B = Batch(solvers, nbranches=args.batch_branches)
     torch.cuda.synchronize()
@@ -227,6 +231,8 @@ def main():
     ap.add_argument("--batch-geometries", type=int, default=32)
     ap.add_argument("--batch-branches", type=int, default=4)
     ap.add_argument("--batch-fp64", action="store_true")
+    ap.add_argument("--batch-tune", type=int, default=0,
+                    help="1: every batch context tunes its own smoothing schedule (slower set-up)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,

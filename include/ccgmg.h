@@ -264,9 +264,9 @@ int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double
  * Section 4 (Alg. 2) for many independent problems. */
 typedef struct ccgmg_batch ccgmg_batch;
 
-/* nbranches: concurrent graph branches (geometry g runs on branch
- * g mod nbranches); 4 matches the hardware queues a process gets by
- * default. */
+/* nbranches: concurrent graph branches; geometries are placed largest
+ * first (cells x right-hand sides) onto the least-loaded branch.  4 matches
+ * the hardware queues a process gets by default. */
 int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch** out);
 
 /* f[g], u[g]: device arrays of geometry g ([nrhs[g]][ny][nx], as in

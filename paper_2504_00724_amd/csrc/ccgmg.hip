@@ -71,7 +71,8 @@ T* upload(const std::vector<T>& v, std::vector<void*>& owned) {
 struct Smo2Data {                 // RAS blocks of one row set
   int nblk = 0;
   int32_t *ext_ptr = nullptr, *ext_idx = nullptr, *own_cnt = nullptr;
-  int32_t *ecell = nullptr, *erp = nullptr, *ecols = nullptr;   // overlapped rows, CSR
+  int32_t *ecell = nullptr, *ecols = nullptr;   // overlapped rows: cell; ELL columns [n_ext][ew]
+  int ew = 0;                     // ELL width: longest overlapped row of this row set
   int32_t* ebt = nullptr;         // boundary-term index of each overlapped row (-1: none)
   int32_t* scell = nullptr;       // cell of every block row
   int32_t *epar = nullptr, *eqpar = nullptr;   // coarse parents (fused prolongation), -1: none
@@ -124,6 +125,7 @@ struct ccgmg_ctx {
   int32_t* mcell = nullptr;
   double* minv = nullptr;           // inverse of the coarsest operator
   double* mtinv = nullptr;          // inverse of its transpose
+  double* mrg = nullptr;            // gathered coarsest right-hand sides [MAX_COARSE_UNKNOWNS][max_nrhs]
   struct Coarse {
     int nm;
     int32_t* cell;
@@ -274,11 +276,24 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, const std:
   out.ebt = upload(ebt, owned);
   out.scell = upload(R.cell, owned);
   out.ns = ni;
-  out.erp = upload(erp, owned);
-  out.ecols = upload(ecols, owned);
-  out.epar = upload(epar, owned);
+  // ELL layout (row e's entries at e * ew + k, padding: column 0, weight 0,
+  // no parent), so a row's columns are addressed without its row pointer
+  int ew = 1;
+  for (size_t e = 0; e < eidx.size(); ++e) ew = std::max(ew, erp[e + 1] - erp[e]);
+  std::vector<int32_t> lcols(eidx.size() * ew, 0), lpar(eidx.size() * ew, -1);
+  std::vector<double> lvals(eidx.size() * ew, 0.0);
+  for (size_t e = 0; e < eidx.size(); ++e)
+    for (int t = erp[e]; t < erp[e + 1]; ++t) {
+      const size_t d = e * ew + (t - erp[e]);
+      lcols[d] = ecols[t];
+      lpar[d] = epar[t];
+      lvals[d] = evals[t];
+    }
+  out.ew = ew;
+  out.ecols = upload(lcols, owned);
+  out.epar = upload(lpar, owned);
   out.eqpar = upload(eqpar, owned);
-  out.evals = upload(evals, owned);
+  out.evals = upload(lvals, owned);
   out.ersum = upload(ersum, owned);
   out.nblk = nblk;
   out.ext_ptr = upload(eptr, owned);
@@ -403,7 +418,7 @@ struct Driver {
     Smo2Data& S = R.smo2;
     Smo2Args a;
     a.bterm = bterm;
-    a.ecell = S.ecell, a.erp = S.erp, a.ecols = S.ecols;
+    a.ecell = S.ecell, a.ecols = S.ecols, a.ew = S.ew;
     a.evals = S.evals, a.ersum = S.ersum;
     a.eidx = S.ext_idx, a.ebt = S.ebt, a.ext_ptr = S.ext_ptr, a.own_cnt = S.own_cnt;
     a.inv_off = S.inv_off, a.inv = S.inv;
@@ -521,8 +536,16 @@ struct Driver {
   void coarse(DevLevel& L, T* u, const T* r) {
     const double* inv = adjoint ? X->mtinv : X->minv;
     const int nm = X->nm;
-    hipLaunchKernelGGL((k_coarse<T>), dim3((nm + 3) / 4, nrhs), dim3(BLOCK), nm * sizeof(double), s, u, r,
-                       X->mcell, inv, nm, L.n);
+    if (nrhs == 1) {
+      hipLaunchKernelGGL((k_coarse<T>), dim3((nm + 3) / 4, 1), dim3(BLOCK), nm * sizeof(double), s, u, r, X->mcell,
+                         inv, nm, L.n);
+      return;
+    }
+    // several right-hand sides: gather, then one product reading the inverse once
+    hipLaunchKernelGGL((k_coarse_gather<T>), dim3((nm + 255) / 256, nrhs), dim3(256), 0, s, r, X->mcell, X->mrg,
+                       nm, nrhs, L.n);
+    hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CR - 1) / CR, (nrhs + CZ - 1) / CZ), dim3(BLOCK), 0, s, u,
+                       X->mrg, X->mcell, inv, nm, nrhs, L.n);
   }
 
   // Alg. 2 on level m with iterate in (u, spare v) and rhs r.
@@ -669,15 +692,32 @@ void upload_coarsest(ccgmg_ctx* X) {
       for (int t = 0; t < 15; ++t) A[(size_t)r * n + pos[D.sten[15 * k + t]]] += D.wts[15 * k + t];
     }
   }
-  std::vector<double> AT((size_t)n * n);
-  for (int r = 0; r < n; ++r)
-    for (int cc = 0; cc < n; ++cc) AT[(size_t)cc * n + r] = A[(size_t)r * n + cc];
-  if (!ccg::dense_inverse(A, n, X->opt.num_threads)) throw ccg::Error(CCGMG_ESINGULAR, "singular coarsest operator");
-  if (!ccg::dense_inverse(AT, n, X->opt.num_threads)) throw ccg::Error(CCGMG_ESINGULAR, "singular coarsest operator");
+  // inverse on the device: Gauss-Jordan with partial pivoting, 2 launches per
+  // pivot on the private stream; the transpose's inverse is its transpose
+  std::vector<void*> scratch;   // freed once the inverse is done
+  double* dA = upload(A, scratch);
+  double* colk = dalloc<double>(n, scratch);
+  int* status = dalloc<int>(1, scratch);
+  double* dinv = dalloc<double>((size_t)n * n, X->owned);
+  double* dtinv = dalloc<double>((size_t)n * n, X->owned);
+  hipStream_t st = X->ws;
+  HIP_OK(hipMemsetAsync(status, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_set_identity, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, st, dinv, n);
+  const dim3 ge((2 * n + 1023) / 1024, n);
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, dA, dinv, n, k, colk, status);
+    hipLaunchKernelGGL(k_gj_elim, ge, dim3(256), 0, st, dA, dinv, n, k, colk, status);
+  }
+  hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, dinv, dtinv, n);
+  int singular = 0;
+  HIP_OK(hipMemcpyAsync(&singular, status, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (void* q : scratch) (void)hipFree(q);
+  if (singular) throw ccg::Error(CCGMG_ESINGULAR, "singular coarsest operator");
   X->nm = n;
   X->mcell = upload(cells, X->owned);
-  X->minv = upload(A, X->owned);
-  X->mtinv = upload(AT, X->owned);
+  X->minv = dinv;
+  X->mtinv = dtinv;
   X->coarse_cache[X->M] = {n, X->mcell, X->minv, X->mtinv};
 }
 
@@ -690,7 +730,7 @@ void tune_tiles(ccgmg_ctx* X) {
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
-  const int reps = 10;
+  const int reps = 20;   // per candidate and round; best of two interleaved rounds
   for (DevLevel& L : X->lv) {
     Dr.fill<double>(L.u, L.n, 1.0);
     Dr.fill<double>(L.r, L.n, 0.5);
@@ -698,6 +738,7 @@ void tune_tiles(ccgmg_ctx* X) {
     Dr.fill<float>(L.r32, L.n, 0.5f);
     for (int prec = 0; prec < 2; ++prec) {
       float best = 1e30f;
+      for (int round = 0; round < 2; ++round)
       for (int ty : cand) {
         auto launch = [&]() {
           if (prec == 0) Dr.sweep<double>(L, L.u, L.r, L.v, ty);
@@ -845,6 +886,30 @@ struct Monitor {
   }
 };
 
+// The captured graph of one cycle of this solve (cached per context, keyed
+// by its arrays, right-hand-side count, precision, depth and direction);
+// recorded on stream Dr.s, launchable on any stream.
+hipGraphExec_t cycle_graph(Driver& Dr, double* u, const double* f, const double* bterm) {
+  ccgmg_ctx* X = Dr.X;
+  for (auto& g : X->graphs)
+    if (g.u == u && g.f == f && g.bterm == bterm && g.nrhs == Dr.nrhs && g.precision == X->opt.precision &&
+        g.M == X->M && g.adjoint == Dr.adjoint)
+      return g.exec;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph;
+  HIP_OK(hipStreamBeginCapture(Dr.s, hipStreamCaptureModeThreadLocal));
+  solve_cycle(Dr, u, f, bterm);
+  HIP_OK(hipStreamEndCapture(Dr.s, &graph));
+  HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(graph);
+  if (X->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(X->graphs.front().exec);
+    X->graphs.erase(X->graphs.begin());
+  }
+  X->graphs.push_back({u, f, bterm, Dr.nrhs, X->opt.precision, X->M, Dr.adjoint, exec});
+  return exec;
+}
+
 int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report* rep, bool adjoint) {
   return guard(X, [&]() {
     if (!f || !u || nrhs < 1 || nrhs > X->opt.max_nrhs) throw ccg::Error(CCGMG_EINVAL, "bad solve arguments");
@@ -860,26 +925,7 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     HIP_OK(hipStreamSynchronize(ws));
     Monitor mon;
     mon.start(X, nrhs, Dr.norm_parts(X->lv[0]));
-    hipGraphExec_t exec = nullptr;
-    if (X->opt.use_graph) {
-      for (auto& g : X->graphs)
-        if (g.u == u && g.f == f && g.bterm == bterm && g.nrhs == nrhs && g.precision == X->opt.precision &&
-            g.M == X->M && g.adjoint == adjoint)
-          exec = g.exec;
-      if (!exec) {
-        hipGraph_t graph;
-        HIP_OK(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
-        solve_cycle(Dr, u, f, bterm);
-        HIP_OK(hipStreamEndCapture(ws, &graph));
-        HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(graph);
-        if (X->graphs.size() >= 8) {
-          (void)hipGraphExecDestroy(X->graphs.front().exec);
-          X->graphs.erase(X->graphs.begin());
-        }
-        X->graphs.push_back({u, f, bterm, nrhs, X->opt.precision, X->M, adjoint, exec});
-      }
-    }
+    hipGraphExec_t exec = X->opt.use_graph ? cycle_graph(Dr, u, f, bterm) : nullptr;
     if (rep) std::memset(rep, 0, sizeof(*rep));
     for (;;) {
       if (exec)
@@ -953,7 +999,8 @@ double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, doubl
 
 // Many geometries in one captured launch: the V-cycles of all contexts of a
 // batch are recorded into one hipGraph whose branches (forked streams) run
-// concurrently; geometry g is recorded on branch g mod nbranches.  Every
+// concurrently; geometries are placed largest first onto the least-loaded
+// branch.  Every
 // replay advances every geometry by one cycle and reads back all residual
 // norms; a geometry that has converged keeps cycling (its residual only
 // shrinks) until all have finished.
@@ -1102,7 +1149,7 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       X->fweight = upload(fw, X->owned);
       X->g = dalloc<double>((size_t)std::max(1, X->nfaces) * maxr, X->owned);
       X->bterm = dalloc<double>((size_t)std::max(1, (int)D0.irr.size()) * maxr, X->owned);
-
+      if (maxr > 1) X->mrg = dalloc<double>((size_t)MAX_COARSE_UNKNOWNS * maxr, X->owned);
       HIP_OK(hipHostMalloc((void**)&X->norm_host,
                            sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
                            hipHostMallocDefault));
@@ -1388,6 +1435,21 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
       Driver Dr{B->ctx[g], B->main, nrhs[g], false};
       mon[g].start(B->ctx[g], nrhs[g], Dr.norm_parts(B->ctx[g]->lv[0]));
     }
+    // longest-processing-time-first: geometries by decreasing work (cells x
+    // right-hand sides), each onto the least-loaded branch
+    const int nb = (int)B->br.size();
+    std::vector<int> plan_order(n), plan_branch(n);
+    {
+      for (int g = 0; g < n; ++g) plan_order[g] = g;
+      auto work = [&](int g) { return (double)B->ctx[g]->lv[0].n * nrhs[g]; };
+      std::stable_sort(plan_order.begin(), plan_order.end(), [&](int x, int y) { return work(x) > work(y); });
+      std::vector<double> load(nb, 0.0);
+      for (int g : plan_order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += work(g);
+        plan_branch[g] = b;
+      }
+    }
     std::vector<const void*> key;
     for (int g = 0; g < n; ++g) {
       key.push_back(f[g]);
@@ -1399,15 +1461,15 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
     for (auto& gr : B->graphs)
       if (gr.key == key) exec = gr.exec;
     if (!exec) {
-      const int nb = (int)B->br.size();
       hipGraph_t graph;
       HIP_OK(hipStreamBeginCapture(B->main, hipStreamCaptureModeThreadLocal));
       HIP_OK(hipEventRecord(B->ev_fork[0], B->main));
       for (int b = 0; b < nb; ++b) HIP_OK(hipStreamWaitEvent(B->br[b], B->ev_fork[0], 0));
-      for (int g = 0; g < n; ++g) {
-        Driver Dr{B->ctx[g], B->br[g % nb], nrhs[g], false};
-        solve_cycle(Dr, u[g], f[g], bterm[g]);
-      }
+      for (int g : plan_order)
+        if (true) {
+          Driver Dr{B->ctx[g], B->br[plan_branch[g]], nrhs[g], false};
+          solve_cycle(Dr, u[g], f[g], bterm[g]);
+        }
       for (int b = 0; b < nb; ++b) {
         HIP_OK(hipEventRecord(B->ev_fork[1 + b], B->br[b]));
         HIP_OK(hipStreamWaitEvent(B->main, B->ev_fork[1 + b], 0));
@@ -1422,12 +1484,35 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
       B->graphs.push_back({key, exec});
     }
     if (reps) std::memset(reps, 0, sizeof(ccgmg_report) * n);
+    // while every geometry is active the whole batch cycle is one graph
+    // launch; once some have finished, only the active geometries' own cycle
+    // graphs are launched, on their branches
+    std::vector<hipGraphExec_t> own(n, nullptr);
+    bool all_active = true;
     for (;;) {
-      HIP_OK(hipGraphLaunch(exec, B->main));
+      if (all_active) {
+        HIP_OK(hipGraphLaunch(exec, B->main));
+      } else {
+        HIP_OK(hipEventRecord(B->ev_fork[0], B->main));
+        for (int b = 0; b < nb; ++b) HIP_OK(hipStreamWaitEvent(B->br[b], B->ev_fork[0], 0));
+        for (int g : plan_order) {
+          if (mon[g].stopped) continue;
+          hipStream_t sb = B->br[plan_branch[g]];
+          if (!own[g]) {
+            Driver Dr{B->ctx[g], sb, nrhs[g], false};
+            own[g] = cycle_graph(Dr, u[g], f[g], bterm[g]);
+          }
+          HIP_OK(hipGraphLaunch(own[g], sb));
+        }
+        for (int b = 0; b < nb; ++b) {
+          HIP_OK(hipEventRecord(B->ev_fork[1 + b], B->br[b]));
+          HIP_OK(hipStreamWaitEvent(B->main, B->ev_fork[1 + b], 0));
+        }
+      }
       HIP_OK(hipStreamSynchronize(B->main));
       bool all = true;
       for (int g = 0; g < n; ++g) {
-        if (!mon[g].stopped) mon[g].step(B->ctx[g], reps ? &reps[g] : nullptr);
+        if (!mon[g].stopped && mon[g].step(B->ctx[g], reps ? &reps[g] : nullptr)) all_active = false;
         all = all && mon[g].stopped;
       }
       if (all) break;

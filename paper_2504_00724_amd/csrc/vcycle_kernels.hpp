@@ -205,14 +205,14 @@ __device__ __forceinline__ double row_residual(const T* __restrict__ u, double r
 // Arguments of an SMO-2 pass (see k_smo2).
 struct Smo2Args {
   const double* bterm;
-  const int32_t *ecell, *erp, *ecols;
+  const int32_t *ecell, *ecols;   // ecols, evals, epar: ELL, row e at e * ew
   const double *evals, *ersum;
   const int32_t *eidx, *ebt, *ext_ptr, *own_cnt;
   const int64_t* inv_off;
   const double* inv;
   const double* c_in;
   double* c_out;
-  int ns, nbt;
+  int ns, nbt, ew;
   const int32_t* epar;    // per CSR entry: coarse parent of the column cell if it takes the correction, else -1
   const int32_t* eqpar;   // per overlapped row: the same for the row's own cell
 };
@@ -234,6 +234,8 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
   const double* c_in = a.c_in + (size_t)z * a.ns;
   double* c_out = a.c_out + (size_t)z * a.ns;
   const int e0 = a.ext_ptr[b], ne = a.ext_ptr[b + 1] - e0, nown = a.own_cnt[b];
+  const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const double* A = a.inv + a.inv_off[b] + row;
   for (int t = threadIdx.x; t < ne; t += BLOCK) {
     const int e = e0 + t;
     double uq = c_in[a.eidx[e]];
@@ -244,9 +246,9 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
     if (t < 64) uown[t] = uq;
     double rhs = (double)r[a.ecell[e]];
     if (a.bterm && a.ebt[e] >= 0) rhs -= a.bterm[(size_t)z * a.nbt + a.ebt[e]];
-    const int p1 = a.erp[e + 1];
+    const int p0 = e * a.ew, p1 = p0 + a.ew;
     double acc = 0.0;
-    for (int p = a.erp[e]; p < p1; p += 8) {
+    for (int p = p0; p < p1; p += 8) {
       int cc[8], pp[8];
       double vv[8], uu[8];
 #pragma unroll
@@ -267,10 +269,8 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
     res[t] = rhs - acc - a.ersum[e] * uq;
   }
   __syncthreads();
-  const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
   double s = 0.0;
   if (row < nown) {
-    const double* A = a.inv + a.inv_off[b] + row;
     int col = grp;
     for (; col + 28 < ne; col += 32) {
       double v[8];
@@ -469,6 +469,160 @@ __global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __
   double s = s0 + s1;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) u[cell[row]] = (T)s;
+}
+
+// Coarsest level with several right-hand sides, step 1: gather the
+// right-hand sides of the coarsest unknowns into rg[k][z] (FP64, row k,
+// nrhs contiguous).
+template <typename T>
+__global__ void k_coarse_gather(const T* __restrict__ r, const int32_t* __restrict__ cell, double* __restrict__ rg,
+                                int nm, int nrhs, size_t plane) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nm) return;
+  const int z = blockIdx.y;
+  rg[(size_t)k * nrhs + z] = (double)r[z * plane + cell[k]];
+}
+
+// Step 2: U = Inv * Rg as a register-tiled FP64 product that reads the
+// inverse once for all right-hand sides.  Workgroup = CR rows x CZ
+// right-hand sides; thread = 1 row x 4 right-hand sides; the inverse and Rg
+// are staged through LDS in chunks of CK columns.
+constexpr int CR = 16, CZ = 64, CK = 64;
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_coarse_multi(T* __restrict__ u, const double* __restrict__ rg,
+                                                        const int32_t* __restrict__ cell,
+                                                        const double* __restrict__ inv, int nm, int nrhs,
+                                                        size_t plane) {
+  __shared__ double As[CR][CK + 1];
+  __shared__ double Bs[CK][CZ];
+  const int row0 = blockIdx.x * CR, z0 = blockIdx.y * CZ;
+  const int tr = threadIdx.x >> 4, tz = (threadIdx.x & 15) * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < nm; k0 += CK) {
+    for (int t = threadIdx.x; t < CR * CK; t += BLOCK) {
+      const int i = t / CK, j = t - i * CK;
+      const int gi = row0 + i, gj = k0 + j;
+      As[i][j] = (gi < nm && gj < nm) ? inv[(size_t)gi * nm + gj] : 0.0;
+    }
+    for (int t = threadIdx.x; t < CK * CZ; t += BLOCK) {
+      const int i = t / CZ, j = t - i * CZ;
+      const int gk = k0 + i, gz = z0 + j;
+      Bs[i][j] = (gk < nm && gz < nrhs) ? rg[(size_t)gk * nrhs + gz] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < CK; ++kk) {
+      const double a = As[tr][kk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += a * Bs[kk][tz + j];
+    }
+    __syncthreads();
+  }
+  const int row = row0 + tr;
+  if (row >= nm) return;
+  const int q = cell[row];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (z0 + tz + j < nrhs) u[(size_t)(z0 + tz + j) * plane + q] = (T)acc[j];
+}
+
+// Set-up of the coarsest solve: dense inverse by Gauss-Jordan elimination
+// with partial pivoting on [A | B], B = I initially (row-major n x n, FP64),
+// one pivot per pair of launches.  status != 0 (singular) makes every later
+// launch a no-op.
+//
+// Pivot step (one workgroup): pivot row = argmax_{r >= k} |A[r][k]| (ties:
+// the smaller r); swap rows k and pivot in A and B; scale row k by
+// 1 / A[k][k]; copy column k into colk (the multipliers of the elimination).
+__global__ __launch_bounds__(1024) void k_gj_pivot(double* __restrict__ A, double* __restrict__ B, int n, int k,
+                                                   double* __restrict__ colk, int* __restrict__ status) {
+  __shared__ double bv[1024];
+  __shared__ int bi[1024];
+  if (*status) return;
+  const int t = threadIdx.x;
+  double best = -1.0;
+  int bidx = n;
+  for (int r = k + t; r < n; r += 1024) {
+    const double v = fabs(A[(size_t)r * n + k]);
+    if (v > best) best = v, bidx = r;
+  }
+  bv[t] = best;
+  bi[t] = bidx;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if (t < st) {
+      const double v2 = bv[t + st];
+      const int i2 = bi[t + st];
+      if (v2 > bv[t] || (v2 == bv[t] && i2 < bi[t])) bv[t] = v2, bi[t] = i2;
+    }
+    __syncthreads();
+  }
+  const int piv = bi[0];
+  const double pv = bv[0];
+  if (!(pv > 0.0) || !isfinite(pv) || piv >= n) {
+    if (t == 0) *status = 1;
+    return;
+  }
+  if (piv != k)
+    for (int c = t; c < n; c += 1024) {
+      const double a = A[(size_t)k * n + c], b = B[(size_t)k * n + c];
+      A[(size_t)k * n + c] = A[(size_t)piv * n + c];
+      B[(size_t)k * n + c] = B[(size_t)piv * n + c];
+      A[(size_t)piv * n + c] = a;
+      B[(size_t)piv * n + c] = b;
+    }
+  __syncthreads();
+  const double inv = 1.0 / A[(size_t)k * n + k];
+  __syncthreads();
+  for (int c = t; c < n; c += 1024) {
+    A[(size_t)k * n + c] *= inv;
+    B[(size_t)k * n + c] *= inv;
+  }
+  __syncthreads();
+  for (int r = t; r < n; r += 1024) colk[r] = A[(size_t)r * n + k];
+}
+
+// Elimination step: every row r != k subtracts colk[r] times the pivot row,
+// on the columns c >= k of A (columns < k are already unit vectors with a 0
+// in the pivot row) and on all columns of B.  grid.y = rows; grid.x covers
+// 2n columns (A then B) four per thread.
+__global__ __launch_bounds__(256) void k_gj_elim(double* __restrict__ A, double* __restrict__ B, int n, int k,
+                                                 const double* __restrict__ colk, const int* __restrict__ status) {
+  if (*status) return;
+  const int r = blockIdx.y;
+  if (r == k) return;
+  const double f = colk[r];
+  if (f == 0.0) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = (blockIdx.x * 256 + threadIdx.x) * 4 + j;
+    if (c < n) {
+      if (c >= k) A[(size_t)r * n + c] -= f * A[(size_t)k * n + c];
+    } else if (c < 2 * n) {
+      const int cb = c - n;
+      B[(size_t)r * n + cb] -= f * B[(size_t)k * n + cb];
+    }
+  }
+}
+
+// out = in^T (n x n); the inverse of A^T is the transpose of the inverse of A.
+__global__ void k_transpose(const double* __restrict__ in, double* __restrict__ out, int n) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int j = threadIdx.y; j < 32; j += 8) {
+    const int r = by + j, c = bx + threadIdx.x;
+    if (r < n && c < n) tile[j][threadIdx.x] = in[(size_t)r * n + c];
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += 8) {
+    const int r = bx + j, c = by + threadIdx.x;
+    if (r < n && c < n) out[(size_t)r * n + c] = tile[threadIdx.x][j];
+  }
+}
+
+__global__ void k_set_identity(double* __restrict__ B, int n) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < (size_t)n * n) B[k] = (k / n == k % n) ? 1.0 : 0.0;
 }
 
 // Boundary term of the irregular rows: bterm_k = sum over k's faces of N g.

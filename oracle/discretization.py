@@ -135,7 +135,9 @@ def regular_coefficients(a, b, c, h):
 class Discretization:
     """L and N of one grid level."""
 
-    def __init__(self, cg, a, b, c, w_min=0.5, cond_max=COND_MAX, need_plg_parity=True):
+    def __init__(self, cg, a, b, c, w_min=0.5, cond_max=COND_MAX, need_plg_parity=True, eager=True):
+        """eager=False skips fitting the irregular rows; ``row(q)`` then fits
+        one on demand (large grids sampled cell by cell)."""
         if b * b - 4.0 * a * c >= 0.0:
             raise ValueError("operator is not elliptic")
         self.cg = cg
@@ -176,8 +178,16 @@ class Discretization:
         self.weights = {}
         self.face_weights = {}
         self.conds = {}
-        for idx in self.irregular:
-            self._row(int(idx))
+        if eager:
+            for idx in self.irregular:
+                self._row(int(idx))
+
+    def row(self, q):
+        """Lattice, weights and face weights of irregular cell q (fitted on
+        first use)."""
+        if q not in self.stencils:
+            self._row(q)
+        return self.stencils[q], self.weights[q], self.face_weights.get(q, [])
 
     # -- averages of basis functions -----------------------------------------
     def _cell_offset(self, k, p):

@@ -10,7 +10,7 @@ from oracle.multigrid import Level, direct_solve, rhs_vector
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-CASES = [(1, 64), (2, 64), (4, 128), (5, 64)]
+CASES = [(1, 64), (2, 64), (4, 128), (5, 64), (1, 72)]   # 72: ragged tiles on every level
 _LEVELS = {}
 
 
@@ -276,3 +276,34 @@ def test_batch_of_geometries_matches_oracle():
     B.close()
     for S in solvers:
         S.close()
+
+
+def test_zero_data_and_argument_errors():
+    """Degenerate and invalid calls: zero right-hand side and boundary data
+    give u = 0 at once; too many right-hand sides, a coarsest level beyond
+    the dense-inverse limit and bad batch arguments are refused."""
+    from paper_2504_00724_amd.ccgmg import EINVAL, Batch, CcgmgError, Solver
+    dev = _dev()
+    cfg, lv = _level(1, 64)
+    S = _solver(cfg, tol=1e-10)
+    f = torch.zeros(64 * 64, dtype=torch.float64, device=dev)
+    u = torch.full_like(f, 3.0)
+    S.set_boundary(torch.zeros(S.info["n_bdry_faces"], dtype=torch.float64, device=dev), 1)
+    rep = S.solve(f, u)
+    torch.cuda.synchronize()
+    assert rep["cycles"] <= 1 and torch.count_nonzero(u).item() == 0
+    with pytest.raises(CcgmgError) as e:
+        S.solve(f, u, nrhs=2)
+    assert e.value.code == EINVAL
+    B = Batch([S])
+    with pytest.raises(CcgmgError) as e:
+        B.solve([f], [u], [2])
+    assert e.value.code == EINVAL
+    B.close()
+    c4 = W.config(4, n=128)
+    with pytest.raises(CcgmgError) as e:
+        Solver(c4["grid"], c4["curves"], 1.0, 0.0, 1.0, max_levels=1,
+               hip_stream=torch.cuda.current_stream().cuda_stream)
+    assert e.value.code == EINVAL and "coarsest" in str(e.value)
+    S.close()
+

@@ -261,6 +261,12 @@ def main():
     print("set-up %.1f s: %s" % (setup_s, info), file=sys.stderr, flush=True)
     f, g, exact, kinds = make_inputs(S, cfg, torch, dev)
     S.set_boundary(g, 1)
+    # set-up, untimed: schedule and depth re-chosen on this problem
+    t1 = time.perf_counter()
+    S.tune(f)
+    setup_s += time.perf_counter() - t1
+    info = S.info
+    print("tuned on the workload: %s" % info, file=sys.stderr, flush=True)
     u = torch.zeros_like(f)
     torch.cuda.synchronize()
 
@@ -315,6 +321,7 @@ def main():
                     hip_stream=stream.cuda_stream, precision=1, prolongation=args.prolongation,
                     smo2_every_sweep=args.smo2_every_sweep)
         Sm.set_boundary(g, 1)
+        Sm.tune(f)
         um = torch.zeros_like(f)
         for _ in range(args.warmup):
             Sm.solve(f, um)
@@ -351,7 +358,8 @@ def main():
                                "u = sin(pi x) sin(pi y), FP64 V-cycles from zero to 1e-10" % args.n,
                    "n_unknowns": nu, "n_irregular": info["n_irregular"], "levels": info["n_levels"],
                    "coarsest": info["nx_coarsest"], "nrhs": 1,
-                   "schedule": {"smoother_fused": info["smoother_fused"], "nu1": info["nu1"], "nu2": info["nu2"]},
+                   "schedule": {"smoother_fused": info["smoother_fused"], "nu1": info["nu1"], "nu2": info["nu2"],
+                                "nu1_coarse": info["nu1_coarse"], "nu2_coarse": info["nu2_coarse"]},
                    "sweep_tile_rows": [S.tuning(m)[0] for m in range(info["n_levels"])]},
         "cycles": reps[-1]["cycles"],
         "rel_res_inf": reps[-1]["rel_res_inf"],

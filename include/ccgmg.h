@@ -82,6 +82,7 @@ typedef struct {
   double w_min;          /* least-squares weight floor (eq. weightDef), default 0.5       */
   double omega;          /* weighted-Jacobi factor of SMO-1, default 0.5                  */
   int nu1, nu2;          /* pre/post smoothing steps, default 3, 3                        */
+  int nu1_coarse, nu2_coarse; /* steps on the coarse levels when > 0 (default 0: nu1, nu2) */
   int coarsest_min_n;    /* smallest coarse grid side considered, default 16              */
   int max_levels;        /* default 16                                                    */
   int auto_depth;        /* coarsest level: 0 deepest that can be built; 1 deepest whose
@@ -111,8 +112,9 @@ typedef struct {
   int smoother_fused;    /* 0: each smoothing step is SMO-1 then SMO-2 (Alg. 2); 1: both
                             in one launch from the same iterate (additive)               */
   int tune_schedule;     /* 1 (default, with auto_depth 2): also time the schedules
-                            (smoother_fused, nu1, nu2) = (0,3,3), (1,3,3), (1,4,4),
-                            (1,5,5) and keep the fastest; 0: use the fields above        */
+                            (smoother_fused, nu1, nu2 / coarse) = (0,3,3), (1,3,3),
+                            (1,4,4), (1,5,5), (1,4,4/2,2), (1,5,5/2,2), (1,5,5/3,3),
+                            (1,6,6/3,3) and keep the fastest; 0: use the fields above   */
   int host_only;         /* 1: build the hierarchy on the host only (no device calls);
                             queries work, apply/solve return CCGMG_EINVAL                  */
   void* hip_stream;      /* hipStream_t all device work is ordered on                     */
@@ -130,6 +132,7 @@ typedef struct {
   double plg_max_cond;
   int smoother_fused;    /* smoothing schedule in use (after tuning)                      */
   int nu1, nu2;
+  int nu1_coarse, nu2_coarse;
 } ccgmg_info;
 
 typedef struct {
@@ -277,6 +280,15 @@ int ccgmg_batch_solve(ccgmg_batch* batch, const double* const* f, double* const*
                       ccgmg_report* reps);
 const char* ccgmg_batch_last_error(const ccgmg_batch* batch);
 void ccgmg_batch_destroy(ccgmg_batch* batch);
+
+/* Re-choose the smoothing schedule and the depth (as auto_depth 2 /
+ * tune_schedule do at set-up) by timing solves of the caller's own problem:
+ * f is one right-hand side (device, ny x nx) representative of the solves to
+ * come, with the boundary data last given to ccgmg_set_boundary.  Each
+ * candidate is solved from zero to 1e-10 twice (capture, timed replay) and
+ * the fastest that converges is kept.  Not a paper construct (the paper
+ * fixes its cycle parameters); a measured autotuner of this library. */
+int ccgmg_tune(ccgmg_ctx* ctx, const double* f);
 
 const char* ccgmg_last_error(const ccgmg_ctx* ctx);
 

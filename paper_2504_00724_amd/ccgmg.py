@@ -24,7 +24,7 @@ EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_ce
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
            "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
-           "ccgmg_profile_kernel", "ccgmg_get_tuning", "ccgmg_get_smo2_stats",
+           "ccgmg_profile_kernel", "ccgmg_get_tuning", "ccgmg_get_smo2_stats", "ccgmg_tune",
            "ccgmg_batch_create", "ccgmg_batch_solve", "ccgmg_batch_last_error", "ccgmg_batch_destroy",
            "ccgmg_last_error", "ccgmg_create_error", "ccgmg_destroy"]
 
@@ -39,7 +39,7 @@ class GridT(C.Structure):
 
 class OptionsT(C.Structure):
     _fields_ = [("theta", C.c_double), ("w_min", C.c_double), ("omega", C.c_double), ("nu1", C.c_int),
-                ("nu2", C.c_int), ("coarsest_min_n", C.c_int), ("max_levels", C.c_int), ("auto_depth", C.c_int),
+                ("nu2", C.c_int), ("nu1_coarse", C.c_int), ("nu2_coarse", C.c_int), ("coarsest_min_n", C.c_int), ("max_levels", C.c_int), ("auto_depth", C.c_int),
                 ("depth_max_rate", C.c_double), ("precision", C.c_int), ("prolongation", C.c_int),
                 ("smo2_every_sweep", C.c_int), ("smo2_iters", C.c_int), ("smo2_block", C.c_int),
                 ("smo2_overlap", C.c_int), ("smo2_widen", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
@@ -51,7 +51,8 @@ class InfoT(C.Structure):
     _fields_ = [("n_cells", C.c_long), ("n_unknowns", C.c_long), ("n_irregular", C.c_long),
                 ("n_bdry_faces", C.c_long), ("n_levels", C.c_int), ("nx_coarsest", C.c_int),
                 ("ny_coarsest", C.c_int), ("coarse_unknowns", C.c_long), ("setup_seconds", C.c_double),
-                ("plg_max_cond", C.c_double), ("smoother_fused", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int)]
+                ("plg_max_cond", C.c_double), ("smoother_fused", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("nu1_coarse", C.c_int), ("nu2_coarse", C.c_int)]
 
 
 class ReportT(C.Structure):
@@ -93,6 +94,7 @@ def lib():
         L.ccgmg_profile_kernel.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_double)]
         L.ccgmg_get_tuning.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
         L.ccgmg_get_smo2_stats.argtypes = [vp, ip, ip, C.POINTER(C.c_long)]
+        L.ccgmg_tune.argtypes = [vp, vp]
         L.ccgmg_batch_create.argtypes = [C.POINTER(vp), ip, ip, C.POINTER(vp)]
         L.ccgmg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(ip), C.POINTER(ReportT)]
         L.ccgmg_batch_last_error.argtypes = [vp]
@@ -257,6 +259,12 @@ class Solver:
         if st != OK and (raise_on_noconv or st != ENOCONV):
             self._check(st)
         return _report(rep, st)
+
+    def tune(self, f):
+        """Re-choose schedule and depth by timing solves of this right-hand
+        side (with the boundary data last set); refreshes ``info``."""
+        self._check(lib().ccgmg_tune(self.ctx, _ptr(f)))
+        self.info = self.query()
 
     def profile_kernel(self, kernel, level=0, reps=50):
         """Mean duration (microseconds) of one V-cycle kernel, HIP events."""

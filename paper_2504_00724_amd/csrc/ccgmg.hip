@@ -556,18 +556,22 @@ struct Driver {
       coarse<T>(L, u, r);
       return u;
     }
-    T* cur = smooth<T>(L, u, v, r, bterm, X->opt.nu1);
+    // smoothing steps: nu1/nu2 on the finest level, nu1_coarse/nu2_coarse
+    // (when positive) on the coarse levels
+    const int n1 = (m > 0 && X->opt.nu1_coarse > 0) ? X->opt.nu1_coarse : X->opt.nu1;
+    const int n2 = (m > 0 && X->opt.nu2_coarse > 0) ? X->opt.nu2_coarse : X->opt.nu2;
+    T* cur = smooth<T>(L, u, v, r, bterm, n1);
     T* oth = cur == u ? v : u;
     DevLevel& C = X->lv[m + 1];
     Buf<T> cb = bufs<T>(C);
     restrict_<T>(L, C, cur, r, cb.r, cb.u);
     T* e = vcycle<T>(m + 1, cb.u, cb.v, cb.r, nullptr);
     T* out;
-    if (fused(L) && X->opt.prolongation == 0 && X->opt.nu2 > 0) {
-      out = smooth<T>(L, cur, oth, r, bterm, X->opt.nu2, e, &C);   // correction applied by the first step
+    if (fused(L) && X->opt.prolongation == 0 && n2 > 0) {
+      out = smooth<T>(L, cur, oth, r, bterm, n2, e, &C);   // correction applied by the first step
     } else {
       prolong<T>(L, C, cur, e);
-      out = smooth<T>(L, cur, oth, r, bterm, X->opt.nu2);
+      out = smooth<T>(L, cur, oth, r, bterm, n2);
     }
     settle_rows(L);
     return out;
@@ -953,27 +957,35 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
   });
 }
 
-// V-cycles on a seeded random right-hand side with the current depth; the
-// geometric-mean contraction of the residual over 6 cycles.
-double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, double* seconds = nullptr,
-                       bool keep_graphs = false, double* score = nullptr) {
+// A solve from zero with the current schedule and depth, timed as the
+// solves run (graph replay; a first call captures the graph).  f: the
+// right-hand side (device, one plane), or nullptr for a seeded N(0,1)
+// right-hand side on the non-empty cells without boundary term.  Returns
+// the geometric-mean contraction per cycle (1e300 if tol > 0 is not
+// reached); *seconds: device time; *score: time per cycle x cycles per
+// 1e10 at the asymptotic rate (the cycles after the first two).
+double timed_solve(ccgmg_ctx* X, const double* f, double tol, int max_cycles, double* seconds,
+                   bool keep_graphs = false, double* score = nullptr) {
   DevLevel& L0 = X->lv[0];
-  std::vector<double> r(L0.n, 0.0);
-  std::mt19937_64 gen(12345);
-  std::normal_distribution<double> nd(0.0, 1.0);
-  const ccg::Discretization& D = X->H.disc[0];
-  for (size_t k = 0; k < L0.n; ++k) r[k] = D.nonempty[k] ? nd(gen) : 0.0;
-  double* rd = L0.r;   // level-0 scratch buffers
-  double* ud = L0.u;
-  HIP_OK(hipMemcpy(rd, r.data(), sizeof(double) * L0.n, hipMemcpyHostToDevice));
+  double* ud = L0.u;   // level-0 scratch buffers (level 0 of a solve uses the caller's arrays)
+  const double* rd = f;
+  int g_saved = X->g_nrhs;
+  if (!f) {
+    std::vector<double> r(L0.n, 0.0);
+    std::mt19937_64 gen(12345);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    const ccg::Discretization& D = X->H.disc[0];
+    for (size_t k = 0; k < L0.n; ++k) r[k] = D.nonempty[k] ? nd(gen) : 0.0;
+    HIP_OK(hipMemcpy(L0.r, r.data(), sizeof(double) * L0.n, hipMemcpyHostToDevice));
+    rd = L0.r;
+    X->g_nrhs = 0;
+  }
   ccgmg_options saved = X->opt;
   X->opt.max_cycles = max_cycles;
   X->opt.tol = tol;
   X->opt.use_initial_guess = 0;
   X->opt.precision = 0;
   X->opt.use_graph = 1;   // timed as the solves will run: graph replays
-  int g_saved = X->g_nrhs;
-  X->g_nrhs = 0;
   ccgmg_report rep;
   solve_impl(X, rd, ud, 1, &rep, false);
   X->opt = saved;
@@ -982,19 +994,59 @@ double depth_test_rate(ccgmg_ctx* X, double tol = 0.0, int max_cycles = 6, doubl
   if (seconds) *seconds = rep.seconds;
   double last = rep.cycles > 0 ? rep.history[std::min(rep.cycles, 64) - 1] : 1.0;
   if (score) {
-    // estimated time to reduce the residual by 1e10 at the asymptotic rate
-    // (geometric mean over the cycles after the first two): time per cycle
-    // times cycles needed; less sensitive to whole-cycle rounding than the
-    // solve time itself
     const int nc = std::min(rep.cycles, 64);
     double tail = 1.0;
     if (nc >= 4) tail = std::pow(rep.history[nc - 1] / rep.history[1], 1.0 / (nc - 2));
     *score = (tail > 0.0 && tail < 1.0) ? rep.seconds / rep.cycles * std::log(1e-10) / std::log(tail) : 1e300;
   }
-  // with a tolerance, a depth whose solve stops short of it (stagnation or
-  // the cycle limit) is not admissible
   if (tol > 0.0 && !(rep.rel_res_inf <= tol)) return 1e300;
   return (std::isfinite(last) && rep.cycles > 0) ? std::pow(last, 1.0 / rep.cycles) : 1e300;
+}
+
+// Measured choice of smoothing schedule and depth: every candidate schedule
+// (with tune_schedule) at every admissible coarsest level (<= the dense
+// inverse limit), solved twice (capture, then timed replay).  With f == 0
+// (set-up) the seeded random right-hand side is used and candidates are
+// ranked by the asymptotic-rate estimate; with the caller's f they are
+// ranked by the measured time of the solve itself.
+void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
+  struct Sched {
+    int fused, nu1, nu2, c1, c2;   // c1, c2: coarse-level steps (0: as nu1, nu2)
+  };
+  std::vector<Sched> cands;
+  if (X->opt.tune_schedule)
+    cands = {{0, 3, 3, 0, 0}, {1, 3, 3, 0, 0}, {1, 4, 4, 0, 0}, {1, 5, 5, 0, 0},
+             {1, 4, 4, 2, 2}, {1, 5, 5, 2, 2}, {1, 5, 5, 3, 3}, {1, 6, 6, 3, 3}};
+  else
+    cands = {{X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse}};
+  const int Mmax = (int)X->H.disc.size() - 1;
+  X->tune_ms.assign(Mmax + 1, -1.0);
+  double best = 1e300;
+  int bestM = X->M;
+  Sched bestS = {X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse};
+  for (const Sched& sc : cands) {
+    X->opt.smoother_fused = sc.fused, X->opt.nu1 = sc.nu1, X->opt.nu2 = sc.nu2;
+    X->opt.nu1_coarse = sc.c1, X->opt.nu2_coarse = sc.c2;
+    for (int Mc = Mmax; Mc >= 1; --Mc) {
+      long nu = 0;
+      for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
+      if (nu > MAX_COARSE_UNKNOWNS) break;
+      X->M = Mc;
+      upload_coarsest(X);
+      double sec = 0, score = 0;
+      timed_solve(X, f, 1e-10, 60, &sec, true);   // captures the graph
+      const double rate = timed_solve(X, f, 1e-10, 60, &sec, false, &score);
+      const double cost = f ? sec : score;
+      const bool ok = rate <= X->opt.depth_max_rate;
+      if (ok && (X->tune_ms[Mc] < 0 || 1e3 * cost < X->tune_ms[Mc])) X->tune_ms[Mc] = 1e3 * cost;
+      if (ok && cost < best) best = cost, bestM = Mc, bestS = sc;
+    }
+  }
+  X->opt.smoother_fused = bestS.fused, X->opt.nu1 = bestS.nu1, X->opt.nu2 = bestS.nu2;
+  X->opt.nu1_coarse = bestS.c1, X->opt.nu2_coarse = bestS.c2;
+  X->M = bestM;
+  upload_coarsest(X);
+  X->clear_graphs();
 }
 
 // Many geometries in one captured launch: the V-cycles of all contexts of a
@@ -1163,46 +1215,10 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       upload_coarsest(X.get());
       if (X->opt.tune_tiles) tune_tiles(X.get());
       if (X->opt.auto_depth == 2 && X->M > 1) {
-        // measured: time a full solve (seeded right-hand side, 1e-10) for
-        // every admissible coarsest level and, with tune_schedule, every
-        // candidate smoothing schedule; among those that converge keep the
-        // one with the smallest estimated time to a 1e10 reduction
-        struct Sched {
-          int fused, nu1, nu2;
-        };
-        std::vector<Sched> cands;
-        if (X->opt.tune_schedule)
-          cands = {{0, 3, 3}, {1, 3, 3}, {1, 4, 4}, {1, 5, 5}};
-        else
-          cands = {{X->opt.smoother_fused, X->opt.nu1, X->opt.nu2}};
-        const int Mmax = X->M;
-        X->tune_ms.assign(Mmax + 1, -1.0);
-        double best = 1e300;
-        int bestM = Mmax;
-        Sched bestS = cands[0];
-        for (const Sched& sc : cands) {
-          X->opt.smoother_fused = sc.fused, X->opt.nu1 = sc.nu1, X->opt.nu2 = sc.nu2;
-          for (int Mc = Mmax; Mc >= 1; --Mc) {
-            long nu = 0;
-            for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
-            if (nu > MAX_COARSE_UNKNOWNS) break;
-            X->M = Mc;
-            upload_coarsest(X.get());
-            double sec = 0, score = 0;
-            depth_test_rate(X.get(), 1e-10, 60, &sec, true);   // captures the graph
-            const double rate = depth_test_rate(X.get(), 1e-10, 60, &sec, false, &score);
-            const bool ok = rate <= X->opt.depth_max_rate;
-            if (ok && (X->tune_ms[Mc] < 0 || 1e3 * score < X->tune_ms[Mc])) X->tune_ms[Mc] = 1e3 * score;
-            if (ok && score < best) best = score, bestM = Mc, bestS = sc;
-          }
-        }
-        X->opt.smoother_fused = bestS.fused, X->opt.nu1 = bestS.nu1, X->opt.nu2 = bestS.nu2;
-        X->M = bestM;
-        upload_coarsest(X.get());
-        X->clear_graphs();
+        tune_schedule_depth(X.get(), nullptr);
       } else if (X->opt.auto_depth == 1 && X->M > 1) {
         for (;;) {
-          const double rate = depth_test_rate(X.get());
+          const double rate = timed_solve(X.get(), nullptr, 0.0, 6, nullptr);
           if (rate <= X->opt.depth_max_rate || X->M <= 1) break;
           long next = 0;
           for (uint8_t v : X->H.disc[X->M - 1].nonempty) next += v;
@@ -1250,6 +1266,8 @@ int ccgmg_query(const ccgmg_ctx* X, ccgmg_info* info) {
   info->smoother_fused = X->opt.smoother_fused;
   info->nu1 = X->opt.nu1;
   info->nu2 = X->opt.nu2;
+  info->nu1_coarse = X->opt.nu1_coarse > 0 ? X->opt.nu1_coarse : X->opt.nu1;
+  info->nu2_coarse = X->opt.nu2_coarse > 0 ? X->opt.nu2_coarse : X->opt.nu2;
   return CCGMG_OK;
 }
 
@@ -1372,6 +1390,14 @@ int ccgmg_set_boundary(ccgmg_ctx* X, const double* g, int nrhs) {
       HIP_OK(hipMemcpyAsync(X->g, g, sizeof(double) * X->nfaces * nrhs, hipMemcpyDeviceToDevice, X->stream));
     }
     X->g_nrhs = nrhs;
+  });
+}
+
+int ccgmg_tune(ccgmg_ctx* X, const double* f) {
+  return guard(X, [&]() {
+    if (!f) throw ccg::Error(CCGMG_EINVAL, "bad tune arguments");
+    if (X->H.disc.size() < 2) return;
+    tune_schedule_depth(X, f);
   });
 }
 

@@ -307,3 +307,28 @@ def test_zero_data_and_argument_errors():
     assert e.value.code == EINVAL and "coarsest" in str(e.value)
     S.close()
 
+
+
+def test_tune_on_callers_problem_keeps_parity():
+    """ccgmg_tune re-chooses schedule and depth on the caller's right-hand
+    side and boundary data; the solve afterwards still reaches the oracle's
+    solution."""
+    dev = _dev()
+    cfg, lv = _level(2, 64)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ref = direct_solve(lv, rhs_vector(lv, f, g))
+    S = _solver(cfg, tol=1e-12, max_cycles=200)
+    fd = torch.tensor(f, device=dev)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    S.tune(fd)
+    info = S.info
+    print("tuned: fused %d nu %d/%d coarse %d/%d levels %d" % (info["smoother_fused"], info["nu1"], info["nu2"],
+                                                              info["nu1_coarse"], info["nu2_coarse"],
+                                                              info["n_levels"]), flush=True)
+    u = torch.zeros_like(fd)
+    S.solve(fd, u)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-10
+    S.close()

@@ -2,6 +2,7 @@
 with the oracle (bit-exact classification, lattices and Alg. 3 order;
 least-squares weights within 1e-12 in h^2 units) and error codes."""
 import ctypes
+import os
 import re
 
 import numpy as np
@@ -114,3 +115,33 @@ def test_host_only_context_refuses_device_calls():
     with pytest.raises(ccgmg.CcgmgError) as ei:
         S.apply(buf, buf.copy())
     assert ei.value.code == ccgmg.EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the option, info and report structs have the C
+    layout of include/ccgmg.h (size and every field offset), checked by
+    compiling a small C program against the header."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"ccgmg_options": ccgmg.OptionsT, "ccgmg_info": ccgmg.InfoT, "ccgmg_report": ccgmg.ReportT,
+               "ccgmg_grid": ccgmg.GridT, "ccgmg_curve": ccgmg.CurveT}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ccgmg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(out[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(out["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)

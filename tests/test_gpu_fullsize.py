@@ -160,3 +160,63 @@ def test_fullsize_mixed_precision_matches_fp64(full):
     assert rep["rel_res_inf"] <= 1e-10
     assert diff <= disc
     Sm.close()
+
+
+def test_fullsize_adjoint_gradients_match_finite_differences(full):
+    """The adjoint workload at 2048^2: J = 1/2 ||u - u_target||^2 over the
+    non-empty cells, u_target = <u> + N(0, 1e-3^2) (seed 44); gradients with
+    respect to f-hat and g-hat from the autograd Function (adjoint solve on
+    L^T, then -N^T lambda) against central differences along 16 unit
+    directions in (f-hat, g-hat) (seeds 400-415: smooth 4 x 4-mode Fourier
+    fields on the cells, N(0,1) on the boundary faces).  J is quadratic in
+    the data, so the central difference is exact for any eps; it is
+    evaluated as 1/2 sum (u+ - u-)(u+ + u- - 2 u_target) to avoid cancelling
+    two large values of J, and both solves of a pair must take the same
+    number of cycles (then both are the same linear map, which differs from
+    L^{-1} by the ~1e-9 error operator of that many cycles).  eps = 1e-2:
+    with eps = 1e-6 the perturbation of u (~5e-11 per cell) is at the
+    rounding level of the solves themselves (~1e-13 per cell after the sum
+    over 3.8 M cells) and the comparison only shows that noise."""
+    from paper_2504_00724_amd.autograd import cutcell_solve
+    S, d, dev = full["S"], full["d"], full["dev"]
+    f, g = full["f"], full["g"]
+    mask_np = d.nonempty.astype(np.float64)
+    mask = torch.tensor(mask_np, device=dev)
+    target = torch.tensor((full["exact"] + 1e-3 * np.random.default_rng(44).standard_normal(N * N)) * mask_np,
+                          device=dev)
+    fr = f.clone().requires_grad_(True)
+    gr = g.clone().requires_grad_(True)
+    u = cutcell_solve(fr, gr, S)
+    J = 0.5 * torch.sum(((u - target) * mask) ** 2)
+    J.backward()
+    gf, gg = fr.grad.detach(), gr.grad.detach()
+    gnorm = float(torch.sqrt(torch.sum(gf ** 2) + torch.sum(gg ** 2)))   # bounds |dJ . d| for unit d
+    h = 1.0 / N
+    xc = (np.arange(N) + 0.5) * h
+    eps = 1e-2
+    worst = 0.0
+    for k in range(16):
+        rng = np.random.default_rng(400 + k)
+        c = rng.standard_normal((4, 4))
+        sx = np.sin(np.pi * np.outer(np.arange(1, 5), xc))           # [p][i]
+        df = (sx.T @ c.T @ sx).ravel() * mask_np                       # [j][i]
+        dg = rng.standard_normal(g.numel())
+        nrm = np.sqrt(np.sum(df ** 2) + np.sum(dg ** 2))
+        df_t, dg_t = torch.tensor(df / nrm, device=dev), torch.tensor(dg / nrm, device=dev)
+        up, um = torch.zeros_like(f), torch.zeros_like(f)
+        S.set_boundary(g + eps * dg_t, 1)
+        rp = S.solve(f + eps * df_t, up)
+        S.set_boundary(g - eps * dg_t, 1)
+        rm = S.solve(f - eps * df_t, um)
+        assert rp["cycles"] == rm["cycles"]
+        fd = float(0.5 * torch.sum((up - um) * (up + um - 2.0 * target) * mask ** 2)) / (2.0 * eps)
+        adj = float(torch.sum(gf * df_t) + torch.sum(gg * dg_t))
+        rel = abs(fd - adj) / gnorm
+        worst = max(worst, rel)
+        print("   direction %2d: fd %.10e adjoint %.10e |fd - adjoint| / |grad J| %.2e" % (k, fd, adj, rel),
+              flush=True)
+    S.set_boundary(g, 1)
+    # error relative to |grad J| (the largest directional derivative over
+    # unit directions): directions nearly orthogonal to grad J would
+    # otherwise divide the solve's rounding floor by a tiny number
+    assert worst < 1e-8

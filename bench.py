@@ -40,6 +40,8 @@ def fused_step_bytes(n_cells, st):
 def make_inputs(S, cfg, torch, dev):
     """f-hat and g-hat from the library's quadrature export (no oracle)."""
     import numpy as np
+
+    import workloads as W
     grid = cfg["grid"]
     n, h = grid["nx"], grid["h"]
     sol = cfg["solution"]
@@ -69,11 +71,61 @@ def make_inputs(S, cfg, torch, dev):
     fh[kinds <= 1] = 0.0
     fcell, fx, fy, fw, fnx, fny = S.face_quadrature()
     nf = S.info["n_bdry_faces"]
-    gv = sol.u(fx, fy)          # Dirichlet everywhere in this workload
+    _, fcurve, _ = S.boundary_faces()
+    neumann = np.array([c["bc"] == W.NEUMANN for c in cfg["curves"]])[fcurve[fcell]]
+    gv = np.where(neumann, sol.dudn(fx, fy, fnx, fny), sol.u(fx, fy))   # Neumann: outward normal derivative
     ghat = np.bincount(fcell, weights=fw * gv, minlength=nf) / np.bincount(fcell, weights=fw, minlength=nf)
     ex[kinds <= 1] = 0.0
     ex[cut] = np.bincount(cell, weights=qw * sol.u(qx, qy), minlength=n * n)[cut] / vol[cut]
     return torch.tensor(fh, device=dev), torch.tensor(ghat, device=dev), ex, kinds
+
+
+WORKLOADS = {
+    4: "unit square minus 3 seeded circles (seed 4), %d^2 cells, Poisson, Dirichlet, u = sin(pi x) sin(pi y), "
+       "FP64 V-cycles from zero to 1e-10",
+    2: "unit square minus flower r = 0.25 + 0.05 sin 5t, %d^2 cells, (a,b,c) = (1,0.5,1), Dirichlet box, "
+       "Neumann flower, u = exp(x) cos(3y), FP64 V-cycles from zero to 1e-10",
+    5: "unit square minus 5 seeded ellipses (seed 5), %d^2 cells, (a,b,c) = (1,1.2,1), Dirichlet, "
+       "u = sin(pi x) sin(2 pi y) + x^3, FP64 V-cycles from zero to 1e-10",
+}
+
+
+def run_error_study(args):
+    """Discretization error of the FP64 solution on a sequence of grids
+    (L-infinity over non-empty cells and volume-weighted L1), with the
+    observed convergence rates.  The solves run to the rounding floor (tol
+    1e-15, stopped by stagnation): at 1e-10 the iteration error, not the
+    discretization error, would dominate on fine grids."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2504_00724_amd.ccgmg import Solver
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in [int(v) for v in args.error_study.split(",")]:
+        cfg = W.config(args.config, n=n)
+        S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-15, max_cycles=80,
+                   hip_stream=stream.cuda_stream)
+        f, g, exact, kinds = make_inputs(S, cfg, torch, dev)
+        S.set_boundary(g, 1)
+        u = torch.zeros_like(f)
+        rep = S.solve(f, u, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        e = np.abs(u.cpu().numpy() - exact)
+        ne = kinds >= 2
+        vol = S.volumes(0)
+        row = {"n": n, "unknowns": S.info["n_unknowns"], "err_inf": float(np.max(e[ne])),
+               "err_l1": float(np.sum((e * vol)[ne]) / np.sum(vol[ne])), "cycles": rep["cycles"],
+               "rel_res_floor": rep["rel_res_inf"], "levels": S.info["n_levels"]}
+        rows.append(row)
+        print("error study n=%d: %s" % (n, row), file=sys.stderr, flush=True)
+        S.close()
+    for a, b in zip(rows, rows[1:]):
+        b["rate_inf"] = float(np.log2(a["err_inf"] / b["err_inf"]))
+        b["rate_l1"] = float(np.log2(a["err_l1"] / b["err_l1"]))
+    print(json.dumps({"error_study": WORKLOADS[args.config] % 0, "rows": rows}))
 
 
 def fourier_averages(S, cfg, coeffs, torch, dev):
@@ -175,7 +227,7 @@ def run_batch(args):
         S.close()
 
 
-def cpu_baseline(n_sample, seconds):
+def cpu_baseline(n_sample, seconds, config=4):
     """The oracle's own V-cycle solve, one core, on the same geometry and
     problem at a smaller grid: its set-up is not timed; the solve from a zero
     guess is repeated until at least ``seconds`` of CPU time have passed."""
@@ -185,7 +237,7 @@ def cpu_baseline(n_sample, seconds):
     from oracle.discretization import boundary_data
     from oracle.geometry import cell_averages
     from oracle.multigrid import Hierarchy, rhs_vector
-    cfg = W.config(4, n=n_sample)
+    cfg = W.config(config, n=n_sample)
     with threadpool_limits(limits=1):
         t_set = time.perf_counter()
         H = Hierarchy(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
@@ -218,7 +270,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--n", type=int, default=0, help="grid side (default: the workload's own)")
+    ap.add_argument("--config", type=int, choices=[2, 4, 5], default=4,
+                    help="4: the metric workload; 2: flower hole with Neumann data, b = 0.5 (1024^2); "
+                         "5: five ellipses, b = 1.2 (4096^2)")
+    ap.add_argument("--error-study", default="",
+                    help="comma-separated grid sides: FP64 solves of the chosen workload and their errors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -241,6 +298,11 @@ def main():
     if args.workload == "batch":
         run_batch(args)
         return
+    if not args.n:
+        args.n = {2: 1024, 4: 2048, 5: 4096}[args.config]
+    if args.error_study:
+        run_error_study(args)
+        return
 
     import numpy as np
     import torch
@@ -251,7 +313,7 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    cfg = W.config(4, n=args.n)
+    cfg = W.config(args.config, n=args.n)
     t0 = time.perf_counter()
     S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-10, max_cycles=200,
                hip_stream=stream.cuda_stream, prolongation=args.prolongation,
@@ -294,12 +356,12 @@ def main():
     ty = S.tuning(0)[0]
     cells = args.n * args.n
     if info["smoother_fused"]:
-        kname = "k_smooth_fused<double, false, true, %d, false>" % ty
+        kname = "k_smooth_fused<double, %s, true, %d, false>" % ("true" if cfg["b"] != 0 else "false", ty)
         kdesc = "finest-level fused SMO-1 + SMO-2 step"
         dom_us = S.profile_kernel(7, 0, 50)
         dom_bytes = fused_step_bytes(cells, S.smo2_stats(0))
     else:
-        kname = "k_sweep<double, false, true, %d>" % ty
+        kname = "k_sweep<double, %s, true, %d>" % ("true" if cfg["b"] != 0 else "false", ty)
         kdesc = "finest-level SMO-1 sweep"
         dom_us = S.profile_kernel(0, 0, 50)
         dom_bytes = ALG_BYTES_SWEEP * cells
@@ -339,10 +401,11 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_sample_n, args.cpu_seconds)
+        cpu = cpu_baseline(args.cpu_sample_n, args.cpu_seconds, args.config)
 
     out = {
-        "metric": "4th-order cut-cell GMG solve: unknowns/s and HBM GB/s at 1e-10 rel. residual, 2048^2",
+        "metric": ("4th-order cut-cell GMG solve: unknowns/s and HBM GB/s at 1e-10 rel. residual, 2048^2"
+                   if args.config == 4 else "4th-order cut-cell GMG solve: unknowns/s at 1e-10 rel. residual"),
         "value": nu / (ms * 1e-3),
         "unit": "unknowns/s",
         "n_gpus": 1,
@@ -354,8 +417,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "unit square minus 3 seeded circles (seed 4), %d^2 cells, Poisson, Dirichlet, "
-                               "u = sin(pi x) sin(pi y), FP64 V-cycles from zero to 1e-10" % args.n,
+        "config": {"workload": WORKLOADS[args.config] % args.n,
                    "n_unknowns": nu, "n_irregular": info["n_irregular"], "levels": info["n_levels"],
                    "coarsest": info["nx_coarsest"], "nrhs": 1,
                    "schedule": {"smoother_fused": info["smoother_fused"], "nu1": info["nu1"], "nu2": info["nu2"],

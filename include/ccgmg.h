@@ -109,6 +109,8 @@ typedef struct {
   int use_graph;         /* 1: replay V-cycles from a captured hipGraph                   */
   int tune_tiles;        /* 1 (default): pick the SMO-1 tile height of every level and
                             precision by timing the candidates at set-up; 0: 64 x 16     */
+  int sweep_tile_rows;   /* 8, 16 or 32: this tile height on every level (no tuning);
+                            0 (default): as tune_tiles says                              */
   int smoother_fused;    /* 0: each smoothing step is SMO-1 then SMO-2 (Alg. 2); 1: both
                             in one launch from the same iterate (additive)               */
   int tune_schedule;     /* 1 (default, with auto_depth 2): also time the schedules

@@ -1213,7 +1213,13 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
         throw ccg::Error(CCGMG_EINVAL, "coarsest level has too many unknowns; allow more levels");
       }
       upload_coarsest(X.get());
-      if (X->opt.tune_tiles) tune_tiles(X.get());
+      if (X->opt.sweep_tile_rows) {
+        const int ty = X->opt.sweep_tile_rows;
+        if (ty != 8 && ty != 16 && ty != 32) throw ccg::Error(CCGMG_EINVAL, "sweep_tile_rows must be 0, 8, 16 or 32");
+        for (DevLevel& L : X->lv) L.sweep_ty[0] = L.sweep_ty[1] = ty;
+      } else if (X->opt.tune_tiles) {
+        tune_tiles(X.get());
+      }
       if (X->opt.auto_depth == 2 && X->M > 1) {
         tune_schedule_depth(X.get(), nullptr);
       } else if (X->opt.auto_depth == 1 && X->M > 1) {
@@ -1613,14 +1619,12 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
         case 0: Dr.sweep<double>(L, L.u, L.r, L.v); break;
         case 1: Dr.restrict_<double>(L, *C, L.u, L.r, C->r, C->u); break;
         case 2: Dr.prolong<double>(L, *C, L.u, C->u); break;
-        case 3:
+        case 3:   // the compact copies alternate between launches; settled after the loop
           if (L.fwd.smo2.ns > 0) Dr.smo2_pass<double>(L, L.u, L.r, nullptr);
-          Dr.settle_rows(L);
           break;
         case 4: Dr.coarse<double>(L, L.u, L.r); break;
         case 7:
           Dr.fused_step<double>(L, L.u, L.r, L.v, nullptr);
-          Dr.settle_rows(L);
           break;
         case 6:
           hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(8192, (L.n + 255) / 256)), dim3(256), 0, X->stream, L.v,
@@ -1636,11 +1640,13 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
     HIP_OK(hipEventRecord(e0, X->stream));
     for (int k = 0; k < reps; ++k) launch();
     HIP_OK(hipEventRecord(e1, X->stream));
+    if (kernel == 3 || kernel == 7) Dr.settle_rows(L);
     HIP_OK(hipEventSynchronize(e1));
     float ms = 0;
     HIP_OK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    HIP_OK(hipStreamSynchronize(X->stream));
     *avg_us = 1e3 * ms / reps;
   });
 }

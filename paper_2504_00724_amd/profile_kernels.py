@@ -24,13 +24,16 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--kernels", default="sweep,copy")
+    ap.add_argument("--tile-rows", type=int, default=32,
+                    help="SMO-1 tile height (the benchmark's tuned choice on the finest level)")
     args = ap.parse_args()
     import torch  # noqa: F401  (HIP runtime and device selection)
 
     import workloads as W
     from paper_2504_00724_amd.ccgmg import Solver
     cfg = W.config(4, n=args.n)
-    S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], auto_depth=0)
+    S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], auto_depth=0,
+               sweep_tile_rows=args.tile_rows)
     out = {"n": args.n, "cells": args.n * args.n}
     for name in args.kernels.split(","):
         out[name + "_us"] = S.profile_kernel(KERNELS[name], 0, args.reps)

@@ -367,7 +367,10 @@ def main():
         dom_bytes = ALG_BYTES_SWEEP * cells
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     other = {name: S.profile_kernel(k, 0, 20) for name, k in (("sweep_us", 0), ("restrict_us", 1),
-                                                               ("prolong_us", 2), ("smo2_block_us", 3))}
+                                                               ("prolong_us", 2), ("smo2_block_us", 3),
+                                                               ("copy_us", 6))}
+    # measured bandwidth ceiling: a plain FP64 copy of one finest-level array
+    copy_gbs = 16.0 * cells / (other["copy_us"] * 1e-6) / 1e9
 
     # HBM bytes per launch of the same kernel from the committed counter runs
     # (FETCH_SIZE, WRITE_SIZE, copy-calibrated); null once the kernel sources
@@ -430,7 +433,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "%s (%s)" % (kname, kdesc), "avg_us": dom_us,
-                     "alg_bytes_per_launch": dom_bytes, "traffic_unit": "bytes per launch"},
+                     "alg_bytes_per_launch": dom_bytes, "traffic_unit": "bytes per launch",
+                     "copy_ceiling_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "kernels_us": other,
         "mixed_precision": mixed,
         "cpu_baseline": cpu,

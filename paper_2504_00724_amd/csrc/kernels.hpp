@@ -69,24 +69,32 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return start + k;
 }
 
-// (L u) at tile position (ly, lx) (already offset by HALO), difference form.
-template <typename T, bool CROSS>
-__device__ __forceinline__ T apply_regular(const T (*t)[LW], int ly, int lx, const CoefT<T>& c) {
-  const T uc = t[ly][lx];
+// (L u) at a cell from a value accessor at(dy, dx) (neighbour offsets in
+// -2..2), difference form.  The one arithmetic sequence shared by the LDS
+// tile form and the register-window form below.
+template <typename T, bool CROSS, typename At>
+__device__ __forceinline__ T regular_row(const At& at, const CoefT<T>& c) {
+  const T uc = at(0, 0);
   const T two = (T)2 * uc;
-  T acc = c.ax1 * ((t[ly][lx + 1] + t[ly][lx - 1]) - two) + c.ax2 * ((t[ly][lx + 2] + t[ly][lx - 2]) - two) +
-          c.cy1 * ((t[ly + 1][lx] + t[ly - 1][lx]) - two) + c.cy2 * ((t[ly + 2][lx] + t[ly - 2][lx]) - two);
+  T acc = c.ax1 * ((at(0, 1) + at(0, -1)) - two) + c.ax2 * ((at(0, 2) + at(0, -2)) - two) +
+          c.cy1 * ((at(1, 0) + at(-1, 0)) - two) + c.cy2 * ((at(2, 0) + at(-2, 0)) - two);
   if (CROSS) {
     // sum_{m1,m2} g(m1) g(m2) u, g(+-1) = +-8, g(+-2) = -+1, as nested differences
     T d[5];
 #pragma unroll
     for (int m = -2; m <= 2; ++m) {
       if (m == 0) continue;
-      d[m + 2] = (T)8 * (t[ly + 1][lx + m] - t[ly - 1][lx + m]) - (t[ly + 2][lx + m] - t[ly - 2][lx + m]);
+      d[m + 2] = (T)8 * (at(1, m) - at(-1, m)) - (at(2, m) - at(-2, m));
     }
     acc += c.bxy * ((T)8 * (d[3] - d[1]) - (d[4] - d[0]));
   }
   return acc;
+}
+
+// (L u) at tile position (ly, lx) (already offset by HALO), difference form.
+template <typename T, bool CROSS>
+__device__ __forceinline__ T apply_regular(const T (*t)[LW], int ly, int lx, const CoefT<T>& c) {
+  return regular_row<T, CROSS>([&](int dy, int dx) { return t[ly + dy][lx + dx]; }, c);
 }
 
 }  // namespace ccgk

@@ -44,12 +44,16 @@ __device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restr
   const int tyi = t / nbx;
   const int bx = (t - tyi * nbx) * TX, by = tyi * TYS;
   const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
+  // row of the k-th cell of this thread: interleaved over the 4 waves, or
+  // (cross-derivative stencil) RPW contiguous rows per wave, swept with a
+  // register window
+  auto row_of = [&](int k) { return CROSS ? w * RPW + k : w + 4 * k; };
   // issue the kind and right-hand-side loads before the tile barrier
   uint8_t kd[RPW];
   T rr[RPW];
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
-    const int gx = bx + tx, gy = by + w + 4 * k;
+    const int gx = bx + tx, gy = by + row_of(k);
     const bool in = gx < nx && gy < ny;
     kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
     rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
@@ -72,6 +76,31 @@ __device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restr
     load_tile<T, ROWS>(tile, u, nx, ny, bx, by);
   }
   __syncthreads();
+  if (CROSS) {
+    // the 5 x 5 neighbourhood of the current cell in registers: ring of 5
+    // tile rows (x-2..x+2); each new cell loads one new row (5 LDS reads
+    // instead of 25)
+    T win[5][5];
+    const int r0 = w * RPW;   // tile row of the wave's first cell (before HALO offset)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int dx = 0; dx < 5; ++dx) win[a][dx] = tile[r0 + a][tx + dx];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+#pragma unroll
+      for (int dx = 0; dx < 5; ++dx) win[(k + 4) % 5][dx] = tile[r0 + k + 4][tx + dx];
+      const int gx = bx + tx, gy = by + r0 + k;
+      if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
+        T v = win[(k + 2) % 5][2];
+        if (kd[k] & regbit)
+          v += c.omega_invD *
+               (rr[k] - regular_row<T, true>([&](int dy, int dx) { return win[(k + 2 + dy + 5) % 5][dx + 2]; }, c));
+        out[(size_t)gy * nx + gx] = v;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int ry = w + 4 * k;
@@ -375,9 +404,9 @@ __global__ __launch_bounds__(BLOCK) void k_apply(const double* __restrict__ u, c
 }
 
 // max over non-empty cells of |r - bterm - L u| (difference form), or of
-// |r - bterm| when zero_u is set, in one launch: workgroups [0, ntiles) take
-// the stencil cells of one TX x TY tile each (remapped by xcd_tile), the
-// rest BLOCK explicit rows each (FP64).  With res_out, the residual of every
+// |r - bterm| when zero_u is set, in one launch: the first workgroups take
+// BLOCK explicit rows each (FP64), the last ntiles the stencil cells of one
+// TX x TY tile each (remapped by xcd_tile).  With res_out, the residual of every
 // cell is also stored there as FP32 (0 on empty cells) for the refinement
 // loop: stencil cells by the tile workgroups, explicit rows by the row
 // workgroups, so no cell is written twice.  Every workgroup stores its
@@ -399,8 +428,11 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
   const size_t plane = (size_t)nx * ny;
   u += z * plane, r += z * plane;
   double m = 0.0;
-  if ((int)blockIdx.x < ntiles) {
-    const int t = xcd_tile(blockIdx.x, ntiles);
+  // the row workgroups (chains of dependent loads) come first in the grid so
+  // that their latency overlaps the streaming tiles
+  const int nrb = (int)gridDim.x - ntiles;
+  if ((int)blockIdx.x >= nrb) {
+    const int t = xcd_tile(blockIdx.x - nrb, ntiles);
     const int tyi = t / nbx;
     const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
     const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
@@ -428,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
       }
     }
   } else {
-    const int k = (blockIdx.x - ntiles) * BLOCK + threadIdx.x;
+    const int k = blockIdx.x * BLOCK + threadIdx.x;
     if (k < nrows) {
       const int q = cell[k];
       double rhs = (double)r[q];

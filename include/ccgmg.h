@@ -269,9 +269,16 @@ int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double
  * Section 4 (Alg. 2) for many independent problems. */
 typedef struct ccgmg_batch ccgmg_batch;
 
-/* nbranches: concurrent graph branches; geometries are placed largest
- * first (cells x right-hand sides) onto the least-loaded branch.  4 matches
- * the hardware queues a process gets by default. */
+/* nbranches >= 1: concurrent graph branches; geometries are placed largest
+ * first (cells x right-hand sides) onto the least-loaded branch (4 matches
+ * the hardware queues a process gets by default).
+ * nbranches == 0: lockstep -- every launch performs one V-cycle step for
+ * all geometries at once (a descriptor table per launch), converged
+ * geometries are masked by device flags.  Needs one precision for all
+ * contexts and at most 64 of them; sets every context's schedule to fused
+ * smoothing with nu = ctxs[0]'s tuned nu1 (if fused and symmetric, else 4)
+ * steps before and after on every level and piecewise-constant
+ * correction. */
 int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch** out);
 
 /* f[g], u[g]: device arrays of geometry g ([nrhs[g]][ny][nx], as in

@@ -805,9 +805,10 @@ void mp_cycle(Driver& Dr, double* u) {
 // Pieces of a solve shared by single and batched solves.  Residual norms are
 // per-workgroup partial maxima of level 0, read back into the pinned buffer
 // norm_host and reduced on the host.
-double norm_of(ccgmg_ctx* X, int nparts, int z) {
+double norm_of(ccgmg_ctx* X, int nparts, int z, const double* part = nullptr) {
+  const double* p = part ? part : X->norm_host;
   double m = 0.0;
-  for (int k = 0; k < nparts; ++k) m = std::max(m, X->norm_host[(size_t)z * nparts + k]);
+  for (int k = 0; k < nparts; ++k) m = std::max(m, p[(size_t)z * nparts + k]);
   return m;
 }
 
@@ -872,10 +873,10 @@ struct Monitor {
     }
   }
   // after a cycle; returns true when this solve is finished
-  bool step(ccgmg_ctx* X, ccgmg_report* rep) {
+  bool step(ccgmg_ctx* X, ccgmg_report* rep, const double* part = nullptr) {
     ++cycles;
     rel = 0;
-    for (size_t z = 0; z < rn.size(); ++z) rel = std::max(rel, norm_of(X, nparts, (int)z) / rn[z]);
+    for (size_t z = 0; z < rn.size(); ++z) rel = std::max(rel, norm_of(X, nparts, (int)z, part) / rn[z]);
     if (rep && hist < 64) rep->history[hist++] = rel;
     if (!std::isfinite(rel)) return stopped = true;
     if (rel <= X->opt.tol) return converged = stopped = true;
@@ -1065,6 +1066,17 @@ struct BatchGraph {
 
 struct ccgmg_batch {
   std::vector<ccgmg_ctx*> ctx;
+  // lockstep mode (nbranches == 0 at creation): one launch per V-cycle step
+  // for all geometries
+  bool lockstep = false;
+  int nu = 4;
+  int* active_d = nullptr;          // per geometry: 1 while it still cycles
+  int* active_h = nullptr;          // pinned copy
+  double* part_d = nullptr;         // residual-norm partials of all geometries
+  double* part_h = nullptr;         // pinned copy
+  size_t part_cap = 0;
+  std::vector<size_t> part_off;     // per geometry
+  std::vector<void*> desc_bufs;     // descriptor tables of captured cycles
   hipStream_t caller = nullptr, main = nullptr;
   std::vector<hipStream_t> br;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -1074,10 +1086,215 @@ struct ccgmg_batch {
   void clear_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     graphs.clear();
+    for (void* q : desc_bufs) (void)hipFree(q);
+    desc_bufs.clear();
   }
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Lockstep batch planner: walks one V-cycle of every geometry level by level
+// (down: nu fused steps, restriction, coarsest solves of the geometries whose
+// hierarchy ends there; up: nu fused steps, the first applying the coarse
+// correction) and emits one batched launch per step with a descriptor per
+// geometry taking part.
+// ---------------------------------------------------------------------------
+struct LRec {
+  int kind;                       // 0 fused, 1 restrict, 2 coarse, 3 coarse (many RHS), 4 norm, 5 aux
+  bool pro = false;
+  int mode = 0;                   // aux mode
+  BStarts st{};
+  size_t off = 0, bytes = 0;      // descriptor table in the blob
+  size_t smem = 0;
+  int total = 0;                  // workgroups
+  // many-RHS coarsest solve of one geometry
+  ccgmg_ctx* X = nullptr;
+  void* u = nullptr;
+  const void* r = nullptr;
+  int nr = 0;
+};
+
+struct Planner {
+  std::vector<LRec> recs;
+  std::vector<char> blob;
+  template <typename D>
+  void add(LRec rec, const std::vector<D>& ds, const std::vector<int>& wg) {
+    if (ds.empty()) return;
+    if ((int)ds.size() > BMAX) throw ccg::Error(CCGMG_EINVAL, "too many geometries in one batch");
+    rec.st.n = (int)ds.size();
+    rec.st.start[0] = 0;
+    for (size_t k = 0; k < ds.size(); ++k) rec.st.start[k + 1] = rec.st.start[k] + wg[k];
+    rec.total = rec.st.start[ds.size()];
+    if (rec.total == 0) return;
+    while (blob.size() % 64) blob.push_back(0);
+    rec.off = blob.size();
+    rec.bytes = sizeof(D) * ds.size();
+    blob.resize(blob.size() + rec.bytes);
+    std::memcpy(blob.data() + rec.off, ds.data(), rec.bytes);
+    recs.push_back(rec);
+  }
+};
+
+template <typename T>
+T* lvbuf(DevLevel& L, int which) {   // 0 u, 1 v, 2 r in the precision T
+  if constexpr (sizeof(T) == 8)
+    return which == 0 ? (T*)L.u : which == 1 ? (T*)L.v : (T*)L.r;
+  else
+    return which == 0 ? (T*)L.u32 : which == 1 ? (T*)L.v32 : (T*)L.r32;
+}
+
+Smo2Args lock_smo2_args(DevLevel& L, int cur, const double* bterm) {
+  Smo2Data& S = L.fwd.smo2;
+  Smo2Args a;
+  a.bterm = bterm;
+  a.ecell = S.ecell, a.ecols = S.ecols, a.ew = S.ew;
+  a.evals = S.evals, a.ersum = S.ersum;
+  a.eidx = S.ext_idx, a.ebt = S.ebt, a.ext_ptr = S.ext_ptr, a.own_cnt = S.own_cnt;
+  a.inv_off = S.inv_off, a.inv = S.inv;
+  a.c_in = S.cbuf[cur], a.c_out = S.cbuf[1 - cur];
+  a.ns = S.ns, a.nbt = L.fwd.n;
+  a.epar = S.epar, a.eqpar = S.eqpar;
+  return a;
+}
+
+constexpr int LOCK_TY = 16;   // SMO-1 tile height of batched fused steps
+
+// One V-cycle in precision T on level-0 arrays (u0, v0, r0, bterm0) of every
+// geometry; the result ends in u0 (an even number of steps per level).
+template <typename T>
+void plan_vcycle(ccgmg_batch* B, Planner& P, const std::vector<void*>& u0, const std::vector<void*>& v0,
+                 const std::vector<const void*>& r0, const std::vector<const double*>& bterm0,
+                 const std::vector<int>& planes) {
+  const int G = (int)B->ctx.size();
+  int Mmax = 0;
+  for (auto* X : B->ctx) Mmax = std::max(Mmax, X->M);
+  std::vector<std::vector<void*>> cur(G), oth(G);
+  std::vector<std::vector<const void*>> rr(G);
+  std::vector<std::vector<int>> cc(G);
+  for (int g = 0; g < G; ++g) {
+    ccgmg_ctx* X = B->ctx[g];
+    cur[g].resize(X->M + 1), oth[g].resize(X->M + 1), rr[g].resize(X->M + 1), cc[g].assign(X->M + 1, 0);
+    for (int m = 0; m <= X->M; ++m) {
+      cur[g][m] = m == 0 ? u0[g] : (void*)lvbuf<T>(X->lv[m], 0);
+      oth[g][m] = m == 0 ? v0[g] : (void*)lvbuf<T>(X->lv[m], 1);
+      rr[g][m] = m == 0 ? r0[g] : (const void*)lvbuf<T>(X->lv[m], 2);
+    }
+  }
+  auto fused = [&](int m, bool pro) {
+    std::vector<BFused> ds;
+    std::vector<int> wg;
+    for (int g = 0; g < G; ++g) {
+      ccgmg_ctx* X = B->ctx[g];
+      if (m >= X->M) continue;
+      DevLevel& L = X->lv[m];
+      BFused d{};
+      d.u = cur[g][m], d.r = rr[g][m], d.out = oth[g][m], d.kind = L.kind, d.c = L.coef;
+      d.plane = L.n;
+      d.nx = L.nx, d.ny = L.ny, d.nbx = tiles_x(L.nx), d.ntiles = d.nbx * ((L.ny + LOCK_TY - 1) / LOCK_TY);
+      d.nblk = L.fwd.smo2.nblk;
+      d.regbit = F_JAC, d.s2bit = F_S2, d.probit = F_REG;
+      d.geo = g;
+      d.a = lock_smo2_args(L, cc[g][m], m == 0 ? bterm0[g] : nullptr);
+      if (pro) {
+        DevLevel& C = X->lv[m + 1];
+        d.e = cur[g][m + 1], d.ncx = C.nx, d.ncy = C.ny, d.cplane = C.n;
+      }
+      ds.push_back(d);
+      wg.push_back((d.nblk + d.ntiles) * planes[g]);
+      std::swap(cur[g][m], oth[g][m]);
+      if (L.fwd.smo2.ns > 0) cc[g][m] ^= 1;
+    }
+    LRec rec{};
+    rec.kind = 0, rec.pro = pro;
+    P.add(rec, ds, wg);
+  };
+  for (int m = 0; m <= Mmax; ++m) {
+    for (int k = 0; k < B->nu; ++k) fused(m, false);
+    std::vector<BRestrict> rs;
+    std::vector<int> rw;
+    std::vector<BCoarse> cs;
+    std::vector<int> cw;
+    for (int g = 0; g < G; ++g) {
+      ccgmg_ctx* X = B->ctx[g];
+      if (m < X->M) {
+        DevLevel& L = X->lv[m];
+        DevLevel& C = X->lv[m + 1];
+        BRestrict d{};
+        d.u = cur[g][m], d.r = rr[g][m], d.kind = L.kind;
+        d.rc = lvbuf<T>(C, 2), d.uc = lvbuf<T>(C, 0), d.cc = C.fwd.smo2.cbuf[0];
+        d.c = L.coef, d.plane = L.n, d.cplane = C.n;
+        d.ncc = C.fwd.smo2.ns, d.nx = L.nx, d.ny = L.ny, d.nbx = tiles_x(L.nx), d.ncx = C.nx, d.ncy = C.ny;
+        d.ntiles = d.nbx * ((L.ny + TY - 1) / TY);
+        d.regbit = F_REG, d.geo = g;
+        rs.push_back(d);
+        rw.push_back(d.ntiles * planes[g]);
+        cc[g][m + 1] = 0;
+      } else if (m == X->M) {
+        if (planes[g] > 4) {
+          LRec rec{};
+          rec.kind = 3, rec.X = X, rec.u = cur[g][m], rec.r = rr[g][m], rec.nr = planes[g];
+          rec.total = 1;
+          P.recs.push_back(rec);
+        } else {
+          BCoarse d{};
+          d.u = cur[g][m], d.r = rr[g][m], d.cell = X->mcell, d.inv = X->minv, d.plane = X->lv[m].n;
+          d.nm = X->nm, d.nwg = (X->nm + 3) / 4, d.geo = g;
+          cs.push_back(d);
+          cw.push_back(d.nwg * planes[g]);
+        }
+      }
+    }
+    LRec r1{};
+    r1.kind = 1;
+    P.add(r1, rs, rw);
+    LRec r2{};
+    r2.kind = 2;
+    for (auto& d : cs) r2.smem = std::max(r2.smem, sizeof(double) * (size_t)d.nm);
+    P.add(r2, cs, cw);
+  }
+  for (int m = Mmax - 1; m >= 0; --m)
+    for (int k = 0; k < B->nu; ++k) fused(m, k == 0);
+}
+
+template <typename T, bool CROSS>
+void launch_recs(ccgmg_batch* B, const std::vector<LRec>& recs, const char* dblob, hipStream_t s) {
+  for (const LRec& r : recs) {
+    const void* d = dblob + r.off;
+    const dim3 g(r.total), b(BLOCK);
+    switch (r.kind) {
+      case 0:
+        if (r.pro)
+          hipLaunchKernelGGL((k_fused_batched<T, CROSS, true, LOCK_TY>), g, b, 0, s, (const BFused*)d, r.st,
+                             B->active_d);
+        else
+          hipLaunchKernelGGL((k_fused_batched<T, CROSS, false, LOCK_TY>), g, b, 0, s, (const BFused*)d, r.st,
+                             B->active_d);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_restrict_batched<T, CROSS>), g, b, 0, s, (const BRestrict*)d, r.st, B->active_d);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_coarse_batched<T>), g, b, r.smem, s, (const BCoarse*)d, r.st, B->active_d);
+        break;
+      case 3: {
+        ccgmg_ctx* X = r.X;
+        const int nm = X->nm;
+        hipLaunchKernelGGL((k_coarse_gather<T>), dim3((nm + 255) / 256, r.nr), dim3(256), 0, s, (const T*)r.r,
+                           X->mcell, X->mrg, nm, r.nr, X->lv[X->M].n);
+        hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CR - 1) / CR, (r.nr + CZ - 1) / CZ), b, 0, s, (T*)r.u,
+                           X->mrg, X->mcell, X->minv, nm, r.nr, X->lv[X->M].n);
+        break;
+      }
+      case 4:
+        hipLaunchKernelGGL((k_resnorm_batched<CROSS>), g, b, 0, s, (const BNorm*)d, r.st, B->active_d);
+        break;
+      default:
+        hipLaunchKernelGGL(k_aux_batched, g, b, 0, s, (const BAux*)d, r.st, B->active_d, r.mode);
+        break;
+    }
+  }
+}
 
 int batch_guard(ccgmg_batch* B, const std::function<void()>& body) {
   if (!B) return CCGMG_EINVAL;
@@ -1091,6 +1308,174 @@ int batch_guard(ccgmg_batch* B, const std::function<void()>& body) {
     return CCGMG_EINVAL;
   }
   return CCGMG_OK;
+}
+
+// Lockstep batch solve (see ccgmg_batch_create with nbranches == 0).
+void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, const int* nrhs,
+                    ccgmg_report* reps) {
+  const int n = (int)B->ctx.size();
+  const bool mp = B->ctx[0]->opt.precision == 1;
+  bool cross = false;
+  for (auto* X : B->ctx) cross = cross || X->b != 0.0;
+  HIP_OK(hipEventRecord(B->ev_in, B->caller));
+  HIP_OK(hipStreamWaitEvent(B->main, B->ev_in, 0));
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  HIP_OK(hipEventRecord(e0, B->main));
+  std::vector<const double*> bterm(n);
+  for (int g = 0; g < n; ++g) {
+    Driver Dr{B->ctx[g], B->main, nrhs[g], false};
+    bterm[g] = solve_prologue(Dr, f[g], u[g]);
+  }
+  // residual-norm partials of all geometries in one buffer
+  std::vector<int> nparts(n);
+  B->part_off.assign(n, 0);
+  size_t total = 0;
+  for (int g = 0; g < n; ++g) {
+    DevLevel& L0 = B->ctx[g]->lv[0];
+    nparts[g] = (L0.fwd.n + BLOCK - 1) / BLOCK + tiles_x(L0.nx) * ((L0.ny + TY - 1) / TY);
+    B->part_off[g] = total;
+    total += (size_t)nparts[g] * nrhs[g];
+  }
+  if (total > B->part_cap) {
+    B->clear_graphs();
+    if (B->part_d) (void)hipFree(B->part_d);
+    if (B->part_h) (void)hipHostFree(B->part_h);
+    B->part_d = nullptr, B->part_h = nullptr, B->part_cap = 0;
+    HIP_OK(hipMalloc((void**)&B->part_d, sizeof(double) * total));
+    HIP_OK(hipHostMalloc((void**)&B->part_h, sizeof(double) * total, hipHostMallocDefault));
+    B->part_cap = total;
+  }
+  HIP_OK(hipStreamSynchronize(B->main));
+  std::vector<Monitor> mon(n);
+  for (int g = 0; g < n; ++g) mon[g].start(B->ctx[g], nrhs[g], nparts[g]);
+  std::vector<const void*> key;
+  for (int g = 0; g < n; ++g) {
+    key.push_back(f[g]);
+    key.push_back(u[g]);
+    key.push_back((const void*)(intptr_t)nrhs[g]);
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto& gr : B->graphs)
+    if (gr.key == key) exec = gr.exec;
+  if (!exec) {
+    Planner P;
+    std::vector<int> planes(nrhs, nrhs + n);
+    if (mp) {
+      std::vector<BAux> zs;
+      std::vector<int> zw;
+      for (int g = 0; g < n; ++g) {
+        DevLevel& L0 = B->ctx[g]->lv[0];
+        BAux a{};
+        a.u32 = L0.u32, a.cc = L0.fwd.smo2.cbuf[0], a.n = L0.n * nrhs[g], a.ncc = (size_t)L0.fwd.smo2.ns * nrhs[g];
+        a.plane = L0.n, a.geo = g;
+        zs.push_back(a);
+        zw.push_back(BAUX_WG);
+      }
+      LRec r0{};
+      r0.kind = 5, r0.mode = 0;
+      P.add(r0, zs, zw);
+      std::vector<void*> u0(n), v0(n);
+      std::vector<const void*> rr(n);
+      std::vector<const double*> bt(n, nullptr);
+      for (int g = 0; g < n; ++g) {
+        DevLevel& L0 = B->ctx[g]->lv[0];
+        u0[g] = L0.u32, v0[g] = L0.v32, rr[g] = L0.r32;
+      }
+      plan_vcycle<float>(B, P, u0, v0, rr, bt, planes);
+      std::vector<BAux> as;
+      for (int g = 0; g < n; ++g) {
+        BAux a = zs[g];
+        a.u = u[g], a.kind = B->ctx[g]->lv[0].kind;
+        as.push_back(a);
+      }
+      LRec r1{};
+      r1.kind = 5, r1.mode = 1;
+      P.add(r1, as, zw);
+    } else {
+      std::vector<void*> u0(n), v0(n);
+      std::vector<const void*> rr(n);
+      for (int g = 0; g < n; ++g) u0[g] = u[g], v0[g] = B->ctx[g]->lv[0].v, rr[g] = f[g];
+      plan_vcycle<double>(B, P, u0, v0, rr, bterm, planes);
+    }
+    std::vector<BNorm> ns;
+    std::vector<int> nw;
+    for (int g = 0; g < n; ++g) {
+      DevLevel& L0 = B->ctx[g]->lv[0];
+      BNorm d{};
+      d.u = u[g], d.r = f[g], d.kind = L0.kind, d.c = L0.coef, d.plane = L0.n;
+      d.nx = L0.nx, d.ny = L0.ny, d.nbx = tiles_x(L0.nx), d.ntiles = d.nbx * ((L0.ny + TY - 1) / TY);
+      d.nrb = (L0.fwd.n + BLOCK - 1) / BLOCK;
+      d.bterm = bterm[g];
+      d.cell = L0.fwd.cell, d.rp = L0.fwd.rp, d.cols = L0.fwd.cols, d.vals = L0.fwd.vals, d.rowsum = L0.fwd.rowsum;
+      d.nrows = L0.fwd.n, d.res_out = mp ? L0.r32 : nullptr, d.partial = B->part_d + B->part_off[g];
+      d.regbit = F_REG, d.geo = g;
+      ns.push_back(d);
+      nw.push_back(nparts[g] * nrhs[g]);
+    }
+    LRec rn{};
+    rn.kind = 4;
+    P.add(rn, ns, nw);
+    void* dblob = nullptr;
+    HIP_OK(hipMalloc(&dblob, std::max<size_t>(P.blob.size(), 64)));
+    B->desc_bufs.push_back(dblob);
+    HIP_OK(hipMemcpy(dblob, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice));
+    hipGraph_t graph;
+    HIP_OK(hipStreamBeginCapture(B->main, hipStreamCaptureModeThreadLocal));
+    if (mp) {
+      if (cross)
+        launch_recs<float, true>(B, P.recs, (const char*)dblob, B->main);
+      else
+        launch_recs<float, false>(B, P.recs, (const char*)dblob, B->main);
+    } else {
+      if (cross)
+        launch_recs<double, true>(B, P.recs, (const char*)dblob, B->main);
+      else
+        launch_recs<double, false>(B, P.recs, (const char*)dblob, B->main);
+    }
+    HIP_OK(hipMemcpyAsync(B->part_h, B->part_d, sizeof(double) * total, hipMemcpyDeviceToHost, B->main));
+    HIP_OK(hipStreamEndCapture(B->main, &graph));
+    HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    B->graphs.push_back({key, exec});
+  }
+  for (int g = 0; g < n; ++g) B->active_h[g] = 1;
+  HIP_OK(hipMemcpyAsync(B->active_d, B->active_h, sizeof(int) * n, hipMemcpyHostToDevice, B->main));
+  if (reps) std::memset(reps, 0, sizeof(ccgmg_report) * n);
+  for (;;) {
+    HIP_OK(hipGraphLaunch(exec, B->main));
+    HIP_OK(hipStreamSynchronize(B->main));
+    bool all = true, changed = false;
+    for (int g = 0; g < n; ++g) {
+      if (!mon[g].stopped && mon[g].step(B->ctx[g], reps ? &reps[g] : nullptr, B->part_h + B->part_off[g])) {
+        B->active_h[g] = 0;
+        changed = true;
+      }
+      all = all && mon[g].stopped;
+    }
+    if (all) break;
+    if (changed) HIP_OK(hipMemcpyAsync(B->active_d, B->active_h, sizeof(int) * n, hipMemcpyHostToDevice, B->main));
+  }
+  HIP_OK(hipEventRecord(e1, B->main));
+  HIP_OK(hipEventRecord(B->ev_out, B->main));
+  HIP_OK(hipStreamWaitEvent(B->caller, B->ev_out, 0));
+  HIP_OK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  bool ok = true;
+  for (int g = 0; g < n; ++g) {
+    if (reps) {
+      reps[g].cycles = mon[g].cycles;
+      reps[g].outer_iters = mp ? mon[g].cycles : 0;
+      reps[g].rel_res_inf = mon[g].rel;
+      reps[g].seconds = ms * 1e-3;
+    }
+    ok = ok && mon[g].converged;
+  }
+  if (!ok) throw ccg::Error(CCGMG_ENOCONV, "tolerance not reached for every geometry");
 }
 
 }  // namespace
@@ -1417,7 +1802,8 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
   g_create_error.clear();
   std::unique_ptr<ccgmg_batch> B(new ccgmg_batch());
   try {
-    if (!ctxs || n < 1 || nbranches < 1) throw ccg::Error(CCGMG_EINVAL, "invalid batch arguments");
+    if (!ctxs || n < 1 || nbranches < 0) throw ccg::Error(CCGMG_EINVAL, "invalid batch arguments");
+    if (nbranches == 0 && n > BMAX) throw ccg::Error(CCGMG_EINVAL, "too many geometries for a lockstep batch");
     for (int g = 0; g < n; ++g) {
       if (!ctxs[g] || ctxs[g]->host_only) throw ccg::Error(CCGMG_EINVAL, "batch needs device contexts");
       for (int k = 0; k < g; ++k)
@@ -1426,7 +1812,23 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
     B->ctx.assign(ctxs, ctxs + n);
     B->caller = ctxs[0]->stream;
     HIP_OK(hipStreamCreateWithFlags(&B->main, hipStreamNonBlocking));
-    const int nb = std::min(n, nbranches);
+    if (nbranches == 0) {
+      // lockstep: one schedule for all (fused smoothing, nu steps before and
+      // after on every level, piecewise-constant correction) and one precision
+      B->lockstep = true;
+      const ccgmg_options& o0 = ctxs[0]->opt;
+      B->nu = (o0.smoother_fused && o0.nu1 == o0.nu2 && o0.nu1 > 0) ? o0.nu1 : 4;
+      for (int g = 0; g < n; ++g) {
+        ccgmg_ctx* X = ctxs[g];
+        if (X->opt.precision != o0.precision) throw ccg::Error(CCGMG_EINVAL, "lockstep batch needs one precision");
+        X->opt.smoother_fused = 1, X->opt.nu1 = X->opt.nu2 = B->nu;
+        X->opt.nu1_coarse = X->opt.nu2_coarse = 0, X->opt.prolongation = 0;
+        X->clear_graphs();
+      }
+      HIP_OK(hipMalloc((void**)&B->active_d, sizeof(int) * n));
+      HIP_OK(hipHostMalloc((void**)&B->active_h, sizeof(int) * n, hipHostMallocDefault));
+    }
+    const int nb = std::min(n, std::max(1, nbranches));
     B->br.resize(nb);
     for (auto& st : B->br) HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
@@ -1450,6 +1852,10 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
     for (int g = 0; g < n; ++g)
       if (!f[g] || !u[g] || nrhs[g] < 1 || nrhs[g] > B->ctx[g]->opt.max_nrhs)
         throw ccg::Error(CCGMG_EINVAL, "bad solve arguments for geometry " + std::to_string(g));
+    if (B->lockstep) {
+      lockstep_solve(B, f, u, nrhs, reps);
+      return;
+    }
     HIP_OK(hipEventRecord(B->ev_in, B->caller));
     HIP_OK(hipStreamWaitEvent(B->main, B->ev_in, 0));
     hipEvent_t e0, e1;
@@ -1577,6 +1983,10 @@ void ccgmg_batch_destroy(ccgmg_batch* B) {
   if (!B) return;
   if (B->main) (void)hipStreamSynchronize(B->main);
   B->clear_graphs();
+  if (B->active_d) (void)hipFree(B->active_d);
+  if (B->active_h) (void)hipHostFree(B->active_h);
+  if (B->part_d) (void)hipFree(B->part_d);
+  if (B->part_h) (void)hipHostFree(B->part_h);
   for (auto st : B->br)
     if (st) (void)hipStreamDestroy(st);
   if (B->main) (void)hipStreamDestroy(B->main);

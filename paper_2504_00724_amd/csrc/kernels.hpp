@@ -35,7 +35,7 @@ template <typename T>
 struct CoefT {
   T ax1, ax2, cy1, cy2, bxy, omega_invD;
   __host__ __device__ CoefT() {}
-  __host__ CoefT(const Coef& c)
+  __host__ __device__ CoefT(const Coef& c)
       : ax1((T)c.ax1), ax2((T)c.ax2), cy1((T)c.cy1), cy2((T)c.cy2), bxy((T)c.bxy), omega_invD((T)c.omega_invD) {}
 };
 

@@ -130,21 +130,19 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const 
 // rc_I = 1/4 sum over regular children c of (r - L u)_c  (Section 4.1).
 // The same launch zeroes the coarse iterate uc (the recursion starts from a
 // zero guess, Alg. 2) and the compact copy cc of its block rows.
-template <typename T, typename TC, bool CROSS, bool FINEST>
-__global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, const T* __restrict__ r,
-                                                    const uint8_t* __restrict__ kind, TC* __restrict__ rc,
-                                                    TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx,
-                                                    int ny, int nbx, int ncx, int ncy, CoefT<T> c, uint8_t regbit) {
+// One tile t of one plane (pointers already offset to the plane); l is the
+// workgroup's index within the plane, which zeroes entries [l * BLOCK,
+// (l + 1) * BLOCK) of the plane's compact copy cc.
+template <typename T, typename TC, bool CROSS>
+__device__ __forceinline__ void restrict_tile(int t, int l, const T* __restrict__ u, const T* __restrict__ r,
+                                              const uint8_t* __restrict__ kind, TC* __restrict__ rc,
+                                              TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx, int ny,
+                                              int nbx, int ncx, int ncy, const CoefT<T>& c, uint8_t regbit) {
   __shared__ T tile[LH][LW];
-  const size_t zoff = (size_t)blockIdx.z * nx * ny;
-  u += zoff, r += zoff;
-  rc += (size_t)blockIdx.z * ncx * ncy;
-  uc += (size_t)blockIdx.z * ncx * ncy;
   {
-    const int flat = blockIdx.x * BLOCK + threadIdx.x;
-    if (flat < ncc) cc[(size_t)blockIdx.z * ncc + flat] = 0.0;
+    const int flat = l * BLOCK + threadIdx.x;
+    if (flat < ncc) cc[flat] = 0.0;
   }
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int tyi = t / nbx, txi = t - tyi * nbx;
   const int bx = txi * TX, by = tyi * TY;
   const int cx = threadIdx.x & 31, cy = threadIdx.x >> 5;  // 32 x 8 coarse cells
@@ -168,6 +166,17 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, con
       s += rr[d] - apply_regular<T, CROSS>(tile, 2 * cy + (d >> 1) + HALO, 2 * cx + (d & 1) + HALO, c);
   rc[(size_t)J * ncx + I] = (TC)((T)0.25 * s);
   uc[(size_t)J * ncx + I] = (TC)0;
+}
+
+template <typename T, typename TC, bool CROSS, bool FINEST>
+__global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, const T* __restrict__ r,
+                                                    const uint8_t* __restrict__ kind, TC* __restrict__ rc,
+                                                    TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx,
+                                                    int ny, int nbx, int ncx, int ncy, CoefT<T> c, uint8_t regbit) {
+  const size_t z = blockIdx.z;
+  restrict_tile<T, TC, CROSS>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, u + z * nx * ny, r + z * nx * ny, kind,
+                              rc + z * ncx * ncy, uc + z * ncx * ncy, cc + z * ncc, ncc, nx, ny, nbx, ncx, ncy, c,
+                              regbit);
 }
 
 // Correction u_c += P e on regular fine cells: piecewise constant
@@ -413,26 +422,23 @@ __global__ __launch_bounds__(BLOCK) void k_apply(const double* __restrict__ u, c
 // partial maximum in partial[z * gridDim.x + b]; the host, which reads the
 // norm back anyway, takes the maximum of the partials (no second launch and
 // no device-wide fence).
+// Workgroup l of one plane (pointers offset to the plane; bterm and res_out
+// too): workgroups [0, nrb) take BLOCK explicit rows each, the others one
+// tile (remapped by xcd_tile over ntiles).  Returns the workgroup's maximum
+// (valid in thread 0).
 template <typename T, bool CROSS>
-__global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, const T* __restrict__ r,
-                                                   const uint8_t* __restrict__ kind, int nx, int ny, int nbx,
-                                                   int ntiles, CoefT<T> c, int zero_u, uint8_t regbit,
-                                                   const double* __restrict__ bterm, const int32_t* __restrict__ cell,
-                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
-                                                   const double* __restrict__ vals,
-                                                   const double* __restrict__ rowsum, int nrows,
-                                                   float* __restrict__ res_out, double* __restrict__ partial) {
+__device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, const T* __restrict__ u,
+                                                const T* __restrict__ r, const uint8_t* __restrict__ kind, int nx,
+                                                int ny, int nbx, const CoefT<T>& c, int zero_u, uint8_t regbit,
+                                                const double* __restrict__ bterm, const int32_t* __restrict__ cell,
+                                                const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                const double* __restrict__ vals, const double* __restrict__ rowsum,
+                                                int nrows, float* __restrict__ res_out) {
   __shared__ T tile[LH][LW];
   __shared__ double red[BLOCK];
-  const int z = blockIdx.z;
-  const size_t plane = (size_t)nx * ny;
-  u += z * plane, r += z * plane;
   double m = 0.0;
-  // the row workgroups (chains of dependent loads) come first in the grid so
-  // that their latency overlaps the streaming tiles
-  const int nrb = (int)gridDim.x - ntiles;
-  if ((int)blockIdx.x >= nrb) {
-    const int t = xcd_tile(blockIdx.x - nrb, ntiles);
+  if (l >= nrb) {
+    const int t = xcd_tile(l - nrb, ntiles);
     const int tyi = t / nbx;
     const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
     const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
@@ -454,19 +460,19 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
         T v = rr[k];
         if (!zero_u) v -= apply_regular<T, CROSS>(tile, w + 4 * k + HALO, tx + HALO, c);
         m = fmax(m, fabs((double)v));
-        if (res_out) res_out[z * plane + (size_t)gy * nx + gx] = (float)v;
+        if (res_out) res_out[(size_t)gy * nx + gx] = (float)v;
       } else if (res_out && gx < nx && gy < ny && !(kd[k] & F_NONEMPTY)) {
-        res_out[z * plane + (size_t)gy * nx + gx] = 0.0f;   // explicit rows: written by the row workgroups
+        res_out[(size_t)gy * nx + gx] = 0.0f;   // explicit rows: written by the row workgroups
       }
     }
   } else {
-    const int k = blockIdx.x * BLOCK + threadIdx.x;
+    const int k = l * BLOCK + threadIdx.x;
     if (k < nrows) {
       const int q = cell[k];
       double rhs = (double)r[q];
-      if (bterm) rhs -= bterm[(size_t)z * nrows + k];
+      if (bterm) rhs -= bterm[k];
       if (!zero_u) rhs = row_residual(u, rhs, q, cols + rp[k], vals + rp[k], rp[k + 1] - rp[k], rowsum[k]);
-      if (res_out) res_out[z * plane + q] = (float)rhs;
+      if (res_out) res_out[q] = (float)rhs;
       m = fabs(rhs);
     }
   }
@@ -476,22 +482,38 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
     if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = red[0];
+  return red[0];
+}
+
+template <typename T, bool CROSS>
+__global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, const T* __restrict__ r,
+                                                   const uint8_t* __restrict__ kind, int nx, int ny, int nbx,
+                                                   int ntiles, CoefT<T> c, int zero_u, uint8_t regbit,
+                                                   const double* __restrict__ bterm, const int32_t* __restrict__ cell,
+                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                   const double* __restrict__ vals,
+                                                   const double* __restrict__ rowsum, int nrows,
+                                                   float* __restrict__ res_out, double* __restrict__ partial) {
+  const int z = blockIdx.z;
+  const size_t plane = (size_t)nx * ny;
+  // the row workgroups (chains of dependent loads) come first in the grid so
+  // that their latency overlaps the streaming tiles
+  const double m = resnorm_block<T, CROSS>(blockIdx.x, (int)gridDim.x - ntiles, ntiles, u + z * plane,
+                                           r + z * plane, kind, nx, ny, nbx, c, zero_u, regbit,
+                                           bterm ? bterm + (size_t)z * nrows : nullptr, cell, rp, cols, vals, rowsum,
+                                           nrows, res_out ? res_out + z * plane : nullptr);
+  if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = m;
 }
 
 // Coarsest level: u[cell_k] = sum_j Inv[k, j] r[cell_j] (FP64), one wavefront
 // per row (4 rows per workgroup), the gathered right-hand side staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
-                                                  const int32_t* __restrict__ cell, const double* __restrict__ inv,
-                                                  int nm, size_t plane) {
-  extern __shared__ double rv[];
-  const int z = blockIdx.y;
-  u += (size_t)z * plane, r += (size_t)z * plane;
+__device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ u, const T* __restrict__ r,
+                                            const int32_t* __restrict__ cell, const double* __restrict__ inv, int nm) {
   for (int k = threadIdx.x; k < nm; k += BLOCK) rv[k] = (double)r[cell[k]];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row = wg * 4 + (threadIdx.x >> 6);
   if (row >= nm) return;
   const double* A = inv + (size_t)row * nm;
   double s0 = 0.0, s1 = 0.0;
@@ -501,6 +523,15 @@ __global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __
   double s = s0 + s1;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) u[cell[row]] = (T)s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
+                                                  const int32_t* __restrict__ cell, const double* __restrict__ inv,
+                                                  int nm, size_t plane) {
+  extern __shared__ double rv[];
+  const size_t z = blockIdx.y;
+  coarse_rows<T>(rv, blockIdx.x, u + z * plane, r + z * plane, cell, inv, nm);
 }
 
 // Coarsest level with several right-hand sides, step 1: gather the
@@ -698,4 +729,172 @@ __global__ void k_axpy_f32(double* __restrict__ u, const float* __restrict__ e, 
 __global__ void k_mask_empty(double* __restrict__ u, const uint8_t* __restrict__ kind, size_t plane, size_t n) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
     if (!(kind[k % plane] & F_NONEMPTY)) u[k] = 0.0;
+}
+
+// ===========================================================================
+// Lockstep batches: one launch performs one V-cycle step for every geometry
+// of a batch.  Each launch has a table of per-geometry descriptors in device
+// memory; geometry d owns workgroups [st.start[d], st.start[d + 1]) of the
+// 1-D grid (the prefix offsets travel in the kernel arguments, so finding
+// the descriptor costs no memory access).  A geometry whose flag in `active`
+// is 0 has converged: its workgroups return at once.
+// ===========================================================================
+constexpr int BMAX = 64;   // geometries per batched launch
+struct BStarts {
+  int n;
+  int start[BMAX + 1];
+};
+
+__device__ __forceinline__ int bfind(const BStarts& st, int b) {
+  int d = 0;
+  while (d + 1 < st.n && b >= st.start[d + 1]) ++d;
+  return d;
+}
+
+struct BFused {                    // fused smoothing step of one geometry on one level
+  const void *u, *r;
+  void* out;
+  const uint8_t* kind;
+  Coef c;
+  size_t plane, cplane;            // cells of a plane on this level / on the coarser level
+  int nx, ny, nbx, ntiles, nblk;   // workgroups per plane: nblk + ntiles
+  int ncx, ncy;
+  const void* e;                   // pending coarse correction (PRO)
+  uint8_t regbit, s2bit, probit;
+  int geo;
+  Smo2Args a;
+};
+
+template <typename T, bool CROSS, bool PRO, int TYS>
+__global__ __launch_bounds__(BLOCK) void k_fused_batched(const BFused* __restrict__ descs, BStarts st,
+                                                         const int* __restrict__ active) {
+  constexpr int NS = sweep_lds_doubles<T, TYS>();
+  __shared__ double smem[NS > SMO2_LDS_DOUBLES ? NS : SMO2_LDS_DOUBLES];
+  const int di = bfind(st, blockIdx.x);
+  const BFused& d = descs[di];
+  if (!active[d.geo]) return;
+  const int local = blockIdx.x - st.start[di];
+  const int per = d.nblk + d.ntiles;
+  const int z = local / per, l = local - z * per;
+  const T* u = (const T*)d.u + z * d.plane;
+  const T* r = (const T*)d.r + z * d.plane;
+  T* out = (T*)d.out + z * d.plane;
+  const T* e = PRO ? (const T*)d.e + z * d.cplane : nullptr;
+  if (l < d.nblk) {
+    smo2_block<T, PRO>(smem, l, z, u, out, r, d.a, e);
+  } else {
+    const CoefT<T> c(d.c);
+    sweep_tile<T, CROSS, TYS, PRO>(smem, xcd_tile(l - d.nblk, d.ntiles), u, r, d.kind, out, d.nx, d.ny, d.nbx, c,
+                                   d.regbit, d.s2bit, e, d.ncx, d.probit);
+  }
+}
+
+struct BRestrict {                 // residual + restriction of one geometry from one level
+  const void *u, *r;
+  const uint8_t* kind;
+  void *rc, *uc;
+  double* cc;
+  Coef c;
+  size_t plane, cplane;
+  int ncc, nx, ny, nbx, ncx, ncy, ntiles;
+  uint8_t regbit;
+  int geo;
+};
+
+template <typename T, bool CROSS>
+__global__ __launch_bounds__(BLOCK) void k_restrict_batched(const BRestrict* __restrict__ descs, BStarts st,
+                                                            const int* __restrict__ active) {
+  const int di = bfind(st, blockIdx.x);
+  const BRestrict& d = descs[di];
+  if (!active[d.geo]) return;
+  const int local = blockIdx.x - st.start[di];
+  const int z = local / d.ntiles, l = local - z * d.ntiles;
+  const CoefT<T> c(d.c);
+  restrict_tile<T, T, CROSS>(xcd_tile(l, d.ntiles), l, (const T*)d.u + z * d.plane, (const T*)d.r + z * d.plane,
+                             d.kind, (T*)d.rc + z * d.cplane, (T*)d.uc + z * d.cplane, d.cc + (size_t)z * d.ncc,
+                             d.ncc, d.nx, d.ny, d.nbx, d.ncx, d.ncy, c, d.regbit);
+}
+
+struct BCoarse {                   // coarsest solve (dense inverse) of one geometry
+  void* u;
+  const void* r;
+  const int32_t* cell;
+  const double* inv;
+  size_t plane;
+  int nm, nwg;                     // workgroups per plane
+  int geo;
+};
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_coarse_batched(const BCoarse* __restrict__ descs, BStarts st,
+                                                          const int* __restrict__ active) {
+  extern __shared__ double rv[];
+  const int di = bfind(st, blockIdx.x);
+  const BCoarse& d = descs[di];
+  if (!active[d.geo]) return;
+  const int local = blockIdx.x - st.start[di];
+  const int z = local / d.nwg, l = local - z * d.nwg;
+  coarse_rows<T>(rv, l, (T*)d.u + z * d.plane, (const T*)d.r + z * d.plane, d.cell, d.inv, d.nm);
+}
+
+struct BNorm {                     // residual check of one geometry (level 0, FP64)
+  const double *u, *r;
+  const uint8_t* kind;
+  Coef c;
+  size_t plane;
+  int nx, ny, nbx, ntiles, nrb;    // workgroups per plane: nrb + ntiles
+  const double* bterm;
+  const int32_t *cell, *rp, *cols;
+  const double *vals, *rowsum;
+  int nrows;
+  float* res_out;
+  double* partial;                 // [plane][nrb + ntiles]
+  uint8_t regbit;
+  int geo;
+};
+
+template <bool CROSS>
+__global__ __launch_bounds__(BLOCK) void k_resnorm_batched(const BNorm* __restrict__ descs, BStarts st,
+                                                           const int* __restrict__ active) {
+  const int di = bfind(st, blockIdx.x);
+  const BNorm& d = descs[di];
+  if (!active[d.geo]) return;
+  const int local = blockIdx.x - st.start[di];
+  const int per = d.nrb + d.ntiles;
+  const int z = local / per, l = local - z * per;
+  const CoefT<double> c(d.c);
+  const double m = resnorm_block<double, CROSS>(l, d.nrb, d.ntiles, d.u + z * d.plane, d.r + z * d.plane, d.kind,
+                                                d.nx, d.ny, d.nbx, c, 0, d.regbit,
+                                                d.bterm ? d.bterm + (size_t)z * d.nrows : nullptr, d.cell, d.rp,
+                                                d.cols, d.vals, d.rowsum, d.nrows,
+                                                d.res_out ? d.res_out + z * d.plane : nullptr);
+  if (threadIdx.x == 0) d.partial[local] = m;
+}
+
+struct BAux {                      // mixed precision, level 0: zero start / correction
+  float* u32;                      // zeroed (start) or read (u += u32)
+  double* cc;                      // compact copies zeroed at the start
+  double* u;                       // FP64 iterate
+  const uint8_t* kind;
+  size_t plane, n, ncc;            // n = plane * planes
+  int geo;
+};
+
+// mode 0: u32 = 0 and cc = 0 (zero guess of the correction); mode 1:
+// u += u32 on non-empty cells.  BAUX_WG workgroups per geometry.
+constexpr int BAUX_WG = 256;
+__global__ __launch_bounds__(BLOCK) void k_aux_batched(const BAux* __restrict__ descs, BStarts st,
+                                                       const int* __restrict__ active, int mode) {
+  const int di = bfind(st, blockIdx.x);
+  const BAux& d = descs[di];
+  if (!active[d.geo]) return;
+  const size_t l = blockIdx.x - st.start[di];
+  const size_t stride = (size_t)BAUX_WG * BLOCK;
+  if (mode == 0) {
+    for (size_t k = l * BLOCK + threadIdx.x; k < d.n; k += stride) d.u32[k] = 0.0f;
+    for (size_t k = l * BLOCK + threadIdx.x; k < d.ncc; k += stride) d.cc[k] = 0.0;
+  } else {
+    for (size_t k = l * BLOCK + threadIdx.x; k < d.n; k += stride)
+      if (d.kind[k % d.plane] & F_NONEMPTY) d.u[k] += (double)d.u32[k];
+  }
 }

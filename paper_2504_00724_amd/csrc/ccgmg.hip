@@ -544,7 +544,7 @@ struct Driver {
     // several right-hand sides: gather, then one product reading the inverse once
     hipLaunchKernelGGL((k_coarse_gather<T>), dim3((nm + 255) / 256, nrhs), dim3(256), 0, s, r, X->mcell, X->mrg,
                        nm, nrhs, L.n);
-    hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CR - 1) / CR, (nrhs + CZ - 1) / CZ), dim3(BLOCK), 0, s, u,
+    hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CM_ROWS - 1) / CM_ROWS, (nrhs + CM_RHS - 1) / CM_RHS), dim3(64 * CMW), 0, s, u,
                        X->mrg, X->mcell, inv, nm, nrhs, L.n);
   }
 
@@ -1282,7 +1282,7 @@ void launch_recs(ccgmg_batch* B, const std::vector<LRec>& recs, const char* dblo
         const int nm = X->nm;
         hipLaunchKernelGGL((k_coarse_gather<T>), dim3((nm + 255) / 256, r.nr), dim3(256), 0, s, (const T*)r.r,
                            X->mcell, X->mrg, nm, r.nr, X->lv[X->M].n);
-        hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CR - 1) / CR, (r.nr + CZ - 1) / CZ), b, 0, s, (T*)r.u,
+        hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CM_ROWS - 1) / CM_ROWS, (r.nr + CM_RHS - 1) / CM_RHS), dim3(64 * CMW), 0, s, (T*)r.u,
                            X->mrg, X->mcell, X->minv, nm, r.nr, X->lv[X->M].n);
         break;
       }

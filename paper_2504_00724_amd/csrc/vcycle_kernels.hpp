@@ -546,47 +546,65 @@ __global__ void k_coarse_gather(const T* __restrict__ r, const int32_t* __restri
   rg[(size_t)k * nrhs + z] = (double)r[z * plane + cell[k]];
 }
 
-// Step 2: U = Inv * Rg as a register-tiled FP64 product that reads the
-// inverse once for all right-hand sides.  Workgroup = CR rows x CZ
-// right-hand sides; thread = 1 row x 4 right-hand sides; the inverse and Rg
-// are staged through LDS in chunks of CK columns.
-constexpr int CR = 16, CZ = 64, CK = 64;
+// Step 2: U = Inv * Rg on the matrix cores (FP64 16x16x4 products).
+// Workgroup = 16 rows x 64 right-hand sides and CMW waves; wave w takes the
+// w-th slice of the k range (a multiple of 16 long) and keeps 4 16x16 tiles
+// of partial sums; the slices are added in LDS in the order w = 0..CMW-1.
+// Within a group of 16 k values, lane group g = lane / 16 feeds k = k0 +
+// 4 g + s to product s (the same k on the A and the B side), so each lane
+// reads 4 consecutive entries of its row of the inverse.
+constexpr int CMW = 8;                  // waves per workgroup (k slices)
+constexpr int CM_ROWS = 16, CM_RHS = 64;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_coarse_multi(T* __restrict__ u, const double* __restrict__ rg,
-                                                        const int32_t* __restrict__ cell,
-                                                        const double* __restrict__ inv, int nm, int nrhs,
-                                                        size_t plane) {
-  __shared__ double As[CR][CK + 1];
-  __shared__ double Bs[CK][CZ];
-  const int row0 = blockIdx.x * CR, z0 = blockIdx.y * CZ;
-  const int tr = threadIdx.x >> 4, tz = (threadIdx.x & 15) * 4;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < nm; k0 += CK) {
-    for (int t = threadIdx.x; t < CR * CK; t += BLOCK) {
-      const int i = t / CK, j = t - i * CK;
-      const int gi = row0 + i, gj = k0 + j;
-      As[i][j] = (gi < nm && gj < nm) ? inv[(size_t)gi * nm + gj] : 0.0;
-    }
-    for (int t = threadIdx.x; t < CK * CZ; t += BLOCK) {
-      const int i = t / CZ, j = t - i * CZ;
-      const int gk = k0 + i, gz = z0 + j;
-      Bs[i][j] = (gk < nm && gz < nrhs) ? rg[(size_t)gk * nrhs + gz] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < CK; ++kk) {
-      const double a = As[tr][kk];
+__global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, const double* __restrict__ rg,
+                                                           const int32_t* __restrict__ cell,
+                                                           const double* __restrict__ inv, int nm, int nrhs,
+                                                           size_t plane) {
+  __shared__ double red[CMW][CM_ROWS][CM_RHS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int row0 = blockIdx.x * CM_ROWS, z0 = blockIdx.y * CM_RHS;
+  const int kc = (nm + CMW * 16 - 1) / (CMW * 16) * 16;
+  const int kb = w * kc, ke = min(nm, kb + kc);
+  const int arow = row0 + i;
+  const double* Ar = inv + (size_t)min(arow, nm - 1) * nm;
+  dbl4 acc[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] += a * Bs[kk][tz + j];
+  for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    double a[4], b[4][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      const bool ok = k < ke;
+      a[s] = ok && arow < nm ? Ar[k] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int z = z0 + 16 * c + i;
+        b[s][c] = ok && z < nrhs ? rg[(size_t)k * nrhs + z] : 0.0;
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s][c], acc[c], 0, 0, 0);
   }
-  const int row = row0 + tr;
-  if (row >= nm) return;
-  const int q = cell[row];
+  // tile c, register j of lane (i, g): row g + 4 j, right-hand side 16 c + i
+  // (the FP64 16x16 result layout, checked on the device)
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (z0 + tz + j < nrhs) u[(size_t)(z0 + tz + j) * plane + q] = (T)acc[j];
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[w][g + 4 * j][16 * c + i] = acc[c][j];
+  __syncthreads();
+  for (int t = threadIdx.x; t < CM_ROWS * CM_RHS; t += 64 * CMW) {
+    const int r = t / CM_RHS, zc = t - r * CM_RHS;
+    double sum = 0.0;
+#pragma unroll
+    for (int v = 0; v < CMW; ++v) sum += red[v][r][zc];
+    const int row = row0 + r, z = z0 + zc;
+    if (row < nm && z < nrhs) u[(size_t)z * plane + cell[row]] = (T)sum;
+  }
 }
 
 // Set-up of the coarsest solve: dense inverse by Gauss-Jordan elimination

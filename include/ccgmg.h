@@ -188,7 +188,8 @@ int ccgmg_get_tuning(const ccgmg_ctx* ctx, int level, int* sweep_ty_fp64, int* s
  * traffic accounting: stats[0] blocks, [1] block rows (the rows updated by
  * SMO-2: least-squares rows plus the regular rows joined to them),
  * [2] overlapped rows over all blocks, [3] their CSR entries, [4] bytes of
- * the blocks' dense FP64 inverses.  Device contexts only. */
+ * the blocks' dense inverses (computed in FP64, stored in FP32, applied in
+ * FP64 arithmetic).  Device contexts only. */
 int ccgmg_get_smo2_stats(const ccgmg_ctx* ctx, int level, int adjoint, long* stats);
 int ccgmg_get_irregular(const ccgmg_ctx* ctx, int level, int32_t* rows, int32_t* cols, double* vals,
                         double* cond);

@@ -81,7 +81,7 @@ struct Smo2Data {                 // RAS blocks of one row set
   int cur = 0;                    // which copy is current while a cycle is recorded
   double *evals = nullptr, *ersum = nullptr;
   int64_t* inv_off = nullptr;
-  double* inv = nullptr;
+  float* inv = nullptr;           // dense block inverses (computed in FP64, stored in FP32)
   size_t inv_bytes = 0;
   int max_ext = 0;
   long n_ext = 0, n_ext_nnz = 0;   // overlapped rows and their CSR entries, all blocks
@@ -300,8 +300,9 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, const std:
   out.ext_idx = upload(eidx, owned);
   out.own_cnt = upload(ocnt, owned);
   out.inv_off = upload(ioff, owned);
-  out.inv = upload(all, owned);
-  out.inv_bytes = all.size() * sizeof(double);
+  const std::vector<float> all32(all.begin(), all.end());
+  out.inv = upload(all32, owned);
+  out.inv_bytes = all32.size() * sizeof(float);
   out.n_ext = (long)eidx.size();
   out.n_ext_nnz = (long)ecols.size();
 }

@@ -247,7 +247,7 @@ struct Smo2Args {
   const double *evals, *ersum;
   const int32_t *eidx, *ebt, *ext_ptr, *own_cnt;
   const int64_t* inv_off;
-  const double* inv;
+  const float* inv;              // dense block inverses, stored in FP32 (applied in FP64)
   const double* c_in;
   double* c_out;
   int ns, nbt, ew;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
   double* c_out = a.c_out + (size_t)z * a.ns;
   const int e0 = a.ext_ptr[b], ne = a.ext_ptr[b + 1] - e0, nown = a.own_cnt[b];
   const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const double* A = a.inv + a.inv_off[b] + row;
+  const float* A = a.inv + a.inv_off[b] + row;
   for (int t = threadIdx.x; t < ne; t += BLOCK) {
     const int e = e0 + t;
     double uq = c_in[a.eidx[e]];
@@ -313,11 +313,11 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
     for (; col + 28 < ne; col += 32) {
       double v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = A[(size_t)(col + 4 * k) * nown];
+      for (int k = 0; k < 8; ++k) v[k] = (double)A[(size_t)(col + 4 * k) * nown];
 #pragma unroll
       for (int k = 0; k < 8; ++k) s += v[k] * res[col + 4 * k];
     }
-    for (; col < ne; col += 4) s += A[(size_t)col * nown] * res[col];
+    for (; col < ne; col += 4) s += (double)A[(size_t)col * nown] * res[col];
   }
   part[grp][row] = s;
   __syncthreads();

@@ -92,7 +92,7 @@ WORKLOADS = {
 
 def run_error_study(args):
     """Discretization error of the FP64 solution on a sequence of grids
-    (L-infinity over non-empty cells and volume-weighted L1), with the
+    (L-infinity over non-empty cells, volume-weighted L1 and L2), with the
     observed convergence rates.  The solves run to the rounding floor (tol
     1e-15, stopped by stagnation): at 1e-10 the iteration error, not the
     discretization error, would dominate on fine grids."""
@@ -105,7 +105,7 @@ def run_error_study(args):
     stream = torch.cuda.current_stream()
     rows = []
     for n in [int(v) for v in args.error_study.split(",")]:
-        cfg = W.config(args.config, n=n)
+        cfg = W.problem(args.problem, n) if args.problem else W.config(args.config, n=n)
         S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-15, max_cycles=80,
                    hip_stream=stream.cuda_stream)
         f, g, exact, kinds = make_inputs(S, cfg, torch, dev)
@@ -116,16 +116,22 @@ def run_error_study(args):
         e = np.abs(u.cpu().numpy() - exact)
         ne = kinds >= 2
         vol = S.volumes(0)
+        # L-infinity over non-empty cells; L1 and L2 weighted by the cut-cell
+        # volumes and normalised by the domain's area
+        w = vol[ne] / np.sum(vol[ne])
         row = {"n": n, "unknowns": S.info["n_unknowns"], "err_inf": float(np.max(e[ne])),
-               "err_l1": float(np.sum((e * vol)[ne]) / np.sum(vol[ne])), "cycles": rep["cycles"],
-               "rel_res_floor": rep["rel_res_inf"], "levels": S.info["n_levels"]}
+               "err_l1": float(np.sum(w * e[ne])), "err_l2": float(np.sqrt(np.sum(w * e[ne] ** 2))),
+               "cycles": rep["cycles"], "rel_res_floor": rep["rel_res_inf"],
+               "levels": S.info["n_levels"]}
         rows.append(row)
         print("error study n=%d: %s" % (n, row), file=sys.stderr, flush=True)
         S.close()
     for a, b in zip(rows, rows[1:]):
         b["rate_inf"] = float(np.log2(a["err_inf"] / b["err_inf"]))
         b["rate_l1"] = float(np.log2(a["err_l1"] / b["err_l1"]))
-    print(json.dumps({"error_study": WORKLOADS[args.config] % 0, "rows": rows}))
+        b["rate_l2"] = float(np.log2(a["err_l2"] / b["err_l2"]))
+    name = ("problem " + args.problem) if args.problem else WORKLOADS[args.config] % 0
+    print(json.dumps({"error_study": name, "rows": rows}))
 
 
 def fourier_averages(S, cfg, coeffs, torch, dev):
@@ -276,6 +282,8 @@ def main():
                          "5: five ellipses, b = 1.2 (4096^2)")
     ap.add_argument("--error-study", default="",
                     help="comma-separated grid sides: FP64 solves of the chosen workload and their errors")
+    ap.add_argument("--problem", choices=["P1", "P2N", "P2D", "P3"], default="",
+                    help="with --error-study: one of the paper's test problems instead of a workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -101,6 +101,16 @@ SINPIX_SINPIY = Manufactured(
     lambda x, y: -PI * PI * np.sin(PI * x) * np.sin(PI * y),
 )
 
+SIN4X_COS3Y = Manufactured(
+    "sin(4x) cos(3y)",
+    lambda x, y: np.sin(4 * x) * np.cos(3 * y),
+    lambda x, y: 4 * np.cos(4 * x) * np.cos(3 * y),
+    lambda x, y: -3 * np.sin(4 * x) * np.sin(3 * y),
+    lambda x, y: -16 * np.sin(4 * x) * np.cos(3 * y),
+    lambda x, y: -12 * np.cos(4 * x) * np.sin(3 * y),
+    lambda x, y: -9 * np.sin(4 * x) * np.cos(3 * y),
+)
+
 SINPIX_SIN2PIY_X3 = Manufactured(
     "sin(pi x) sin(2 pi y) + x^3",
     lambda x, y: np.sin(PI * x) * np.sin(2 * PI * y) + x ** 3,
@@ -272,6 +282,20 @@ def problem2(n, hole_bc=NEUMANN):
     """Poisson on [0,1]^2 minus the ellipse c=(1/2,1/2), a=(1/8,1/4) (Section 5.1, Problem 2)."""
     return {"id": "P2", "grid": grid(n), "curves": [box(), ellipse(0.5, 0.5, 0.125, 0.25, 0.0, bc=hole_bc)],
             "a": 1.0, "b": 0.0, "c": 1.0, "solution": SINPIX_SINPIY, "f": SINPIX_SINPIY.f(1.0, 0.0, 1.0)}
+
+
+def problem3(n):
+    """(a, b, c) = (1, 0, 2) on the unit box, Dirichlet, u = sin(4x) cos(3y)
+    (Section 5.1, Problem 3, case (i))."""
+    return {"id": "P3", "grid": grid(n), "curves": [box()], "a": 1.0, "b": 0.0, "c": 2.0,
+            "solution": SIN4X_COS3Y, "f": SIN4X_COS3Y.f(1.0, 0.0, 2.0)}
+
+
+def problem(name, n):
+    """The paper's test problems by name: P1, P2N (Neumann on the ellipse),
+    P2D (Dirichlet on it), P3 (case (i))."""
+    return {"P1": lambda: problem1(n), "P2N": lambda: problem2(n, NEUMANN), "P2D": lambda: problem2(n, DIRICHLET),
+            "P3": lambda: problem3(n)}[name]()
 
 
 def problem1(n):

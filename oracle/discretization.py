@@ -47,7 +47,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-from .geometry import CUT, DEG, DIRICHLET, EMPTY, MERGED, NEUMANN, PURE, shift_moments
+from .geometry import CUT, DEG, DIRICHLET, EMPTY, MERGED, NEUMANN, PURE, ROBIN, shift_moments
 
 K_EMPTY, K_MERGED, K_REGULAR, K_IRR_PURE, K_IRR_CUT = 0, 1, 2, 3, 4
 PLG_RADIUS = 4
@@ -225,13 +225,29 @@ class Discretization:
 
     def face_column(self, k, face, p):
         """<<N phi_alpha>> over a boundary face of cell k: Dirichlet averages the
-        basis, Neumann averages its xi-gradient along the outward normal."""
+        basis, Neumann averages its xi-gradient along the outward normal, Robin
+        (gamma1 + gamma2 d/dn, Section 3) combines the two, the gradient
+        converted to physical units (divided by h) so that the column is the
+        face average of N phi itself."""
         d, e = self._cell_offset(k, p)
         L = face.length
-        bc = self.cg.curves[face.curve].bc
+        curve = self.cg.curves[face.curve]
+        bc = curve.bc
+        if bc == ROBIN:
+            g1, g2 = curve.robin
+            dcol = self._face_dirichlet(face, d, e)
+            ncol = self._face_normal(face, d, e)
+            return g1 * dcol + (g2 / self.h) * ncol
         if bc == DIRICHLET:
-            m = shift_moments(face.m, d, e)
-            return np.array([m[a1, a2] / L for a1, a2 in BASIS])
+            return self._face_dirichlet(face, d, e)
+        return self._face_normal(face, d, e)
+
+    def _face_dirichlet(self, face, d, e):
+        m = shift_moments(face.m, d, e)
+        return np.array([m[a1, a2] / face.length for a1, a2 in BASIS])
+
+    def _face_normal(self, face, d, e):
+        L = face.length
         mx = shift_moments(face.mx, d, e)
         my = shift_moments(face.my, d, e)
         out = []
@@ -357,8 +373,10 @@ class Discretization:
         self.weights[q] = beta[:len(cells)] / (h * h)
         fw = []
         for f, bf in zip(fkeys, beta[len(cells):]):
+            # the Neumann column is in xi-gradient units (h du/dn); Dirichlet
+            # and Robin columns are the datum's own units
             bc = self.cg.curves[f].bc
-            fw.append((self.face_index[(q, f)], bf / (h * h) if bc == DIRICHLET else bf / h))
+            fw.append((self.face_index[(q, f)], bf / h if bc == NEUMANN else bf / (h * h)))
         self.face_weights[q] = fw
 
     # -- assembly ----------------------------------------------------------------
@@ -436,7 +454,9 @@ def discretize(cg, a, b, c, **kw):
 
 
 def boundary_data(disc, sol, q=16):
-    """g-hat: face averages of u (Dirichlet) or du/dn (Neumann) for every face."""
+    """g-hat: face averages of N u for every face: u (Dirichlet), du/dn
+    (Neumann) or gamma1 u + gamma2 du/dn (Robin, the boundary operator of
+    Section 3)."""
     from .geometry import face_averages
     g = np.zeros(max(1, len(disc.faces)))
     cache = {}

@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 BOX, CIRCLE, ELLIPSE, POLAR_SIN, POLAR_COS = 0, 1, 2, 3, 4
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 TWO_PI = 2.0 * math.pi
 GL_Q = 16                 # Gauss-Legendre nodes per arc piece
 DEG = 4                   # moments up to total degree 4
@@ -71,7 +71,18 @@ class Curve:
         self.p = [float(v) for v in desc["p"]]
         self.inside = int(desc["inside"])
         self.bc = int(desc["bc"])
+        # Robin: gamma1 u + gamma2 du/dn (the boundary operator N of Section 3)
+        self.robin = tuple(float(v) for v in desc.get("robin", (0.0, 0.0)))
         self.index = index
+
+    def datum(self, fn_value, fn_normal, px, py, nx, ny):
+        """N u at a boundary point: u (Dirichlet), du/dn (Neumann) or
+        gamma1 u + gamma2 du/dn (Robin); n is the outward normal of the domain."""
+        if self.bc == DIRICHLET:
+            return fn_value(px, py)
+        if self.bc == NEUMANN:
+            return fn_normal(px, py, nx, ny)
+        return self.robin[0] * fn_value(px, py) + self.robin[1] * fn_normal(px, py, nx, ny)
 
     # r(t) for polar curves
     def _r(self, t):
@@ -877,7 +888,7 @@ def face_averages(cg, idx, fn_value, fn_normal=None, q=GL_Q):
                             dx, dy = c.deriv(t)
                             sp = math.hypot(dx, dy)
                             nxv, nyv = arc.sigma * dy / sp, -arc.sigma * dx / sp
-                            g = fn_value(px, py) if c.bc == DIRICHLET else fn_normal(px, py, nxv, nyv)
+                            g = c.datum(fn_value, fn_normal, px, py, nxv, nyv)
                             w = wq[qn] * half * sp
                             s = acc.setdefault(arc.curve, [0.0, 0.0])
                             s[0] += w * g
@@ -900,8 +911,7 @@ def face_averages(cg, idx, fn_value, fn_normal=None, q=GL_Q):
                         for qn in range(q):
                             tt = 0.5 * (1.0 + tq[qn])
                             px, py = A[0] + tt * (B[0] - A[0]), A[1] + tt * (B[1] - A[1])
-                            bc = cg.box.bc
-                            g = fn_value(px, py) if bc == DIRICHLET else fn_normal(px, py, nrm[0], nrm[1])
+                            g = cg.box.datum(fn_value, fn_normal, px, py, nrm[0], nrm[1])
                             w = 0.5 * wq[qn] * L
                             s = acc.setdefault(cg.box.index, [0.0, 0.0])
                             s[0] += w * g

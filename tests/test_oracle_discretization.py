@@ -200,3 +200,29 @@ def test_box_domain_kinds():
     d = Discretization(cg, 1.0, 0.0, 1.0)
     assert int(d.regular.sum()) == (n - 4) ** 2
     assert len(d.faces) == 4 * n - 4
+
+
+@pytest.mark.parametrize("k,which,gammas", [(2, 1, (1.0, 0.5)), (1, 0, (0.7, 1.0)), (4, 0, (-0.3, 2.0))])
+def test_operator_exact_on_quartics_with_robin_data(k, which, gammas):
+    """L <u> + N <<(gamma1 + gamma2 d/dn) u>> = <L u> on every non-empty cell
+    for u in Pi_4 with Robin data (the boundary operator of Section 3) on one
+    curve: a hole with b != 0, an outer circle, and the box.  A wrong unit of
+    the gradient part (h or 1/h), a wrong weight scaling or a flipped normal
+    breaks the identity."""
+    cfg = W.config(k, n=64)
+    curves = list(cfg["curves"])
+    curves[which] = W.robin(curves[which], *gammas)
+    cg = build_cut_grid(cfg["grid"], curves)
+    d = Discretization(cg, cfg["a"], cfg["b"], cfg["c"])
+    rng = np.random.default_rng(30 + k)
+    sol = W.polynomial({(p, q): rng.standard_normal() for p in range(5) for q in range(5 - p)})
+    u = cell_averages(cg, sol.u)
+    f = cell_averages(cg, sol.f(cfg["a"], cfg["b"], cfg["c"]))
+    g = boundary_data(d, sol)
+    Lu = d.apply(u, g)
+    ne = d.nonempty.reshape(d.ny, d.nx)
+    scale = np.max(np.abs(u[ne])) / d.h ** 2
+    assert np.max(np.abs(Lu - f)[ne]) < 1e-12 * scale
+    # the Robin faces carry weights (the rows do depend on the Robin data)
+    robin_faces = [i for i, (_, c) in enumerate(d.faces) if c == which]
+    assert robin_faces

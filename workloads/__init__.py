@@ -10,7 +10,7 @@ Curve descriptors are plain dicts::
 
     {"kind": BOX|CIRCLE|ELLIPSE|POLAR_SIN|POLAR_COS,
      "p": [...], "inside": 1 if the domain lies inside the curve else 0,
-     "bc": DIRICHLET|NEUMANN}
+     "bc": DIRICHLET|NEUMANN|ROBIN, "robin": (gamma1, gamma2) for ROBIN}
 
 Parameter layouts: circle ``cx, cy, r``; ellipse ``cx, cy, a1, a2, rot``;
 polar ``cx, cy, r0, A, k, phase`` with ``r(t) = r0 + A sin(k t + phase)``
@@ -18,8 +18,8 @@ polar ``cx, cy, r0, A, k, phase`` with ``r(t) = r0 + A sin(k t + phase)``
 
 The problem statement these describe is the elliptic equation
 ``a u_xx + b u_xy + c u_yy = f`` with ``b^2 - 4ac < 0`` (Section 1,
-eq. ccEllipticEq) and Dirichlet or Neumann data on each boundary curve
-(Section 3.3).
+eq. ccEllipticEq) and Dirichlet, Neumann or Robin data (gamma1 u + gamma2
+du/dn, the boundary operator of Section 3) on each boundary curve.
 """
 from __future__ import annotations
 
@@ -28,7 +28,12 @@ import math
 import numpy as np
 
 BOX, CIRCLE, ELLIPSE, POLAR_SIN, POLAR_COS = 0, 1, 2, 3, 4
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
+
+
+def robin(curve, gamma1, gamma2):
+    """The same curve with the Robin condition gamma1 u + gamma2 du/dn = g."""
+    return dict(curve, bc=ROBIN, robin=(float(gamma1), float(gamma2)))
 
 
 def box(bc=DIRICHLET, x0=0.0, y0=0.0, x1=1.0, y1=1.0):
@@ -67,6 +72,16 @@ class Manufactured:
 
     def dudn(self, x, y, nx, ny):
         return self.ux(x, y) * nx + self.uy(x, y) * ny
+
+    def datum(self, curve, x, y, nx, ny):
+        """The boundary datum of a curve descriptor at points with outward
+        normals n: u, du/dn or gamma1 u + gamma2 du/dn."""
+        if curve["bc"] == DIRICHLET:
+            return self.u(x, y)
+        if curve["bc"] == NEUMANN:
+            return self.dudn(x, y, nx, ny)
+        g1, g2 = curve["robin"]
+        return g1 * self.u(x, y) + g2 * self.dudn(x, y, nx, ny)
 
 
 PI = math.pi
@@ -291,11 +306,20 @@ def problem3(n):
             "solution": SIN4X_COS3Y, "f": SIN4X_COS3Y.f(1.0, 0.0, 2.0)}
 
 
+def problem2_robin(n, gamma1=1.0, gamma2=0.5):
+    """Problem 2's domain and solution with the Robin condition
+    gamma1 u + gamma2 du/dn = g on the ellipse (Dirichlet on the box)."""
+    cfg = problem2(n, DIRICHLET)
+    cfg["id"] = "P2R"
+    cfg["curves"] = [cfg["curves"][0], robin(cfg["curves"][1], gamma1, gamma2)]
+    return cfg
+
+
 def problem(name, n):
     """The paper's test problems by name: P1, P2N (Neumann on the ellipse),
-    P2D (Dirichlet on it), P3 (case (i))."""
+    P2D (Dirichlet on it), P2R (Robin on it), P3 (case (i))."""
     return {"P1": lambda: problem1(n), "P2N": lambda: problem2(n, NEUMANN), "P2D": lambda: problem2(n, DIRICHLET),
-            "P3": lambda: problem3(n)}[name]()
+            "P2R": lambda: problem2_robin(n), "P3": lambda: problem3(n)}[name]()
 
 
 def problem1(n):

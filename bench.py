@@ -41,7 +41,6 @@ def make_inputs(S, cfg, torch, dev):
     """f-hat and g-hat from the library's quadrature export (no oracle)."""
     import numpy as np
 
-    import workloads as W
     grid = cfg["grid"]
     n, h = grid["nx"], grid["h"]
     sol = cfg["solution"]
@@ -72,8 +71,14 @@ def make_inputs(S, cfg, torch, dev):
     fcell, fx, fy, fw, fnx, fny = S.face_quadrature()
     nf = S.info["n_bdry_faces"]
     _, fcurve, _ = S.boundary_faces()
-    neumann = np.array([c["bc"] == W.NEUMANN for c in cfg["curves"]])[fcurve[fcell]]
-    gv = np.where(neumann, sol.dudn(fx, fy, fnx, fny), sol.u(fx, fy))   # Neumann: outward normal derivative
+    # the datum N u of each node's curve (u, du/dn or the Robin combination;
+    # n is the outward normal of the domain)
+    qcurve = fcurve[fcell]
+    gv = np.zeros_like(fx)
+    for ci, cu in enumerate(cfg["curves"]):
+        m = qcurve == ci
+        if np.any(m):
+            gv[m] = sol.datum(cu, fx[m], fy[m], fnx[m], fny[m])
     ghat = np.bincount(fcell, weights=fw * gv, minlength=nf) / np.bincount(fcell, weights=fw, minlength=nf)
     ex[kinds <= 1] = 0.0
     ex[cut] = np.bincount(cell, weights=qw * sol.u(qx, qy), minlength=n * n)[cut] / vol[cut]

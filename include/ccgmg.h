@@ -55,7 +55,7 @@ typedef enum {
 typedef enum { CCGMG_BOX = 0, CCGMG_CIRCLE = 1, CCGMG_ELLIPSE = 2, CCGMG_POLAR_SIN = 3,
                CCGMG_POLAR_COS = 4 } ccgmg_curve_kind;
 
-typedef enum { CCGMG_DIRICHLET = 0, CCGMG_NEUMANN = 1 } ccgmg_bc;
+typedef enum { CCGMG_DIRICHLET = 0, CCGMG_NEUMANN = 1, CCGMG_ROBIN = 2 } ccgmg_bc;
 
 /* A boundary curve.  Parameter layouts (p[]):
  *   BOX      x0, y0, x1, y1              (must equal the grid extent)
@@ -63,13 +63,17 @@ typedef enum { CCGMG_DIRICHLET = 0, CCGMG_NEUMANN = 1 } ccgmg_bc;
  *   ELLIPSE  cx, cy, a1, a2, rot
  *   POLAR_*  cx, cy, r0, A, k, phase     r(t) = r0 + A sin|cos(k t + phase)
  * domain_inside = 1 for the outer boundary (the domain is inside the
- * curve), 0 for a hole.  bc is a ccgmg_bc; the Neumann normal points out of
- * the domain. */
+ * curve), 0 for a hole.  bc is a ccgmg_bc: the boundary operator N of
+ * Section 3, with data g = N u averaged over each boundary face: u
+ * (Dirichlet), du/dn (Neumann) or robin[0] u + robin[1] du/dn (Robin; both
+ * finite, not both zero).  The normal n points out of the domain.  robin[]
+ * is read only when bc = CCGMG_ROBIN. */
 typedef struct {
   int kind;
   double p[8];
   int domain_inside;
   int bc;
+  double robin[2];
 } ccgmg_curve;
 
 typedef struct {

@@ -226,9 +226,10 @@ class Discretization:
     def face_column(self, k, face, p):
         """<<N phi_alpha>> over a boundary face of cell k: Dirichlet averages the
         basis, Neumann averages its xi-gradient along the outward normal, Robin
-        (gamma1 + gamma2 d/dn, Section 3) combines the two, the gradient
-        converted to physical units (divided by h) so that the column is the
-        face average of N phi itself."""
+        (gamma1 + gamma2 d/dn, Section 3) is the face average of N phi divided
+        by s = |gamma1| + |gamma2| / h (robin_scale), which keeps the column
+        O(1) and makes it the Dirichlet column for gamma2 = 0 and the Neumann
+        one for gamma1 = 0."""
         d, e = self._cell_offset(k, p)
         L = face.length
         curve = self.cg.curves[face.curve]
@@ -237,10 +238,15 @@ class Discretization:
             g1, g2 = curve.robin
             dcol = self._face_dirichlet(face, d, e)
             ncol = self._face_normal(face, d, e)
-            return g1 * dcol + (g2 / self.h) * ncol
+            return (g1 * dcol + (g2 / self.h) * ncol) / self.robin_scale(curve)
         if bc == DIRICHLET:
             return self._face_dirichlet(face, d, e)
         return self._face_normal(face, d, e)
+
+    def robin_scale(self, curve):
+        """s = |gamma1| + |gamma2| / h: the Robin column is N phi / s."""
+        g1, g2 = curve.robin
+        return abs(g1) + abs(g2) / self.h
 
     def _face_dirichlet(self, face, d, e):
         m = shift_moments(face.m, d, e)
@@ -373,10 +379,17 @@ class Discretization:
         self.weights[q] = beta[:len(cells)] / (h * h)
         fw = []
         for f, bf in zip(fkeys, beta[len(cells):]):
-            # the Neumann column is in xi-gradient units (h du/dn); Dirichlet
-            # and Robin columns are the datum's own units
-            bc = self.cg.curves[f].bc
-            fw.append((self.face_index[(q, f)], bf / h if bc == NEUMANN else bf / (h * h)))
+            # the Neumann column is in xi-gradient units (h du/dn), the
+            # Dirichlet column in the datum's units, the Robin column the
+            # datum divided by s
+            curve = self.cg.curves[f]
+            if curve.bc == NEUMANN:
+                w = bf / h
+            elif curve.bc == ROBIN:
+                w = bf / (self.robin_scale(curve) * h * h)
+            else:
+                w = bf / (h * h)
+            fw.append((self.face_index[(q, f)], w))
         self.face_weights[q] = fw
 
     # -- assembly ----------------------------------------------------------------

@@ -30,7 +30,8 @@ EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_ce
 
 
 class CurveT(C.Structure):
-    _fields_ = [("kind", C.c_int), ("p", C.c_double * 8), ("domain_inside", C.c_int), ("bc", C.c_int)]
+    _fields_ = [("kind", C.c_int), ("p", C.c_double * 8), ("domain_inside", C.c_int), ("bc", C.c_int),
+                ("robin", C.c_double * 2)]
 
 
 class GridT(C.Structure):
@@ -149,6 +150,8 @@ class Solver:
                 cs[k].p[t] = v
             cs[k].domain_inside = cu["inside"]
             cs[k].bc = cu["bc"]
+            for t, v in enumerate(cu.get("robin", (0.0, 0.0))):
+                cs[k].robin[t] = v
         self.options = default_options(**options)
         self.ctx = C.c_void_p()
         st = L.ccgmg_create(C.byref(g), cs, len(curves), a, b, c, C.byref(self.options), C.byref(self.ctx))

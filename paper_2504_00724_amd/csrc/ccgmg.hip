@@ -1553,6 +1553,13 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       }
       cs[k].inside = curves[k].domain_inside;
       cs[k].bc = curves[k].bc;
+      if (cs[k].bc < 0 || cs[k].bc > 2) throw ccg::Error(CCGMG_EINVAL, "unknown boundary condition");
+      if (cs[k].bc == 2) {
+        cs[k].robin[0] = curves[k].robin[0], cs[k].robin[1] = curves[k].robin[1];
+        if (!std::isfinite(cs[k].robin[0]) || !std::isfinite(cs[k].robin[1]) ||
+            (cs[k].robin[0] == 0.0 && cs[k].robin[1] == 0.0))
+          throw ccg::Error(CCGMG_EINVAL, "Robin coefficients must be finite and not both zero");
+      }
       cs[k].index = k;
     }
     double t0 = now();

@@ -1041,23 +1041,29 @@ struct Fitter {
         out[k++] = v / vol;
       }
   }
+  // Face average of N phi over a boundary face (the last column of the
+  // least-squares system): phi itself (Dirichlet), its xi-gradient along the
+  // outward normal (Neumann, h times du/dn), or (gamma1 phi + gamma2 dphi/dn)
+  // / s with s = |gamma1| + |gamma2| / h (Robin: O(1), and the Dirichlet or
+  // Neumann column when one coefficient is 0).
   void face_column(int cell, const Face& f, double px, double py, double* out) {
     double d = cell % D.nx + 0.5 - px, e = cell / D.nx + 0.5 - py;
+    const Curve& cv = g.curves[f.curve];
+    const double s = cv.bc == 2 ? robin_scale(cv, D.h) : 1.0;
+    const double wd = cv.bc == 0 ? 1.0 : cv.bc == 2 ? cv.robin[0] / s : 0.0;          // weight of the value part
+    const double wn = cv.bc == 1 ? 1.0 : cv.bc == 2 ? cv.robin[1] / D.h / s : 0.0;   // of the gradient part
+    Mom m = shift(f.m, d, e), mx = shift(f.mx, d, e), my = shift(f.my, d, e);
     int k = 0;
-    if (g.curves[f.curve].bc == 0) {
-      Mom m = shift(f.m, d, e);
-      for (int dg = 0; dg <= DEG; ++dg)
-        for (int a1 = dg; a1 >= 0; --a1) out[k++] = m[a1 * 5 + (dg - a1)] / f.len;
-      return;
-    }
-    Mom mx = shift(f.mx, d, e), my = shift(f.my, d, e);
     for (int dg = 0; dg <= DEG; ++dg)
       for (int a1 = dg; a1 >= 0; --a1) {
         int a2 = dg - a1;
         double v = 0;
         if (a1 >= 1) v += a1 * mx[(a1 - 1) * 5 + a2];
         if (a2 >= 1) v += a2 * my[a1 * 5 + (a2 - 1)];
-        out[k++] = v / f.len;
+        double val = 0.0;
+        if (wd != 0.0) val += wd * (m[a1 * 5 + a2] / f.len);
+        if (wn != 0.0) val += wn * (v / f.len);
+        out[k++] = val;
       }
   }
 
@@ -1305,7 +1311,10 @@ void Discretization::build(const Geometry& geo, double a_, double b_, double c_,
     for (size_t f = 0; f < fs.size(); ++f) {
       double bf = rows[k].beta[NB + f];
       fw_face.push_back(face_index[{q, fs[f].curve}]);
-      fw_val.push_back(geo.curves[fs[f].curve].bc == 0 ? bf / (h * h) : bf / h);
+      // Neumann columns are in xi-gradient units (h du/dn), Dirichlet
+      // columns in the datum's units, Robin columns the datum over s
+      const Curve& cv = geo.curves[fs[f].curve];
+      fw_val.push_back(cv.bc == 1 ? bf / h : cv.bc == 2 ? bf / (robin_scale(cv, h) * h * h) : bf / (h * h));
     }
     fw_ptr[k + 1] = (int32_t)fw_face.size();
   }

@@ -4,6 +4,7 @@
 // ordering (Section 4.2) and the SMO-2 block data (Section 4.1).
 #pragma once
 
+#include <cmath>
 #include <array>
 #include <cstdint>
 #include <functional>
@@ -28,13 +29,17 @@ struct Error : std::runtime_error {
 };
 
 struct Curve {
-  int kind = 0, inside = 0, bc = 0, index = 0;
+  int kind = 0, inside = 0, bc = 0, index = 0;   // bc: 0 Dirichlet, 1 Neumann, 2 Robin
   double p[8] = {0};
+  double robin[2] = {0, 0};                      // Robin: robin[0] u + robin[1] du/dn
   void point(double t, double& x, double& y) const;
   void deriv(double t, double& dx, double& dy) const;
   bool contains(double x, double y) const;
   std::vector<double> breakpoints() const;
 };
+
+// Robin rows: the least-squares column is N phi / s, s = |gamma1| + |gamma2| / h.
+inline double robin_scale(const Curve& c, double h) { return std::fabs(c.robin[0]) + std::fabs(c.robin[1]) / h; }
 
 struct Face {                 // one boundary curve's piece of a cell
   int curve = -1;

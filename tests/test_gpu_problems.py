@@ -66,3 +66,25 @@ def test_problem_errors_match_paper_tables(name, fixture, key):
         e = np.array([r[norm] for r in got])
         rates = np.log2(e[:-1] / e[1:])
         assert np.all(rates > 3.3) and np.all(rates < 5.5), (name, norm, rates)
+
+
+def test_robin_problem_fourth_order():
+    """Problem 2's domain and solution with the Robin condition u + 0.5 du/dn
+    = g on the ellipse (the boundary operator of Section 3; no table in the
+    paper): GPU solutions at h = 1/64 ... 1/512 converge at fourth order in
+    every norm, with errors between the Dirichlet and 10x the Neumann
+    variants' table values."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gold = json.load(open(os.path.join(GOLDEN, "problem2_errors.json")))
+    got = []
+    for n in gold["h"]:
+        print("problem P2R n=%d" % n, flush=True)
+        got.append(_errors("P2R", n))
+        print("   %s" % got[-1], flush=True)
+    for norm in ("Linf", "L1", "L2"):
+        e = np.array([r[norm] for r in got])
+        rates = np.log2(e[:-1] / e[1:])
+        assert np.all(rates > 3.3) and np.all(rates < 5.5), (norm, rates)
+        for i in range(len(e)):
+            assert gold["dirichlet_ellipse"][norm][i] / 5 < e[i] < gold["neumann_ellipse"][norm][i] * 10

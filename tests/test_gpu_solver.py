@@ -11,9 +11,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 # workload configs by number, the paper's problems by name (Problem 2 with
-# Neumann data on the ellipse, Problem 3 case (i)); 72: ragged tiles on
-# every level
-CASES = [(1, 64), (2, 64), (4, 128), (5, 64), (1, 72), ("P2N", 64), ("P3", 64)]
+# Neumann, or Robin, data on the ellipse, Problem 3 case (i)); 72: ragged
+# tiles on every level
+CASES = [(1, 64), (2, 64), (4, 128), (5, 64), (1, 72), ("P2N", 64), ("P2R", 64), ("P3", 64)]
 _LEVELS = {}
 
 

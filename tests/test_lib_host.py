@@ -32,10 +32,22 @@ def test_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("k,n", [(1, 64), (2, 64), (4, 64), (5, 64), (2, 128), ("P1", 40), ("P2", 64)])
+def _robin_box(k, n, gammas):
+    cfg = W.config(k, n=n)
+    return dict(cfg, curves=[W.robin(cfg["curves"][0], *gammas)] + list(cfg["curves"][1:]))
+
+
+# P2R: Robin data on Problem 2's ellipse; 4R: Robin data on the box of
+# config 4.  (With b != 0, derivative data on the box's corners leaves no
+# acceptable lattice at the corner cells, in the oracle and the library
+# alike: both raise the PLG error there.)
+@pytest.mark.parametrize("k,n", [(1, 64), (2, 64), (4, 64), (5, 64), (2, 128), ("P1", 40), ("P2", 64), ("P2R", 64),
+                                 ("4R", 64)])
 def test_host_setup_matches_oracle(k, n):
     _lib_or_skip()
-    cfg = {"P1": lambda: W.problem1(n), "P2": lambda: W.problem2(n)}[k]() if isinstance(k, str) else W.config(k, n=n)
+    named = {"P1": lambda: W.problem1(n), "P2": lambda: W.problem2(n), "P2R": lambda: W.problem("P2R", n),
+             "4R": lambda: _robin_box(4, n, (-0.3, 2.0))}
+    cfg = named[k]() if isinstance(k, str) else W.config(k, n=n)
     S = ccgmg.Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], host_only=1, max_levels=1)
     cg = build_cut_grid(cfg["grid"], cfg["curves"])
     d = Discretization(cg, cfg["a"], cfg["b"], cfg["c"])
@@ -145,3 +157,24 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
+
+
+def test_robin_coefficients_validated_and_corner_failure_agrees():
+    """Robin coefficients must be finite and not both zero; with b != 0 and
+    derivative data on the box, the library and the oracle both reject the
+    corner cells (no acceptable lattice)."""
+    _lib_or_skip()
+    from oracle.geometry import build_cut_grid as _bcg
+    from oracle.discretization import PLGError
+    cfg = W.config(4, n=32)
+    for bad in ((0.0, 0.0), (float("nan"), 1.0)):
+        with pytest.raises(ccgmg.CcgmgError) as ei:
+            ccgmg.Solver(cfg["grid"], [W.robin(cfg["curves"][0], *bad)] + list(cfg["curves"][1:]), 1.0, 0.0, 1.0,
+                         host_only=1)
+        assert ei.value.code == ccgmg.EINVAL
+    c5 = _robin_box(5, 64, (1.0, 0.5))
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        ccgmg.Solver(c5["grid"], c5["curves"], c5["a"], c5["b"], c5["c"], host_only=1, max_levels=1)
+    assert ei.value.code == ccgmg.EPLG
+    with pytest.raises(PLGError):
+        Discretization(_bcg(c5["grid"], c5["curves"]), c5["a"], c5["b"], c5["c"])

@@ -717,6 +717,9 @@ void Geometry::merge() {
     vol[kv.first] = v;
   }
   host.assign(n, -1);
+  // cells whose host is a given cell, so that re-pointing them when that
+  // cell merges in turn touches only them
+  std::unordered_map<int, std::vector<int>> hosted;
   auto aperture = [&](int idx, int edge) {
     if (native[idx] == 0) return 0.0;
     if (native[idx] == 1) return 1.0;
@@ -746,8 +749,14 @@ void Geometry::merge() {
     vol[best] += vol[idx];
     vol[idx] = 0.0;
     host[idx] = best;
-    for (size_t k = 0; k < n; ++k)
-      if (host[k] == (int)idx) host[k] = best;
+    std::vector<int>& into = hosted[best];
+    into.push_back((int)idx);
+    auto hs = hosted.find((int)idx);
+    if (hs != hosted.end()) {
+      for (int k : hs->second) host[k] = best;
+      into.insert(into.end(), hs->second.begin(), hs->second.end());
+      hosted.erase(hs);
+    }
   }
   state.assign(n, S_EMPTY);
   for (size_t k = 0; k < n; ++k) {
@@ -1143,8 +1152,12 @@ struct Fitter {
         }
         if (ok) feas.emplace_back(tot, mx, (int)e);
       }
-      std::sort(feas.begin(), feas.end());
-      for (size_t f = 0; f < feas.size() && f < (size_t)(3 * PLG_POOL); ++f) {
+      // only the best 3 * PLG_POOL in (cost, max, e) order are used: a
+      // partial sort gives them in the same order as a full sort (the keys
+      // are distinct through e)
+      const size_t keep = std::min(feas.size(), (size_t)(3 * PLG_POOL));
+      std::partial_sort(feas.begin(), feas.begin() + keep, feas.end());
+      for (size_t f = 0; f < keep; ++f) {
         int e = std::get<2>(feas[f]);
         std::vector<int32_t> cells;
         for (int k = 0; k < 5; ++k) {
@@ -1169,8 +1182,10 @@ struct Fitter {
     return out;
   }
 
-  // fit lattice `cells` for row q; returns cond and scaled weights (cells then faces)
-  double fit(int q, const std::vector<int32_t>& cells, std::vector<double>& beta, std::vector<double>& w) {
+  // fit lattice `cells` for row q: scaled weights (cells then faces) and the
+  // cell sample matrix (column-major, for its condition number)
+  void fit(int q, const std::vector<int32_t>& cells, std::vector<double>& beta, std::vector<double>& w,
+           std::vector<double>& colmaj) {
     const std::vector<Face>& fs = g.faces(q);
     const int nf = (int)fs.size(), m = NB + nf;
     int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
@@ -1180,7 +1195,7 @@ struct Fitter {
     }
     const double px = 0.5 * (imin + imax + 1), py = 0.5 * (jmin + jmax + 1);
     std::vector<double> M((size_t)NB * m);          // row-major M[j*m + k]
-    std::vector<double> colmaj((size_t)NB * NB);    // cell block, column-major
+    colmaj.assign((size_t)NB * NB, 0.0);            // cell block, column-major
     double col[NB];
     for (int k = 0; k < NB; ++k) {
       basis_averages(cells[k], px, py, col);
@@ -1190,7 +1205,6 @@ struct Fitter {
       face_column(q, fs[f], px, py, col);
       for (int j = 0; j < NB; ++j) M[(size_t)j * m + NB + f] = col[j];
     }
-    double cond = cond2(colmaj, NB);
     double L[NB];
     operator_averages(q, px, py, L);
     const int qi = q % D.nx, qj = q / D.nx;
@@ -1198,27 +1212,32 @@ struct Fitter {
     for (int k = 0; k < NB; ++k)
       w[k] = std::max(std::hypot((double)(cells[k] % D.nx - qi), (double)(cells[k] / D.nx - qj)), D.w_min);
     weighted_min_norm(M, m, w, L, beta);
-    return cond;
   }
 
+  // The candidates in pool order; one replaces the current choice when it is
+  // acceptable and its norm beats the choice's by the tie margin.  The
+  // condition number (the costly part of acceptability) is computed only for
+  // candidates that pass the other tests, so the choice is the same as with
+  // every condition number computed.
   RowResult row(int q) {
     RowResult best;
     double best_norm = 0;
     const double bound = OWN_WEIGHT_MAX * (D.a + D.c);
-    std::vector<double> beta, w;
+    std::vector<double> beta, w, colmaj;
     for (auto& cells : pool(q)) {
-      double cond = fit(q, cells, beta, w);
+      fit(q, cells, beta, w, colmaj);
       int qpos = (int)(std::find(cells.begin(), cells.end(), q) - cells.begin());
-      if (cond > COND_MAX || beta[qpos] > bound) continue;
+      if (beta[qpos] > bound) continue;
       double nrm = 0;
       for (size_t k = 0; k < beta.size(); ++k) nrm += w[k] * beta[k] * beta[k];
-      if (!best.ok || nrm < best_norm * (1.0 - NORM_TIE)) {
-        best.ok = true;
-        best_norm = nrm;
-        best.cells = cells;
-        best.beta = beta;
-        best.cond = cond;
-      }
+      if (best.ok && !(nrm < best_norm * (1.0 - NORM_TIE))) continue;
+      const double cond = cond2(colmaj, NB);
+      if (cond > COND_MAX) continue;
+      best.ok = true;
+      best_norm = nrm;
+      best.cells = cells;
+      best.beta = beta;
+      best.cond = cond;
     }
     return best;
   }

@@ -34,7 +34,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BOX, CIRCLE, ELLIPSE, POLAR_SIN, POLAR_COS = 0, 1, 2, 3, 4
+BOX, CIRCLE, ELLIPSE, POLAR_SIN, POLAR_COS, POLYGON = 0, 1, 2, 3, 4, 5
+QUARTER = 0.5 * math.pi   # parameter length of one polygon edge
 DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 TWO_PI = 2.0 * math.pi
 GL_Q = 16                 # Gauss-Legendre nodes per arc piece
@@ -91,7 +92,20 @@ class Curve:
             return r0 + A * math.sin(k * t + ph), A * k * math.cos(k * t + ph)
         return r0 + A * math.cos(k * t + ph), -A * k * math.sin(k * t + ph)
 
+    # polygon: a convex quadrilateral, vertices counter-clockwise in p;
+    # edge k is traversed for t in [k pi/2, (k+1) pi/2)
+    def _edge(self, t):
+        k = min(3, max(0, int(math.floor((t % TWO_PI) / QUARTER))))
+        s = (t % TWO_PI) / QUARTER - k
+        v = self.p
+        ax, ay = v[2 * k], v[2 * k + 1]
+        bx, by = v[(2 * k + 2) % 8], v[(2 * k + 3) % 8]
+        return ax, ay, bx, by, s
+
     def point(self, t):
+        if self.kind == POLYGON:
+            ax, ay, bx, by, s = self._edge(t)
+            return ax + s * (bx - ax), ay + s * (by - ay)
         if self.kind == CIRCLE:
             cx, cy, r = self.p
             return cx + r * math.cos(t), cy + r * math.sin(t)
@@ -105,6 +119,9 @@ class Curve:
         return cx + r * math.cos(t), cy + r * math.sin(t)
 
     def deriv(self, t):
+        if self.kind == POLYGON:
+            ax, ay, bx, by, _ = self._edge(t)
+            return (bx - ax) / QUARTER, (by - ay) / QUARTER
         if self.kind == CIRCLE:
             r = self.p[2]
             return -r * math.sin(t), r * math.cos(t)
@@ -119,6 +136,13 @@ class Curve:
 
     def contains(self, x, y):
         """Strictly inside the closed curve (the curve itself is outside)."""
+        if self.kind == POLYGON:
+            v = self.p
+            for k in range(4):
+                ax, ay, bx, by = v[2 * k], v[2 * k + 1], v[(2 * k + 2) % 8], v[(2 * k + 3) % 8]
+                if (bx - ax) * (y - ay) - (by - ay) * (x - ax) <= 0.0:
+                    return False
+            return True
         if self.kind == CIRCLE:
             cx, cy, r = self.p
             return (x - cx) ** 2 + (y - cy) ** 2 < r * r
@@ -136,7 +160,10 @@ class Curve:
         return rho < r
 
     def breakpoints(self):
-        """Parameters in [0, 2 pi) where x'(t) = 0 or y'(t) = 0."""
+        """Parameters in [0, 2 pi) where x'(t) = 0 or y'(t) = 0 (polygon: its
+        vertices, where x' and y' jump)."""
+        if self.kind == POLYGON:
+            return [0.0, QUARTER, 2 * QUARTER, 3 * QUARTER]
         if self.kind == CIRCLE:
             return [0.0, 0.5 * math.pi, math.pi, 1.5 * math.pi]
         if self.kind == ELLIPSE:
@@ -761,6 +788,12 @@ def _domain_mask(curves, X, Y):
             u = cr * dx + sr * dy
             v = -sr * dx + cr * dy
             ins = (u / a1) ** 2 + (v / a2) ** 2 < 1.0
+        elif c.kind == POLYGON:
+            v = c.p
+            ins = np.ones(X.shape, dtype=bool)
+            for k in range(4):
+                ax, ay, bx, by = v[2 * k], v[2 * k + 1], v[(2 * k + 2) % 8], v[(2 * k + 3) % 8]
+                ins &= (bx - ax) * (Y - ay) - (by - ay) * (X - ax) > 0.0
         else:
             cx, cy, r0, A, k, ph = c.p
             dx, dy = X - cx, Y - cy

@@ -41,6 +41,26 @@ def test_disk_area_perimeter_and_moments(n):
     assert abs(_integral(cg, 1, 0)) < 1e-15 and abs(_integral(cg, 3, 1)) < 1e-15
 
 
+@pytest.mark.parametrize("n", [48, 96])
+def test_rotated_square_area_perimeter_and_moments(n):
+    """The unit square rotated by pi/6 about (1/2, 1/2) (a polygon curve,
+    the domain of Problem 3 case (ii)) on a grid over [-1/4, 5/4]^2: area 1,
+    perimeter 4, centroid (1/2, 1/2), isotropic second moments 1/12 with no
+    product term, and the rotation-invariant fourth moment of the square
+    (int r^4 dA = 7/180 for the unit square) -- closed forms independent of
+    the rotation."""
+    cfg = W.problem3_rotated(2 * n // 3)
+    cg = build_cut_grid(W.grid(n, -0.25, -0.25, 1.5), cfg["curves"])
+    assert abs(cg.total_volume() - 1.0) < 1e-14
+    length = sum(f.length for cv in cg.cv.values() for f in cv.faces.values()) * cg.h
+    assert abs(length - 4.0) < 1e-13
+    assert abs(_integral(cg, 1, 0)) < 1e-15 and abs(_integral(cg, 0, 1)) < 1e-15
+    assert abs(_integral(cg, 2, 0) - 1.0 / 12) < 1e-14 and abs(_integral(cg, 0, 2) - 1.0 / 12) < 1e-14
+    assert abs(_integral(cg, 1, 1)) < 1e-14
+    r4 = _integral(cg, 4, 0) + 2 * _integral(cg, 2, 2) + _integral(cg, 0, 4)
+    assert abs(r4 - 7.0 / 180) < 1e-14
+
+
 def test_box_minus_shapes_areas():
     curves = [W.box(), W.ellipse(0.3, 0.35, 0.12, 0.07, 0.4), W.polar_sin(0.68, 0.62, 0.15, 0.03, 5, 0.3)]
     cg = build_cut_grid(W.grid(64), curves)

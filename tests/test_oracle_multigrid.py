@@ -196,3 +196,28 @@ def test_problem2_robin_fourth_order():
     assert np.all(rates > 3.5) and np.all(rates < 5.0), rates
     gold = json.load(open(os.path.join(GOLDEN, "problem2_errors.json")))
     assert gold["dirichlet_ellipse"]["Linf"][0] / 5 < ea[2] < gold["neumann_ellipse"]["Linf"][0] * 10
+
+
+def test_problem3_rotated_box_matches_paper_table():
+    """Problem 3 case (ii) (Section 5.1, Table tab:errorsOfBox): the unit box
+    rotated by pi/6 (a polygon curve; corner cells of the cut-cell grid),
+    (a,b,c) = (5/4, -sqrt(3)/2, 7/4); oracle direct solutions at h = 1/64 and
+    1/128 within a factor 3 of the table in every norm (measured 1.4-2.1),
+    and fourth order."""
+    from oracle.norms import norms as _norms
+    p3 = json.load(open(os.path.join(GOLDEN, "problem3_errors.json")))
+    e = []
+    for n in (64, 128):
+        cfg = W.problem3_rotated(n)
+        lv = Level(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
+        f = cell_averages(lv.cg, cfg["f"]).ravel()
+        g = boundary_data(lv.disc, cfg["solution"])
+        ue = cell_averages(lv.cg, cfg["solution"].u).ravel()
+        u = direct_solve(lv, rhs_vector(lv, f, g))
+        e.append(dict(zip(("L1", "L2", "Linf"), _norms((u - ue) * lv.nonempty, lv.cg.vol))))
+    for k in range(2):
+        for norm in ("L1", "L2", "Linf"):
+            table = p3["case_ii"][norm][k]
+            assert table / 3 < e[k][norm] < table * 3, (k, norm, e[k][norm], table)
+    for norm in ("L1", "L2", "Linf"):
+        assert 3.7 < np.log2(e[0][norm] / e[1][norm]) < 5.0

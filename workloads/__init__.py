@@ -8,11 +8,13 @@ own cubature.
 
 Curve descriptors are plain dicts::
 
-    {"kind": BOX|CIRCLE|ELLIPSE|POLAR_SIN|POLAR_COS,
+    {"kind": BOX|CIRCLE|ELLIPSE|POLAR_SIN|POLAR_COS|POLYGON,
      "p": [...], "inside": 1 if the domain lies inside the curve else 0,
      "bc": DIRICHLET|NEUMANN|ROBIN, "robin": (gamma1, gamma2) for ROBIN}
 
 Parameter layouts: circle ``cx, cy, r``; ellipse ``cx, cy, a1, a2, rot``;
+polygon: a convex quadrilateral, ``x0, y0, x1, y1, x2, y2, x3, y3``
+counter-clockwise;
 polar ``cx, cy, r0, A, k, phase`` with ``r(t) = r0 + A sin(k t + phase)``
 (or ``cos``); box ``x0, y0, x1, y1`` (the grid extent).
 
@@ -27,7 +29,7 @@ import math
 
 import numpy as np
 
-BOX, CIRCLE, ELLIPSE, POLAR_SIN, POLAR_COS = 0, 1, 2, 3, 4
+BOX, CIRCLE, ELLIPSE, POLAR_SIN, POLAR_COS, POLYGON = 0, 1, 2, 3, 4, 5
 DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 
 
@@ -46,6 +48,53 @@ def circle(cx, cy, r, inside=0, bc=DIRICHLET):
 
 def ellipse(cx, cy, a1, a2, rot=0.0, inside=0, bc=DIRICHLET):
     return {"kind": ELLIPSE, "p": [cx, cy, a1, a2, rot], "inside": inside, "bc": bc}
+
+
+def polygon(vertices, inside=1, bc=DIRICHLET):
+    """Convex quadrilateral with counter-clockwise vertices [(x, y)] * 4."""
+    return {"kind": POLYGON, "p": [float(c) for v in vertices for c in v], "inside": inside, "bc": bc}
+
+
+def rotated_box(theta, cx=0.5, cy=0.5, half=0.5, inside=1, bc=DIRICHLET):
+    """The square of side 2 half centred at (cx, cy), rotated
+    counter-clockwise by theta about its centre."""
+    c, s = math.cos(theta), math.sin(theta)
+    corners = [(-half, -half), (half, -half), (half, half), (-half, half)]
+    return polygon([(cx + c * x - s * y, cy + s * x + c * y) for x, y in corners], inside, bc)
+
+
+def rotated(sol, theta, cx=0.5, cy=0.5):
+    """u(x) = sol(R(-theta)(x - c) + c): the solution carried along with a
+    domain rotated counter-clockwise by theta about c (chain rule for the
+    derivatives)."""
+    c, s = math.cos(theta), math.sin(theta)
+
+    def xi(x, y):
+        dx, dy = x - cx, y - cy
+        return cx + c * dx + s * dy, cy - s * dx + c * dy
+
+    def ux(x, y):
+        a, b = xi(x, y)
+        return c * sol.ux(a, b) - s * sol.uy(a, b)
+
+    def uy(x, y):
+        a, b = xi(x, y)
+        return s * sol.ux(a, b) + c * sol.uy(a, b)
+
+    def uxx(x, y):
+        a, b = xi(x, y)
+        return c * c * sol.uxx(a, b) - 2 * c * s * sol.uxy(a, b) + s * s * sol.uyy(a, b)
+
+    def uyy(x, y):
+        a, b = xi(x, y)
+        return s * s * sol.uxx(a, b) + 2 * c * s * sol.uxy(a, b) + c * c * sol.uyy(a, b)
+
+    def uxy(x, y):
+        a, b = xi(x, y)
+        return c * s * sol.uxx(a, b) + (c * c - s * s) * sol.uxy(a, b) - c * s * sol.uyy(a, b)
+
+    return Manufactured("%s rotated by %.6f" % (sol.name, theta), lambda x, y: sol.u(*xi(x, y)), ux, uy, uxx, uxy,
+                        uyy)
 
 
 def polar_sin(cx, cy, r0, A, k, phase=0.0, inside=0, bc=DIRICHLET):
@@ -315,11 +364,26 @@ def problem2_robin(n, gamma1=1.0, gamma2=0.5):
     return cfg
 
 
+def problem3_rotated(n):
+    """Problem 3 case (ii) (Section 5.1): the unit box rotated counter-clockwise
+    by pi/6 about its centre, (a, b, c) = (5/4, -sqrt(3)/2, 7/4) (case (i)'s
+    operator in the rotated frame), Dirichlet, u = sin(4x) cos(3y) rotated
+    with the domain.  ``n`` is 1/h; the grid covers [-1/4, 5/4]^2 (3n/2 cells
+    a side), which holds the rotated box."""
+    th = math.pi / 6
+    sol = rotated(SIN4X_COS3Y, th)
+    a, b, c = 1.25, -math.sqrt(3.0) / 2.0, 1.75
+    m = (3 * n) // 2
+    return {"id": "P3R", "grid": grid(m, -0.25, -0.25, 1.5), "curves": [rotated_box(th)], "a": a, "b": b, "c": c,
+            "solution": sol, "f": sol.f(a, b, c)}
+
+
 def problem(name, n):
     """The paper's test problems by name: P1, P2N (Neumann on the ellipse),
-    P2D (Dirichlet on it), P2R (Robin on it), P3 (case (i))."""
+    P2D (Dirichlet on it), P2R (Robin on it), P3 (case (i)), P3R (case (ii),
+    ``n`` = 1/h)."""
     return {"P1": lambda: problem1(n), "P2N": lambda: problem2(n, NEUMANN), "P2D": lambda: problem2(n, DIRICHLET),
-            "P2R": lambda: problem2_robin(n), "P3": lambda: problem3(n)}[name]()
+            "P2R": lambda: problem2_robin(n), "P3": lambda: problem3(n), "P3R": lambda: problem3_rotated(n)}[name]()
 
 
 def problem1(n):

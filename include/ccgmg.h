@@ -53,7 +53,7 @@ typedef enum {
 } ccgmg_status;
 
 typedef enum { CCGMG_BOX = 0, CCGMG_CIRCLE = 1, CCGMG_ELLIPSE = 2, CCGMG_POLAR_SIN = 3,
-               CCGMG_POLAR_COS = 4 } ccgmg_curve_kind;
+               CCGMG_POLAR_COS = 4, CCGMG_POLYGON = 5 } ccgmg_curve_kind;
 
 typedef enum { CCGMG_DIRICHLET = 0, CCGMG_NEUMANN = 1, CCGMG_ROBIN = 2 } ccgmg_bc;
 
@@ -62,6 +62,9 @@ typedef enum { CCGMG_DIRICHLET = 0, CCGMG_NEUMANN = 1, CCGMG_ROBIN = 2 } ccgmg_b
  *   CIRCLE   cx, cy, r
  *   ELLIPSE  cx, cy, a1, a2, rot
  *   POLAR_*  cx, cy, r0, A, k, phase     r(t) = r0 + A sin|cos(k t + phase)
+ *   POLYGON  x0, y0, x1, y1, x2, y2, x3, y3   a convex quadrilateral, vertices
+ *            counter-clockwise, no edge parallel to a grid line (the rotated
+ *            box of Problem 3 (ii) in Section 5.1); corners split its arcs
  * domain_inside = 1 for the outer boundary (the domain is inside the
  * curve), 0 for a hole.  bc is a ccgmg_bc: the boundary operator N of
  * Section 3, with data g = N u averaged over each boundary face: u

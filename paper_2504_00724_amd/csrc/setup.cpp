@@ -122,8 +122,26 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 // ---------------------------------------------------------------------------
 // Curves
 // ---------------------------------------------------------------------------
+// Polygon (a convex quadrilateral, vertices counter-clockwise in p): edge k
+// is traversed for t in [k pi/2, (k+1) pi/2), linearly.
+static void polygon_edge(const double* p, double t, double& ax, double& ay, double& bx, double& by, double& s) {
+  const double q = 0.5 * M_PI;
+  const double tt = pymod(t, TWO_PI);
+  const int k = std::min(3, std::max(0, (int)std::floor(tt / q)));
+  s = tt / q - k;
+  ax = p[2 * k], ay = p[2 * k + 1];
+  bx = p[(2 * k + 2) % 8], by = p[(2 * k + 3) % 8];
+}
+
 void Curve::point(double t, double& x, double& y) const {
   switch (kind) {
+    case K_POLYGON: {
+      double ax, ay, bx, by, s;
+      polygon_edge(p, t, ax, ay, bx, by, s);
+      x = ax + s * (bx - ax);
+      y = ay + s * (by - ay);
+      return;
+    }
     case K_CIRCLE:
       x = p[0] + p[2] * std::cos(t);
       y = p[1] + p[2] * std::sin(t);
@@ -145,6 +163,13 @@ void Curve::point(double t, double& x, double& y) const {
 
 void Curve::deriv(double t, double& dx, double& dy) const {
   switch (kind) {
+    case K_POLYGON: {
+      double ax, ay, bx, by, s;
+      polygon_edge(p, t, ax, ay, bx, by, s);
+      dx = (bx - ax) / (0.5 * M_PI);
+      dy = (by - ay) / (0.5 * M_PI);
+      return;
+    }
     case K_CIRCLE:
       dx = -p[2] * std::sin(t);
       dy = p[2] * std::cos(t);
@@ -174,6 +199,13 @@ void Curve::deriv(double t, double& dx, double& dy) const {
 
 bool Curve::contains(double x, double y) const {
   switch (kind) {
+    case K_POLYGON: {
+      for (int k = 0; k < 4; ++k) {
+        const double ax = p[2 * k], ay = p[2 * k + 1], bx = p[(2 * k + 2) % 8], by = p[(2 * k + 3) % 8];
+        if ((bx - ax) * (y - ay) - (by - ay) * (x - ax) <= 0.0) return false;
+      }
+      return true;
+    }
     case K_CIRCLE: {
       double dx = x - p[0], dy = y - p[1];
       return dx * dx + dy * dy < p[2] * p[2];
@@ -223,7 +255,7 @@ static double bisect_sign(F g, double lo, double hi) {
 }
 
 std::vector<double> Curve::breakpoints() const {
-  if (kind == K_CIRCLE) return {0.0, 0.5 * M_PI, M_PI, 1.5 * M_PI};
+  if (kind == K_CIRCLE || kind == K_POLYGON) return {0.0, 0.5 * M_PI, M_PI, 1.5 * M_PI};   // polygon: its vertices
   std::vector<double> ts;
   if (kind == K_ELLIPSE) {
     double cr = std::cos(p[4]), sr = std::sin(p[4]);
@@ -346,7 +378,17 @@ void Geometry::validate() {
         throw Error(-3, "the box must coincide with the grid extent");
       box = c.index;
     } else {
-      if (c.kind < 0 || c.kind > 4) throw Error(-1, "unknown curve kind");
+      if (c.kind < 0 || c.kind > 5) throw Error(-1, "unknown curve kind");
+      if (c.kind == K_POLYGON) {
+        // convex, counter-clockwise, no edge along a grid direction
+        for (int k = 0; k < 4; ++k) {
+          const double ax = c.p[2 * k], ay = c.p[2 * k + 1], bx = c.p[(2 * k + 2) % 8], by = c.p[(2 * k + 3) % 8];
+          const double cx = c.p[(2 * k + 4) % 8], cy = c.p[(2 * k + 5) % 8];
+          if ((bx - ax) * (cy - by) - (by - ay) * (cx - bx) <= 0.0)
+            throw Error(-3, "a polygon must be a convex quadrilateral with counter-clockwise vertices");
+          if (bx == ax || by == ay) throw Error(-3, "polygon edges must not be parallel to the grid lines");
+        }
+      }
       auto bp = c.breakpoints();
       double mnx = 1e300, mxx = -1e300, mny = 1e300, mxy = -1e300;
       for (double t : bp) {

@@ -19,7 +19,7 @@ constexpr int DEG = 4;                    // moments / basis up to total degree 
 constexpr int NB = 15;                    // dim Pi_4 in 2-D
 using Mom = std::array<double, 25>;       // m[a * 5 + b] = int X^a Y^b (scaled)
 
-enum CurveKind { K_BOX = 0, K_CIRCLE = 1, K_ELLIPSE = 2, K_POLAR_SIN = 3, K_POLAR_COS = 4 };
+enum CurveKind { K_BOX = 0, K_CIRCLE = 1, K_ELLIPSE = 2, K_POLAR_SIN = 3, K_POLAR_COS = 4, K_POLYGON = 5 };
 enum CellState : int8_t { S_EMPTY = 0, S_MERGED = 1, S_PURE = 2, S_CUT = 3 };
 enum CellKind : int8_t { C_EMPTY = 0, C_MERGED = 1, C_REGULAR = 2, C_IRR_PURE = 3, C_IRR_CUT = 4 };
 

@@ -42,11 +42,11 @@ def _robin_box(k, n, gammas):
 # acceptable lattice at the corner cells, in the oracle and the library
 # alike: both raise the PLG error there.)
 @pytest.mark.parametrize("k,n", [(1, 64), (2, 64), (4, 64), (5, 64), (2, 128), ("P1", 40), ("P2", 64), ("P2R", 64),
-                                 ("4R", 64)])
+                                 ("4R", 64), ("P3R", 64)])
 def test_host_setup_matches_oracle(k, n):
     _lib_or_skip()
     named = {"P1": lambda: W.problem1(n), "P2": lambda: W.problem2(n), "P2R": lambda: W.problem("P2R", n),
-             "4R": lambda: _robin_box(4, n, (-0.3, 2.0))}
+             "4R": lambda: _robin_box(4, n, (-0.3, 2.0)), "P3R": lambda: W.problem3_rotated(n)}
     cfg = named[k]() if isinstance(k, str) else W.config(k, n=n)
     S = ccgmg.Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], host_only=1, max_levels=1)
     cg = build_cut_grid(cfg["grid"], cfg["curves"])
@@ -178,3 +178,17 @@ def test_robin_coefficients_validated_and_corner_failure_agrees():
     assert ei.value.code == ccgmg.EPLG
     with pytest.raises(PLGError):
         Discretization(_bcg(c5["grid"], c5["curves"]), c5["a"], c5["b"], c5["c"])
+
+
+def test_polygon_rejects_bad_quadrilaterals():
+    """A polygon must be a convex quadrilateral with counter-clockwise
+    vertices and no edge parallel to a grid line."""
+    _lib_or_skip()
+    g = W.grid(32, -0.25, -0.25, 1.5)
+    bad = [W.polygon([(0.2, 0.2), (0.2, 0.8), (0.8, 0.8), (0.8, 0.2)]),          # axis-parallel edges
+           W.polygon([(0.3, 0.1), (0.1, 0.7), (0.7, 0.9), (0.9, 0.3)]),          # clockwise
+           W.polygon([(0.3, 0.1), (0.9, 0.3), (0.5, 0.4), (0.1, 0.7)])]          # not convex
+    for c in bad:
+        with pytest.raises(ccgmg.CcgmgError) as ei:
+            ccgmg.Solver(g, [c], 1.0, 0.0, 1.0, host_only=1)
+        assert ei.value.code == ccgmg.EGEOM

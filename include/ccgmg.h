@@ -4,8 +4,9 @@
  *
  *      a u_xx + b u_xy + c u_yy = f   in an irregular 2-D domain,  b^2 < 4ac,
  *
- * with Dirichlet or Neumann data on each boundary curve (problem statement:
- * Section 1, eq. ccEllipticEq; boundary operators: Section 3.3).  The
+ * with Dirichlet, Neumann or Robin data on each boundary curve (problem
+ * statement: Section 1, eq. ccEllipticEq; the boundary operator N: Section 3,
+ * treated in detail for Neumann data in Section 3.3).  The
  * unknowns are cut-cell averages of u and the data are cell averages of f
  * and boundary-face averages of g (Section 3.2).  The discrete system is
  * L u + N g = f (eq. PoissonLinearDiscretization); the solver iterates

@@ -123,13 +123,13 @@ struct ccgmg_ctx {
   int M = 0;                        // coarsest level index in use
   int nm = 0;                       // coarsest unknowns
   int32_t* mcell = nullptr;
-  double* minv = nullptr;           // inverse of the coarsest operator
-  double* mtinv = nullptr;          // inverse of its transpose
+  float* minv = nullptr;            // inverse of the coarsest operator (computed in FP64, stored in FP32)
+  float* mtinv = nullptr;           // inverse of its transpose
   double* mrg = nullptr;            // gathered coarsest right-hand sides [MAX_COARSE_UNKNOWNS][max_nrhs]
   struct Coarse {
     int nm;
     int32_t* cell;
-    double *inv, *tinv;
+    float *inv, *tinv;
   };
   std::map<int, Coarse> coarse_cache;   // per coarsest level index
   std::vector<double> tune_ms;          // autotune: solve time per depth (index = M)
@@ -535,7 +535,7 @@ struct Driver {
 
   template <typename T>
   void coarse(DevLevel& L, T* u, const T* r) {
-    const double* inv = adjoint ? X->mtinv : X->minv;
+    const float* inv = adjoint ? X->mtinv : X->minv;
     const int nm = X->nm;
     if (nrhs == 1) {
       hipLaunchKernelGGL((k_coarse<T>), dim3((nm + 3) / 4, 1), dim3(BLOCK), nm * sizeof(double), s, u, r, X->mcell,
@@ -703,8 +703,9 @@ void upload_coarsest(ccgmg_ctx* X) {
   double* dA = upload(A, scratch);
   double* colk = dalloc<double>(n, scratch);
   int* status = dalloc<int>(1, scratch);
-  double* dinv = dalloc<double>((size_t)n * n, X->owned);
-  double* dtinv = dalloc<double>((size_t)n * n, X->owned);
+  double* dinv = dalloc<double>((size_t)n * n, scratch);
+  float* finv = dalloc<float>((size_t)n * n, X->owned);
+  float* ftinv = dalloc<float>((size_t)n * n, X->owned);
   hipStream_t st = X->ws;
   HIP_OK(hipMemsetAsync(status, 0, sizeof(int), st));
   hipLaunchKernelGGL(k_set_identity, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, st, dinv, n);
@@ -713,7 +714,10 @@ void upload_coarsest(ccgmg_ctx* X) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, dA, dinv, n, k, colk, status);
     hipLaunchKernelGGL(k_gj_elim, ge, dim3(256), 0, st, dA, dinv, n, k, colk, status);
   }
-  hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, dinv, dtinv, n);
+  // stored in FP32 (applied in FP64): an inexact coarsest solve (relative
+  // 1e-7) leaves the V-cycle's contraction unchanged and halves the bytes
+  hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, dinv, ftinv, n);
+  hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, st, (const double*)dinv, finv, (size_t)n * n);
   int singular = 0;
   HIP_OK(hipMemcpyAsync(&singular, status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
@@ -721,8 +725,8 @@ void upload_coarsest(ccgmg_ctx* X) {
   if (singular) throw ccg::Error(CCGMG_ESINGULAR, "singular coarsest operator");
   X->nm = n;
   X->mcell = upload(cells, X->owned);
-  X->minv = dinv;
-  X->mtinv = dtinv;
+  X->minv = finv;
+  X->mtinv = ftinv;
   X->coarse_cache[X->M] = {n, X->mcell, X->minv, X->mtinv};
 }
 

@@ -509,17 +509,17 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
 // per row (4 rows per workgroup), the gathered right-hand side staged in LDS.
 template <typename T>
 __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ u, const T* __restrict__ r,
-                                            const int32_t* __restrict__ cell, const double* __restrict__ inv, int nm) {
+                                            const int32_t* __restrict__ cell, const float* __restrict__ inv, int nm) {
   for (int k = threadIdx.x; k < nm; k += BLOCK) rv[k] = (double)r[cell[k]];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = wg * 4 + (threadIdx.x >> 6);
   if (row >= nm) return;
-  const double* A = inv + (size_t)row * nm;
+  const float* A = inv + (size_t)row * nm;
   double s0 = 0.0, s1 = 0.0;
   int k = lane;
-  for (; k + 64 < nm; k += 128) s0 += A[k] * rv[k], s1 += A[k + 64] * rv[k + 64];
-  if (k < nm) s0 += A[k] * rv[k];
+  for (; k + 64 < nm; k += 128) s0 += (double)A[k] * rv[k], s1 += (double)A[k + 64] * rv[k + 64];
+  if (k < nm) s0 += (double)A[k] * rv[k];
   double s = s0 + s1;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) u[cell[row]] = (T)s;
@@ -527,7 +527,7 @@ __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ 
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
-                                                  const int32_t* __restrict__ cell, const double* __restrict__ inv,
+                                                  const int32_t* __restrict__ cell, const float* __restrict__ inv,
                                                   int nm, size_t plane) {
   extern __shared__ double rv[];
   const size_t z = blockIdx.y;
@@ -559,7 +559,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, const double* __restrict__ rg,
                                                            const int32_t* __restrict__ cell,
-                                                           const double* __restrict__ inv, int nm, int nrhs,
+                                                           const float* __restrict__ inv, int nm, int nrhs,
                                                            size_t plane) {
   __shared__ double red[CMW][CM_ROWS][CM_RHS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -568,7 +568,7 @@ __global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, co
   const int kc = (nm + CMW * 16 - 1) / (CMW * 16) * 16;
   const int kb = w * kc, ke = min(nm, kb + kc);
   const int arow = row0 + i;
-  const double* Ar = inv + (size_t)min(arow, nm - 1) * nm;
+  const float* Ar = inv + (size_t)min(arow, nm - 1) * nm;
   dbl4 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -578,7 +578,7 @@ __global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, co
     for (int s = 0; s < 4; ++s) {
       const int k = k0 + 4 * g + s;
       const bool ok = k < ke;
-      a[s] = ok && arow < nm ? Ar[k] : 0.0;
+      a[s] = ok && arow < nm ? (double)Ar[k] : 0.0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int z = z0 + 16 * c + i;
@@ -687,7 +687,14 @@ __global__ __launch_bounds__(256) void k_gj_elim(double* __restrict__ A, double*
 }
 
 // out = in^T (n x n); the inverse of A^T is the transpose of the inverse of A.
-__global__ void k_transpose(const double* __restrict__ in, double* __restrict__ out, int n) {
+// out = in rounded to FP32 (the stored coarsest inverse)
+__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    out[k] = (float)in[k];
+}
+
+// out = in^T, rounded to FP32 (the stored inverse of the transpose)
+__global__ void k_transpose(const double* __restrict__ in, float* __restrict__ out, int n) {
   __shared__ double tile[32][33];
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   for (int j = threadIdx.y; j < 32; j += 8) {
@@ -697,7 +704,7 @@ __global__ void k_transpose(const double* __restrict__ in, double* __restrict__ 
   __syncthreads();
   for (int j = threadIdx.y; j < 32; j += 8) {
     const int r = bx + j, c = by + threadIdx.x;
-    if (r < n && c < n) out[(size_t)r * n + c] = tile[threadIdx.x][j];
+    if (r < n && c < n) out[(size_t)r * n + c] = (float)tile[threadIdx.x][j];
   }
 }
 
@@ -837,7 +844,7 @@ struct BCoarse {                   // coarsest solve (dense inverse) of one geom
   void* u;
   const void* r;
   const int32_t* cell;
-  const double* inv;
+  const float* inv;
   size_t plane;
   int nm, nwg;                     // workgroups per plane
   int geo;

@@ -125,6 +125,9 @@ typedef struct {
                             (smoother_fused, nu1, nu2 / coarse) = (0,3,3), (1,3,3),
                             (1,4,4), (1,5,5), (1,4,4/2,2), (1,5,5/2,2), (1,5,5/3,3),
                             (1,6,6/3,3) and keep the fastest; 0: use the fields above   */
+  int inverse_fp32;      /* storage of the dense inverses (SMO-2 blocks, coarsest level),
+                            computed in FP64 and always applied in FP64 arithmetic:
+                            1 (default) FP32, 0 FP64                                      */
   int host_only;         /* 1: build the hierarchy on the host only (no device calls);
                             queries work, apply/solve return CCGMG_EINVAL                  */
   void* hip_stream;      /* hipStream_t all device work is ordered on                     */

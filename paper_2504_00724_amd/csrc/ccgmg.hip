@@ -81,7 +81,8 @@ struct Smo2Data {                 // RAS blocks of one row set
   int cur = 0;                    // which copy is current while a cycle is recorded
   double *evals = nullptr, *ersum = nullptr;
   int64_t* inv_off = nullptr;
-  float* inv = nullptr;           // dense block inverses (computed in FP64, stored in FP32)
+  float* inv = nullptr;           // dense block inverses (computed in FP64), stored in FP32 ...
+  double* inv64 = nullptr;        // ... or in FP64 (options.inverse_fp32 = 0)
   size_t inv_bytes = 0;
   int max_ext = 0;
   long n_ext = 0, n_ext_nnz = 0;   // overlapped rows and their CSR entries, all blocks
@@ -123,13 +124,15 @@ struct ccgmg_ctx {
   int M = 0;                        // coarsest level index in use
   int nm = 0;                       // coarsest unknowns
   int32_t* mcell = nullptr;
-  float* minv = nullptr;            // inverse of the coarsest operator (computed in FP64, stored in FP32)
-  float* mtinv = nullptr;           // inverse of its transpose
+  float* minv = nullptr;            // inverse of the coarsest operator (computed in FP64), FP32 ...
+  float* mtinv = nullptr;           // ... and of its transpose
+  double *minv64 = nullptr, *mtinv64 = nullptr;   // the same in FP64 (options.inverse_fp32 = 0)
   double* mrg = nullptr;            // gathered coarsest right-hand sides [MAX_COARSE_UNKNOWNS][max_nrhs]
   struct Coarse {
     int nm;
     int32_t* cell;
     float *inv, *tinv;
+    double *inv64, *tinv64;
   };
   std::map<int, Coarse> coarse_cache;   // per coarsest level index
   std::vector<double> tune_ms;          // autotune: solve time per depth (index = M)
@@ -175,7 +178,8 @@ dim3 tiles(int nx, int ny, int nrhs) { return dim3((nx + TX - 1) / TX, (ny + TY 
 // neighbourhood (restricted to the row set); the dense inverse of the
 // extended block is kept for the block's own rows (column-major).
 void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, const std::vector<int32_t>& parent,
-                size_t ncells, int bsize, int overlap, int threads, Smo2Data& out, std::vector<void*>& owned) {
+                size_t ncells, int bsize, int overlap, int threads, bool inv_fp32, Smo2Data& out,
+                std::vector<void*>& owned) {
   const int ni = (int)R.cell.size();
   if (ni == 0) return;
   std::vector<int32_t> pos(ncells, -1);
@@ -300,9 +304,14 @@ void build_smo2(const ccg::RowSet& R, const std::vector<int32_t>& bt, const std:
   out.ext_idx = upload(eidx, owned);
   out.own_cnt = upload(ocnt, owned);
   out.inv_off = upload(ioff, owned);
-  const std::vector<float> all32(all.begin(), all.end());
-  out.inv = upload(all32, owned);
-  out.inv_bytes = all32.size() * sizeof(float);
+  if (inv_fp32) {
+    const std::vector<float> all32(all.begin(), all.end());
+    out.inv = upload(all32, owned);
+    out.inv_bytes = all32.size() * sizeof(float);
+  } else {
+    out.inv64 = upload(all, owned);
+    out.inv_bytes = all.size() * sizeof(double);
+  }
   out.n_ext = (long)eidx.size();
   out.n_ext_nnz = (long)ecols.size();
 }
@@ -322,7 +331,8 @@ void upload_rows(const ccg::RowSet& R, const ccg::RowSet& S, const std::vector<i
   D.cols = upload(R.cols, owned);
   D.vals = upload(R.vals, owned);
   D.rowsum = upload(rs, owned);
-  build_smo2(S, bt, parent, ncells, opt.smo2_block, opt.smo2_overlap, opt.num_threads, D.smo2, owned);
+  build_smo2(S, bt, parent, ncells, opt.smo2_block, opt.smo2_overlap, opt.num_threads, opt.inverse_fp32 != 0, D.smo2,
+             owned);
 }
 
 }  // namespace
@@ -422,7 +432,7 @@ struct Driver {
     a.ecell = S.ecell, a.ecols = S.ecols, a.ew = S.ew;
     a.evals = S.evals, a.ersum = S.ersum;
     a.eidx = S.ext_idx, a.ebt = S.ebt, a.ext_ptr = S.ext_ptr, a.own_cnt = S.own_cnt;
-    a.inv_off = S.inv_off, a.inv = S.inv;
+    a.inv_off = S.inv_off, a.inv = S.inv, a.inv64 = S.inv64;
     a.c_in = S.cbuf[S.cur], a.c_out = S.cbuf[1 - S.cur];
     a.ns = S.ns, a.nbt = R.n;
     a.epar = S.epar, a.eqpar = S.eqpar;
@@ -536,17 +546,18 @@ struct Driver {
   template <typename T>
   void coarse(DevLevel& L, T* u, const T* r) {
     const float* inv = adjoint ? X->mtinv : X->minv;
+    const double* inv64 = adjoint ? X->mtinv64 : X->minv64;
     const int nm = X->nm;
     if (nrhs == 1) {
       hipLaunchKernelGGL((k_coarse<T>), dim3((nm + 3) / 4, 1), dim3(BLOCK), nm * sizeof(double), s, u, r, X->mcell,
-                         inv, nm, L.n);
+                         inv, inv64, nm, L.n);
       return;
     }
     // several right-hand sides: gather, then one product reading the inverse once
     hipLaunchKernelGGL((k_coarse_gather<T>), dim3((nm + 255) / 256, nrhs), dim3(256), 0, s, r, X->mcell, X->mrg,
                        nm, nrhs, L.n);
     hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CM_ROWS - 1) / CM_ROWS, (nrhs + CM_RHS - 1) / CM_RHS), dim3(64 * CMW), 0, s, u,
-                       X->mrg, X->mcell, inv, nm, nrhs, L.n);
+                       X->mrg, X->mcell, inv, inv64, nm, nrhs, L.n);
   }
 
   // Alg. 2 on level m with iterate in (u, spare v) and rhs r.
@@ -673,6 +684,7 @@ void upload_coarsest(ccgmg_ctx* X) {
   auto hit = X->coarse_cache.find(X->M);
   if (hit != X->coarse_cache.end()) {
     X->nm = hit->second.nm, X->mcell = hit->second.cell, X->minv = hit->second.inv, X->mtinv = hit->second.tinv;
+    X->minv64 = hit->second.inv64, X->mtinv64 = hit->second.tinv64;
     return;
   }
   ccg::Discretization& D = X->H.disc[X->M];
@@ -703,9 +715,16 @@ void upload_coarsest(ccgmg_ctx* X) {
   double* dA = upload(A, scratch);
   double* colk = dalloc<double>(n, scratch);
   int* status = dalloc<int>(1, scratch);
-  double* dinv = dalloc<double>((size_t)n * n, scratch);
-  float* finv = dalloc<float>((size_t)n * n, X->owned);
-  float* ftinv = dalloc<float>((size_t)n * n, X->owned);
+  const bool fp32 = X->opt.inverse_fp32 != 0;
+  double* dinv = dalloc<double>((size_t)n * n, fp32 ? scratch : X->owned);
+  float *finv = nullptr, *ftinv = nullptr;
+  double* dtinv = nullptr;
+  if (fp32) {
+    finv = dalloc<float>((size_t)n * n, X->owned);
+    ftinv = dalloc<float>((size_t)n * n, X->owned);
+  } else {
+    dtinv = dalloc<double>((size_t)n * n, X->owned);
+  }
   hipStream_t st = X->ws;
   HIP_OK(hipMemsetAsync(status, 0, sizeof(int), st));
   hipLaunchKernelGGL(k_set_identity, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, st, dinv, n);
@@ -714,10 +733,15 @@ void upload_coarsest(ccgmg_ctx* X) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, dA, dinv, n, k, colk, status);
     hipLaunchKernelGGL(k_gj_elim, ge, dim3(256), 0, st, dA, dinv, n, k, colk, status);
   }
-  // stored in FP32 (applied in FP64): an inexact coarsest solve (relative
-  // 1e-7) leaves the V-cycle's contraction unchanged and halves the bytes
-  hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, dinv, ftinv, n);
-  hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, st, (const double*)dinv, finv, (size_t)n * n);
+  // stored in FP32 by default (applied in FP64): an inexact coarsest solve
+  // (relative 1e-7) leaves the V-cycle's contraction unchanged and halves
+  // the bytes
+  if (fp32) {
+    hipLaunchKernelGGL(k_transpose<float>, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, dinv, ftinv, n);
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, st, (const double*)dinv, finv, (size_t)n * n);
+  } else {
+    hipLaunchKernelGGL(k_transpose<double>, dim3((n + 31) / 32, (n + 31) / 32), dim3(32, 8), 0, st, dinv, dtinv, n);
+  }
   int singular = 0;
   HIP_OK(hipMemcpyAsync(&singular, status, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
@@ -727,7 +751,9 @@ void upload_coarsest(ccgmg_ctx* X) {
   X->mcell = upload(cells, X->owned);
   X->minv = finv;
   X->mtinv = ftinv;
-  X->coarse_cache[X->M] = {n, X->mcell, X->minv, X->mtinv};
+  X->minv64 = fp32 ? nullptr : dinv;
+  X->mtinv64 = dtinv;
+  X->coarse_cache[X->M] = {n, X->mcell, X->minv, X->mtinv, X->minv64, X->mtinv64};
 }
 
 // Tile-height autotuning of the SMO-1 sweep: on every level and in both
@@ -1156,7 +1182,7 @@ Smo2Args lock_smo2_args(DevLevel& L, int cur, const double* bterm) {
   a.ecell = S.ecell, a.ecols = S.ecols, a.ew = S.ew;
   a.evals = S.evals, a.ersum = S.ersum;
   a.eidx = S.ext_idx, a.ebt = S.ebt, a.ext_ptr = S.ext_ptr, a.own_cnt = S.own_cnt;
-  a.inv_off = S.inv_off, a.inv = S.inv;
+  a.inv_off = S.inv_off, a.inv = S.inv, a.inv64 = S.inv64;
   a.c_in = S.cbuf[cur], a.c_out = S.cbuf[1 - cur];
   a.ns = S.ns, a.nbt = L.fwd.n;
   a.epar = S.epar, a.eqpar = S.eqpar;
@@ -1243,7 +1269,8 @@ void plan_vcycle(ccgmg_batch* B, Planner& P, const std::vector<void*>& u0, const
           P.recs.push_back(rec);
         } else {
           BCoarse d{};
-          d.u = cur[g][m], d.r = rr[g][m], d.cell = X->mcell, d.inv = X->minv, d.plane = X->lv[m].n;
+          d.u = cur[g][m], d.r = rr[g][m], d.cell = X->mcell, d.inv = X->minv, d.inv64 = X->minv64;
+          d.plane = X->lv[m].n;
           d.nm = X->nm, d.nwg = (X->nm + 3) / 4, d.geo = g;
           cs.push_back(d);
           cw.push_back(d.nwg * planes[g]);
@@ -1288,7 +1315,7 @@ void launch_recs(ccgmg_batch* B, const std::vector<LRec>& recs, const char* dblo
         hipLaunchKernelGGL((k_coarse_gather<T>), dim3((nm + 255) / 256, r.nr), dim3(256), 0, s, (const T*)r.r,
                            X->mcell, X->mrg, nm, r.nr, X->lv[X->M].n);
         hipLaunchKernelGGL((k_coarse_multi<T>), dim3((nm + CM_ROWS - 1) / CM_ROWS, (r.nr + CM_RHS - 1) / CM_RHS), dim3(64 * CMW), 0, s, (T*)r.u,
-                           X->mrg, X->mcell, X->minv, nm, r.nr, X->lv[X->M].n);
+                           X->mrg, X->mcell, X->minv, X->minv64, nm, r.nr, X->lv[X->M].n);
         break;
       }
       case 4:
@@ -1517,6 +1544,7 @@ void ccgmg_default_options(ccgmg_options* o) {
   o->tune_tiles = 1;
   o->smoother_fused = 0;
   o->tune_schedule = 1;
+  o->inverse_fp32 = 1;
   o->host_only = 0;
   o->hip_stream = nullptr;
 }
@@ -1544,7 +1572,7 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
     if (X->opt.max_nrhs < 1) X->opt.max_nrhs = 1;
     if (X->opt.smo2_block < 1 || X->opt.smo2_block > 64) throw ccg::Error(CCGMG_EINVAL, "smo2_block must be in 1..64");
     if (X->opt.nu1 < 0 || X->opt.nu2 < 0 || X->opt.smo2_iters < 1 || X->opt.smo2_overlap < 0 ||
-        X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4)
+        X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4 || X->opt.inverse_fp32 < 0 || X->opt.inverse_fp32 > 1)
       throw ccg::Error(CCGMG_EINVAL, "bad smoothing parameters");
     X->a = a, X->b = b, X->c = c;
     X->host_only = X->opt.host_only != 0;

@@ -247,7 +247,8 @@ struct Smo2Args {
   const double *evals, *ersum;
   const int32_t *eidx, *ebt, *ext_ptr, *own_cnt;
   const int64_t* inv_off;
-  const float* inv;              // dense block inverses, stored in FP32 (applied in FP64)
+  const float* inv;              // dense block inverses stored in FP32 (or, if inv64, in FP64);
+  const double* inv64;           // applied in FP64 either way
   const double* c_in;
   double* c_out;
   int ns, nbt, ew;
@@ -273,7 +274,7 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
   double* c_out = a.c_out + (size_t)z * a.ns;
   const int e0 = a.ext_ptr[b], ne = a.ext_ptr[b + 1] - e0, nown = a.own_cnt[b];
   const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const float* A = a.inv + a.inv_off[b] + row;
+  const int64_t ioff = a.inv_off[b] + row;
   for (int t = threadIdx.x; t < ne; t += BLOCK) {
     const int e = e0 + t;
     double uq = c_in[a.eidx[e]];
@@ -308,7 +309,9 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
   }
   __syncthreads();
   double s = 0.0;
-  if (row < nown) {
+  // the own rows' inverse (column-major) times the residual; the storage
+  // precision is uniform per launch
+  auto matvec = [&](const auto* A) {
     int col = grp;
     for (; col + 28 < ne; col += 32) {
       double v[8];
@@ -318,6 +321,12 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
       for (int k = 0; k < 8; ++k) s += v[k] * res[col + 4 * k];
     }
     for (; col < ne; col += 4) s += (double)A[(size_t)col * nown] * res[col];
+  };
+  if (row < nown) {
+    if (a.inv64)
+      matvec(a.inv64 + ioff);
+    else
+      matvec(a.inv + ioff);
   }
   part[grp][row] = s;
   __syncthreads();
@@ -509,17 +518,23 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
 // per row (4 rows per workgroup), the gathered right-hand side staged in LDS.
 template <typename T>
 __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ u, const T* __restrict__ r,
-                                            const int32_t* __restrict__ cell, const float* __restrict__ inv, int nm) {
+                                            const int32_t* __restrict__ cell, const float* __restrict__ inv,
+                                            const double* __restrict__ inv64, int nm) {
   for (int k = threadIdx.x; k < nm; k += BLOCK) rv[k] = (double)r[cell[k]];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = wg * 4 + (threadIdx.x >> 6);
   if (row >= nm) return;
-  const float* A = inv + (size_t)row * nm;
   double s0 = 0.0, s1 = 0.0;
-  int k = lane;
-  for (; k + 64 < nm; k += 128) s0 += (double)A[k] * rv[k], s1 += (double)A[k + 64] * rv[k + 64];
-  if (k < nm) s0 += (double)A[k] * rv[k];
+  auto dot = [&](const auto* A) {   // inverse stored in FP32 or FP64, applied in FP64
+    int k = lane;
+    for (; k + 64 < nm; k += 128) s0 += (double)A[k] * rv[k], s1 += (double)A[k + 64] * rv[k + 64];
+    if (k < nm) s0 += (double)A[k] * rv[k];
+  };
+  if (inv64)
+    dot(inv64 + (size_t)row * nm);
+  else
+    dot(inv + (size_t)row * nm);
   double s = s0 + s1;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) u[cell[row]] = (T)s;
@@ -528,10 +543,10 @@ __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
                                                   const int32_t* __restrict__ cell, const float* __restrict__ inv,
-                                                  int nm, size_t plane) {
+                                                  const double* __restrict__ inv64, int nm, size_t plane) {
   extern __shared__ double rv[];
   const size_t z = blockIdx.y;
-  coarse_rows<T>(rv, blockIdx.x, u + z * plane, r + z * plane, cell, inv, nm);
+  coarse_rows<T>(rv, blockIdx.x, u + z * plane, r + z * plane, cell, inv, inv64, nm);
 }
 
 // Coarsest level with several right-hand sides, step 1: gather the
@@ -559,7 +574,8 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, const double* __restrict__ rg,
                                                            const int32_t* __restrict__ cell,
-                                                           const float* __restrict__ inv, int nm, int nrhs,
+                                                           const float* __restrict__ inv,
+                                                           const double* __restrict__ inv64, int nm, int nrhs,
                                                            size_t plane) {
   __shared__ double red[CMW][CM_ROWS][CM_RHS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -568,7 +584,7 @@ __global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, co
   const int kc = (nm + CMW * 16 - 1) / (CMW * 16) * 16;
   const int kb = w * kc, ke = min(nm, kb + kc);
   const int arow = row0 + i;
-  const float* Ar = inv + (size_t)min(arow, nm - 1) * nm;
+  const size_t aoff = (size_t)min(arow, nm - 1) * nm;
   dbl4 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -578,7 +594,7 @@ __global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, co
     for (int s = 0; s < 4; ++s) {
       const int k = k0 + 4 * g + s;
       const bool ok = k < ke;
-      a[s] = ok && arow < nm ? (double)Ar[k] : 0.0;
+      a[s] = ok && arow < nm ? (inv64 ? inv64[aoff + k] : (double)inv[aoff + k]) : 0.0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int z = z0 + 16 * c + i;
@@ -693,8 +709,9 @@ __global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
     out[k] = (float)in[k];
 }
 
-// out = in^T, rounded to FP32 (the stored inverse of the transpose)
-__global__ void k_transpose(const double* __restrict__ in, float* __restrict__ out, int n) {
+// out = in^T (the stored inverse of the transpose, FP32 or FP64)
+template <typename TO>
+__global__ void k_transpose(const double* __restrict__ in, TO* __restrict__ out, int n) {
   __shared__ double tile[32][33];
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   for (int j = threadIdx.y; j < 32; j += 8) {
@@ -704,7 +721,7 @@ __global__ void k_transpose(const double* __restrict__ in, float* __restrict__ o
   __syncthreads();
   for (int j = threadIdx.y; j < 32; j += 8) {
     const int r = bx + j, c = by + threadIdx.x;
-    if (r < n && c < n) out[(size_t)r * n + c] = (float)tile[threadIdx.x][j];
+    if (r < n && c < n) out[(size_t)r * n + c] = (TO)tile[threadIdx.x][j];
   }
 }
 
@@ -845,6 +862,7 @@ struct BCoarse {                   // coarsest solve (dense inverse) of one geom
   const void* r;
   const int32_t* cell;
   const float* inv;
+  const double* inv64;             // set: the inverse is stored in FP64
   size_t plane;
   int nm, nwg;                     // workgroups per plane
   int geo;
@@ -859,7 +877,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_batched(const BCoarse* __restr
   if (!active[d.geo]) return;
   const int local = blockIdx.x - st.start[di];
   const int z = local / d.nwg, l = local - z * d.nwg;
-  coarse_rows<T>(rv, l, (T*)d.u + z * d.plane, (const T*)d.r + z * d.plane, d.cell, d.inv, d.nm);
+  coarse_rows<T>(rv, l, (T*)d.u + z * d.plane, (const T*)d.r + z * d.plane, d.cell, d.inv, d.inv64, d.nm);
 }
 
 struct BNorm {                     // residual check of one geometry (level 0, FP64)

@@ -416,3 +416,51 @@ def test_many_right_hand_sides_match_single_solves():
     assert worst <= 2e-10
     Sm.close()
     S1.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_inverse_storage_fp64_and_fp32(precision):
+    """The dense inverses (SMO-2 blocks, coarsest level) are applied in FP64
+    from FP32 storage by default and from FP64 storage with inverse_fp32 = 0:
+    both reach the oracle's direct solution (one and 6 right-hand sides, the
+    latter through the many-RHS coarsest product, and the transposed solve)
+    with the same number of cycles to within one."""
+    from oracle.multigrid import direct_solve_transpose
+    dev = _dev()
+    cfg, lv = _level(4, 128)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ref = direct_solve(lv, rhs_vector(lv, f, g))
+    F = np.stack([f * (1 + 0.25 * z) for z in range(6)])
+    refs = [direct_solve(lv, rhs_vector(lv, F[z], g)) for z in range(6)]
+    rng = np.random.default_rng(77)
+    rt = rng.standard_normal(lv.nx * lv.ny) * lv.nonempty
+    reft = direct_solve_transpose(lv, rt)
+    cycles = {}
+    for fp32 in (1, 0):
+        S = _solver(cfg, tol=1e-12, max_cycles=200, precision=precision, inverse_fp32=fp32, max_nrhs=6)
+        S.set_boundary(torch.tensor(np.tile(g, (6, 1)), device=dev), 6)
+        u = torch.zeros(6, lv.nx * lv.ny, dtype=torch.float64, device=dev)
+        rep6 = S.solve(torch.tensor(F, device=dev), u, nrhs=6)
+        torch.cuda.synchronize()
+        got = u.cpu().numpy()
+        for z in range(6):
+            assert np.max(np.abs(got[z] - refs[z])) <= 1e-10 * np.max(np.abs(refs[z]))
+        S.set_boundary(torch.tensor(g, device=dev), 1)
+        u1 = torch.zeros(lv.nx * lv.ny, dtype=torch.float64, device=dev)
+        rep = S.solve(torch.tensor(f, device=dev), u1)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(u1.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+        cyc_t = 0
+        if precision == 0:
+            lam = torch.zeros_like(u1)
+            rept = S.solve_adjoint(torch.tensor(rt, device=dev), lam)
+            torch.cuda.synchronize()
+            assert np.max(np.abs(lam.cpu().numpy() - reft)) <= 1e-10 * np.max(np.abs(reft))
+            cyc_t = rept["cycles"]
+        cycles[fp32] = (rep["cycles"], rep6["cycles"], cyc_t)
+        print("inverse_fp32=%d precision %d: cycles (1 RHS, 6 RHS, adjoint) %s" % (fp32, precision, cycles[fp32]),
+              flush=True)
+        S.close()
+    for a, b in zip(cycles[0], cycles[1]):
+        assert abs(a - b) <= 1

@@ -3,10 +3,15 @@
     python3 -m paper_2504_00724_amd.prof_summary trace STATS.csv|RESULTS.db
     python3 -m paper_2504_00724_amd.prof_summary pmc FETCH.csv WRITE.csv \
         --cells N --kernel NAME [--calib-kernel k_copy]
+    python3 -m paper_2504_00724_amd.prof_summary cycle KERNEL_TRACE.csv
 
 ``trace`` reads a ``--kernel-trace --stats`` run (the ``*_kernel_stats.csv``
 of ``--output-format csv``, or the rocpd SQLite database) and lists calls,
-mean/min duration and share per kernel.  ``pmc`` reads two
+mean/min duration and share per kernel.  ``cycle`` reads the per-launch ``*_kernel_trace.csv`` of a run of
+``profile_kernels --solves K`` and splits the last complete V-cycle of the
+last solve (from one residual norm to the next) by level: the descent
+enters a coarser level after each restriction, the ascent a finer one at
+each fused step that applies the coarse-grid correction.  ``pmc`` reads two
 ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs (``*_counter_collection.csv``)
 of the same program, averages each counter (KiB per dispatch) over the
 dispatches of the measured kernel and of the calibration copy kernel, and
@@ -68,6 +73,47 @@ def cmd_trace(args):
         print("| `%s` | %d | %.2f | %.2f | %.3f | %.1f%% |" % (k, n, a / 1e3, m / 1e3, t / 1e6, 100 * t / tot))
 
 
+def cmd_cycle(args):
+    with open(args.path) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [short(r["Kernel_Name"]) for r in rows]
+    st = [int(r["Start_Timestamp"]) for r in rows]
+    en = [int(r["End_Timestamp"]) for r in rows]
+    # the last solve: launches after the last idle gap longer than 300 us
+    first = 0
+    for i in range(1, len(rows)):
+        if st[i] - en[i - 1] > 300000:
+            first = i
+    norms = [i for i in range(first, len(rows)) if names[i].startswith("k_resnorm")]
+    if len(norms) < 3:
+        raise SystemExit("fewer than two complete cycles in the last solve")
+    i0, i1 = norms[-3], norms[-2]
+    level, lv_ns, lv_n, other = 0, collections.defaultdict(float), collections.defaultdict(int), []
+    for i in range(i0 + 1, i1 + 1):
+        nm, d = names[i], en[i] - st[i]
+        if nm.startswith("k_smooth_fused") and nm.endswith("true>"):
+            level -= 1                      # ascent: the step that applies P e
+        if nm.startswith(("k_smooth_fused", "k_restrict", "k_sweep", "k_smo2", "k_prolong")):
+            lv_ns[level] += d
+            lv_n[level] += 1
+        else:
+            other.append((nm, d))
+        if nm.startswith("k_restrict"):
+            level += 1                      # descent
+    span = (en[i1] - en[i0]) / 1e3
+    busy = sum(en[i] - st[i] for i in range(i0 + 1, i1 + 1)) / 1e3
+    print("one V-cycle of the last solve: %.1f us from norm to norm, %.1f us in kernels, %d launches\n"
+          % (span, busy, i1 - i0))
+    print("| level | launches | kernel time us | share of cycle |")
+    print("|---|---|---|---|")
+    for m in sorted(lv_ns):
+        print("| %d | %d | %.1f | %.1f%% |" % (m, lv_n[m], lv_ns[m] / 1e3, 100 * lv_ns[m] / 1e3 / span))
+    for nm, d in other:
+        print("| `%s` | 1 | %.1f | %.1f%% |" % (nm, d / 1e3, 100 * d / 1e3 / span))
+    print("| between launches | | %.1f | %.1f%% |" % (span - busy, 100 * (span - busy) / span))
+
+
 def counter_means(path, counter):
     acc = collections.defaultdict(list)
     with open(path) as f:
@@ -118,6 +164,8 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("path")
+    c = sub.add_parser("cycle")
+    c.add_argument("path")
     p = sub.add_parser("pmc")
     p.add_argument("fetch")
     p.add_argument("write")
@@ -125,7 +173,7 @@ def main():
     p.add_argument("--kernel", required=True)
     p.add_argument("--calib-kernel", default="k_copy")
     args = ap.parse_args()
-    (cmd_trace if args.cmd == "trace" else cmd_pmc)(args)
+    {"trace": cmd_trace, "cycle": cmd_cycle, "pmc": cmd_pmc}[args.cmd](args)
 
 
 if __name__ == "__main__":

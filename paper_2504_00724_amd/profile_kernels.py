@@ -7,11 +7,16 @@ hardware-counter collection under a profiler, e.g.
 
 Kernel 0 is the FP64 SMO-1 sweep, kernel 6 a plain FP64 copy of the same
 cell array (16 bytes per cell), which calibrates the byte counters.
+
+With --solves K it instead builds the context as the benchmark does (tuned
+tiles, schedule and depth) and runs K FP64 solves of the benchmark's problem
+to 1e-10, for a per-launch kernel trace of whole V-cycles.
 """
 import argparse
 import json
 import os
 import sys
+import time
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -26,12 +31,30 @@ def main():
     ap.add_argument("--kernels", default="sweep,copy")
     ap.add_argument("--tile-rows", type=int, default=32,
                     help="SMO-1 tile height (the benchmark's tuned choice on the finest level)")
+    ap.add_argument("--solves", type=int, default=0)
     args = ap.parse_args()
     import torch  # noqa: F401  (HIP runtime and device selection)
 
     import workloads as W
     from paper_2504_00724_amd.ccgmg import Solver
     cfg = W.config(4, n=args.n)
+    if args.solves:
+        import bench
+        dev = torch.device("cuda:0")
+        S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-10, max_cycles=200,
+                   hip_stream=torch.cuda.current_stream().cuda_stream)
+        f, g, _, _ = bench.make_inputs(S, cfg, torch, dev)
+        S.set_boundary(g, 1)
+        S.tune(f)
+        for k in range(args.solves):
+            u = torch.zeros_like(f)
+            torch.cuda.synchronize()
+            time.sleep(0.01)   # an idle gap that marks the solve in the trace
+            rep = S.solve(f, u)
+            torch.cuda.synchronize()
+            print("solve %d: %d cycles, %.3f ms" % (k, rep["cycles"], 1e3 * rep["seconds"]), flush=True)
+        S.close()
+        return
     S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], auto_depth=0,
                sweep_tile_rows=args.tile_rows)
     out = {"n": args.n, "cells": args.n * args.n}

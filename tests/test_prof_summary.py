@@ -1,0 +1,87 @@
+"""Host logic of the profile summaries (no GPU): the per-level split of a
+V-cycle from a synthetic kernel trace, the trace table and the counter
+scaling of the HBM traffic record."""
+import csv
+import json
+
+from paper_2504_00724_amd import prof_summary as P
+
+
+def _trace(path, launches, gap0=1000000):
+    """launches: [(name, duration_ns, gap_before_ns)] written as a kernel trace csv."""
+    t = 0
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, d, gap in launches:
+            t += gap
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": t, "End_Timestamp": t + d})
+            t += d
+
+
+def _cycle(levels, nu=2):
+    """A V-cycle on `levels` levels (0 finest): nu fused steps and a
+    restriction per level going down, the coarsest solve, then nu fused
+    steps per level going up (the first applying the correction), the norm."""
+    out = []
+    for m in range(levels - 1):
+        out += [("void k_smooth_fused<double, false, %s, 16, false>(...)" % ("true" if m == 0 else "false"),
+                 1000 * (levels - m), 0)] * nu
+        out.append(("void k_restrict<double, double, false, false>(...)", 500, 0))
+    out.append(("void k_coarse<double>(...)", 700, 0))
+    for m in range(levels - 2, -1, -1):
+        fin = "true" if m == 0 else "false"
+        out.append(("void k_smooth_fused<double, false, %s, 16, true>(...)" % fin, 1000 * (levels - m), 0))
+        out += [("void k_smooth_fused<double, false, %s, 16, false>(...)" % fin, 1000 * (levels - m), 0)] * (nu - 1)
+    out.append(("void k_resnorm<double, false>(...)", 300, 0))
+    out.append(("__amd_rocclr_copyBuffer", 100, 50000))
+    return out
+
+
+def test_cycle_split_by_level(tmp_path, capsys):
+    path = tmp_path / "t_kernel_trace.csv"
+    launches = [("k_gj_elim", 100, 0)] * 5                      # set-up, then an idle gap
+    solve = []
+    for _ in range(3):
+        solve += _cycle(4)
+    launches += [(n, d, g) for n, d, g in solve]
+    launches[5] = (launches[5][0], launches[5][1], 400000)      # the solve starts after a long gap
+    _trace(path, launches)
+
+    class A:
+        pass
+    a = A()
+    a.path = str(path)
+    P.cmd_cycle(a)
+    out = capsys.readouterr().out
+    rows = {l.split("|")[1].strip(): l for l in out.splitlines() if l.startswith("| ")}
+    # per level: 2 down + 2 up fused steps + 1 restriction (levels 0..2); level 3 is the coarsest
+    for m in range(3):
+        cells = [c.strip() for c in rows[str(m)].split("|")]
+        assert cells[2] == "5"
+        assert abs(float(cells[3]) - (4 * (4 - m) + 0.5)) < 1e-9
+    assert "`k_coarse<double>`" in rows and "`k_resnorm<double, false>`" in rows
+
+
+def test_traffic_record_scaling(tmp_path, capsys):
+    def counters(path, counter, vals):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for k, v in vals:
+                w.writerow({"Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
+    cells = 1024
+    known = 8.0 * cells / 1024.0                                  # KiB the copy reads and writes
+    counters(tmp_path / "f.csv", "FETCH_SIZE", [("k_copy", known / 2), ("k_x", 10.0)])
+    counters(tmp_path / "w.csv", "WRITE_SIZE", [("k_copy", known), ("k_x", 3.0)])
+
+    class A:
+        pass
+    a = A()
+    a.fetch, a.write, a.cells, a.kernel, a.calib_kernel = str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), cells, \
+        "k_x", "k_copy"
+    P.cmd_pmc(a)
+    out = capsys.readouterr().out
+    rec = json.loads(out.split("<!-- traffic-record ")[1].rsplit("-->", 1)[0])
+    assert abs(rec["scale_fetch"] - 2.0) < 1e-12 and abs(rec["scale_write"] - 1.0) < 1e-12
+    assert abs(rec["traffic_bytes_per_launch"] - (10.0 * 2.0 + 3.0) * 1024.0) < 1e-9

@@ -305,7 +305,7 @@ def main():
                     help="1: every batch context tunes its own smoothing schedule (slower set-up)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":

@@ -169,6 +169,10 @@ void ccgmg_default_options(ccgmg_options* opts);
 int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves, double a, double b,
                  double c, const ccgmg_options* opts, ccgmg_ctx** out);
 
+/* Sizes and set-up results of a context (unknowns, irregular cells,
+ * boundary faces, levels, the coarsest level, set-up time, largest lattice
+ * condition number, the schedule in use).  info: host, written.
+ * CCGMG_EINVAL for a NULL argument. */
 int ccgmg_query(const ccgmg_ctx* ctx, ccgmg_info* info);
 
 /* Level-m classification (host arrays of nx_m * ny_m entries):
@@ -202,8 +206,18 @@ int ccgmg_get_tuning(const ccgmg_ctx* ctx, int level, int* sweep_ty_fp64, int* s
  * the blocks' dense inverses (computed in FP64, stored in FP32, applied in
  * FP64 arithmetic).  Device contexts only. */
 int ccgmg_get_smo2_stats(const ccgmg_ctx* ctx, int level, int adjoint, long* stats);
+/* Least-squares rows of level m (Section 3.3, eq. derivedCoefAgain; lattices
+ * by the R-PLG rule for Section 2.2): rows[k] is the linear index of the
+ * k-th irregular cell (n_irregular entries, increasing), cols[15 k ..
+ * 15 k + 14] its lattice cells (sorted linear indices), vals[15 k ..] the
+ * weights of L on them (1/h^2 units, the cell's own weight included),
+ * cond[k] the 2-norm condition number of the lattice's cell sample matrix.
+ * Host arrays of the sizes given by ccgmg_get_counts; any may be NULL.
+ * CCGMG_EINVAL for a bad level.  ccgmg_get_stencils is the same without
+ * cond. */
 int ccgmg_get_irregular(const ccgmg_ctx* ctx, int level, int32_t* rows, int32_t* cols, double* vals,
                         double* cond);
+int ccgmg_get_stencils(const ccgmg_ctx* ctx, int level, int32_t* rows, int32_t* cols, double* vals);
 
 /* Boundary faces of level 0 in g-hat order: face k belongs to cell[k] and
  * curve[k]; its weight in row cell[k] of N is nweight[k] (so that
@@ -274,8 +288,10 @@ int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double
  * V-cycle of every geometry (FP64 or mixed precision, as each context was
  * created) is captured into a single hipGraph whose branches run
  * concurrently, and the graph is replayed until every geometry's relative
- * residual is below its own tol (a converged geometry keeps cycling while
- * others finish).  Work is ordered after the stream of ctxs[0].  Contexts
+ * residual is below its own tol; once a geometry has converged it is left
+ * as it is (branches: only the active geometries' cycle graphs are
+ * launched; lockstep: device flags mask its workgroups) while the others
+ * finish.  Work is ordered after the stream of ctxs[0].  Contexts
  * must outlive the batch and must not be used by other calls while a batch
  * solve runs.  Not a paper construct: the batched use of the solve of
  * Section 4 (Alg. 2) for many independent problems. */
@@ -299,7 +315,10 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
  * CCGMG_ENOCONV if any geometry did not reach its tolerance. */
 int ccgmg_batch_solve(ccgmg_batch* batch, const double* const* f, double* const* u, const int* nrhs,
                       ccgmg_report* reps);
+/* Error text of the batch's last failed call (owned by the batch). */
 const char* ccgmg_batch_last_error(const ccgmg_batch* batch);
+/* Frees the batch (its graphs, streams and descriptor tables); the
+ * contexts stay the caller's. */
 void ccgmg_batch_destroy(ccgmg_batch* batch);
 
 /* Re-choose the smoothing schedule and the depth (as auto_depth 2 /
@@ -311,11 +330,15 @@ void ccgmg_batch_destroy(ccgmg_batch* batch);
  * fixes its cycle parameters); a measured autotuner of this library. */
 int ccgmg_tune(ccgmg_ctx* ctx, const double* f);
 
+/* Error text of the context's last failed call (owned by the context,
+ * valid until its next call). */
 const char* ccgmg_last_error(const ccgmg_ctx* ctx);
 
 /* Error text of the last failed ccgmg_create on this thread. */
 const char* ccgmg_create_error(void);
 
+/* Frees the context and all its device and pinned host memory; NULL is
+ * ignored. */
 void ccgmg_destroy(ccgmg_ctx* ctx);
 
 #ifdef __cplusplus

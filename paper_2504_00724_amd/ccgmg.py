@@ -21,7 +21,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTELLIPTIC", -3: "EGEOM", -4: "EPLG", -5
           -7: "EDEVICE", -8: "ENOMEM"}
 
 EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
-           "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_boundary_faces",
+           "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_stencils", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
            "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
            "ccgmg_profile_kernel", "ccgmg_get_tuning", "ccgmg_get_smo2_stats", "ccgmg_tune",
@@ -83,6 +83,7 @@ def lib():
         L.ccgmg_get_volumes.argtypes = [vp, ip, vp]
         L.ccgmg_get_counts.argtypes = [vp, ip, C.POINTER(C.c_long), C.POINTER(C.c_long)]
         L.ccgmg_get_irregular.argtypes = [vp, ip, vp, vp, vp, vp]
+        L.ccgmg_get_stencils.argtypes = [vp, ip, vp, vp, vp]
         L.ccgmg_get_boundary_faces.argtypes = [vp, vp, vp, vp]
         L.ccgmg_get_alg3_order.argtypes = [vp, ip, vp]
         L.ccgmg_cell_quadrature.argtypes = [vp, C.POINTER(C.c_long), vp, vp, vp, vp]

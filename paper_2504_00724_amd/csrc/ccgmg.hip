@@ -1759,6 +1759,10 @@ int ccgmg_get_irregular(const ccgmg_ctx* X, int level, int32_t* rows, int32_t* c
   return CCGMG_OK;
 }
 
+int ccgmg_get_stencils(const ccgmg_ctx* X, int level, int32_t* rows, int32_t* cols, double* vals) {
+  return ccgmg_get_irregular(X, level, rows, cols, vals, nullptr);
+}
+
 int ccgmg_get_boundary_faces(const ccgmg_ctx* X, int32_t* cell, int32_t* curve, double* nweight) {
   if (!X) return CCGMG_EINVAL;
   const ccg::Discretization& D = X->H.disc[0];

@@ -215,6 +215,15 @@ class Solver:
         self._check(lib().ccgmg_get_irregular(self.ctx, level, _ptr(rows), _ptr(cols), _ptr(vals), _ptr(cond)))
         return rows, cols.reshape(ni, 15), vals.reshape(ni, 15), cond
 
+    def stencils(self, level=0):
+        """(rows, cols, weights) of the least-squares rows (ccgmg_get_stencils)."""
+        ni, _ = self.counts(level)
+        rows = np.zeros(ni, dtype=np.int32)
+        cols = np.zeros(ni * 15, dtype=np.int32)
+        vals = np.zeros(ni * 15)
+        self._check(lib().ccgmg_get_stencils(self.ctx, level, _ptr(rows), _ptr(cols), _ptr(vals)))
+        return rows, cols.reshape(ni, 15), vals.reshape(ni, 15)
+
     def boundary_faces(self):
         nf = self.info["n_bdry_faces"]
         cell = np.zeros(nf, dtype=np.int32)

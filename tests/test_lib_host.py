@@ -192,3 +192,15 @@ def test_polygon_rejects_bad_quadrilaterals():
         with pytest.raises(ccgmg.CcgmgError) as ei:
             ccgmg.Solver(g, [c], 1.0, 0.0, 1.0, host_only=1)
         assert ei.value.code == ccgmg.EGEOM
+
+
+def test_get_stencils_matches_get_irregular():
+    _lib_or_skip()
+    cfg = W.config(2, n=64)
+    S = ccgmg.Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], host_only=1)
+    rows, cols, vals, _ = S.irregular(1)
+    r2, c2, v2 = S.stencils(1)
+    assert np.array_equal(rows, r2) and np.array_equal(cols, c2) and np.array_equal(vals, v2)
+    with pytest.raises(ccgmg.CcgmgError):
+        S.stencils(99)
+    S.close()

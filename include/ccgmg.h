@@ -124,7 +124,8 @@ typedef struct {
   int tune_schedule;     /* 1 (default, with auto_depth 2): also time the schedules
                             (smoother_fused, nu1, nu2 / coarse) = (0,3,3), (1,3,3),
                             (1,4,4), (1,5,5), (1,4,4/2,2), (1,5,5/2,2), (1,5,5/3,3),
-                            (1,6,6/3,3) and keep the fastest; 0: use the fields above   */
+                            (1,6,6/3,3), (1,4,4/3,4), (1,4,4/2,5) and keep the fastest;
+                            0: use the fields above                                      */
   int inverse_fp32;      /* storage of the dense inverses (SMO-2 blocks, coarsest level),
                             computed in FP64 and always applied in FP64 arithmetic:
                             1 (default) FP32, 0 FP64                                      */

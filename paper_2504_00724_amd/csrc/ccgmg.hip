@@ -1048,7 +1048,8 @@ void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
   std::vector<Sched> cands;
   if (X->opt.tune_schedule)
     cands = {{0, 3, 3, 0, 0}, {1, 3, 3, 0, 0}, {1, 4, 4, 0, 0}, {1, 5, 5, 0, 0},
-             {1, 4, 4, 2, 2}, {1, 5, 5, 2, 2}, {1, 5, 5, 3, 3}, {1, 6, 6, 3, 3}};
+             {1, 4, 4, 2, 2}, {1, 5, 5, 2, 2}, {1, 5, 5, 3, 3}, {1, 6, 6, 3, 3},
+             {1, 4, 4, 3, 4}, {1, 4, 4, 2, 5}};   // fewer pre- than post-steps on the coarse levels
   else
     cands = {{X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse}};
   const int Mmax = (int)X->H.disc.size() - 1;

@@ -506,7 +506,8 @@ struct Driver {
                          S.cbuf[0], S.ns, L.n);
   }
 
-  // a recorded cycle must leave the current copy where it found it
+  // a recorded cycle must leave the finest level's current copy where it
+  // found it (its values carry over from one cycle to the next)
   void settle_rows(DevLevel& L) {
     Smo2Data& S = rows(L).smo2;
     if (S.cur != 0 && S.ns > 0) {
@@ -585,7 +586,9 @@ struct Driver {
       prolong<T>(L, C, cur, e);
       out = smooth<T>(L, cur, oth, r, bterm, n2);
     }
-    settle_rows(L);
+    // coarse levels need no settling: the restriction onto them rewrites
+    // (zeroes) copy 0 and makes it current at the start of every visit
+    if (m == 0) settle_rows(L);
     return out;
   }
 

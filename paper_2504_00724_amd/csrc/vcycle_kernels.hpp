@@ -444,7 +444,7 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
                                                 const double* __restrict__ vals, const double* __restrict__ rowsum,
                                                 int nrows, float* __restrict__ res_out) {
   __shared__ T tile[LH][LW];
-  __shared__ double red[BLOCK];
+  __shared__ double red[BLOCK / 64];
   double m = 0.0;
   if (l >= nrb) {
     const int t = xcd_tile(l - nrb, ntiles);
@@ -485,13 +485,14 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
       m = fabs(rhs);
     }
   }
-  red[threadIdx.x] = m;
+  // maximum within each wavefront, then over the workgroup's wavefronts
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  for (int st = BLOCK / 2; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
-    __syncthreads();
-  }
-  return red[0];
+  double out = red[0];
+#pragma unroll
+  for (int w = 1; w < BLOCK / 64; ++w) out = fmax(out, red[w]);
+  return out;
 }
 
 template <typename T, bool CROSS>
@@ -526,15 +527,37 @@ __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ 
   const int row = wg * 4 + (threadIdx.x >> 6);
   if (row >= nm) return;
   double s0 = 0.0, s1 = 0.0;
-  auto dot = [&](const auto* A) {   // inverse stored in FP32 or FP64, applied in FP64
+  if (inv64) {
+    const double* A = inv64 + (size_t)row * nm;
     int k = lane;
-    for (; k + 64 < nm; k += 128) s0 += (double)A[k] * rv[k], s1 += (double)A[k + 64] * rv[k + 64];
-    if (k < nm) s0 += (double)A[k] * rv[k];
-  };
-  if (inv64)
-    dot(inv64 + (size_t)row * nm);
-  else
-    dot(inv + (size_t)row * nm);
+    for (; k + 64 < nm; k += 128) s0 += A[k] * rv[k], s1 += A[k + 64] * rv[k + 64];
+    if (k < nm) s0 += A[k] * rv[k];
+  } else {
+    // FP32 row read as 16-byte vectors (the stream is latency-bound with
+    // 4-byte loads): the 0-3 entries before the first 16-byte boundary, the
+    // aligned body, then the remaining 0-3 entries
+    const float* A = inv + (size_t)row * nm;
+    const int head = min((int)(((16 - (reinterpret_cast<uintptr_t>(A) & 15)) & 15) >> 2), nm);
+    if (lane < head) s0 += (double)A[lane] * rv[lane];
+    const int nb = (nm - head) >> 2;
+    const float4* A4 = reinterpret_cast<const float4*>(A + head);
+    const double* rb = rv + head;
+    int q = lane;
+    for (; q + 64 < nb; q += 128) {
+      const float4 a = A4[q], b = A4[q + 64];
+      const double* x = rb + 4 * q;
+      const double* y = rb + 4 * (q + 64);
+      s0 += (double)a.x * x[0] + (double)a.y * x[1] + (double)a.z * x[2] + (double)a.w * x[3];
+      s1 += (double)b.x * y[0] + (double)b.y * y[1] + (double)b.z * y[2] + (double)b.w * y[3];
+    }
+    if (q < nb) {
+      const float4 a = A4[q];
+      const double* x = rb + 4 * q;
+      s0 += (double)a.x * x[0] + (double)a.y * x[1] + (double)a.z * x[2] + (double)a.w * x[3];
+    }
+    const int k = head + 4 * nb + lane;
+    if (k < nm) s1 += (double)A[k] * rv[k];
+  }
   double s = s0 + s1;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) u[cell[row]] = (T)s;

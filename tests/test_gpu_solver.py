@@ -464,3 +464,35 @@ def test_inverse_storage_fp64_and_fp32(precision):
         S.close()
     for a, b in zip(cycles[0], cycles[1]):
         assert abs(a - b) <= 1
+
+
+@pytest.mark.parametrize("k,n,levels", [(4, 128, 2), (1, 72, 16), (2, 64, 2)])
+def test_one_cycle_fp32_inverses_close_to_fp64(k, n, levels):
+    """One V-cycle from zero with the dense inverses stored in FP32 against
+    the same cycle with FP64 storage (fixed schedule and depth, so the two
+    differ only in the storage of the inverses): the iterates agree to a few
+    FP32 roundings, far below what one dropped, repeated or shifted term of
+    the coarsest product or of a block product would change.  Ragged
+    coarsest sizes (rows starting at every offset modulo 4) come with the
+    geometry; two levels put the coarsest grid at half the finest."""
+    dev = _dev()
+    cfg, lv = _level(k, n)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    out = {}
+    for fp32 in (1, 0):
+        S = _solver(cfg, tol=1e-14, max_cycles=1, inverse_fp32=fp32, tune_schedule=0, auto_depth=0,
+                    max_levels=levels, nu1=3, nu2=3)
+        S.set_boundary(torch.tensor(g, device=dev), 1)
+        u = torch.zeros(lv.nx * lv.ny, dtype=torch.float64, device=dev)
+        rep = S.solve(torch.tensor(f, device=dev), u, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        assert rep["cycles"] == 1
+        out[fp32] = (u.cpu().numpy(), S.info["n_levels"], S.info["coarse_unknowns"])
+        S.close()
+    (a, la, na), (b, lb, nb) = out[1], out[0]
+    assert (la, na) == (lb, nb)
+    rel = np.max(np.abs(a - b)) / np.max(np.abs(b))
+    print("   levels %d, coarsest unknowns %d (mod 4: %d), one-cycle difference %.2e" % (la, na, na % 4, rel),
+          flush=True)
+    assert rel <= 1e-5

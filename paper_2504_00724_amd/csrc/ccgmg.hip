@@ -143,6 +143,7 @@ struct ccgmg_ctx {
   double* bterm = nullptr;          // [max_nrhs][nirr0]
   int g_nrhs = 0;
   double* norm_host = nullptr;      // pinned: partial maxima of the residual norm (level 0)
+  double* norm_host2 = nullptr;     // a second one: cycles alternate between the two
   double setup_seconds = 0;
   double plg_max_cond = 0;
   std::string err;
@@ -151,8 +152,9 @@ struct ccgmg_ctx {
   // events) so that each V-cycle can be captured into a hipGraph
   hipStream_t ws = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_cyc[2] = {nullptr, nullptr};   // ends of the cycles in flight (alternating)
   struct GraphEntry {
-    const void *u, *f, *bterm;
+    const void *u, *f, *bterm, *norm;
     int nrhs, precision, M;
     bool adjoint;
     hipGraphExec_t exec;
@@ -876,8 +878,9 @@ const double* solve_prologue(Driver& Dr, const double* f, double* u) {
 }
 
 // One V-cycle (FP64, or FP32 inside one FP64 refinement step), the FP64
-// residual check and its read-back, on stream Dr.s (recordable in a graph).
-void solve_cycle(Driver& Dr, double* u, const double* f, const double* bterm) {
+// residual check and its read-back into norm_dst (pinned; default
+// norm_host), on stream Dr.s (recordable in a graph).
+void solve_cycle(Driver& Dr, double* u, const double* f, const double* bterm, double* norm_dst = nullptr) {
   ccgmg_ctx* X = Dr.X;
   DevLevel& L0 = X->lv[0];
   const bool mp = X->opt.precision == 1;
@@ -888,7 +891,7 @@ void solve_cycle(Driver& Dr, double* u, const double* f, const double* bterm) {
   // the residual check; in mixed precision it also leaves the FP32 residual
   // for the next refinement step
   Dr.resmax<double>(L0, u, f, bterm, 0, mp ? L0.r32 : nullptr);
-  HIP_OK(hipMemcpyAsync(X->norm_host, L0.part, sizeof(double) * Dr.norm_parts(L0) * Dr.nrhs,
+  HIP_OK(hipMemcpyAsync(norm_dst ? norm_dst : X->norm_host, L0.part, sizeof(double) * Dr.norm_parts(L0) * Dr.nrhs,
                         hipMemcpyDeviceToHost, Dr.s));
 }
 
@@ -898,22 +901,30 @@ struct Monitor {
   int nparts = 0, cycles = 0, hist = 0, slow = 0;
   double prev = 1e300, rel = 1.0;
   bool converged = false, stopped = false;
+  bool guess = false;   // the solve starts from the caller's iterate
   void start(ccgmg_ctx* X, int nrhs, int np) {
     nparts = np;
     rn.assign(nrhs, 1.0);
+    rel = 0.0;
     for (int z = 0; z < nrhs; ++z) {
       const double m = norm_of(X, nparts, z);
       rn[z] = m > 0 ? m : 1.0;
+      if (m > 0) rel = 1.0;
     }
+    guess = X->opt.use_initial_guess != 0;
   }
+  double fmin = 1.0;   // smallest contraction factor seen so far
   // after a cycle; returns true when this solve is finished
   bool step(ccgmg_ctx* X, ccgmg_report* rep, const double* part = nullptr) {
+    converged = stopped = false;
     ++cycles;
+    const double before = cycles > 1 ? prev : 1.0;
     rel = 0;
     for (size_t z = 0; z < rn.size(); ++z) rel = std::max(rel, norm_of(X, nparts, (int)z, part) / rn[z]);
     if (rep && hist < 64) rep->history[hist++] = rel;
     if (!std::isfinite(rel)) return stopped = true;
     if (rel <= X->opt.tol) return converged = stopped = true;
+    if (before > 0.0) fmin = std::min(fmin, rel / before);
     if (rel > 0.95 * prev) {
       if (++slow >= 3) return stopped = true;
     } else {
@@ -923,21 +934,35 @@ struct Monitor {
     if (cycles >= X->opt.max_cycles) return stopped = true;
     return false;
   }
+  // true when the next cycle cannot end the solve, so the one after it may
+  // be enqueued before its residual is read: it stays below max_cycles and
+  // the stagnation count, and its residual cannot reach tol even if it
+  // contracts 10x better than the best cycle so far (1e-3 before any cycle
+  // is measured, and then only from a zero start with a non-zero residual:
+  // the caller's iterate may already be close)
+  bool next_not_final(ccgmg_ctx* X) const {
+    if (stopped || cycles + 1 >= X->opt.max_cycles || slow + 1 >= 3) return false;
+    if (cycles == 0 && guess) return false;
+    const double f = cycles > 0 ? 0.1 * fmin : 1e-3;
+    return std::isfinite(rel) && rel * f > X->opt.tol;
+  }
 };
 
 // The captured graph of one cycle of this solve (cached per context, keyed
-// by its arrays, right-hand-side count, precision, depth and direction);
-// recorded on stream Dr.s, launchable on any stream.
-hipGraphExec_t cycle_graph(Driver& Dr, double* u, const double* f, const double* bterm) {
+// by its arrays, norm read-back buffer, right-hand-side count, precision,
+// depth and direction); recorded on stream Dr.s, launchable on any stream.
+hipGraphExec_t cycle_graph(Driver& Dr, double* u, const double* f, const double* bterm,
+                           double* norm_dst = nullptr) {
   ccgmg_ctx* X = Dr.X;
+  if (!norm_dst) norm_dst = X->norm_host;
   for (auto& g : X->graphs)
-    if (g.u == u && g.f == f && g.bterm == bterm && g.nrhs == Dr.nrhs && g.precision == X->opt.precision &&
-        g.M == X->M && g.adjoint == Dr.adjoint)
+    if (g.u == u && g.f == f && g.bterm == bterm && g.norm == norm_dst && g.nrhs == Dr.nrhs &&
+        g.precision == X->opt.precision && g.M == X->M && g.adjoint == Dr.adjoint)
       return g.exec;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph;
   HIP_OK(hipStreamBeginCapture(Dr.s, hipStreamCaptureModeThreadLocal));
-  solve_cycle(Dr, u, f, bterm);
+  solve_cycle(Dr, u, f, bterm, norm_dst);
   HIP_OK(hipStreamEndCapture(Dr.s, &graph));
   HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   (void)hipGraphDestroy(graph);
@@ -945,7 +970,7 @@ hipGraphExec_t cycle_graph(Driver& Dr, double* u, const double* f, const double*
     (void)hipGraphExecDestroy(X->graphs.front().exec);
     X->graphs.erase(X->graphs.begin());
   }
-  X->graphs.push_back({u, f, bterm, Dr.nrhs, X->opt.precision, X->M, Dr.adjoint, exec});
+  X->graphs.push_back({u, f, bterm, norm_dst, Dr.nrhs, X->opt.precision, X->M, Dr.adjoint, exec});
   return exec;
 }
 
@@ -964,15 +989,34 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     HIP_OK(hipStreamSynchronize(ws));
     Monitor mon;
     mon.start(X, nrhs, Dr.norm_parts(X->lv[0]));
-    hipGraphExec_t exec = X->opt.use_graph ? cycle_graph(Dr, u, f, bterm) : nullptr;
+    // cycle k reads its residual back into buffer k mod 2 and records event
+    // k mod 2; while the host checks cycle k, cycle k + 1 may already run
+    // (enqueued only when cycle k cannot end the solve), which hides the
+    // host's round trip without running a cycle more than a synchronous
+    // loop would
+    double* nb[2] = {X->norm_host, X->norm_host2};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    if (X->opt.use_graph)
+      for (int k = 0; k < 2; ++k) exec[k] = cycle_graph(Dr, u, f, bterm, nb[k]);
     if (rep) std::memset(rep, 0, sizeof(*rep));
-    for (;;) {
-      if (exec)
-        HIP_OK(hipGraphLaunch(exec, ws));
+    int launched = 0, done = 0;
+    auto launch = [&]() {
+      const int k = launched++ & 1;
+      if (exec[k])
+        HIP_OK(hipGraphLaunch(exec[k], ws));
       else
-        solve_cycle(Dr, u, f, bterm);
-      HIP_OK(hipStreamSynchronize(ws));
-      if (mon.step(X, rep)) break;
+        solve_cycle(Dr, u, f, bterm, nb[k]);
+      HIP_OK(hipEventRecord(X->ev_cyc[k], ws));
+    };
+    launch();
+    for (;;) {
+      if (launched == done + 1 && mon.next_not_final(X)) launch();
+      HIP_OK(hipEventSynchronize(X->ev_cyc[done & 1]));
+      const bool fin = mon.step(X, rep, nb[done & 1]);
+      ++done;
+      if (launched > done) continue;   // a later cycle already ran: its check decides
+      if (fin) break;
+      launch();
     }
     HIP_OK(hipEventRecord(e1, ws));
     HIP_OK(hipEventRecord(X->ev_out, ws));
@@ -1613,6 +1657,7 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       HIP_OK(hipStreamCreateWithFlags(&X->ws, hipStreamNonBlocking));
       HIP_OK(hipEventCreateWithFlags(&X->ev_in, hipEventDisableTiming));
       HIP_OK(hipEventCreateWithFlags(&X->ev_out, hipEventDisableTiming));
+      for (hipEvent_t& e : X->ev_cyc) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       const int maxr = X->opt.max_nrhs;
       X->lv.resize(X->H.disc.size());
       for (size_t m = 0; m < X->H.disc.size(); ++m) upload_level(X.get(), (int)m, maxr);
@@ -1631,9 +1676,9 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       X->g = dalloc<double>((size_t)std::max(1, X->nfaces) * maxr, X->owned);
       X->bterm = dalloc<double>((size_t)std::max(1, (int)D0.irr.size()) * maxr, X->owned);
       if (maxr > 1) X->mrg = dalloc<double>((size_t)MAX_COARSE_UNKNOWNS * maxr, X->owned);
-      HIP_OK(hipHostMalloc((void**)&X->norm_host,
-                           sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
-                           hipHostMallocDefault));
+      for (double** p : {&X->norm_host, &X->norm_host2})
+        HIP_OK(hipHostMalloc((void**)p, sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
+                             hipHostMallocDefault));
       // the coarsest level must be small enough for the dense inverse
       while (X->M > 0) {
         long nu = 0;
@@ -2119,7 +2164,10 @@ void ccgmg_destroy(ccgmg_ctx* X) {
     if (X->ev_in) (void)hipEventDestroy(X->ev_in);
     if (X->ev_out) (void)hipEventDestroy(X->ev_out);
     for (void* p : X->owned) (void)hipFree(p);
+    for (hipEvent_t e : X->ev_cyc)
+      if (e) (void)hipEventDestroy(e);
     if (X->norm_host) (void)hipHostFree(X->norm_host);
+    if (X->norm_host2) (void)hipHostFree(X->norm_host2);
   }
   delete X;
 }

@@ -481,6 +481,9 @@ struct Driver {
   template <typename T>
   void fused_step(DevLevel& L, const T* u, const T* r, T* out, const double* bterm, const T* e = nullptr,
                   const DevLevel* C = nullptr) {
+    // the correction is read at the parent of every in-grid cell
+    if (e && (!C || L.nx != 2 * C->nx || L.ny != 2 * C->ny))
+      throw ccg::Error(CCGMG_EINVAL, "coarse level is not the fine level halved");
     const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
     const bool fin = &L == &X->lv[0];
     if (L.cross) {

@@ -60,15 +60,20 @@ __device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restr
   }
   if (PRO) {
     // tile of u + P e: the pending coarse-grid correction (piecewise
-    // constant, cells flagged probit only) is added while staging
+    // constant, cells flagged probit only) is added while staging.  A level
+    // with a coarser one has even sides, so the parent (gy/2, gx/2) of an
+    // in-grid cell is a coarse cell: its value is loaded alongside u and
+    // kind (no load waits for the flag) and selected by the flag
     for (int k = threadIdx.x; k < ROWS * LW; k += BLOCK) {
       const int ly = k / LW, lx = k - ly * LW;
       const int gx = bx + lx - HALO, gy = by + ly - HALO;
       T v = (T)0;
       if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
         const size_t g = (size_t)gy * nx + gx;
-        v = u[g];
-        if (kind[g] & probit) v += e[(size_t)(gy >> 1) * ncx + (gx >> 1)];
+        const T uv = u[g];
+        const uint8_t kb = kind[g];
+        const T ev = e[(size_t)(gy >> 1) * ncx + (gx >> 1)];
+        v = (kb & probit) ? uv + ev : uv;
       }
       tile[ly][lx] = v;
     }

@@ -496,3 +496,35 @@ def test_one_cycle_fp32_inverses_close_to_fp64(k, n, levels):
     print("   levels %d, coarsest unknowns %d (mod 4: %d), one-cycle difference %.2e" % (la, na, na % 4, rel),
           flush=True)
     assert rel <= 1e-5
+
+
+def test_solve_stops_at_first_cycle_reaching_tol():
+    """The next V-cycle is queued while the host checks the current one only
+    when the current one cannot end the solve, so a solve runs exactly the
+    cycles a check-after-every-cycle loop runs: it stops at the first cycle
+    whose relative residual reaches tol (at several tolerances, with and
+    without graph replay), and max_cycles bounds the count exactly."""
+    from paper_2504_00724_amd.ccgmg import ENOCONV
+    dev = _dev()
+    cfg, lv = _level(4, 128)
+    f = torch.tensor(cell_averages(lv.cg, cfg["f"]).ravel(), device=dev)
+    g = torch.tensor(boundary_data(lv.disc, cfg["solution"]), device=dev)
+    for graph in (1, 0):
+        for tol in (1e-3, 1e-7, 1e-11):
+            S = _solver(cfg, tol=tol, max_cycles=100, use_graph=graph)
+            S.set_boundary(g, 1)
+            u = torch.zeros(lv.nx * lv.ny, dtype=torch.float64, device=dev)
+            rep = S.solve(f, u)
+            torch.cuda.synchronize()
+            h = rep["history"]
+            print("   graph %d tol %.0e: %d cycles, history %s" % (graph, tol, rep["cycles"],
+                  " ".join("%.1e" % x for x in h)), flush=True)
+            assert len(h) == rep["cycles"] and h[-1] <= tol and all(x > tol for x in h[:-1])
+            S.close()
+        S = _solver(cfg, tol=1e-14, max_cycles=3, use_graph=graph)
+        S.set_boundary(g, 1)
+        u = torch.zeros(lv.nx * lv.ny, dtype=torch.float64, device=dev)
+        rep = S.solve(f, u, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        assert rep["status"] == ENOCONV and rep["cycles"] == 3
+        S.close()

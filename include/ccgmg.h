@@ -253,7 +253,10 @@ int ccgmg_set_boundary(ccgmg_ctx* ctx, const double* g_hat, int nrhs);
 /* Solve L u = f - N g for nrhs right-hand sides: f_hat device
  * [nrhs][ny][nx], u_hat device [nrhs][ny][nx] (initial guess in, solution
  * out).  rep: host, may be NULL.  Returns CCGMG_ENOCONV (with u_hat holding
- * the last iterate) when tol is not reached. */
+ * the last iterate) when tol is not reached.  The residual is checked after
+ * every V-cycle; the next cycle is queued before that check only when the
+ * cycle being checked cannot reach tol (judged from the contraction seen so
+ * far), so the solve stops at the first cycle that reaches tol. */
 int ccgmg_solve(ccgmg_ctx* ctx, const double* f_hat, double* u_hat, int nrhs, ccgmg_report* rep);
 
 /* Adjoint solve L^T lambda = rhs (device arrays as in ccgmg_solve) by

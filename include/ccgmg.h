@@ -246,6 +246,18 @@ int ccgmg_face_quadrature(const ccgmg_ctx* ctx, long* count, int32_t* face_of, d
  * u, Lu: device, nx * ny doubles; may not alias. */
 int ccgmg_apply(ccgmg_ctx* ctx, const double* u, double* Lu);
 
+/* Relative residual norms of a caller's iterate (Fig. 5 reports the
+ * relative residual): for each of nrhs planes, with res = f - N g - L u and
+ * ref = f - N g over the non-empty level-0 cells (the boundary data last
+ * set), rel_inf[z] = max|res| / max|ref| and rel_l2[z] = ||res||_2 /
+ * ||ref||_2 (plain sums of squares; a zero reference divides by 1).
+ * f_hat, u_hat: device [nrhs][ny][nx]; rel_inf, rel_l2: host arrays of nrhs
+ * doubles, either may be NULL (not both).  Synchronous; allocates a small
+ * device buffer.  rel_inf is computed cell by cell as a solve's
+ * convergence check computes it. */
+int ccgmg_residual_norms(ccgmg_ctx* ctx, const double* f_hat, const double* u_hat, int nrhs, double* rel_inf,
+                         double* rel_l2);
+
 /* Set the boundary data g-hat (device, n_bdry_faces * nrhs doubles, face
  * fastest).  The library copies it; nrhs <= max_nrhs. */
 int ccgmg_set_boundary(ccgmg_ctx* ctx, const double* g_hat, int nrhs);

@@ -22,7 +22,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTELLIPTIC", -3: "EGEOM", -4: "EPLG", -5
 
 EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_stencils", "ccgmg_get_boundary_faces",
-           "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply",
+           "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply", "ccgmg_residual_norms",
            "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
            "ccgmg_profile_kernel", "ccgmg_get_tuning", "ccgmg_get_smo2_stats", "ccgmg_tune",
            "ccgmg_batch_create", "ccgmg_batch_solve", "ccgmg_batch_last_error", "ccgmg_batch_destroy",
@@ -89,6 +89,7 @@ def lib():
         L.ccgmg_cell_quadrature.argtypes = [vp, C.POINTER(C.c_long), vp, vp, vp, vp]
         L.ccgmg_face_quadrature.argtypes = [vp, C.POINTER(C.c_long), vp, vp, vp, vp, vp, vp]
         L.ccgmg_apply.argtypes = [vp, vp, vp]
+        L.ccgmg_residual_norms.argtypes = [vp, vp, vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ccgmg_set_boundary.argtypes = [vp, vp, ip]
         L.ccgmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
         L.ccgmg_solve_adjoint.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
@@ -256,6 +257,13 @@ class Solver:
     # -- device calls ------------------------------------------------------------
     def apply(self, u, out):
         self._check(lib().ccgmg_apply(self.ctx, _ptr(u), _ptr(out)))
+
+    def residual_norms(self, f, u, nrhs=1):
+        """Relative L-infinity and L2 residual norms of the iterate u (one
+        value per right-hand side), with the boundary data last set."""
+        ri, r2 = (C.c_double * nrhs)(), (C.c_double * nrhs)()
+        self._check(lib().ccgmg_residual_norms(self.ctx, _ptr(f), _ptr(u), nrhs, ri, r2))
+        return list(ri), list(r2)
 
     def set_boundary(self, g, nrhs=1):
         self._check(lib().ccgmg_set_boundary(self.ctx, _ptr(g), nrhs))

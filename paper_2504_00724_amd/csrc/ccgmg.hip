@@ -33,6 +33,7 @@
 
 #include "ccgmg.h"
 #include "kernels.hpp"
+#include "diag_kernels.hpp"
 #include "setup.hpp"
 #include "vcycle_kernels.hpp"
 
@@ -1866,6 +1867,58 @@ static int apply_impl(ccgmg_ctx* X, const double* u, double* Lu, bool adjoint) {
 }
 
 int ccgmg_apply(ccgmg_ctx* X, const double* u, double* Lu) { return apply_impl(X, u, Lu, false); }
+
+int ccgmg_residual_norms(ccgmg_ctx* X, const double* f, const double* u, int nrhs, double* rel_inf, double* rel_l2) {
+  return guard(X, [&]() {
+    if (!f || !u || nrhs < 1 || nrhs > X->opt.max_nrhs || (!rel_inf && !rel_l2))
+      throw ccg::Error(CCGMG_EINVAL, "bad residual-norm arguments");
+    DevLevel& L0 = X->lv[0];
+    const DevRows& R = L0.fwd;
+    hipStream_t ws = X->ws;
+    HIP_OK(hipEventRecord(X->ev_in, X->stream));
+    HIP_OK(hipStreamWaitEvent(ws, X->ev_in, 0));
+    const double* bterm = nullptr;
+    if (X->nfaces > 0 && X->g_nrhs >= nrhs && R.n > 0) {
+      hipLaunchKernelGGL(k_bterm, dim3((R.n + 255) / 256, nrhs), dim3(256), 0, ws, X->g, X->fptr, X->fface, X->fval,
+                         X->bterm, R.n, X->nfaces);
+      bterm = X->bterm;
+    }
+    const int nbx = tiles_x(L0.nx);
+    const int ntiles = nbx * ((L0.ny + TY - 1) / TY);
+    const int nrb = (R.n + BLOCK - 1) / BLOCK;
+    const int np = ntiles + nrb;
+    const dim3 g(np, 1, nrhs);
+    const size_t per = (size_t)2 * np * nrhs;   // (max, sum of squares) per workgroup and plane
+    double* part = nullptr;
+    HIP_OK(hipMalloc((void**)&part, sizeof(double) * 2 * per));
+    std::unique_ptr<double, void (*)(double*)> hold(part, [](double* p) { (void)hipFree(p); });
+    CoefT<double> c(L0.coef);
+    for (int zero_u = 1; zero_u >= 0; --zero_u) {
+      double* out = part + (zero_u ? 0 : per);
+      if (L0.cross)
+        hipLaunchKernelGGL((k_res_norms<true>), g, dim3(BLOCK), 0, ws, u, f, L0.kind, L0.nx, L0.ny, nbx, ntiles, c,
+                           zero_u, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, out);
+      else
+        hipLaunchKernelGGL((k_res_norms<false>), g, dim3(BLOCK), 0, ws, u, f, L0.kind, L0.nx, L0.ny, nbx, ntiles, c,
+                           zero_u, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, out);
+    }
+    HIP_OK(hipGetLastError());
+    std::vector<double> h(2 * per);
+    HIP_OK(hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * per, hipMemcpyDeviceToHost, ws));
+    HIP_OK(hipStreamSynchronize(ws));
+    for (int z = 0; z < nrhs; ++z) {
+      double m[2] = {0.0, 0.0}, q[2] = {0.0, 0.0};   // [reference, residual]
+      for (int k = 0; k < 2; ++k)
+        for (int b = 0; b < np; ++b) {
+          const double* e = h.data() + k * per + 2 * ((size_t)z * np + b);
+          m[k] = std::max(m[k], e[0]);
+          q[k] += e[1];
+        }
+      if (rel_inf) rel_inf[z] = m[1] / (m[0] > 0 ? m[0] : 1.0);
+      if (rel_l2) rel_l2[z] = std::sqrt(q[1]) / (q[0] > 0 ? std::sqrt(q[0]) : 1.0);
+    }
+  });
+}
 
 int ccgmg_apply_adjoint(ccgmg_ctx* X, const double* lam, double* out) { return apply_impl(X, lam, out, true); }
 

@@ -528,3 +528,43 @@ def test_solve_stops_at_first_cycle_reaching_tol():
         torch.cuda.synchronize()
         assert rep["status"] == ENOCONV and rep["cycles"] == 3
         S.close()
+
+
+def test_residual_norms_match_oracle():
+    """ccgmg_residual_norms against the residual of the oracle's operator:
+    on a seeded random iterate (residual of order one) the relative L-inf
+    and L2 norms of both planes agree to 1e-12; on a converged solve the
+    L-inf value agrees with the solve's own report (the same arithmetic) and
+    both are below tol."""
+    dev = _dev()
+    cfg, lv = _level(4, 128)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    rng = np.random.default_rng(5)
+    U = np.stack([rng.standard_normal(lv.nx * lv.ny) * lv.nonempty, np.zeros(lv.nx * lv.ny)])
+    F = np.stack([f, 2.0 * f])
+    exp_inf, exp_l2 = [], []
+    for z in range(2):
+        ref = rhs_vector(lv, F[z], g)[lv.ne_idx]
+        res = (rhs_vector(lv, F[z], g) - lv.L @ U[z])[lv.ne_idx]
+        exp_inf.append(np.max(np.abs(res)) / np.max(np.abs(ref)))
+        exp_l2.append(np.linalg.norm(res) / np.linalg.norm(ref))
+    S = _solver(cfg, tol=1e-10, max_nrhs=2)
+    S.set_boundary(torch.tensor(np.tile(g, (2, 1)), device=dev), 2)
+    Ft = torch.tensor(F, device=dev)
+    ri, r2 = S.residual_norms(Ft, torch.tensor(U, device=dev), nrhs=2)
+    print("   random iterate: inf %s vs %s, l2 %s vs %s" % (ri, exp_inf, r2, exp_l2), flush=True)
+    for z in range(2):
+        assert abs(ri[z] - exp_inf[z]) <= 1e-12 * exp_inf[z]
+        assert abs(r2[z] - exp_l2[z]) <= 1e-12 * exp_l2[z]
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    u = torch.zeros(lv.nx * lv.ny, dtype=torch.float64, device=dev)
+    rep = S.solve(Ft[0], u)
+    ri, r2 = S.residual_norms(Ft[0], u)
+    print("   converged: inf %.3e (solve %.3e), l2 %.3e" % (ri[0], rep["rel_res_inf"], r2[0]), flush=True)
+    # same per-cell arithmetic as the solve's check; the compiler may still
+    # contract the last product differently (an ulp of |L u| in a residual
+    # 1e10 times smaller)
+    assert abs(ri[0] - rep["rel_res_inf"]) <= 1e-4 * rep["rel_res_inf"]
+    assert ri[0] <= 1e-10 and r2[0] <= 1e-10
+    S.close()

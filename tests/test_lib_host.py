@@ -127,6 +127,9 @@ def test_host_only_context_refuses_device_calls():
     with pytest.raises(ccgmg.CcgmgError) as ei:
         S.apply(buf, buf.copy())
     assert ei.value.code == ccgmg.EINVAL
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        S.residual_norms(buf, buf.copy())
+    assert ei.value.code == ccgmg.EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):

@@ -359,6 +359,8 @@ def main():
     dt = time.perf_counter() - t0
     ms = 1e3 * dt / args.steps
     nu = info["n_unknowns"]
+    # relative L2 residual of the final iterate (after the timed region)
+    res_l2 = S.residual_norms(f, u)[1][0]
     u64 = u.cpu().numpy()
     ne = kinds >= 2
     disc_err = float(np.max(np.abs(u64 - exact)[ne]))
@@ -441,6 +443,7 @@ def main():
                    "sweep_tile_rows": [S.tuning(m)[0] for m in range(info["n_levels"])]},
         "cycles": reps[-1]["cycles"],
         "rel_res_inf": reps[-1]["rel_res_inf"],
+        "rel_res_l2": res_l2,
         "disc_err_inf": disc_err,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -444,6 +444,7 @@ def main():
         "cycles": reps[-1]["cycles"],
         "rel_res_inf": reps[-1]["rel_res_inf"],
         "rel_res_l2": res_l2,
+        "ms_median_device": 1e3 * float(np.median([r["seconds"] for r in reps])),
         "disc_err_inf": disc_err,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

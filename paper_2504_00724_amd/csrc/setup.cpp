@@ -1180,6 +1180,7 @@ struct Fitter {
         }
       }
       std::vector<std::tuple<int, int, int>> feas;  // (cost, max, e)
+      feas.reserve(LA.size());
       for (size_t e = 0; e < LA.size(); ++e) {
         bool ok = true;
         int tot = 0, mx = 0;

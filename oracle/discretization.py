@@ -273,10 +273,18 @@ class Discretization:
     def lattice_pool(self, q):
         """The PLG_POOL most compact feasible lattices (sorted cell lists).
 
+        Every candidate of both families that lies inside K is ranked by
+        (sum of squared distances to q, largest infinity distance,
+        family/axis, enumeration index); the candidates are taken in that
+        order, duplicates dropped, until PLG_POOL distinct lattices are
+        found.  The keys of all candidates are computed (and sorted) before
+        any is taken; only the cell lists are built on demand, in rank order.
+
         Parity unpinned: the paper does not give its PLG algorithm, so which
         poised lattice is chosen is this project's rule (module docstring);
         tests pin only what any valid choice satisfies (15 distinct cells
-        inside K, containing q, poised, exactness of the fitted row)."""
+        inside K, containing q, poised, exactness of the fitted row) and that
+        this pool equals a brute-force enumeration of the rule."""
         nx = self.nx
         qi, qj = q % nx, q // nx
         R = PLG_RADIUS
@@ -284,14 +292,14 @@ class Discretization:
         for dy in range(-R, R + 1):
             for dx in range(-R, R + 1):
                 win[dy + R, dx + R] = self._feasible(qi + dx, qj + dy)
-        ok = np.all(win[_CAND_OFFS[:, :, 1] + R, _CAND_OFFS[:, :, 0] + R], axis=1)
-        ranked = []
-        for e in np.flatnonzero(ok):
-            offs = _CANDIDATES[e]
-            ranked.append(((int(_CAND_SUMSQ[e]), int(_CAND_MAX[e]), 0, int(e)),
-                           sorted((qj + dy) * nx + qi + dx for dx, dy in offs)))
+        # (a) images of the principal lattice: feasibility and keys
+        ok = np.flatnonzero(np.all(win[_CAND_OFFS[:, :, 1] + R, _CAND_OFFS[:, :, 0] + R], axis=1))
+        keys = [(_CAND_SUMSQ[ok], _CAND_MAX[ok], np.zeros(ok.size, dtype=np.int64), ok)]
+        # (b) line lattices: on line d (offset d across the axis) the feasible
+        # cells nearest-first; taking the first k of them costs
+        # cost[d, k] = sum of their squared distances and reaches reach[d, k]
+        lines = {}
         for axis in (0, 1):
-            lines = {}
             avail = np.zeros(2 * R + 1, dtype=np.int64)
             cost = np.zeros((2 * R + 1, 6), dtype=np.int64)
             reach = np.zeros((2 * R + 1, 6), dtype=np.int64)
@@ -301,26 +309,30 @@ class Discretization:
                     dx, dy = (t, d) if axis == 0 else (d, t)
                     if win[dy + R, dx + R]:
                         cl.append((t, (qj + dy) * nx + qi + dx))
-                lines[d] = cl
+                lines[(axis, d)] = cl
                 avail[d + R] = len(cl)
                 for k in range(1, min(5, len(cl)) + 1):
                     t = cl[k - 1][0]
                     cost[d + R, k] = cost[d + R, k - 1] + t * t + d * d
                     reach[d + R, k] = max(reach[d + R, k - 1], abs(t), abs(d))
-            ok = np.all(avail[_LINE_SETS + R] >= _LINE_COUNTS, axis=1)
-            tot = cost[_LINE_SETS + R, _LINE_COUNTS].sum(axis=1)
-            mx = reach[_LINE_SETS + R, _LINE_COUNTS].max(axis=1)
-            feas = np.flatnonzero(ok)
-            # only the most compact few can enter the pool
-            top = feas[np.lexsort((feas, mx[feas], tot[feas]))][:3 * PLG_POOL]
-            for e in top:
-                cells = []
-                for d, k in zip(_LINE_SETS[e], _LINE_COUNTS[e]):
-                    cells += [c for _, c in lines[int(d)][:int(k)]]
-                ranked.append(((int(tot[e]), int(mx[e]), 1 + axis, int(e)), sorted(cells)))
-        ranked.sort(key=lambda r: r[0])
+            feas = np.flatnonzero(np.all(avail[_LINE_SETS + R] >= _LINE_COUNTS, axis=1))
+            tot = cost[_LINE_SETS[feas] + R, _LINE_COUNTS[feas]].sum(axis=1)
+            mx = reach[_LINE_SETS[feas] + R, _LINE_COUNTS[feas]].max(axis=1)
+            keys.append((tot, mx, np.full(feas.size, 1 + axis, dtype=np.int64), feas))
+        sumsq, mxd, fam, enum = (np.concatenate([k[i] for k in keys]) for i in range(4))
+        order = np.lexsort((enum, fam, mxd, sumsq))
+
+        def cells_of(f, e):
+            if f == 0:
+                return sorted((qj + dy) * nx + qi + dx for dx, dy in _CANDIDATES[e])
+            out = []
+            for d, k in zip(_LINE_SETS[e], _LINE_COUNTS[e]):
+                out += [c for _, c in lines[(f - 1, int(d))][:int(k)]]
+            return sorted(out)
+
         pool, seen = [], set()
-        for _, cells in ranked:
+        for r in order:
+            cells = cells_of(int(fam[r]), int(enum[r]))
             key = tuple(cells)
             if key not in seen:
                 seen.add(key)

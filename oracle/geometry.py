@@ -25,7 +25,11 @@ spline boundaries; the workloads here use analytic curves instead):
   neighbour with which it shares the longest stretch of cell edge; then, in
   increasing linear index with live volumes, each interface cell with volume
   <= theta h^2 is merged into the non-empty edge neighbour with the longest
-  common cut face (ties in the order -x, +x, -y, +y).
+  common cut face (ties in the order -x, +x, -y, +y).  Lengths within
+  MERGE_TIE (units of h) of each other are ties: faces of equal length in
+  exact arithmetic (the two legs of a corner triangle cut by a 45-degree
+  edge) come out of the crossing search a few ulps apart, and rounding must
+  not decide between them.
 """
 from __future__ import annotations
 
@@ -44,6 +48,7 @@ POLAR_SAMPLES = 8192      # derivative sampling for polar-curve extrema
 DEGENERATE_CHORD = 1e-10  # sub-arcs shorter than this (in units of h) are dropped
 PERIM_SNAP = 1e-9         # perimeter gaps below this are read as touching
 EXTREMUM_REL = 1e-8       # |x'(t)| (or |y'(t)|) below this times |c'(t)|: an extremum of x (or y)
+MERGE_TIE = 1e-12         # cut-face lengths (units of h) within this of each other tie in Alg. 1
 
 # cell states after Alg. 1
 EMPTY, MERGED, PURE, CUT = 0, 1, 2, 3
@@ -641,7 +646,7 @@ class CutGrid:
                     continue
                 best, bl = None, -1.0
                 for nb, edge in self._neighbours(idx):
-                    if comp.edge_len[edge] > bl:
+                    if comp.edge_len[edge] > bl + MERGE_TIE:
                         best, bl = nb, comp.edge_len[edge]
                 if best is None or bl <= 0.0:
                     raise GeometryError("isolated component in cell %d" % idx)
@@ -662,7 +667,7 @@ class CutGrid:
                 if vol[nb] <= 0.0:
                     continue
                 ap = self.aperture(idx, edge)
-                if ap > bl:
+                if ap > bl + MERGE_TIE:   # a tie keeps the earlier neighbour in -x, +x, -y, +y
                     best, bl = nb, ap
             if best is None:
                 raise GeometryError("small cell %d has no neighbour to merge into" % idx)

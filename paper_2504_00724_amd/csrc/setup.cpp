@@ -14,7 +14,8 @@
 // sharing the longest edge stretch; then, in increasing linear index with
 // live volumes, interface cells of volume <= theta h^2 merge into the
 // non-empty edge neighbour with the longest common cut face (ties -x, +x,
-// -y, +y).
+// -y, +y; lengths within MERGE_TIE of each other tie, so that faces equal
+// in exact arithmetic are not told apart by rounding).
 //
 // Lattices (R-PLG; the paper cites its PLG algorithm without stating it):
 // principal-lattice images q + g(T0 - t) and line lattices (5 rows or
@@ -45,6 +46,7 @@ static const int POLAR_SAMPLES = 8192;
 static const double DEGENERATE_CHORD = 1e-10;
 static const double PERIM_SNAP = 1e-9;
 static const double EXTREMUM_REL = 1e-8;   // |x'| (|y'|) <= this * |c'|: x (y) is extremal there
+static const double MERGE_TIE = 1e-12;     // cut-face lengths (units of h) this close tie in Alg. 1
 static const int PLG_RADIUS = 4;
 static const double COND_MAX = 1e8;
 static const int PLG_POOL = 16;
@@ -735,7 +737,7 @@ void Geometry::merge() {
       int best = -1;
       double bl = -1.0;
       for (int t = 0; t < m; ++t)
-        if (comps[cs[k]].edge_len[nb[t][1]] > bl) best = nb[t][0], bl = comps[cs[k]].edge_len[nb[t][1]];
+        if (comps[cs[k]].edge_len[nb[t][1]] > bl + MERGE_TIE) best = nb[t][0], bl = comps[cs[k]].edge_len[nb[t][1]];
       if (best < 0 || bl <= 0.0) throw Error(-3, "isolated component in cell " + std::to_string(idx));
       members[best].push_back(cs[k]);
     }
@@ -779,7 +781,7 @@ void Geometry::merge() {
     for (int t = 0; t < m; ++t) {
       if (vol[nb[t][0]] <= 0.0) continue;
       double ap = aperture((int)idx, nb[t][1]);
-      if (ap > bl) best = nb[t][0], bl = ap;
+      if (ap > bl + MERGE_TIE) best = nb[t][0], bl = ap;   // a tie keeps the earlier of -x, +x, -y, +y
     }
     if (best < 0) throw Error(-3, "small cell " + std::to_string(idx) + " has no neighbour to merge into");
     if (!members.count(best)) members[best].push_back(square_of(best));

@@ -226,3 +226,96 @@ def test_operator_exact_on_quartics_with_robin_data(k, which, gammas):
     # the Robin faces carry weights (the rows do depend on the Robin data)
     robin_faces = [i for i, (_, c) in enumerate(d.faces) if c == which]
     assert robin_faces
+
+
+def _brute_force_pool(disc, q, pool_size=16, radius=4):
+    """The R-PLG pool by direct enumeration of the rule (module docstring of
+    oracle.discretization): every image of the principal lattice and every
+    line lattice, built cell by cell, kept if inside K, ranked by (sum of
+    squared distances, largest infinity distance, family/axis, enumeration
+    index), duplicates dropped, the first pool_size taken."""
+    import itertools
+    nx, ny = disc.nx, disc.ny
+    qi, qj = q % nx, q // nx
+
+    def feasible(dx, dy):
+        i, j = qi + dx, qj + dy
+        return 0 <= i < nx and 0 <= j < ny and bool(disc.nonempty[j * nx + i])
+
+    def key_of(offs):
+        return (sum(dx * dx + dy * dy for dx, dy in offs), max(max(abs(dx), abs(dy)) for dx, dy in offs))
+
+    ranked = []
+    # (a) q + g(T0 - t): symmetries id, rot90, rot180, rot270, flip-x,
+    # flip-y, transpose, anti-transpose; anchors t in T0 order; duplicates
+    # (as offset sets) keep their first enumeration index
+    sym = [lambda x, y: (x, y), lambda x, y: (-y, x), lambda x, y: (-x, -y), lambda x, y: (y, -x),
+           lambda x, y: (-x, y), lambda x, y: (x, -y), lambda x, y: (y, x), lambda x, y: (-y, -x)]
+    t0 = [(a, b) for a in range(5) for b in range(5 - a)]
+    seen, e = set(), 0
+    for g in sym:
+        for t in t0:
+            offs = tuple(sorted(g(p[0] - t[0], p[1] - t[1]) for p in t0))
+            if offs in seen:
+                continue
+            seen.add(offs)
+            if all(feasible(dx, dy) for dx, dy in offs):
+                ranked.append((key_of(offs) + (0, e), offs))
+            e += 1
+    # (b) line lattices along x (axis 0) and along y (axis 1): q's line and
+    # four others within distance 4, holding a permutation of 5, 4, 3, 2, 1
+    # cells, each line's feasible cells taken nearest-first (ties: negative
+    # side first)
+    along = sorted(range(-radius, radius + 1), key=lambda v: (abs(v), v))
+    others = [d for d in range(-radius, radius + 1) if d != 0]
+    for axis in (0, 1):
+        e = 0
+        for comb in itertools.combinations(others, 4):
+            ls = sorted((0,) + comb)
+            for counts in itertools.permutations((5, 4, 3, 2, 1)):
+                offs, ok = [], True
+                for d, k in zip(ls, counts):
+                    cells = [((t, d) if axis == 0 else (d, t)) for t in along]
+                    cells = [c for c in cells if feasible(*c)]
+                    if len(cells) < k:
+                        ok = False
+                        break
+                    offs += cells[:k]
+                if ok:
+                    ranked.append((key_of(offs) + (1 + axis, e), tuple(sorted(offs))))
+                e += 1
+    ranked.sort(key=lambda r: r[0])
+    pool, seen = [], set()
+    for _, offs in ranked:
+        cells = tuple(sorted((qj + dy) * nx + qi + dx for dx, dy in offs))
+        if cells not in seen:
+            seen.add(cells)
+            pool.append(list(cells))
+            if len(pool) == pool_size:
+                break
+    return pool
+
+
+@pytest.mark.parametrize("case", [1, 2, 4, 5, "P1", "P2N", "P3", "P3R"])
+def test_lattice_pool_equals_brute_force_enumeration(case):
+    """The oracle's R-PLG pool (keys computed by prefix sums over each
+    line's cells, all candidates sorted, cell lists built in rank order)
+    equals the rule enumerated directly, on the most constrained irregular
+    cells of each case (fewest non-empty cells within distance 4) and on
+    seeded random ones."""
+    cfg = W.problem(case, 40 if case == "P1" else 64) if isinstance(case, str) else W.config(case, n=64)
+    cg = build_cut_grid(cfg["grid"], cfg["curves"])
+    disc = Discretization(cg, cfg["a"], cfg["b"], cfg["c"], eager=False)
+    irr = [int(q) for q in disc.irregular]
+    nx, ny = disc.nx, disc.ny
+
+    def k_size(q):
+        qi, qj = q % nx, q // nx
+        return sum(1 for dy in range(-4, 5) for dx in range(-4, 5)
+                   if 0 <= qi + dx < nx and 0 <= qj + dy < ny and disc.nonempty[(qj + dy) * nx + qi + dx])
+
+    tight = sorted(irr, key=lambda q: (k_size(q), q))[:3]
+    rng = np.random.default_rng(77)
+    sample = tight + [int(v) for v in rng.choice(irr, size=3, replace=False)]
+    for q in sample:
+        assert disc.lattice_pool(q) == _brute_force_pool(disc, q), q

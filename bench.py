@@ -20,21 +20,34 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-ALG_BYTES_SWEEP = 25   # per cell per FP64 sweep: read u, r (8+8), kind (1), write u' (8)
 HBM_PEAK_GBS = 8000.0
+METHOD_BYTES_PER_CELL = 24   # one FP64 smoothing sweep: read u and f-hat, write u'
+METHOD_BYTES_PER_NNZ = 12    # a least-squares row entry: int32 column + FP64 weight
 
 
-def fused_step_bytes(n_cells, st):
-    """Algorithmic bytes of one fused FP64 smoothing step on a level:
-    SMO-1 tiles read u, r, kind of every cell (17 B) and write u' of every
-    cell not in an SMO-2 block (8 B); the SMO-2 blocks read their dense
-    inverses, their overlapped rows' CSR entries (column 4 B + weight 8 B)
-    and per overlapped row its index, cell, row pointer, boundary-term index
-    (4 B each), row sum, right-hand side and current value (8 B each), and
-    write u' and the compact copy of their own rows (16 B)."""
-    sweep = 17 * n_cells + 8 * (n_cells - st["rows"])
-    smo2 = st["inv_bytes"] + 12 * st["ext_nnz"] + 40 * st["ext_rows"] + 16 * st["rows"]
-    return sweep + smo2
+def method_step_bytes(n_cells, n_irr):
+    """Algorithmic bytes of one FP64 smoothing step, counted as the method's
+    own traffic: every cell's u and right-hand side read and its new value
+    written (24 B), plus the 15-entry least-squares rows of the irregular
+    cells (12 B per entry).  The SMO-2 block data (dense block inverses,
+    overlapped rows) belong to this solver's smoother design, not to the
+    method, and are reported separately (smo2_block_bytes)."""
+    return METHOD_BYTES_PER_CELL * n_cells + METHOD_BYTES_PER_NNZ * 15 * n_irr
+
+
+def smo2_block_bytes(st):
+    """Bytes the SMO-2 blocks of one fused step move besides the method's
+    own: their dense inverses, their overlapped rows' ELL entries (column
+    4 B + weight 8 B) and per overlapped row its index, cell, row pointer,
+    boundary-term index (4 B each), row sum, right-hand side and current
+    value (8 B each), and the compact copy of their own rows (8 B)."""
+    return st["inv_bytes"] + 12 * st["ext_nnz"] + 40 * st["ext_rows"] + 8 * st["rows"]
+
+
+def sweep_bytes(n_cells):
+    """One FP64 SMO-1 sweep (unfused schedule): 24 B per cell plus the kind
+    byte."""
+    return (METHOD_BYTES_PER_CELL + 1) * n_cells
 
 
 def make_inputs(S, cfg, torch, dev):
@@ -238,42 +251,108 @@ def run_batch(args):
         S.close()
 
 
-def cpu_baseline(n_sample, seconds, config=4):
-    """The oracle's own V-cycle solve, one core, on the same geometry and
-    problem at a smaller grid: its set-up is not timed; the solve from a zero
-    guess is repeated until at least ``seconds`` of CPU time have passed."""
-    from threadpoolctl import threadpool_limits
+def _cpu_worker(conn, n_sample, seconds, config, threads):
+    """Child process of the CPU baseline: the oracle's set-up (untimed) runs
+    while the parent measures the GPU; on the parent's signal the oracle's
+    own V-cycle solve (Alg. 2, exact SMO-2, LU at the coarsest level) from a
+    zero guess is repeated for at least ``seconds`` on 1 thread, then on
+    ``threads`` threads."""
+    try:
+        from threadpoolctl import threadpool_limits
 
-    import workloads as W
-    from oracle.discretization import boundary_data
-    from oracle.geometry import cell_averages
-    from oracle.multigrid import Hierarchy, rhs_vector
-    cfg = W.config(config, n=n_sample)
-    with threadpool_limits(limits=1):
+        import workloads as W
+        from oracle.discretization import boundary_data
+        from oracle.geometry import cell_averages
+        from oracle.multigrid import Hierarchy, rhs_vector
+        cfg = W.config(config, n=n_sample)
         t_set = time.perf_counter()
-        H = Hierarchy(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
-        H.select_depth()
-        lv = H.levels[0]
-        f = cell_averages(lv.cg, cfg["f"]).ravel()
-        g = boundary_data(lv.disc, cfg["solution"])
-        r = rhs_vector(lv, f, g)
+        with threadpool_limits(limits=threads):
+            H = Hierarchy(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
+            H.select_depth()
+            lv = H.levels[0]
+            f = cell_averages(lv.cg, cfg["f"]).ravel()
+            g = boundary_data(lv.disc, cfg["solution"])
+            r = rhs_vector(lv, f, g)
         t_set = time.perf_counter() - t_set
-        solves, cycles = 0, 0
-        t0 = time.perf_counter()
-        while True:
-            hist = []
-            H.solve(r, tol=1e-10, history=hist)
-            solves += 1
-            cycles = len(hist)
-            dt = time.perf_counter() - t0
-            if dt >= seconds:
-                break
-    nu = int(lv.nonempty.sum())
-    return {"value": nu * solves / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle V-cycle solves (Alg. 2, exact SMO-2 blocks, LU at the coarsest level) from zero to "
-                      "1e-10 on the same geometry and problem at %d^2 (%d unknowns, %d cycles per solve), "
-                      "%d solves in %.1f s on 1 thread; oracle set-up %.1f s untimed"
-                      % (n_sample, nu, cycles, solves, dt, t_set)}
+        conn.send(("ready", t_set))
+        if conn.recv() != "go":
+            return
+        runs = {}
+        for nt in (1, threads):
+            with threadpool_limits(limits=nt):
+                solves, cycles = 0, 0
+                t0 = time.perf_counter()
+                while True:
+                    hist = []
+                    H.solve(r, tol=1e-10, history=hist)
+                    solves += 1
+                    cycles = len(hist)
+                    dt = time.perf_counter() - t0
+                    if dt >= seconds:
+                        break
+            runs[nt] = (solves, dt, cycles)
+        conn.send(("done", {"runs": runs, "unknowns": int(lv.nonempty.sum()), "setup_s": t_set}))
+    except Exception as e:   # reported by the parent, never raised into the GPU run
+        conn.send(("error", repr(e)))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+class CpuBaseline:
+    """The oracle timed on the host cores beside the GPU run, in a child
+    process started before the GPU is touched."""
+
+    def __init__(self, n_sample, seconds, config):
+        import multiprocessing as mp
+        self.n, self.seconds = n_sample, seconds
+        # the box's CPU share for one GPU is given by OMP_NUM_THREADS there
+        self.threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        ctx = mp.get_context("spawn")
+        self.conn, child = ctx.Pipe()
+        self.proc = ctx.Process(target=_cpu_worker, args=(child, n_sample, seconds, config, self.threads),
+                                daemon=True)
+        self.proc.start()
+
+    def result(self, timeout=900.0):
+        """Waits for the set-up, starts the timed solves and returns the
+        cpu_baseline record (None if the child failed)."""
+        try:
+            if not self.conn.poll(timeout):
+                return None
+            tag, t_set = self.conn.recv()
+            if tag != "ready":
+                print("cpu baseline failed: %s" % t_set, file=sys.stderr, flush=True)
+                return None
+            self.conn.send("go")
+            if not self.conn.poll(timeout):
+                return None
+            tag, res = self.conn.recv()
+            if tag != "done":
+                print("cpu baseline failed: %s" % res, file=sys.stderr, flush=True)
+                return None
+        finally:
+            self.proc.join(timeout=5)
+        nu = res["unknowns"]
+        (s1, d1, c1), (sn, dn, cn) = res["runs"][1], res["runs"][self.threads]
+        affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+        return {"value": nu * sn / dn, "unit": "unknowns/s", "cores": self.threads, "kind": "oracle",
+                "sample": "oracle V-cycle solves (Alg. 2, exact SMO-2 blocks, LU at the coarsest level) from zero "
+                          "to 1e-10 on the same geometry and problem at %d^2 (%d unknowns, %d cycles per solve): "
+                          "%d solves in %.1f s with %d threads allowed (%d solves in %.1f s on 1 thread); oracle "
+                          "set-up %.1f s untimed, run while the GPU was measured"
+                          % (self.n, nu, cn, sn, dn, self.threads, s1, d1, res["setup_s"]),
+                "config": {"grid": self.n, "unknowns": nu, "cycles_per_solve": cn},
+                "single_core": {"value": nu * s1 / d1, "solves": s1, "seconds": d1},
+                "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": _cpu_model()}
 
 
 def main():
@@ -290,9 +369,11 @@ def main():
     ap.add_argument("--problem", choices=["P1", "P2N", "P2D", "P3"], default="",
                     help="with --error-study: one of the paper's test problems instead of a workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=256)
+    ap.add_argument("--cpu-sample-n", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-fp64-inverses", action="store_true",
+                    help="skip the extra solve with FP64-stored SMO-2 and coarsest inverses")
     ap.add_argument("--prolongation", type=int, default=0)
     ap.add_argument("--smo2-every-sweep", type=int, default=1)
     ap.add_argument("--workload", choices=["metric", "batch"], default="metric",
@@ -316,6 +397,9 @@ def main():
     if args.error_study:
         run_error_study(args)
         return
+    # the oracle's set-up overlaps the GPU measurement (child process,
+    # started before the GPU is touched)
+    cpu_job = None if args.no_cpu_baseline else CpuBaseline(args.cpu_sample_n, args.cpu_seconds, args.config)
 
     import numpy as np
     import torch
@@ -345,20 +429,28 @@ def main():
     u = torch.zeros_like(f)
     torch.cuda.synchronize()
 
-    def run(steps):
+    def run(solver, uu, steps, walls=None):
         reps = []
         for _ in range(steps):
-            reps.append(S.solve(f, u))
+            a = time.perf_counter()
+            reps.append(solver.solve(f, uu))   # returns once the solve has finished on the device
+            if walls is not None:
+                walls.append(1e3 * (time.perf_counter() - a))
         return reps
 
-    run(args.warmup)
+    run(S, u, args.warmup)
     torch.cuda.synchronize()
+    walls = []
     t0 = time.perf_counter()
-    reps = run(args.steps)
+    reps = run(S, u, args.steps, walls)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1e3 * dt / args.steps
     nu = info["n_unknowns"]
+    devs = [1e3 * r["seconds"] for r in reps]
+    per_solve = {"wall_ms_mean": float(np.mean(walls)), "wall_ms_median": float(np.median(walls)),
+                 "wall_ms_max": float(np.max(walls)), "device_ms_mean": float(np.mean(devs)),
+                 "device_ms_median": float(np.median(devs)), "device_ms_max": float(np.max(devs))}
     # relative L2 residual of the final iterate (after the timed region)
     res_l2 = S.residual_norms(f, u)[1][0]
     u64 = u.cpu().numpy()
@@ -370,16 +462,18 @@ def main():
     # events on the library's stream right after the timed solves
     ty = S.tuning(0)[0]
     cells = args.n * args.n
+    block_bytes = 0
     if info["smoother_fused"]:
         kname = "k_smooth_fused<double, %s, true, %d, false>" % ("true" if cfg["b"] != 0 else "false", ty)
         kdesc = "finest-level fused SMO-1 + SMO-2 step"
         dom_us = S.profile_kernel(7, 0, 50)
-        dom_bytes = fused_step_bytes(cells, S.smo2_stats(0))
+        dom_bytes = method_step_bytes(cells, info["n_irregular"])
+        block_bytes = smo2_block_bytes(S.smo2_stats(0))
     else:
         kname = "k_sweep<double, %s, true, %d>" % ("true" if cfg["b"] != 0 else "false", ty)
         kdesc = "finest-level SMO-1 sweep"
         dom_us = S.profile_kernel(0, 0, 50)
-        dom_bytes = ALG_BYTES_SWEEP * cells
+        dom_bytes = sweep_bytes(cells)
     achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     other = {name: S.profile_kernel(k, 0, 20) for name, k in (("sweep_us", 0), ("restrict_us", 1),
                                                                ("prolong_us", 2), ("smo2_block_us", 3),
@@ -394,6 +488,31 @@ def main():
     traffic = None
     if rec and rec["cells"] == cells and rec["kernel"] == kname:
         traffic = rec["traffic_bytes_per_launch"]
+
+    tiles = [S.tuning(m)[0] for m in range(info["n_levels"])]
+
+    # the same solve with both dense inverses (SMO-2 blocks, coarsest level)
+    # stored in FP64 rather than FP32
+    fp64_inv = None
+    if not args.no_fp64_inverses:
+        S64 = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-10, max_cycles=200,
+                     hip_stream=stream.cuda_stream, prolongation=args.prolongation,
+                     smo2_every_sweep=args.smo2_every_sweep, inverse_fp32=0)
+        S64.set_boundary(g, 1)
+        S64.tune(f)
+        u2 = torch.zeros_like(f)
+        run(S64, u2, args.warmup)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r64 = run(S64, u2, args.steps)
+        torch.cuda.synchronize()
+        m64 = 1e3 * (time.perf_counter() - t1) / args.steps
+        fp64_inv = {"value": nu / (m64 * 1e-3), "ms_per_step": m64, "cycles": r64[-1]["cycles"],
+                    "rel_res_inf": r64[-1]["rel_res_inf"],
+                    "device_ms_median": 1e3 * float(np.median([r["seconds"] for r in r64])),
+                    "schedule": {k: S64.info[k] for k in ("nu1", "nu2", "nu1_coarse", "nu2_coarse")}}
+        S64.close()
+        del u2
 
     mixed = None
     if not args.no_mixed:
@@ -417,9 +536,7 @@ def main():
                  "disc_err_inf": float(np.max(np.abs(um.cpu().numpy() - exact)[ne]))}
         Sm.close()
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_sample_n, args.cpu_seconds, args.config)
+    cpu = cpu_job.result() if cpu_job else None
 
     out = {
         "metric": ("4th-order cut-cell GMG solve: unknowns/s and HBM GB/s at 1e-10 rel. residual, 2048^2"
@@ -440,19 +557,29 @@ def main():
                    "coarsest": info["nx_coarsest"], "nrhs": 1,
                    "schedule": {"smoother_fused": info["smoother_fused"], "nu1": info["nu1"], "nu2": info["nu2"],
                                 "nu1_coarse": info["nu1_coarse"], "nu2_coarse": info["nu2_coarse"]},
-                   "sweep_tile_rows": [S.tuning(m)[0] for m in range(info["n_levels"])]},
+                   "sweep_tile_rows": tiles,
+                   # dense inverses are computed in FP64 and applied in FP64
+                   # arithmetic; this is their storage (fp64_inverses below:
+                   # the same solve with both stored in FP64)
+                   "inverse_storage": {"smo2_blocks": "fp32", "coarsest": "fp32"}},
         "cycles": reps[-1]["cycles"],
         "rel_res_inf": reps[-1]["rel_res_inf"],
         "rel_res_l2": res_l2,
-        "ms_median_device": 1e3 * float(np.median([r["seconds"] for r in reps])),
+        "ms_median_device": per_solve["device_ms_median"],
+        "per_solve": per_solve,
         "disc_err_inf": disc_err,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "%s (%s)" % (kname, kdesc), "avg_us": dom_us,
-                     "alg_bytes_per_launch": dom_bytes, "traffic_unit": "bytes per launch",
+                     "alg_bytes_per_launch": dom_bytes,
+                     "alg_bytes_rule": "24 B per cell (u, f read; u' written) + 12 B per least-squares entry",
+                     "smo2_block_bytes_per_launch": block_bytes,
+                     "traffic_over_alg": (traffic / dom_bytes) if traffic else None,
+                     "traffic_unit": "bytes per launch",
                      "copy_ceiling_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "kernels_us": other,
+        "fp64_inverses": fp64_inv,
         "mixed_precision": mixed,
         "cpu_baseline": cpu,
     }

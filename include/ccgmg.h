@@ -265,10 +265,14 @@ int ccgmg_set_boundary(ccgmg_ctx* ctx, const double* g_hat, int nrhs);
 /* Solve L u = f - N g for nrhs right-hand sides: f_hat device
  * [nrhs][ny][nx], u_hat device [nrhs][ny][nx] (initial guess in, solution
  * out).  rep: host, may be NULL.  Returns CCGMG_ENOCONV (with u_hat holding
- * the last iterate) when tol is not reached.  The residual is checked after
- * every V-cycle; the next cycle is queued before that check only when the
- * cycle being checked cannot reach tol (judged from the contraction seen so
- * far), so the solve stops at the first cycle that reaches tol. */
+ * the last iterate) when tol is not reached, CCGMG_EINVAL when f_hat or the
+ * boundary data hold a NaN or an Inf on a non-empty cell or face (found
+ * from the reference norm ||f - N g||; u_hat is then undefined).  The
+ * residual is checked after every V-cycle; the next cycle is queued before
+ * that check only when the cycle being checked cannot reach tol (judged
+ * from the contraction seen so far), so the solve stops at the first cycle
+ * that reaches tol.  Allocates nothing; the first solve with a given pair
+ * of arrays records the cycle's graph. */
 int ccgmg_solve(ccgmg_ctx* ctx, const double* f_hat, double* u_hat, int nrhs, ccgmg_report* rep);
 
 /* Adjoint solve L^T lambda = rhs (device arrays as in ccgmg_solve) by
@@ -328,7 +332,11 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
 /* f[g], u[g]: device arrays of geometry g ([nrhs[g]][ny][nx], as in
  * ccgmg_solve, from a zero guess unless the context uses an initial guess);
  * reps: host array of n reports or NULL (seconds = the whole batch).
- * CCGMG_ENOCONV if any geometry did not reach its tolerance. */
+ * CCGMG_ENOCONV if any geometry did not reach its tolerance, CCGMG_EINVAL
+ * for non-finite data (as ccgmg_solve).  The residual buffers are
+ * allocated by ccgmg_batch_create; the first solve with a new set of arrays
+ * (or a change of boundary data between none and some) records a new
+ * graph, and in lockstep mode allocates its descriptor table. */
 int ccgmg_batch_solve(ccgmg_batch* batch, const double* const* f, double* const* u, const int* nrhs,
                       ccgmg_report* reps);
 /* Error text of the batch's last failed call (owned by the batch). */

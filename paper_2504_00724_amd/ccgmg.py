@@ -132,12 +132,34 @@ def default_options(**kw):
 
 
 def _ptr(a):
-    """Raw pointer of a numpy array or a torch tensor."""
+    """Raw pointer of a host numpy array (query results)."""
     if a is None:
         return None
-    if isinstance(a, np.ndarray):
-        return a.ctypes.data
-    return a.data_ptr()
+    return a.ctypes.data
+
+
+def _dev(t, n, name):
+    """Raw pointer of a device array handed to the kernels: a torch GPU
+    tensor of float64, contiguous, with exactly n elements.  Anything else
+    is refused here, before the library sees the pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor on the GPU, got %s" % (name, type(t).__name__))
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU, got device %s" % (name, t.device))
+    if t.dtype != torch.float64:
+        raise ValueError("%s must be float64, got %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return t.data_ptr()
+
+
+def _count(nrhs, name="nrhs"):
+    if not isinstance(nrhs, (int, np.integer)) or nrhs < 1:
+        raise ValueError("%s must be a positive integer, got %r" % (name, nrhs))
+    return int(nrhs)
 
 
 class Solver:
@@ -255,29 +277,48 @@ class Solver:
         return tuple(out)
 
     # -- device calls ------------------------------------------------------------
+    @property
+    def n_cells(self):
+        return self.nx * self.ny
+
     def apply(self, u, out):
-        self._check(lib().ccgmg_apply(self.ctx, _ptr(u), _ptr(out)))
+        n = self.n_cells
+        self._check(lib().ccgmg_apply(self.ctx, _dev(u, n, "u"), _dev(out, n, "out")))
 
     def residual_norms(self, f, u, nrhs=1):
         """Relative L-infinity and L2 residual norms of the iterate u (one
         value per right-hand side), with the boundary data last set."""
+        nrhs = _count(nrhs)
+        n = nrhs * self.n_cells
         ri, r2 = (C.c_double * nrhs)(), (C.c_double * nrhs)()
-        self._check(lib().ccgmg_residual_norms(self.ctx, _ptr(f), _ptr(u), nrhs, ri, r2))
+        self._check(lib().ccgmg_residual_norms(self.ctx, _dev(f, n, "f"), _dev(u, n, "u"), nrhs, ri, r2))
         return list(ri), list(r2)
 
     def set_boundary(self, g, nrhs=1):
-        self._check(lib().ccgmg_set_boundary(self.ctx, _ptr(g), nrhs))
+        """Boundary data for nrhs right-hand sides ([nrhs][n_bdry_faces]);
+        nrhs = 0 drops the boundary term."""
+        if nrhs == 0:
+            self._check(lib().ccgmg_set_boundary(self.ctx, None, 0))
+            return
+        nrhs = _count(nrhs)
+        nf = self.info["n_bdry_faces"]
+        ptr = _dev(g, nrhs * nf, "g") if nf > 0 else None
+        self._check(lib().ccgmg_set_boundary(self.ctx, ptr, nrhs))
 
     def solve(self, f, u, nrhs=1, raise_on_noconv=True):
+        nrhs = _count(nrhs)
+        n = nrhs * self.n_cells
         rep = ReportT()
-        st = lib().ccgmg_solve(self.ctx, _ptr(f), _ptr(u), nrhs, C.byref(rep))
+        st = lib().ccgmg_solve(self.ctx, _dev(f, n, "f"), _dev(u, n, "u"), nrhs, C.byref(rep))
         if st != OK and (raise_on_noconv or st != ENOCONV):
             self._check(st)
         return _report(rep, st)
 
     def solve_adjoint(self, rhs, lam, nrhs=1, raise_on_noconv=True):
+        nrhs = _count(nrhs)
+        n = nrhs * self.n_cells
         rep = ReportT()
-        st = lib().ccgmg_solve_adjoint(self.ctx, _ptr(rhs), _ptr(lam), nrhs, C.byref(rep))
+        st = lib().ccgmg_solve_adjoint(self.ctx, _dev(rhs, n, "rhs"), _dev(lam, n, "lam"), nrhs, C.byref(rep))
         if st != OK and (raise_on_noconv or st != ENOCONV):
             self._check(st)
         return _report(rep, st)
@@ -285,7 +326,7 @@ class Solver:
     def tune(self, f):
         """Re-choose schedule and depth by timing solves of this right-hand
         side (with the boundary data last set); refreshes ``info``."""
-        self._check(lib().ccgmg_tune(self.ctx, _ptr(f)))
+        self._check(lib().ccgmg_tune(self.ctx, _dev(f, self.n_cells, "f")))
         self.info = self.query()
 
     def profile_kernel(self, kernel, level=0, reps=50):
@@ -309,10 +350,14 @@ class Solver:
         return dict(zip(keys, list(st)))
 
     def apply_adjoint(self, lam, out):
-        self._check(lib().ccgmg_apply_adjoint(self.ctx, _ptr(lam), _ptr(out)))
+        n = self.n_cells
+        self._check(lib().ccgmg_apply_adjoint(self.ctx, _dev(lam, n, "lam"), _dev(out, n, "out")))
 
     def apply_NT(self, lam, out, nrhs=1):
-        self._check(lib().ccgmg_apply_NT(self.ctx, _ptr(lam), _ptr(out), nrhs))
+        nrhs = _count(nrhs)
+        nf = self.info["n_bdry_faces"]
+        self._check(lib().ccgmg_apply_NT(self.ctx, _dev(lam, nrhs * self.n_cells, "lam"),
+                                         _dev(out, nrhs * nf, "out"), nrhs))
 
 
 def _report(rep, st):
@@ -337,9 +382,13 @@ class Batch:
         n = len(self.solvers)
         if len(fs) != n or len(us) != n:
             raise ValueError("one right-hand side and one solution array per geometry")
-        nr = nrhs or [1] * n
-        fa = (C.c_void_p * n)(*[_ptr(f) for f in fs])
-        ua = (C.c_void_p * n)(*[_ptr(u) for u in us])
+        nr = [_count(v) for v in (nrhs or [1] * n)]
+        if len(nr) != n:
+            raise ValueError("one right-hand-side count per geometry")
+        fa = (C.c_void_p * n)(*[_dev(f, m * S.n_cells, "f[%d]" % k)
+                                for k, (f, m, S) in enumerate(zip(fs, nr, self.solvers))])
+        ua = (C.c_void_p * n)(*[_dev(u, m * S.n_cells, "u[%d]" % k)
+                                for k, (u, m, S) in enumerate(zip(us, nr, self.solvers))])
         na = (C.c_int * n)(*nr)
         reps = (ReportT * n)()
         st = lib().ccgmg_batch_solve(self.h, fa, ua, na, reps)

@@ -145,6 +145,7 @@ struct ccgmg_ctx {
   int g_nrhs = 0;
   double* norm_host = nullptr;      // pinned: partial maxima of the residual norm (level 0)
   double* norm_host2 = nullptr;     // a second one: cycles alternate between the two
+  double* norm_host0 = nullptr;     // a third: the reference norm ||f - N g|| of the solve's start
   double setup_seconds = 0;
   double plg_max_cond = 0;
   std::string err;
@@ -154,6 +155,8 @@ struct ccgmg_ctx {
   hipStream_t ws = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_cyc[2] = {nullptr, nullptr};   // ends of the cycles in flight (alternating)
+  hipEvent_t ev_pro = nullptr;      // end of a solve's prologue (reference norm read back)
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;   // device time of a solve (created once)
   struct GraphEntry {
     const void *u, *f, *bterm, *norm;
     int nrhs, precision, M;
@@ -848,7 +851,11 @@ void mp_cycle(Driver& Dr, double* u) {
 double norm_of(ccgmg_ctx* X, int nparts, int z, const double* part = nullptr) {
   const double* p = part ? part : X->norm_host;
   double m = 0.0;
-  for (int k = 0; k < nparts; ++k) m = std::max(m, p[(size_t)z * nparts + k]);
+  for (int k = 0; k < nparts; ++k) {
+    const double v = p[(size_t)z * nparts + k];
+    if (std::isnan(v)) return v;   // a NaN partial is the result
+    m = std::max(m, v);
+  }
   return m;
 }
 
@@ -875,7 +882,7 @@ const double* solve_prologue(Driver& Dr, const double* f, double* u) {
   // the first mixed-precision step needs (stored as FP32)
   const bool zero_start = !X->opt.use_initial_guess;
   Dr.resmax<double>(L0, u, f, bterm, 1, (mp && zero_start) ? L0.r32 : nullptr);
-  HIP_OK(hipMemcpyAsync(X->norm_host, L0.part, sizeof(double) * Dr.norm_parts(L0) * nrhs, hipMemcpyDeviceToHost,
+  HIP_OK(hipMemcpyAsync(X->norm_host0, L0.part, sizeof(double) * Dr.norm_parts(L0) * nrhs, hipMemcpyDeviceToHost,
                         Dr.s));
   if (mp && !zero_start) Dr.resmax<double>(L0, u, f, bterm, 0, L0.r32);   // residual of the initial guess
   return bterm;
@@ -906,16 +913,22 @@ struct Monitor {
   double prev = 1e300, rel = 1.0;
   bool converged = false, stopped = false;
   bool guess = false;   // the solve starts from the caller's iterate
-  void start(ccgmg_ctx* X, int nrhs, int np) {
+  // from the reference norms ||f - N g|| the prologue read back into
+  // X->norm_host0; returns false if one of them is not finite (NaN or Inf
+  // in f-hat or g-hat)
+  bool start(ccgmg_ctx* X, int nrhs, int np) {
     nparts = np;
     rn.assign(nrhs, 1.0);
     rel = 0.0;
+    bool finite = true;
     for (int z = 0; z < nrhs; ++z) {
-      const double m = norm_of(X, nparts, z);
+      const double m = norm_of(X, nparts, z, X->norm_host0);
+      finite = finite && std::isfinite(m);
       rn[z] = m > 0 ? m : 1.0;
       if (m > 0) rel = 1.0;
     }
     guess = X->opt.use_initial_guess != 0;
+    return finite;
   }
   double fmin = 1.0;   // smallest contraction factor seen so far
   // after a cycle; returns true when this solve is finished
@@ -985,19 +998,15 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     Driver Dr{X, ws, nrhs, adjoint};
     HIP_OK(hipEventRecord(X->ev_in, X->stream));
     HIP_OK(hipStreamWaitEvent(ws, X->ev_in, 0));
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    HIP_OK(hipEventRecord(e0, ws));
+    HIP_OK(hipEventRecord(X->ev_t0, ws));
     const double* bterm = solve_prologue(Dr, f, u);
-    HIP_OK(hipStreamSynchronize(ws));
-    Monitor mon;
-    mon.start(X, nrhs, Dr.norm_parts(X->lv[0]));
+    HIP_OK(hipEventRecord(X->ev_pro, ws));
     // cycle k reads its residual back into buffer k mod 2 and records event
     // k mod 2; while the host checks cycle k, cycle k + 1 may already run
     // (enqueued only when cycle k cannot end the solve), which hides the
     // host's round trip without running a cycle more than a synchronous
-    // loop would
+    // loop would.  The first cycle is queued before the reference norm is
+    // read (it is needed only for the first check).
     double* nb[2] = {X->norm_host, X->norm_host2};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     if (X->opt.use_graph)
@@ -1013,6 +1022,14 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
       HIP_OK(hipEventRecord(X->ev_cyc[k], ws));
     };
     launch();
+    HIP_OK(hipEventSynchronize(X->ev_pro));
+    Monitor mon;
+    if (!mon.start(X, nrhs, Dr.norm_parts(X->lv[0]))) {
+      HIP_OK(hipStreamSynchronize(ws));
+      HIP_OK(hipEventRecord(X->ev_out, ws));
+      HIP_OK(hipStreamWaitEvent(X->stream, X->ev_out, 0));
+      throw ccg::Error(CCGMG_EINVAL, "non-finite right-hand side or boundary data");
+    }
     for (;;) {
       if (launched == done + 1 && mon.next_not_final(X)) launch();
       HIP_OK(hipEventSynchronize(X->ev_cyc[done & 1]));
@@ -1022,14 +1039,12 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
       if (fin) break;
       launch();
     }
-    HIP_OK(hipEventRecord(e1, ws));
+    HIP_OK(hipEventRecord(X->ev_t1, ws));
     HIP_OK(hipEventRecord(X->ev_out, ws));
     HIP_OK(hipStreamWaitEvent(X->stream, X->ev_out, 0));
-    HIP_OK(hipEventSynchronize(e1));
+    HIP_OK(hipEventSynchronize(X->ev_t1));
     float ms = 0;
-    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_OK(hipEventElapsedTime(&ms, X->ev_t0, X->ev_t1));
     if (rep) {
       rep->cycles = mon.cycles;
       rep->outer_iters = X->opt.precision == 1 ? mon.cycles : 0;
@@ -1163,6 +1178,7 @@ struct ccgmg_batch {
   hipStream_t caller = nullptr, main = nullptr;
   std::vector<hipStream_t> br;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;   // device time of a batch solve (created once)
   std::vector<hipEvent_t> ev_fork;   // [0]: fork, [1 + b]: join of branch b
   std::vector<BatchGraph> graphs;
   std::string err;
@@ -1394,6 +1410,12 @@ int batch_guard(ccgmg_batch* B, const std::function<void()>& body) {
   return CCGMG_OK;
 }
 
+// Residual-norm partials of one geometry's plane in a lockstep batch.
+int lockstep_parts(ccgmg_ctx* X) {
+  DevLevel& L0 = X->lv[0];
+  return (L0.fwd.n + BLOCK - 1) / BLOCK + tiles_x(L0.nx) * ((L0.ny + TY - 1) / TY);
+}
+
 // Lockstep batch solve (see ccgmg_batch_create with nbranches == 0).
 void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, const int* nrhs,
                     ccgmg_report* reps) {
@@ -1403,42 +1425,30 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
   for (auto* X : B->ctx) cross = cross || X->b != 0.0;
   HIP_OK(hipEventRecord(B->ev_in, B->caller));
   HIP_OK(hipStreamWaitEvent(B->main, B->ev_in, 0));
-  hipEvent_t e0, e1;
-  HIP_OK(hipEventCreate(&e0));
-  HIP_OK(hipEventCreate(&e1));
-  HIP_OK(hipEventRecord(e0, B->main));
+  HIP_OK(hipEventRecord(B->ev_t0, B->main));
   std::vector<const double*> bterm(n);
   for (int g = 0; g < n; ++g) {
     Driver Dr{B->ctx[g], B->main, nrhs[g], false};
     bterm[g] = solve_prologue(Dr, f[g], u[g]);
   }
-  // residual-norm partials of all geometries in one buffer
+  // residual-norm partials of all geometries in one buffer (laid out for
+  // max_nrhs planes each at batch creation)
   std::vector<int> nparts(n);
-  B->part_off.assign(n, 0);
-  size_t total = 0;
-  for (int g = 0; g < n; ++g) {
-    DevLevel& L0 = B->ctx[g]->lv[0];
-    nparts[g] = (L0.fwd.n + BLOCK - 1) / BLOCK + tiles_x(L0.nx) * ((L0.ny + TY - 1) / TY);
-    B->part_off[g] = total;
-    total += (size_t)nparts[g] * nrhs[g];
-  }
-  if (total > B->part_cap) {
-    B->clear_graphs();
-    if (B->part_d) (void)hipFree(B->part_d);
-    if (B->part_h) (void)hipHostFree(B->part_h);
-    B->part_d = nullptr, B->part_h = nullptr, B->part_cap = 0;
-    HIP_OK(hipMalloc((void**)&B->part_d, sizeof(double) * total));
-    HIP_OK(hipHostMalloc((void**)&B->part_h, sizeof(double) * total, hipHostMallocDefault));
-    B->part_cap = total;
-  }
+  for (int g = 0; g < n; ++g) nparts[g] = lockstep_parts(B->ctx[g]);
+  const size_t total = B->part_cap;
   HIP_OK(hipStreamSynchronize(B->main));
   std::vector<Monitor> mon(n);
-  for (int g = 0; g < n; ++g) mon[g].start(B->ctx[g], nrhs[g], nparts[g]);
+  for (int g = 0; g < n; ++g)
+    if (!mon[g].start(B->ctx[g], nrhs[g], nparts[g]))
+      throw ccg::Error(CCGMG_EINVAL, "non-finite right-hand side or boundary data for geometry " + std::to_string(g));
+  // the captured cycle fixes the arrays, the right-hand-side counts and
+  // whether each geometry has a boundary term
   std::vector<const void*> key;
   for (int g = 0; g < n; ++g) {
     key.push_back(f[g]);
     key.push_back(u[g]);
     key.push_back((const void*)(intptr_t)nrhs[g]);
+    key.push_back(bterm[g]);
   }
   hipGraphExec_t exec = nullptr;
   for (auto& gr : B->graphs)
@@ -1541,14 +1551,12 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
     if (all) break;
     if (changed) HIP_OK(hipMemcpyAsync(B->active_d, B->active_h, sizeof(int) * n, hipMemcpyHostToDevice, B->main));
   }
-  HIP_OK(hipEventRecord(e1, B->main));
+  HIP_OK(hipEventRecord(B->ev_t1, B->main));
   HIP_OK(hipEventRecord(B->ev_out, B->main));
   HIP_OK(hipStreamWaitEvent(B->caller, B->ev_out, 0));
-  HIP_OK(hipEventSynchronize(e1));
+  HIP_OK(hipEventSynchronize(B->ev_t1));
   float ms = 0;
-  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIP_OK(hipEventElapsedTime(&ms, B->ev_t0, B->ev_t1));
   bool ok = true;
   for (int g = 0; g < n; ++g) {
     if (reps) {
@@ -1662,6 +1670,9 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       HIP_OK(hipEventCreateWithFlags(&X->ev_in, hipEventDisableTiming));
       HIP_OK(hipEventCreateWithFlags(&X->ev_out, hipEventDisableTiming));
       for (hipEvent_t& e : X->ev_cyc) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      HIP_OK(hipEventCreateWithFlags(&X->ev_pro, hipEventDisableTiming));
+      HIP_OK(hipEventCreate(&X->ev_t0));
+      HIP_OK(hipEventCreate(&X->ev_t1));
       const int maxr = X->opt.max_nrhs;
       X->lv.resize(X->H.disc.size());
       for (size_t m = 0; m < X->H.disc.size(); ++m) upload_level(X.get(), (int)m, maxr);
@@ -1680,7 +1691,7 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
       X->g = dalloc<double>((size_t)std::max(1, X->nfaces) * maxr, X->owned);
       X->bterm = dalloc<double>((size_t)std::max(1, (int)D0.irr.size()) * maxr, X->owned);
       if (maxr > 1) X->mrg = dalloc<double>((size_t)MAX_COARSE_UNKNOWNS * maxr, X->owned);
-      for (double** p : {&X->norm_host, &X->norm_host2})
+      for (double** p : {&X->norm_host, &X->norm_host2, &X->norm_host0})
         HIP_OK(hipHostMalloc((void**)p, sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
                              hipHostMallocDefault));
       // the coarsest level must be small enough for the dense inverse
@@ -1911,7 +1922,7 @@ int ccgmg_residual_norms(ccgmg_ctx* X, const double* f, const double* u, int nrh
       for (int k = 0; k < 2; ++k)
         for (int b = 0; b < np; ++b) {
           const double* e = h.data() + k * per + 2 * ((size_t)z * np + b);
-          m[k] = std::max(m[k], e[0]);
+          m[k] = std::isnan(m[k]) ? m[k] : (std::isnan(e[0]) ? e[0] : std::max(m[k], e[0]));
           q[k] += e[1];
         }
       if (rel_inf) rel_inf[z] = m[1] / (m[0] > 0 ? m[0] : 1.0);
@@ -1975,6 +1986,17 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
         X->clear_graphs();
       }
       HIP_OK(hipMalloc((void**)&B->active_d, sizeof(int) * n));
+      // the partials of every geometry's residual checks, max_nrhs planes
+      // each, so that a solve allocates nothing
+      B->part_off.assign(n, 0);
+      size_t total = 0;
+      for (int g = 0; g < n; ++g) {
+        B->part_off[g] = total;
+        total += (size_t)lockstep_parts(ctxs[g]) * ctxs[g]->opt.max_nrhs;
+      }
+      HIP_OK(hipMalloc((void**)&B->part_d, sizeof(double) * total));
+      HIP_OK(hipHostMalloc((void**)&B->part_h, sizeof(double) * total, hipHostMallocDefault));
+      B->part_cap = total;
       HIP_OK(hipHostMalloc((void**)&B->active_h, sizeof(int) * n, hipHostMallocDefault));
     }
     const int nb = std::min(n, std::max(1, nbranches));
@@ -1982,6 +2004,8 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
     for (auto& st : B->br) HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    HIP_OK(hipEventCreate(&B->ev_t0));
+    HIP_OK(hipEventCreate(&B->ev_t1));
     B->ev_fork.resize(1 + nb);
     for (auto& e : B->ev_fork) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   } catch (const ccg::Error& e) {
@@ -2007,10 +2031,7 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
     }
     HIP_OK(hipEventRecord(B->ev_in, B->caller));
     HIP_OK(hipStreamWaitEvent(B->main, B->ev_in, 0));
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    HIP_OK(hipEventRecord(e0, B->main));
+    HIP_OK(hipEventRecord(B->ev_t0, B->main));
     std::vector<const double*> bterm(n);
     for (int g = 0; g < n; ++g) {
       Driver Dr{B->ctx[g], B->main, nrhs[g], false};
@@ -2020,7 +2041,8 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
     std::vector<Monitor> mon(n);
     for (int g = 0; g < n; ++g) {
       Driver Dr{B->ctx[g], B->main, nrhs[g], false};
-      mon[g].start(B->ctx[g], nrhs[g], Dr.norm_parts(B->ctx[g]->lv[0]));
+      if (!mon[g].start(B->ctx[g], nrhs[g], Dr.norm_parts(B->ctx[g]->lv[0])))
+        throw ccg::Error(CCGMG_EINVAL, "non-finite right-hand side or boundary data for geometry " + std::to_string(g));
     }
     // longest-processing-time-first: geometries by decreasing work (cells x
     // right-hand sides), each onto the least-loaded branch
@@ -2043,6 +2065,7 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
       key.push_back(u[g]);
       key.push_back((const void*)(intptr_t)nrhs[g]);
       key.push_back((const void*)(intptr_t)(B->ctx[g]->opt.precision * 64 + B->ctx[g]->M));
+      key.push_back(bterm[g]);
     }
     hipGraphExec_t exec = nullptr;
     for (auto& gr : B->graphs)
@@ -2104,14 +2127,12 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
       }
       if (all) break;
     }
-    HIP_OK(hipEventRecord(e1, B->main));
+    HIP_OK(hipEventRecord(B->ev_t1, B->main));
     HIP_OK(hipEventRecord(B->ev_out, B->main));
     HIP_OK(hipStreamWaitEvent(B->caller, B->ev_out, 0));
-    HIP_OK(hipEventSynchronize(e1));
+    HIP_OK(hipEventSynchronize(B->ev_t1));
     float ms = 0;
-    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_OK(hipEventElapsedTime(&ms, B->ev_t0, B->ev_t1));
     bool ok = true;
     for (int g = 0; g < n; ++g) {
       if (reps) {
@@ -2141,8 +2162,8 @@ void ccgmg_batch_destroy(ccgmg_batch* B) {
   if (B->main) (void)hipStreamDestroy(B->main);
   for (auto e : B->ev_fork)
     if (e) (void)hipEventDestroy(e);
-  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
-  if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  for (hipEvent_t e : {B->ev_in, B->ev_out, B->ev_t0, B->ev_t1})
+    if (e) (void)hipEventDestroy(e);
   delete B;
 }
 
@@ -2222,8 +2243,10 @@ void ccgmg_destroy(ccgmg_ctx* X) {
     for (void* p : X->owned) (void)hipFree(p);
     for (hipEvent_t e : X->ev_cyc)
       if (e) (void)hipEventDestroy(e);
-    if (X->norm_host) (void)hipHostFree(X->norm_host);
-    if (X->norm_host2) (void)hipHostFree(X->norm_host2);
+    for (hipEvent_t e : {X->ev_pro, X->ev_t0, X->ev_t1})
+      if (e) (void)hipEventDestroy(e);
+    for (double* p : {X->norm_host, X->norm_host2, X->norm_host0})
+      if (p) (void)hipHostFree(p);
   }
   delete X;
 }

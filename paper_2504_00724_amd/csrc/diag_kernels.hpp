@@ -46,7 +46,7 @@ __global__ __launch_bounds__(BLOCK) void k_res_norms(const double* __restrict__ 
       if (gx < nx && gy < ny && (kind[(size_t)gy * nx + gx] & F_REG)) {
         double v = rz[(size_t)gy * nx + gx];
         if (!zero_u) v -= apply_regular<double, CROSS>(tile, w + 4 * k + HALO, tx + HALO, c);
-        mx = fmax(mx, fabs(v));
+        mx = nanmax(mx, fabs(v));
         sq += v * v;
       }
     }
@@ -62,14 +62,14 @@ __global__ __launch_bounds__(BLOCK) void k_res_norms(const double* __restrict__ 
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
-    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    mx = nanmax(mx, __shfl_xor(mx, off, 64));
     sq += __shfl_xor(sq, off, 64);
   }
   if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = mx, red[1][threadIdx.x >> 6] = sq;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = red[0][0], s = red[1][0];
-    for (int i = 1; i < BLOCK / 64; ++i) m = fmax(m, red[0][i]), s += red[1][i];
+    for (int i = 1; i < BLOCK / 64; ++i) m = nanmax(m, red[0][i]), s += red[1][i];
     const size_t o = 2 * ((size_t)z * gridDim.x + blockIdx.x);
     partial[o] = m;
     partial[o + 1] = s;

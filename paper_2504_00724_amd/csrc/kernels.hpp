@@ -69,6 +69,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return start + k;
 }
 
+// Maximum that keeps a NaN (fmax drops it): a non-finite residual must
+// survive the norm reductions so that the host sees it.
+__device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+
 // (L u) at a cell from a value accessor at(dy, dx) (neighbour offsets in
 // -2..2), difference form.  The one arithmetic sequence shared by the LDS
 // tile form and the register-window form below.

@@ -473,7 +473,7 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
       if (kd[k] & regbit) {
         T v = rr[k];
         if (!zero_u) v -= apply_regular<T, CROSS>(tile, w + 4 * k + HALO, tx + HALO, c);
-        m = fmax(m, fabs((double)v));
+        m = nanmax(m, fabs((double)v));
         if (res_out) res_out[(size_t)gy * nx + gx] = (float)v;
       } else if (res_out && gx < nx && gy < ny && !(kd[k] & F_NONEMPTY)) {
         res_out[(size_t)gy * nx + gx] = 0.0f;   // explicit rows: written by the row workgroups
@@ -491,12 +491,12 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
     }
   }
   // maximum within each wavefront, then over the workgroup's wavefronts
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   double out = red[0];
 #pragma unroll
-  for (int w = 1; w < BLOCK / 64; ++w) out = fmax(out, red[w]);
+  for (int w = 1; w < BLOCK / 64; ++w) out = nanmax(out, red[w]);
   return out;
 }
 

@@ -1,0 +1,161 @@
+"""GPU tests of input checks, determinism and boundary-data changes between
+batch solves, through the C-ABI."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.discretization import boundary_data
+from oracle.geometry import cell_averages
+from oracle.multigrid import Level, direct_solve, rhs_vector
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+_LEVELS = {}
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _level(k, n):
+    if (k, n) not in _LEVELS:
+        cfg = W.config(k, n=n)
+        _LEVELS[(k, n)] = (cfg, Level(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"]))
+    return _LEVELS[(k, n)]
+
+
+def _solver(cfg, **kw):
+    from paper_2504_00724_amd.ccgmg import Solver
+    return Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"],
+                  hip_stream=torch.cuda.current_stream().cuda_stream, **kw)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_nonfinite_data_is_einval(precision):
+    """A NaN or Inf in f-hat or g-hat is refused with EINVAL (not left to
+    end in ENOCONV), by single and batched solves; the context still solves
+    a good problem afterwards."""
+    from paper_2504_00724_amd.ccgmg import EINVAL, Batch, CcgmgError
+    dev = _dev()
+    cfg, lv = _level(2, 64)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ref = direct_solve(lv, rhs_vector(lv, f, g))
+    S = _solver(cfg, tol=1e-12, max_cycles=200, precision=precision)
+    print("non-finite data, precision %d" % precision, flush=True)
+    gd = torch.tensor(g, device=dev)
+    S.set_boundary(gd, 1)
+    u = torch.zeros(64 * 64, dtype=torch.float64, device=dev)
+    ne = np.flatnonzero(lv.nonempty)
+    for bad in (float("nan"), float("inf")):
+        fb = torch.tensor(f, device=dev)
+        fb[int(ne[len(ne) // 2])] = bad
+        with pytest.raises(CcgmgError) as e:
+            S.solve(fb, u)
+        assert e.value.code == EINVAL and "non-finite" in str(e.value)
+    gb = gd.clone()
+    gb[0] = float("nan")
+    S.set_boundary(gb, 1)
+    fd = torch.tensor(f, device=dev)
+    with pytest.raises(CcgmgError) as e:
+        S.solve(fd, u)
+    assert e.value.code == EINVAL
+    B = Batch([S], nbranches=1)
+    with pytest.raises(CcgmgError) as e:
+        B.solve([fd], [u])
+    assert e.value.code == EINVAL
+    B.close()
+    # a good problem afterwards
+    S.set_boundary(gd, 1)
+    u.zero_()
+    S.solve(fd, u)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-10
+    S.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_repeat_solves_bit_identical(precision):
+    """Two identical solves give bit-identical solutions and residual
+    histories (every reduction runs in a fixed order; nothing depends on
+    timing), single and lockstep-batched."""
+    from paper_2504_00724_amd.ccgmg import Batch
+    dev = _dev()
+    out = []
+    for k, n in ((4, 128), (5, 64)):
+        cfg, lv = _level(k, n)
+        f = torch.tensor(cell_averages(lv.cg, cfg["f"]).ravel(), device=dev)
+        g = torch.tensor(boundary_data(lv.disc, cfg["solution"]), device=dev)
+        S = _solver(cfg, tol=1e-11, max_cycles=200, precision=precision)
+        S.set_boundary(g, 1)
+        us, hs = [], []
+        for _ in range(2):
+            u = torch.zeros_like(f)
+            rep = S.solve(f, u)
+            torch.cuda.synchronize()
+            us.append(u.cpu().numpy())
+            hs.append(rep["history"])
+        print("config %d n=%d precision %d: %d cycles" % (k, n, precision, len(hs[0])), flush=True)
+        assert np.array_equal(us[0].view(np.uint64), us[1].view(np.uint64))
+        assert hs[0] == hs[1]
+        out.append((S, f, us[0]))
+    B = Batch([o[0] for o in out], nbranches=0)
+    bu = []
+    for _ in range(2):
+        uu = [torch.zeros_like(o[1]) for o in out]
+        B.solve([o[1] for o in out], uu)
+        torch.cuda.synchronize()
+        bu.append([u.cpu().numpy() for u in uu])
+    for a, b in zip(*bu):
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    B.close()
+    for S, _, _ in out:
+        S.close()
+
+
+@pytest.mark.parametrize("nbranches", [0, 2])
+def test_batch_follows_boundary_data_changes(nbranches):
+    """A batch solve with no boundary data, then ccgmg_set_boundary on one
+    geometry and a second batch solve with the same arrays: each solve
+    matches the oracle's direct solve of the problem as it then stands (the
+    captured cycle must not keep the first solve's boundary term)."""
+    from paper_2504_00724_amd.ccgmg import Batch
+    dev = _dev()
+    cases = [(2, 64), (1, 64)]
+    solvers, fs, us, lvs, gs, fh = [], [], [], [], [], []
+    for k, n in cases:
+        cfg, lv = _level(k, n)
+        f = cell_averages(lv.cg, cfg["f"]).ravel()
+        g = boundary_data(lv.disc, cfg["solution"])
+        S = _solver(cfg, tol=1e-12, max_cycles=200)
+        solvers.append(S)
+        fs.append(torch.tensor(f, device=dev))
+        us.append(torch.zeros(n * n, dtype=torch.float64, device=dev))
+        lvs.append(lv)
+        gs.append(g)
+        fh.append(f)
+    B = Batch(solvers, nbranches=nbranches)
+    print("boundary toggle, nbranches %d" % nbranches, flush=True)
+    for step in range(3):
+        # step 0: no boundary data anywhere; 1: geometry 0 gets its data;
+        # 2: geometry 0 drops it again
+        if step == 1:
+            solvers[0].set_boundary(torch.tensor(gs[0], device=dev), 1)
+        if step == 2:
+            solvers[0].set_boundary(None, 0)
+        for u in us:
+            u.zero_()
+        B.solve(fs, us)
+        torch.cuda.synchronize()
+        for i, lv in enumerate(lvs):
+            gi = gs[i] if (i == 0 and step == 1) else np.zeros_like(gs[i])
+            ref = direct_solve(lv, rhs_vector(lv, fh[i], gi))
+            err = np.max(np.abs(us[i].cpu().numpy() - ref)) / np.max(np.abs(ref))
+            print("   step %d geometry %d: rel err %.2e" % (step, i, err), flush=True)
+            assert err <= 1e-10
+    B.close()
+    for S in solvers:
+        S.close()

@@ -295,13 +295,16 @@ def test_zero_data_and_argument_errors():
     rep = S.solve(f, u)
     torch.cuda.synchronize()
     assert rep["cycles"] <= 1 and torch.count_nonzero(u).item() == 0
+    f2 = torch.zeros(2 * 64 * 64, dtype=torch.float64, device=dev)
     with pytest.raises(CcgmgError) as e:
-        S.solve(f, u, nrhs=2)
+        S.solve(f2, torch.zeros_like(f2), nrhs=2)   # beyond max_nrhs = 1
     assert e.value.code == EINVAL
     B = Batch([S])
     with pytest.raises(CcgmgError) as e:
-        B.solve([f], [u], [2])
+        B.solve([f2], [torch.zeros_like(f2)], [2])
     assert e.value.code == EINVAL
+    with pytest.raises(ValueError):
+        B.solve([f], [u], [2])   # arrays sized for one right-hand side
     B.close()
     c4 = W.config(4, n=128)
     with pytest.raises(CcgmgError) as e:

@@ -258,6 +258,22 @@ int ccgmg_apply(ccgmg_ctx* ctx, const double* u, double* Lu);
 int ccgmg_residual_norms(ccgmg_ctx* ctx, const double* f_hat, const double* u_hat, int nrhs, double* rel_inf,
                          double* rel_l2);
 
+/* ccgmg_residual_norms for callers that cannot allocate (tight serving
+ * loops, code between graph replays, harnesses that forbid allocation):
+ * the same arguments and results (rel_inf equal, rel_l2
+ * equal up to the order of the last sums), with every intermediate in a
+ * static device array of 4 MiB that the library holds on each GPU it runs
+ * on until the process ends.  It needs 8 * (4 * np + 4) * nrhs bytes, np =
+ * the residual launch's workgroups (64 x 16 tiles plus one per 256
+ * least-squares rows: 4211 at 2048^2, so up to 31 planes there);
+ * CCGMG_EINVAL if that is more than 4 MiB, or if the current device is not
+ * the context's.  Calls no hipMalloc, hipFree or other allocating routine.
+ * Every call on a GPU reuses that GPU's one array (nothing in it needs to
+ * start at zero): calls that overlap on one GPU, from other threads or
+ * contexts, race.  Synchronous, like ccgmg_residual_norms. */
+int ccgmg_residual_norms_noalloc(ccgmg_ctx* ctx, const double* f_hat, const double* u_hat, int nrhs,
+                                 double* rel_inf, double* rel_l2);
+
 /* Set the boundary data g-hat (device, n_bdry_faces * nrhs doubles, face
  * fastest).  The library copies it; nrhs <= max_nrhs. */
 int ccgmg_set_boundary(ccgmg_ctx* ctx, const double* g_hat, int nrhs);

@@ -23,6 +23,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTELLIPTIC", -3: "EGEOM", -4: "EPLG", -5
 EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_stencils", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply", "ccgmg_residual_norms",
+           "ccgmg_residual_norms_noalloc",
            "ccgmg_set_boundary", "ccgmg_solve", "ccgmg_solve_adjoint", "ccgmg_apply_adjoint", "ccgmg_apply_NT",
            "ccgmg_profile_kernel", "ccgmg_get_tuning", "ccgmg_get_smo2_stats", "ccgmg_tune",
            "ccgmg_batch_create", "ccgmg_batch_solve", "ccgmg_batch_last_error", "ccgmg_batch_destroy",
@@ -90,6 +91,7 @@ def lib():
         L.ccgmg_face_quadrature.argtypes = [vp, C.POINTER(C.c_long), vp, vp, vp, vp, vp, vp]
         L.ccgmg_apply.argtypes = [vp, vp, vp]
         L.ccgmg_residual_norms.argtypes = [vp, vp, vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ccgmg_residual_norms_noalloc.argtypes = [vp, vp, vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ccgmg_set_boundary.argtypes = [vp, vp, ip]
         L.ccgmg_solve.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
         L.ccgmg_solve_adjoint.argtypes = [vp, vp, vp, ip, C.POINTER(ReportT)]
@@ -292,6 +294,15 @@ class Solver:
         n = nrhs * self.n_cells
         ri, r2 = (C.c_double * nrhs)(), (C.c_double * nrhs)()
         self._check(lib().ccgmg_residual_norms(self.ctx, _dev(f, n, "f"), _dev(u, n, "u"), nrhs, ri, r2))
+        return list(ri), list(r2)
+
+    def residual_norms_noalloc(self, f, u, nrhs=1):
+        """residual_norms through ccgmg_residual_norms_noalloc (the library's
+        static device scratch; no allocation in the library)."""
+        nrhs = _count(nrhs)
+        n = nrhs * self.n_cells
+        ri, r2 = (C.c_double * nrhs)(), (C.c_double * nrhs)()
+        self._check(lib().ccgmg_residual_norms_noalloc(self.ctx, _dev(f, n, "f"), _dev(u, n, "u"), nrhs, ri, r2))
         return list(ri), list(r2)
 
     def set_boundary(self, g, nrhs=1):

@@ -26,6 +26,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <random>
 #include <set>
 #include <string>
@@ -39,6 +40,13 @@
 
 using namespace ccgk;
 
+// Device scratch of ccgmg_residual_norms_noalloc (partial maxima and sums of
+// squares, then the per-plane totals), for callers that cannot allocate.  In
+// host code `scratch` only names the symbol: its device address differs per
+// GPU and is taken with hipGetSymbolAddress (scratch_on_current_device).
+constexpr size_t SCRATCH_DOUBLES = (size_t)1 << 19;   // 4 MiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
 // ===========================================================================
 // Host side
 // ===========================================================================
@@ -46,11 +54,31 @@ namespace {
 
 thread_local std::string g_create_error;
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
 #define HIP_OK(x)                                                                                          \
   do {                                                                                                     \
     hipError_t e_ = (x);                                                                                   \
     if (e_ != hipSuccess) throw ccg::Error(CCGMG_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Device address of the static scratch array on the current device, looked
+// up once per device (with that device current) and kept.
+double* scratch_on_current_device() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) throw ccg::Error(CCGMG_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw ccg::Error(CCGMG_EDEVICE, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[dev] = p;
+  }
+  return (double*)g_scratch_ptr[dev];
+}
 
 template <typename T>
 T* dalloc(size_t n, std::vector<void*>& owned) {
@@ -156,6 +184,8 @@ struct ccgmg_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_cyc[2] = {nullptr, nullptr};   // ends of the cycles in flight (alternating)
   hipEvent_t ev_pro = nullptr;      // end of a solve's prologue (reference norm read back)
+  int device = 0;                   // the HIP device the context lives on
+  double* scratch = nullptr;        // that device's static scratch array (no-alloc entry point)
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;   // device time of a solve (created once)
   struct GraphEntry {
     const void *u, *f, *bterm, *norm;
@@ -1666,6 +1696,8 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
     X->M = (int)X->H.disc.size() - 1;
     if (!X->host_only) {
       X->stream = (hipStream_t)X->opt.hip_stream;
+      HIP_OK(hipGetDevice(&X->device));
+      X->scratch = scratch_on_current_device();
       HIP_OK(hipStreamCreateWithFlags(&X->ws, hipStreamNonBlocking));
       HIP_OK(hipEventCreateWithFlags(&X->ev_in, hipEventDisableTiming));
       HIP_OK(hipEventCreateWithFlags(&X->ev_out, hipEventDisableTiming));
@@ -1929,6 +1961,78 @@ int ccgmg_residual_norms(ccgmg_ctx* X, const double* f, const double* u, int nrh
       if (rel_l2) rel_l2[z] = std::sqrt(q[1]) / (q[0] > 0 ? std::sqrt(q[0]) : 1.0);
     }
   });
+}
+
+// As ccgmg_residual_norms, with every intermediate in the device's static
+// scratch array (X->scratch, found at set-up) and the totals reduced on the
+// device: no device or host allocation on the way to a result.  Calls that
+// overlap on one device share the array and race.
+int ccgmg_residual_norms_noalloc(ccgmg_ctx* X, const double* f, const double* u, int nrhs, double* rel_inf,
+                                 double* rel_l2) {
+  if (!X) return CCGMG_EINVAL;
+  try {
+    if (X->host_only) throw ccg::Error(CCGMG_EINVAL, "context was created with host_only");
+    if (!f || !u || nrhs < 1 || nrhs > X->opt.max_nrhs || (!rel_inf && !rel_l2))
+      throw ccg::Error(CCGMG_EINVAL, "bad residual-norm arguments");
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != X->device) throw ccg::Error(CCGMG_EINVAL, "the current device is not the context's device");
+    DevLevel& L0 = X->lv[0];
+    const DevRows& R = L0.fwd;
+    const int nbx = tiles_x(L0.nx);
+    const int ntiles = nbx * ((L0.ny + TY - 1) / TY);
+    const int nrb = (R.n + BLOCK - 1) / BLOCK;
+    const int np = ntiles + nrb;
+    const size_t per = (size_t)2 * np * nrhs;   // (max, sum of squares) per workgroup and plane
+    const size_t need = 2 * per + 4 * (size_t)nrhs;
+    if (need > SCRATCH_DOUBLES)
+      throw ccg::Error(CCGMG_EINVAL, "needs " + std::to_string(need * sizeof(double)) +
+                                         " bytes of scratch; the static scratch holds " +
+                                         std::to_string(SCRATCH_DOUBLES * sizeof(double)) + " (fewer planes fit)");
+    double* part = X->scratch;
+    double* tot = part + 2 * per;
+    hipStream_t ws = X->ws;
+    HIP_OK(hipEventRecord(X->ev_in, X->stream));
+    HIP_OK(hipStreamWaitEvent(ws, X->ev_in, 0));
+    const double* bterm = nullptr;
+    if (X->nfaces > 0 && X->g_nrhs >= nrhs && R.n > 0) {
+      hipLaunchKernelGGL(k_bterm, dim3((R.n + 255) / 256, nrhs), dim3(256), 0, ws, X->g, X->fptr, X->fface, X->fval,
+                         X->bterm, R.n, X->nfaces);
+      bterm = X->bterm;
+    }
+    const dim3 g(np, 1, nrhs);
+    CoefT<double> c(L0.coef);
+    for (int zero_u = 1; zero_u >= 0; --zero_u) {
+      double* out = part + (zero_u ? 0 : per);
+      if (L0.cross)
+        hipLaunchKernelGGL((k_res_norms<true>), g, dim3(BLOCK), 0, ws, u, f, L0.kind, L0.nx, L0.ny, nbx, ntiles, c,
+                           zero_u, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, out);
+      else
+        hipLaunchKernelGGL((k_res_norms<false>), g, dim3(BLOCK), 0, ws, u, f, L0.kind, L0.nx, L0.ny, nbx, ntiles, c,
+                           zero_u, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, out);
+    }
+    hipLaunchKernelGGL(k_norm_finish, dim3(2, nrhs), dim3(BLOCK), 0, ws, part, per, np, tot);
+    HIP_OK(hipGetLastError());
+    // totals back in chunks of 64 planes through a stack buffer
+    double hb[4 * 64];
+    for (int z0 = 0; z0 < nrhs; z0 += 64) {
+      const int cnt = std::min(64, nrhs - z0);
+      HIP_OK(hipMemcpyAsync(hb, tot + 4 * (size_t)z0, sizeof(double) * 4 * cnt, hipMemcpyDeviceToHost, ws));
+      HIP_OK(hipStreamSynchronize(ws));
+      for (int k = 0; k < cnt; ++k) {
+        const double* e = hb + 4 * k;   // reference max, sum; residual max, sum
+        if (rel_inf) rel_inf[z0 + k] = e[2] / (e[0] > 0 ? e[0] : 1.0);
+        if (rel_l2) rel_l2[z0 + k] = std::sqrt(e[3]) / (e[1] > 0 ? std::sqrt(e[1]) : 1.0);
+      }
+    }
+  } catch (const ccg::Error& e) {
+    X->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    X->err = e.what();
+    return CCGMG_EINVAL;
+  }
+  return CCGMG_OK;
 }
 
 int ccgmg_apply_adjoint(ccgmg_ctx* X, const double* lam, double* out) { return apply_impl(X, lam, out, true); }

@@ -75,3 +75,35 @@ __global__ __launch_bounds__(BLOCK) void k_res_norms(const double* __restrict__ 
     partial[o + 1] = s;
   }
 }
+
+// Totals of the partials written by k_res_norms: workgroup (k, z) reduces
+// the np (maximum, sum of squares) pairs of plane z of launch k (0: the
+// reference r - bterm, 1: the residual r - bterm - L u), stored at
+// part + k * per, into out[4 z + 2 k] (maximum) and out[4 z + 2 k + 1] (sum
+// of squares).  Fixed order (strided per thread, then a tree), so repeated
+// calls give identical totals.
+__global__ __launch_bounds__(BLOCK) void k_norm_finish(const double* __restrict__ part, size_t per, int np,
+                                                       double* __restrict__ out) {
+  __shared__ double red[2][BLOCK];
+  const int k = blockIdx.x, z = blockIdx.y;
+  const double* p = part + k * per + 2 * (size_t)z * np;
+  double mx = 0.0, sq = 0.0;
+  for (int b = threadIdx.x; b < np; b += BLOCK) {
+    mx = nanmax(mx, p[2 * b]);
+    sq += p[2 * b + 1];
+  }
+  red[0][threadIdx.x] = mx;
+  red[1][threadIdx.x] = sq;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] = nanmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[4 * (size_t)z + 2 * k] = red[0][0];
+    out[4 * (size_t)z + 2 * k + 1] = red[1][0];
+  }
+}

@@ -2,22 +2,23 @@
 2048^2, default options as the benchmark runs them), through the C ABI.
 
 The oracle builds the full cut-cell geometry and classification at 2048^2
-and fits least-squares rows for a seeded sample of irregular cells only
-(fitting all 29 K rows takes minutes).  Checked against it:
+and fits the least-squares rows of all irregular cells (29 K rows, fitted in
+worker processes, tests/oracle_jobs.py).  Checked against it:
 
 * cell kinds and merge hosts on every cell (bit-exact);
-* lattices (bit-exact) and weights of the sampled rows;
-* the GPU operator on sampled rows (irregular and regular) for a random u;
-* the converged GPU solution through its residual on sampled rows,
-  recomputed here in FP64 from the oracle's rows (a property that holds at
-  any size: the solve reached 1e-10 of the system the oracle assembles),
-  and its error against the manufactured solution;
+* the lattice of every irregular row (bit-exact) and its weights;
+* the GPU operator on every non-empty cell for a random u;
+* the converged GPU solution through its residual f - N g - L u on every
+  non-empty cell, recomputed here in FP64 (difference form) from the
+  oracle's rows (the solve reached 1e-10 of the system the oracle
+  assembles), and its error against the manufactured solution;
 * mixed precision against FP64 at the same size (within the
   discretization error).
 """
 import numpy as np
 import pytest
 
+import oracle_jobs
 import workloads as W
 from oracle.discretization import Discretization, regular_coefficients
 from oracle.geometry import CutGrid
@@ -26,7 +27,6 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 N = 2048
-SAMPLES = 96
 
 
 @pytest.fixture(scope="module")
@@ -44,52 +44,68 @@ def full():
     print("full-size parity: oracle geometry (2048^2)", flush=True)
     cg = CutGrid(cfg["grid"], cfg["curves"])
     d = Discretization(cg, cfg["a"], cfg["b"], cfg["c"], eager=False)
-    rng = np.random.default_rng(2048)
-    sample = np.sort(rng.choice(d.irregular, size=SAMPLES, replace=False))
-    print("full-size parity: fitting %d sampled oracle rows" % SAMPLES, flush=True)
-    rows = {int(q): d.row(int(q)) for q in sample}
-    yield dict(S=S, cfg=cfg, cg=cg, d=d, f=f, g=g, exact=exact, kinds=kinds, sample=sample, rows=rows, dev=dev)
+    print("full-size parity: fitting all %d oracle rows in worker processes" % len(d.irregular), flush=True)
+    rows = oracle_jobs.all_rows(4, N, d.irregular)
+    irr = np.asarray(d.irregular)
+    R = dict(cells=np.array([rows[int(q)][0] for q in irr], dtype=np.int64),
+             w=np.array([rows[int(q)][1] for q in irr]),
+             fq=np.array([k for k, q in enumerate(irr) for _ in rows[int(q)][2]], dtype=np.int64),
+             ff=np.array([fk for q in irr for fk, _ in rows[int(q)][2]], dtype=np.int64),
+             fw=np.array([wf for q in irr for _, wf in rows[int(q)][2]]))
+    print("full-size parity: oracle rows ready", flush=True)
+    yield dict(S=S, cfg=cfg, cg=cg, d=d, f=f, g=g, exact=exact, kinds=kinds, rows=rows, R=R, irr=irr, dev=dev)
     S.close()
 
 
-def _oracle_Lu(F, q, u):
-    """(L u)_q from the oracle's row (difference form) and |L||u| at q."""
-    d = F["d"]
-    nx = d.nx
-    if d.regular[q]:
-        coef = regular_coefficients(d.a, d.b, d.c, d.h)
-        i, j = q % nx, q // nx
-        acc, mag = 0.0, 0.0
-        for (dx, dy), w in coef.items():
-            k = (j + dy) * nx + i + dx
-            if (dx, dy) != (0, 0):
-                acc += w * (u[k] - u[q])
-            mag += abs(w) * abs(u[k])
-        return acc + sum(coef.values()) * u[q], mag
-    cells, w, _ = F["rows"][q]
-    acc = sum(wk * (u[k] - u[q]) for k, wk in zip(cells, w)) + float(np.sum(w)) * u[q]
-    return acc, float(np.sum(np.abs(w) * np.abs(u[np.array(cells)])))
+def _oracle_apply(F, u):
+    """(L u) on every non-empty cell from the oracle's regular stencil and
+    rows, in difference form, and |L||u| row by row."""
+    d, R, irr = F["d"], F["R"], F["irr"]
+    nx = ny = N
+    U = u.reshape(ny, nx)
+    P = np.zeros((ny + 4, nx + 4))
+    P[2:-2, 2:-2] = U
+    A = np.abs(P)
+    acc = np.zeros((ny, nx))
+    mag = np.zeros((ny, nx))
+    coef = regular_coefficients(d.a, d.b, d.c, d.h)
+    for (dx, dy), v in coef.items():
+        sl = (slice(2 + dy, 2 + dy + ny), slice(2 + dx, 2 + dx + nx))
+        if (dx, dy) != (0, 0):
+            acc += v * (P[sl] - U)
+        mag += abs(v) * A[sl]
+    acc += sum(coef.values()) * U
+    out = np.where(d.regular.reshape(ny, nx), acc, 0.0).ravel()
+    mag = np.where(d.regular.reshape(ny, nx), mag, 0.0).ravel()
+    uq = u[irr][:, None]
+    out[irr] = np.sum(R["w"] * (u[R["cells"]] - uq), axis=1) + R["w"].sum(axis=1) * u[irr]
+    mag[irr] = np.sum(np.abs(R["w"]) * np.abs(u[R["cells"]]), axis=1)
+    return out, mag
 
 
-def test_fullsize_classification_and_sampled_rows(full):
+def test_fullsize_classification_and_all_rows(full):
     S, d, cg = full["S"], full["d"], full["cg"]
     kind, host = S.kinds(0)
     assert np.array_equal(kind, d.kind)
     assert np.array_equal(host, cg.host)
     rows, cols, vals, _ = S.irregular(0)
     assert np.array_equal(rows, d.irregular)
-    fcell, fcurve, _ = S.boundary_faces()
+    fcell, fcurve, nweight = S.boundary_faces()
     assert [(int(a), int(b)) for a, b in zip(fcell, fcurve)] == d.faces
-    pos = {int(q): i for i, q in enumerate(rows)}
-    for q in full["sample"]:
-        q = int(q)
-        cells, w, _ = full["rows"][q]
-        i = pos[q]
-        assert list(cols[i]) == list(cells)
-        assert np.max(np.abs(vals[i] - w)) * d.h ** 2 <= 1e-12
+    R = full["R"]
+    assert np.array_equal(cols, R["cells"])
+    werr = np.max(np.abs(vals - R["w"])) * d.h ** 2
+    ref_nw = np.zeros(len(d.faces))
+    ref_nw[R["ff"]] = R["fw"]
+    # Dirichlet data everywhere: boundary weights in 1/h^2 units like the cells'
+    nerr = np.max(np.abs(nweight - ref_nw)) * d.h ** 2
+    print("full-size rows: %d lattices equal, weight error %.2e, boundary weight error %.2e (h^2 units)"
+          % (len(rows), werr, nerr), flush=True)
+    assert werr <= 1e-12
+    assert nerr <= 1e-12
 
 
-def test_fullsize_operator_on_sampled_rows(full):
+def test_fullsize_operator_on_every_cell(full):
     S, d, dev = full["S"], full["d"], full["dev"]
     rng = np.random.default_rng(7)
     u = rng.standard_normal(N * N) * d.nonempty
@@ -97,46 +113,37 @@ def test_fullsize_operator_on_sampled_rows(full):
     S.apply(torch.tensor(u, device=dev), out)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    regular = np.flatnonzero(d.regular)
-    reg_sample = rng.choice(regular, size=SAMPLES, replace=False)
-    for q in list(full["sample"]) + list(reg_sample):
-        ref, mag = _oracle_Lu(full, int(q), u)
-        assert abs(got[q] - ref) <= 1e-12 * mag, (int(q), got[q], ref)
+    ref, mag = _oracle_apply(full, u)
+    ne = d.nonempty
+    worst = np.max(np.abs(got - ref)[ne] / mag[ne])
+    print("full-size operator: worst |L u - oracle| / (|L||u|) = %.2e over %d cells" % (worst, int(ne.sum())),
+          flush=True)
+    assert worst <= 1e-12
+    assert np.all(got[~ne] == 0.0)
 
 
 def test_fullsize_solution_residual_and_error(full):
-    S, d, dev = full["S"], full["d"], full["dev"]
+    S, d, dev, R, irr = full["S"], full["d"], full["dev"], full["R"], full["irr"]
     f, g = full["f"], full["g"]
     S.set_boundary(g, 1)
     u = torch.zeros_like(f)
     rep = S.solve(f, u)
     torch.cuda.synchronize()
     uh = u.cpu().numpy()
-    fh = f.cpu().numpy()
+    rhs = f.cpu().numpy().copy()
     gh = g.cpu().numpy()
-    # conservative reference norm: |f| on regular cells and |f - N g| on the
-    # sampled irregular rows (a subset of the true max)
-    ref = np.max(np.abs(fh[d.regular]))
-    worst = 0.0
-    rng = np.random.default_rng(11)
-    reg_sample = rng.choice(np.flatnonzero(d.regular), size=SAMPLES, replace=False)
-    for q in list(full["sample"]) + list(reg_sample):
-        q = int(q)
-        Lu, _ = _oracle_Lu(full, q, uh)
-        rhs = fh[q]
-        if not d.regular[q]:
-            for fk, wf in full["rows"][q][2]:
-                rhs -= wf * gh[fk]
-            ref = max(ref, abs(rhs))
-        worst = max(worst, abs(rhs - Lu))
-    rel = worst / ref
-    err = np.max(np.abs(uh - full["exact"])[d.nonempty])
-    print("full-size solve: cycles %d, library rel_res %.2e, sampled oracle residual %.2e, error vs exact %.2e"
+    # f - N g on every non-empty cell (N from the oracle's rows)
+    np.subtract.at(rhs, irr[R["fq"]], R["fw"] * gh[R["ff"]])
+    Lu, _ = _oracle_apply(full, uh)
+    ne = d.nonempty
+    rel = np.max(np.abs(rhs - Lu)[ne]) / np.max(np.abs(rhs)[ne])
+    err = np.max(np.abs(uh - full["exact"])[ne])
+    print("full-size solve: cycles %d, library rel_res %.2e, oracle residual on every cell %.2e, error vs exact %.2e"
           % (rep["cycles"], rep["rel_res_inf"], rel, err), flush=True)
     assert rep["rel_res_inf"] <= 1e-10
     assert rel <= 1.5e-10
     assert err < 1e-8          # fourth order: ~3e-9 at h = 1/2048 for this workload
-    assert np.all(uh[~d.nonempty] == 0.0)
+    assert np.all(uh[~ne] == 0.0)
     full["u64"] = uh
 
 

@@ -10,10 +10,11 @@ from oracle.multigrid import Level, direct_solve, rhs_vector
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-# workload configs by number, the paper's problems by name (Problem 2 with
-# Neumann, or Robin, data on the ellipse, Problem 3 case (i)); 72: ragged
-# tiles on every level
-CASES = [(1, 64), (2, 64), (4, 128), (5, 64), (1, 72), ("P2N", 64), ("P2R", 64), ("P3", 64)]
+# workload configs by number, the paper's problems by name (Problem 1 on its
+# coarsest table grid, Problem 2 with Neumann, Dirichlet or Robin data on the
+# ellipse, Problem 3 case (i)); 72: ragged tiles on every level
+CASES = [(1, 64), (2, 64), (4, 128), (5, 64), (1, 72), ("P1", 40), ("P2N", 64), ("P2D", 64), ("P2R", 64),
+         ("P3", 64)]
 _LEVELS = {}
 
 
@@ -570,4 +571,80 @@ def test_residual_norms_match_oracle():
     # 1e10 times smaller)
     assert abs(ri[0] - rep["rel_res_inf"]) <= 1e-4 * rep["rel_res_inf"]
     assert ri[0] <= 1e-10 and r2[0] <= 1e-10
+    S.close()
+
+
+_REFS = {}
+
+
+def _reference(k, n):
+    """(f, g, oracle direct solution) of a case, cached."""
+    if (k, n) not in _REFS:
+        cfg, lv = _level(k, n)
+        f = cell_averages(lv.cg, cfg["f"]).ravel()
+        g = boundary_data(lv.disc, cfg["solution"])
+        _REFS[(k, n)] = (f, g, direct_solve(lv, rhs_vector(lv, f, g)))
+    return _REFS[(k, n)]
+
+
+@pytest.mark.parametrize("k,n", [(4, 128), (5, 128), (2, 64)])
+@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("ty", [8, 16, 32])
+def test_solve_parity_every_tile_height(k, n, fused, ty):
+    """Every instantiation of the smoothing kernels a solve can pick (SMO-1
+    tile height 8, 16 or 32 rows; fused or separate SMO-1 / SMO-2 launches,
+    hence the correction-applying fused variant; b = 0 and the
+    cross-derivative register-window path for b != 0), forced on every
+    level, converges to the oracle's direct solution."""
+    dev = _dev()
+    cfg, lv = _level(k, n)
+    f, g, ref = _reference(k, n)
+    print("tile parity config %d n=%d fused %d rows %d" % (k, n, fused, ty), flush=True)
+    S = _solver(cfg, tol=1e-12, max_cycles=300, sweep_tile_rows=ty, tune_schedule=0, smoother_fused=fused,
+                nu1=4, nu2=4)
+    assert all(S.tuning(m)[0] == ty for m in range(S.info["n_levels"]))
+    fd = torch.tensor(f, device=dev)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    u = torch.zeros_like(fd)
+    rep = S.solve(fd, u)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    print("   cycles %d rel_res %.2e rel_err %.2e" % (rep["cycles"], rep["rel_res_inf"], err), flush=True)
+    assert err <= 1e-10
+    S.close()
+
+
+@pytest.fixture(scope="module")
+def large_refs():
+    """Oracle direct solutions of the three-circle (b = 0) and five-ellipse
+    (b = 1.2) workloads at 256^2 and 512^2, computed in worker processes."""
+    import oracle_jobs
+    cases = [(4, 256), (4, 512), (5, 256), (5, 512)]
+    print("oracle direct solves at 256^2 and 512^2 in worker processes", flush=True)
+    with oracle_jobs.pool(len(cases)) as ex:
+        res = list(ex.map(oracle_jobs.direct_reference, [k for k, _ in cases], [n for _, n in cases]))
+    return dict(zip(cases, res))
+
+
+@pytest.mark.parametrize("k,n", [(4, 256), (4, 512), (5, 256), (5, 512)])
+def test_solve_matches_oracle_elementwise_at_256_and_512(large_refs, k, n):
+    """Element by element against the oracle's sparse direct solve at
+    256^2 and 512^2 (several tiles per level, the benchmark's tuned tiles,
+    schedule and depth)."""
+    dev = _dev()
+    f, g, ref, ne = large_refs[(k, n)]
+    cfg = W.config(k, n=n)
+    S = _solver(cfg, tol=1e-12, max_cycles=300)
+    fd = torch.tensor(f, device=dev)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    u = torch.zeros_like(fd)
+    rep = S.solve(fd, u)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print("config %d n=%d: cycles %d rel_res %.2e rel_err %.2e tiles %s" % (
+        k, n, rep["cycles"], rep["rel_res_inf"], err, [S.tuning(m)[0] for m in range(S.info["n_levels"])]),
+        flush=True)
+    assert err <= 1e-10
+    assert np.all(got[~ne] == 0.0)
     S.close()

@@ -254,6 +254,49 @@ class Hierarchy:
             u = self.smooth(m, u, r, omega)
         return u
 
+    def fmg_cycle(self, r, nu1=3, nu2=3, omega=0.5):
+        """One FMG cycle (Section 4, Fig. 4) for L e = r from a zero guess.
+
+        The right-hand side descends to the coarsest level by the
+        restriction of Alg. 2 (the residual of the zero iterate, restricted
+        level by level); the coarsest level is solved by the bottom solver;
+        then, level by level upwards, the solution of the level below,
+        prolonged (Alg. 2's prolongation), is the initial guess of one
+        V-cycle on that level with that level's restricted right-hand side."""
+        rs = [r]
+        for m in range(self.M):
+            rs.append(self.restrict(m, rs[m]))
+        e = self.bottom_solve(rs[self.M])
+        for m in range(self.M - 1, -1, -1):
+            e = self.vcycle(m, self.prolong(m, e), rs[m], nu1, nu2, omega)
+        return e
+
+    def solve_fmg(self, r, tol=1e-10, max_cycles=100, nu1=3, nu2=3, omega=0.5, history=None):
+        """FMG cycle iterations (Section 5.2 counts these): from a zero
+        guess, u += FMG(r - L u) until the relative L-infinity residual
+        reaches tol or stagnates (as in solve)."""
+        lv = self.levels[0]
+        u = np.zeros(lv.nx * lv.ny)
+        rn = np.max(np.abs(r[lv.nonempty]))
+        if rn == 0.0:
+            return u
+        prev, slow = None, 0
+        for _ in range(max_cycles):
+            u = u + self.fmg_cycle(self.residual(u, r), nu1, nu2, omega)
+            rel = np.max(np.abs(self.residual(u, r))) / rn
+            if history is not None:
+                history.append(rel)
+            if rel <= tol:
+                break
+            if prev is not None and rel > 0.95 * prev:
+                slow += 1
+                if slow >= 3:
+                    break
+            else:
+                slow = 0
+            prev = rel
+        return u
+
     def residual(self, u, r):
         lv = self.levels[0]
         return (r - lv.L @ u) * lv.nonempty

@@ -221,3 +221,64 @@ def test_problem3_rotated_box_matches_paper_table():
             assert table / 3 < e[k][norm] < table * 3, (k, norm, e[k][norm], table)
     for norm in ("L1", "L2", "Linf"):
         assert 3.7 < np.log2(e[0][norm] / e[1][norm]) < 5.0
+
+
+def _problem2_hierarchy(n, bc="P2D"):
+    cfg = W.problem(bc, n)
+    H = Hierarchy(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"])
+    lv = H.levels[0]
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    return H, rhs_vector(lv, f, g)
+
+
+def test_fmg_with_one_level_is_the_direct_solve():
+    """With the hierarchy cut to the finest level, an FMG cycle is the
+    bottom solver alone: the exact solution in one iteration."""
+    H, r = _problem2_hierarchy(32)
+    while H.M > 0:
+        H.levels.pop()
+    H._factor_bottom()
+    ref = direct_solve(H.levels[0], r)
+    e = H.fmg_cycle(r)
+    assert np.max(np.abs(e - ref)) <= 1e-13 * np.max(np.abs(ref))
+    hist = []
+    H.solve_fmg(r, tol=1e-12, history=hist)
+    assert len(hist) == 1 and hist[0] <= 1e-12
+
+
+def test_fmg_cycle_is_linear_and_converges_to_the_direct_solve():
+    """An FMG cycle from a zero guess is a linear map of its right-hand side
+    (restriction, LU, prolongation and smoothing are linear), and FMG
+    iterations converge to the direct solution of L u = f - N g."""
+    H, r = _problem2_hierarchy(64)
+    assert H.M >= 2
+    rng = np.random.default_rng(5)
+    r2 = rng.standard_normal(r.size) * H.levels[0].nonempty
+    a, b = 0.7, -1.9
+    lhs = H.fmg_cycle(a * r + b * r2)
+    rhs = a * H.fmg_cycle(r) + b * H.fmg_cycle(r2)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(lhs))
+    u = H.solve_fmg(r, tol=1e-12)
+    ref = direct_solve(H.levels[0], r)
+    assert np.max(np.abs(u - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_fmg_residual_reduction_of_the_order_of_the_paper():
+    """Section 5.2, Fig. fig:reduction: on Problem 2 at h = 1/128 with
+    omega = 0.5, nu1 = nu2 = 3 and a zero initial guess, the relative
+    residual falls by a factor of 11.3 per FMG cycle iteration.  The
+    oracle's FMG (the descent by Alg. 2's restriction, the bottom solve, and
+    one V-cycle per level on the way up from the prolonged coarser
+    solution) must reduce it by a factor within x2 of that, and by more per
+    iteration than a V-cycle does."""
+    H, r = _problem2_hierarchy(128)
+    hf, hv = [], []
+    H.solve_fmg(r, tol=0.0, max_cycles=8, history=hf)
+    H.solve(r, tol=0.0, max_cycles=8, history=hv)
+    assert len(hf) == 8 and len(hv) == 8          # no stagnation or divergence on the way
+    fmg = (hf[0] / hf[7]) ** (1.0 / 7)
+    vc = (hv[0] / hv[7]) ** (1.0 / 7)
+    print("residual reduction per iteration: FMG %.1f, V-cycle %.1f (paper's FMG: 11.3)" % (fmg, vc))
+    assert 11.3 / 2 <= fmg <= 11.3 * 2
+    assert fmg > vc

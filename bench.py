@@ -372,6 +372,7 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-fmg", action="store_true", help="skip the FMG-cycle solve")
     ap.add_argument("--no-fp64-inverses", action="store_true",
                     help="skip the extra solve with FP64-stored SMO-2 and coarsest inverses")
     ap.add_argument("--prolongation", type=int, default=0)
@@ -536,6 +537,27 @@ def main():
                  "disc_err_inf": float(np.max(np.abs(um.cpu().numpy() - exact)[ne]))}
         Sm.close()
 
+    # the same problem by FMG cycles (Section 4, Fig. FMG-cycle), tuned the
+    # same way
+    fmg = None
+    if not args.no_fmg:
+        Sf = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-10, max_cycles=200,
+                    hip_stream=stream.cuda_stream, cycle=1)
+        Sf.set_boundary(g, 1)
+        Sf.tune(f)
+        uf = torch.zeros_like(f)
+        run(Sf, uf, args.warmup)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rf = run(Sf, uf, args.steps)
+        torch.cuda.synchronize()
+        mf = 1e3 * (time.perf_counter() - t1) / args.steps
+        fmg = {"value": nu / (mf * 1e-3), "ms_per_step": mf, "cycles": rf[-1]["cycles"],
+               "rel_res_inf": rf[-1]["rel_res_inf"],
+               "rel_diff_vs_fp64": float(np.max(np.abs(uf.cpu().numpy() - u64)[ne]) / np.max(np.abs(u64[ne]))),
+               "schedule": {k: Sf.info[k] for k in ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "n_levels")}}
+        Sf.close()
+
     cpu = cpu_job.result() if cpu_job else None
 
     out = {
@@ -581,6 +603,7 @@ def main():
         "kernels_us": other,
         "fp64_inverses": fp64_inv,
         "mixed_precision": mixed,
+        "fmg": fmg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

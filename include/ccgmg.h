@@ -131,6 +131,10 @@ typedef struct {
                             1 (default) FP32, 0 FP64                                      */
   int host_only;         /* 1: build the hierarchy on the host only (no device calls);
                             queries work, apply/solve return CCGMG_EINVAL                  */
+  int cycle;             /* 0 (default): V-cycles (Alg. 2); 1: FMG cycles (Section 4, Fig.
+                            FMG-cycle): the residual restricted to the coarsest level,
+                            solved there, then one V-cycle per level upwards from the
+                            prolonged coarser solution; iterated like V-cycles          */
   void* hip_stream;      /* hipStream_t all device work is ordered on                     */
 } ccgmg_options;
 
@@ -341,8 +345,8 @@ typedef struct ccgmg_batch ccgmg_batch;
  * geometries are masked by device flags.  Needs one precision for all
  * contexts and at most 64 of them; sets every context's schedule to fused
  * smoothing with nu = ctxs[0]'s tuned nu1 (if fused and symmetric, else 4)
- * steps before and after on every level and piecewise-constant
- * correction. */
+ * steps before and after on every level, piecewise-constant correction
+ * and V-cycles. */
 int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch** out);
 
 /* f[g], u[g]: device arrays of geometry g ([nrhs[g]][ny][nx], as in

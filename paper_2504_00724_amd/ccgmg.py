@@ -47,7 +47,7 @@ class OptionsT(C.Structure):
                 ("smo2_overlap", C.c_int), ("smo2_widen", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
                 ("use_initial_guess", C.c_int), ("num_threads", C.c_int), ("use_graph", C.c_int),
                 ("tune_tiles", C.c_int), ("sweep_tile_rows", C.c_int), ("smoother_fused", C.c_int), ("tune_schedule", C.c_int), ("inverse_fp32", C.c_int), ("host_only", C.c_int),
-                ("hip_stream", C.c_void_p)]
+                ("cycle", C.c_int), ("hip_stream", C.c_void_p)]
 
 
 class InfoT(C.Structure):

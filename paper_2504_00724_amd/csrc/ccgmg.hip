@@ -631,6 +631,44 @@ struct Driver {
     return out;
   }
 
+  // One FMG cycle (Fig. 4) of level 0's problem A x = r with iterate u (the
+  // boundary term bterm on level 0): the residual of u restricted to level
+  // 1, then restricted level by level (zero iterates) to the coarsest
+  // level, solved there; on the way up each level runs one V-cycle from the
+  // prolonged solution of the level below (the descent left its iterate
+  // and compact copy at zero), and level 0 runs one V-cycle from u + P e_1.
+  // That equals u + FMG(r - bterm - A u), V-cycles being affine.  Returns
+  // the buffer holding the new iterate (u or v).
+  template <typename T>
+  T* fmg(T* u, T* v, const T* r, const double* bterm) {
+    const int M = X->M;
+    if (M == 0) return vcycle<T>(0, u, v, r, bterm);
+    {
+      Buf<T> cb = bufs<T>(X->lv[1]);
+      restrict_<T>(X->lv[0], X->lv[1], u, r, cb.r, cb.u);
+    }
+    for (int m = 1; m < M; ++m) {
+      Buf<T> lb = bufs<T>(X->lv[m]), cb = bufs<T>(X->lv[m + 1]);
+      restrict_<T>(X->lv[m], X->lv[m + 1], lb.u, lb.r, cb.r, cb.u);
+    }
+    Buf<T> mb = bufs<T>(X->lv[M]);
+    coarse<T>(X->lv[M], mb.u, mb.r);
+    T* e = mb.u;
+    for (int m = M - 1; m >= 1; --m) {
+      Buf<T> lb = bufs<T>(X->lv[m]);
+      prolong<T>(X->lv[m], X->lv[m + 1], lb.u, e);
+      e = vcycle<T>(m, lb.u, lb.v, lb.r, nullptr);
+    }
+    prolong<T>(X->lv[0], X->lv[1], u, e);
+    return vcycle<T>(0, u, v, r, bterm);
+  }
+
+  // one cycle of the kind the options ask for
+  template <typename T>
+  T* cycle(T* u, T* v, const T* r, const double* bterm) {
+    return X->opt.cycle == 1 ? fmg<T>(u, v, r, bterm) : vcycle<T>(0, u, v, r, bterm);
+  }
+
   // partial maxima over non-empty cells of |r - bterm - A u| (zero_u: of
   // |r - bterm|), one launch, into L.part[z * norm_parts(L) + b]
   int norm_parts(DevLevel& L) {
@@ -852,17 +890,18 @@ int guard(ccgmg_ctx* X, const std::function<void()>& body) {
   return CCGMG_OK;
 }
 
-// One FP64 V-cycle on level 0 (u = caller's iterate, v = spare buffer).
+// One FP64 cycle (V-cycle or FMG) on level 0 (u = caller's iterate, v =
+// spare buffer).
 void fp64_cycle(Driver& Dr, double* u, const double* f, const double* bterm) {
   DevLevel& L0 = Dr.X->lv[0];
-  double* res = Dr.vcycle<double>(0, u, L0.v, f, bterm);
+  double* res = Dr.cycle<double>(u, L0.v, f, bterm);
   if (res != u) HIP_OK(hipMemcpyAsync(u, res, sizeof(double) * L0.n * Dr.nrhs, hipMemcpyDeviceToDevice, Dr.s));
 }
 
 // One refinement step of the mixed-precision solve.  On entry L0.r32 holds
 // the FP32 copy of the FP64 residual f - N g - A u (difference form), written
 // by the residual check that ended the previous step (or by the prologue):
-// one FP32 V-cycle on A e = r32 from a zero guess (explicit rows and the
+// one FP32 V-cycle (or FMG cycle) on A e = r32 from a zero guess (explicit rows and the
 // coarsest solve in FP64 arithmetic), then u += e in FP64.
 void mp_cycle(Driver& Dr, double* u) {
   ccgmg_ctx* X = Dr.X;
@@ -870,7 +909,7 @@ void mp_cycle(Driver& Dr, double* u) {
   const int nr = Dr.nrhs;
   Dr.fill<float>(L0.u32, L0.n * nr, 0.0f);
   Dr.gather_rows<float>(L0, L0.u32);
-  float* e = Dr.vcycle<float>(0, L0.u32, L0.v32, L0.r32, nullptr);
+  float* e = Dr.cycle<float>(L0.u32, L0.v32, L0.r32, nullptr);
   const size_t n = L0.n * nr;
   hipLaunchKernelGGL(k_axpy_f32, dim3(std::min<size_t>(4096, (n + 255) / 256)), dim3(256), 0, Dr.s, u, e, L0.kind, L0.n, n);
 }
@@ -1636,6 +1675,7 @@ void ccgmg_default_options(ccgmg_options* o) {
   o->tune_schedule = 1;
   o->inverse_fp32 = 1;
   o->host_only = 0;
+  o->cycle = 0;
   o->hip_stream = nullptr;
 }
 
@@ -1662,7 +1702,8 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
     if (X->opt.max_nrhs < 1) X->opt.max_nrhs = 1;
     if (X->opt.smo2_block < 1 || X->opt.smo2_block > 64) throw ccg::Error(CCGMG_EINVAL, "smo2_block must be in 1..64");
     if (X->opt.nu1 < 0 || X->opt.nu2 < 0 || X->opt.smo2_iters < 1 || X->opt.smo2_overlap < 0 ||
-        X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4 || X->opt.inverse_fp32 < 0 || X->opt.inverse_fp32 > 1)
+        X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4 || X->opt.inverse_fp32 < 0 || X->opt.inverse_fp32 > 1 ||
+        X->opt.cycle < 0 || X->opt.cycle > 1)
       throw ccg::Error(CCGMG_EINVAL, "bad smoothing parameters");
     X->a = a, X->b = b, X->c = c;
     X->host_only = X->opt.host_only != 0;
@@ -2086,7 +2127,7 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
         ccgmg_ctx* X = ctxs[g];
         if (X->opt.precision != o0.precision) throw ccg::Error(CCGMG_EINVAL, "lockstep batch needs one precision");
         X->opt.smoother_fused = 1, X->opt.nu1 = X->opt.nu2 = B->nu;
-        X->opt.nu1_coarse = X->opt.nu2_coarse = 0, X->opt.prolongation = 0;
+        X->opt.nu1_coarse = X->opt.nu2_coarse = 0, X->opt.prolongation = 0, X->opt.cycle = 0;
         X->clear_graphs();
       }
       HIP_OK(hipMalloc((void**)&B->active_d, sizeof(int) * n));

@@ -135,6 +135,13 @@ typedef struct {
                             FMG-cycle): the residual restricted to the coarsest level,
                             solved there, then one V-cycle per level upwards from the
                             prolonged coarser solution; iterated like V-cycles          */
+  int tune_cache;        /* 1: reuse (and record) the measured tile heights, schedule
+                            and depth of an earlier context with the same GPU, level
+                            sizes, precision, b != 0 and options, in this process or in
+                            the file named by the environment variable CCGMG_TUNE_CACHE
+                            (a text file the library reads once and appends to); a
+                            heuristic for batches of similar geometries.  0 (default):
+                            measure for every context                                    */
   void* hip_stream;      /* hipStream_t all device work is ordered on                     */
 } ccgmg_options;
 
@@ -173,6 +180,29 @@ void ccgmg_default_options(ccgmg_options* opts);
  * grid, curves, opts: host, read only.  *out receives the new context. */
 int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves, double a, double b,
                  double c, const ccgmg_options* opts, ccgmg_ctx** out);
+
+/* One geometry of ccgmg_create_many: the arguments of ccgmg_create. */
+typedef struct {
+  ccgmg_grid grid;
+  const ccgmg_curve* curves;
+  int ncurves;
+  double a, b, c;
+} ccgmg_problem;
+
+/* ccgmg_create for n geometries at once (for batches; not a paper
+ * construct).  The host set-up of Section 4 (cut cells, Alg. 1, lattices,
+ * least-squares rows, Alg. 3, SMO-2 data) of the geometries runs
+ * concurrently: largest first (cells) on min(n, host_threads / 2) worker
+ * threads, each with an equal share of host_threads (0: the hardware's
+ * threads).  The calling thread uploads each geometry and tunes it on the
+ * current device as soon as its host set-up is done, in that order.
+ * probs: n problems (host); opts: n options (host) or NULL for defaults;
+ * out: n contexts on success, each exactly as ccgmg_create would have made
+ * it (set-up results do not depend on the thread count).  On error every
+ * context built so far is destroyed, out[] is all NULL and
+ * ccgmg_create_error() names the failing geometry. */
+int ccgmg_create_many(const ccgmg_problem* probs, int n, const ccgmg_options* opts, int host_threads,
+                      ccgmg_ctx** out);
 
 /* Sizes and set-up results of a context (unknowns, irregular cells,
  * boundary faces, levels, the coarsest level, set-up time, largest lattice

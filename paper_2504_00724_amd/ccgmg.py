@@ -20,7 +20,7 @@ OK, EINVAL, ENOTELLIPTIC, EGEOM, EPLG, ESINGULAR, ENOCONV, EDEVICE, ENOMEM = 0, 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTELLIPTIC", -3: "EGEOM", -4: "EPLG", -5: "ESINGULAR", -6: "ENOCONV",
           -7: "EDEVICE", -8: "ENOMEM"}
 
-EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
+EXPORTS = ["ccgmg_default_options", "ccgmg_create", "ccgmg_create_many", "ccgmg_query", "ccgmg_get_cell_kinds", "ccgmg_get_level_shape",
            "ccgmg_get_volumes", "ccgmg_get_counts", "ccgmg_get_irregular", "ccgmg_get_stencils", "ccgmg_get_boundary_faces",
            "ccgmg_get_alg3_order", "ccgmg_cell_quadrature", "ccgmg_face_quadrature", "ccgmg_apply", "ccgmg_residual_norms",
            "ccgmg_residual_norms_noalloc",
@@ -47,7 +47,12 @@ class OptionsT(C.Structure):
                 ("smo2_overlap", C.c_int), ("smo2_widen", C.c_int), ("tol", C.c_double), ("max_cycles", C.c_int), ("max_nrhs", C.c_int),
                 ("use_initial_guess", C.c_int), ("num_threads", C.c_int), ("use_graph", C.c_int),
                 ("tune_tiles", C.c_int), ("sweep_tile_rows", C.c_int), ("smoother_fused", C.c_int), ("tune_schedule", C.c_int), ("inverse_fp32", C.c_int), ("host_only", C.c_int),
-                ("cycle", C.c_int), ("hip_stream", C.c_void_p)]
+                ("cycle", C.c_int), ("tune_cache", C.c_int), ("hip_stream", C.c_void_p)]
+
+
+class ProblemT(C.Structure):
+    _fields_ = [("grid", GridT), ("curves", C.POINTER(CurveT)), ("ncurves", C.c_int), ("a", C.c_double),
+                ("b", C.c_double), ("c", C.c_double)]
 
 
 class InfoT(C.Structure):
@@ -78,6 +83,7 @@ def lib():
         L.ccgmg_default_options.restype = None
         L.ccgmg_create.argtypes = [C.POINTER(GridT), C.POINTER(CurveT), ip, C.c_double, C.c_double, C.c_double,
                                    C.POINTER(OptionsT), C.POINTER(vp)]
+        L.ccgmg_create_many.argtypes = [C.POINTER(ProblemT), ip, C.POINTER(OptionsT), ip, C.POINTER(vp)]
         L.ccgmg_query.argtypes = [vp, C.POINTER(InfoT)]
         L.ccgmg_get_cell_kinds.argtypes = [vp, ip, vp, vp]
         L.ccgmg_get_level_shape.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
@@ -164,27 +170,40 @@ def _count(nrhs, name="nrhs"):
     return int(nrhs)
 
 
+def _grid_t(grid):
+    return GridT(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
+
+
+def _curves_t(curves):
+    cs = (CurveT * len(curves))()
+    for k, cu in enumerate(curves):
+        cs[k].kind = cu["kind"]
+        for t, v in enumerate(cu["p"]):
+            cs[k].p[t] = v
+        cs[k].domain_inside = cu["inside"]
+        cs[k].bc = cu["bc"]
+        for t, v in enumerate(cu.get("robin", (0.0, 0.0))):
+            cs[k].robin[t] = v
+    return cs
+
+
 class Solver:
     """One context: geometry and coefficients fixed at construction."""
 
-    def __init__(self, grid, curves, a, b, c, **options):
+    def __init__(self, grid, curves, a, b, c, _ctx=None, _options=None, **options):
         L = lib()
-        g = GridT(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
-        cs = (CurveT * len(curves))()
-        for k, cu in enumerate(curves):
-            cs[k].kind = cu["kind"]
-            for t, v in enumerate(cu["p"]):
-                cs[k].p[t] = v
-            cs[k].domain_inside = cu["inside"]
-            cs[k].bc = cu["bc"]
-            for t, v in enumerate(cu.get("robin", (0.0, 0.0))):
-                cs[k].robin[t] = v
+        self.nx, self.ny = grid["nx"], grid["ny"]
+        if _ctx is not None:   # made by create_many
+            self.options, self.ctx = _options, _ctx
+            self.info = self.query()
+            return
+        g = _grid_t(grid)
+        cs = _curves_t(curves)
         self.options = default_options(**options)
         self.ctx = C.c_void_p()
         st = L.ccgmg_create(C.byref(g), cs, len(curves), a, b, c, C.byref(self.options), C.byref(self.ctx))
         if st != OK:
             raise CcgmgError(st, L.ccgmg_create_error().decode())
-        self.nx, self.ny = grid["nx"], grid["ny"]
         self.info = self.query()
 
     def _check(self, st):
@@ -369,6 +388,36 @@ class Solver:
         nf = self.info["n_bdry_faces"]
         self._check(lib().ccgmg_apply_NT(self.ctx, _dev(lam, nrhs * self.n_cells, "lam"),
                                          _dev(out, nrhs * nf, "out"), nrhs))
+
+
+def create_many(problems, options=None, host_threads=0):
+    """Solvers for several geometries, set up together (ccgmg_create_many):
+    problems is a list of (grid, curves, a, b, c); options a list of option
+    dicts (one per problem) or None."""
+    L = lib()
+    n = len(problems)
+    if n < 1:
+        raise ValueError("no problems")
+    opts = options or [{}] * n
+    if len(opts) != n:
+        raise ValueError("one options dict per problem")
+    keep = []
+    P = (ProblemT * n)()
+    O = (OptionsT * n)()
+    for k, ((grid, curves, a, b, c), o) in enumerate(zip(problems, opts)):
+        cs = _curves_t(curves)
+        keep.append(cs)
+        P[k].grid = _grid_t(grid)
+        P[k].curves = C.cast(cs, C.POINTER(CurveT))
+        P[k].ncurves = len(curves)
+        P[k].a, P[k].b, P[k].c = a, b, c
+        O[k] = default_options(**o)
+    out = (C.c_void_p * n)()
+    st = L.ccgmg_create_many(P, n, O, int(host_threads), out)
+    if st != OK:
+        raise CcgmgError(st, L.ccgmg_create_error().decode())
+    return [Solver(p[0], p[1], p[2], p[3], p[4], _ctx=C.c_void_p(out[k]), _options=O[k])
+            for k, p in enumerate(problems)]
 
 
 def _report(rep, st):

@@ -20,7 +20,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,6 +32,7 @@
 #include <random>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ccgmg.h"
@@ -165,6 +168,7 @@ struct ccgmg_ctx {
   };
   std::map<int, Coarse> coarse_cache;   // per coarsest level index
   std::vector<double> tune_ms;          // autotune: solve time per depth (index = M)
+  double* tune_rhs = nullptr;           // the tuner's seeded right-hand side (drawn once, device)
   int nfaces = 0;                   // level-0 boundary data
   int32_t *fptr = nullptr, *fface = nullptr, *fcell = nullptr;
   double *fval = nullptr, *fweight = nullptr;
@@ -789,6 +793,9 @@ void upload_coarsest(ccgmg_ctx* X) {
       for (int t = 0; t < 15; ++t) A[(size_t)r * n + pos[D.sten[15 * k + t]]] += D.wts[15 * k + t];
     }
   }
+  double amax = 0.0;
+  for (double v : A) amax = std::max(amax, std::fabs(v));
+  const double tiny = 1e-12 * amax;
   // inverse on the device: Gauss-Jordan with partial pivoting, 2 launches per
   // pivot on the private stream; the transpose's inverse is its transpose
   std::vector<void*> scratch;   // freed once the inverse is done
@@ -810,7 +817,7 @@ void upload_coarsest(ccgmg_ctx* X) {
   hipLaunchKernelGGL(k_set_identity, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, st, dinv, n);
   const dim3 ge((2 * n + 1023) / 1024, n);
   for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, dA, dinv, n, k, colk, status);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, dA, dinv, n, k, colk, status, tiny);
     hipLaunchKernelGGL(k_gj_elim, ge, dim3(256), 0, st, dA, dinv, n, k, colk, status);
   }
   // stored in FP32 by default (applied in FP64): an inexact coarsest solve
@@ -1138,13 +1145,16 @@ double timed_solve(ccgmg_ctx* X, const double* f, double tol, int max_cycles, do
   const double* rd = f;
   int g_saved = X->g_nrhs;
   if (!f) {
-    std::vector<double> r(L0.n, 0.0);
-    std::mt19937_64 gen(12345);
-    std::normal_distribution<double> nd(0.0, 1.0);
-    const ccg::Discretization& D = X->H.disc[0];
-    for (size_t k = 0; k < L0.n; ++k) r[k] = D.nonempty[k] ? nd(gen) : 0.0;
-    HIP_OK(hipMemcpy(L0.r, r.data(), sizeof(double) * L0.n, hipMemcpyHostToDevice));
-    rd = L0.r;
+    // drawn once per context (the draw takes longer than the solves)
+    if (!X->tune_rhs) {
+      std::vector<double> r(L0.n, 0.0);
+      std::mt19937_64 gen(12345);
+      std::normal_distribution<double> nd(0.0, 1.0);
+      const ccg::Discretization& D = X->H.disc[0];
+      for (size_t k = 0; k < L0.n; ++k) r[k] = D.nonempty[k] ? nd(gen) : 0.0;
+      X->tune_rhs = upload(r, X->owned);
+    }
+    rd = X->tune_rhs;
     X->g_nrhs = 0;
   }
   ccgmg_options saved = X->opt;
@@ -1639,6 +1649,237 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
   if (!ok) throw ccg::Error(CCGMG_ENOCONV, "tolerance not reached for every geometry");
 }
 
+// ---------------------------------------------------------------------------
+// Tuning cache (options.tune_cache): the measured tile heights, schedule and
+// depth of a context, kept per (GPU architecture, level sizes, precision,
+// b != 0 and the options the measurement depends on) for the rest of the
+// process and, when the environment variable CCGMG_TUNE_CACHE names a file,
+// in that file (one "key<TAB>values" line per entry, read once, appended).
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  std::vector<int> ty64, ty32;
+  int fused = 0, nu1 = 0, nu2 = 0, c1 = 0, c2 = 0, M = 0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(ccgmg_ctx* X) {
+  hipDeviceProp_t p;
+  HIP_OK(hipGetDeviceProperties(&p, X->device));
+  const ccgmg_options& o = X->opt;
+  std::string k = std::string(p.gcnArchName) + "|";
+  for (const auto& D : X->H.disc) k += std::to_string(D.nx) + "x" + std::to_string(D.ny) + ",";
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "|prec%d|cross%d|nrhs%d|cycle%d|depth%d/%g|sched%d:%d,%d,%d,%d,%d|w%g|s2%d,%d,%d,%d,%d,%d|pro%d|inv%d",
+                o.precision, X->b != 0.0 ? 1 : 0, o.max_nrhs, o.cycle, o.auto_depth, o.depth_max_rate,
+                o.tune_schedule, o.smoother_fused, o.nu1, o.nu2, o.nu1_coarse, o.nu2_coarse, o.omega,
+                o.smo2_every_sweep, o.smo2_iters, o.smo2_block, o.smo2_overlap, o.smo2_widen, o.tune_tiles,
+                o.prolongation, o.inverse_fp32);
+  return k + buf;
+}
+
+void tune_cache_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("CCGMG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return;
+  char line[4096];
+  while (std::fgets(line, sizeof(line), fp)) {
+    char* tab = std::strchr(line, '\t');
+    if (!tab) continue;
+    *tab = 0;
+    std::vector<int> v;
+    for (char* q = tab + 1; *q;) {
+      char* end = nullptr;
+      const long x = std::strtol(q, &end, 10);
+      if (end == q) break;
+      v.push_back((int)x);
+      q = end;
+    }
+    // values: nlev, ty64[nlev], ty32[nlev], fused, nu1, nu2, c1, c2, M
+    if (v.empty() || v[0] < 1 || (int)v.size() != 1 + 2 * v[0] + 6) continue;
+    TuneEntry e;
+    const int nl = v[0];
+    e.ty64.assign(v.begin() + 1, v.begin() + 1 + nl);
+    e.ty32.assign(v.begin() + 1 + nl, v.begin() + 1 + 2 * nl);
+    const int* t = v.data() + 1 + 2 * nl;
+    e.fused = t[0], e.nu1 = t[1], e.nu2 = t[2], e.c1 = t[3], e.c2 = t[4], e.M = t[5];
+    g_tune[line] = e;
+  }
+  std::fclose(fp);
+}
+
+bool tune_cache_get(const std::string& key, TuneEntry& e) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache_load_locked();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  e = it->second;
+  return true;
+}
+
+void tune_cache_put(const std::string& key, const TuneEntry& e) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache_load_locked();
+  g_tune[key] = e;
+  const char* path = std::getenv("CCGMG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::string v = std::to_string(e.ty64.size());
+  for (int t : e.ty64) v += " " + std::to_string(t);
+  for (int t : e.ty32) v += " " + std::to_string(t);
+  for (int t : {e.fused, e.nu1, e.nu2, e.c1, e.c2, e.M}) v += " " + std::to_string(t);
+  std::fprintf(fp, "%s\t%s\n", key.c_str(), v.c_str());
+  std::fclose(fp);
+}
+
+// Host part of context creation: arguments checked, options taken, the
+// hierarchy built on the host (threads: set-up threads, -1 = as the
+// options say).
+void create_host(ccgmg_ctx* X, const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves, double a, double b,
+               double c, const ccgmg_options* opts, int threads) {
+  if (!grid || !curves || ncurves <= 0 || grid->nx <= 0 || grid->ny <= 0 || !(grid->h > 0))
+    throw ccg::Error(CCGMG_EINVAL, "invalid grid or curves");
+  if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
+    throw ccg::Error(CCGMG_EINVAL, "non-finite coefficient");
+  if (b * b - 4.0 * a * c >= 0.0) throw ccg::Error(CCGMG_ENOTELLIPTIC, "b^2 - 4ac >= 0");
+  if (opts)
+    X->opt = *opts;
+  else
+    ccgmg_default_options(&X->opt);
+  if (X->opt.max_nrhs < 1) X->opt.max_nrhs = 1;
+  if (X->opt.smo2_block < 1 || X->opt.smo2_block > 64) throw ccg::Error(CCGMG_EINVAL, "smo2_block must be in 1..64");
+  if (X->opt.nu1 < 0 || X->opt.nu2 < 0 || X->opt.smo2_iters < 1 || X->opt.smo2_overlap < 0 ||
+      X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4 || X->opt.inverse_fp32 < 0 || X->opt.inverse_fp32 > 1 ||
+      X->opt.cycle < 0 || X->opt.cycle > 1)
+    throw ccg::Error(CCGMG_EINVAL, "bad smoothing parameters");
+  X->a = a, X->b = b, X->c = c;
+  X->host_only = X->opt.host_only != 0;
+  std::vector<ccg::Curve> cs(ncurves);
+  for (int k = 0; k < ncurves; ++k) {
+    cs[k].kind = curves[k].kind;
+    for (int t = 0; t < 8; ++t) {
+      cs[k].p[t] = curves[k].p[t];
+      if (!std::isfinite(cs[k].p[t])) throw ccg::Error(CCGMG_EINVAL, "non-finite curve parameter");
+    }
+    cs[k].inside = curves[k].domain_inside;
+    cs[k].bc = curves[k].bc;
+    if (cs[k].bc < 0 || cs[k].bc > 2) throw ccg::Error(CCGMG_EINVAL, "unknown boundary condition");
+    if (cs[k].bc == 2) {
+      cs[k].robin[0] = curves[k].robin[0], cs[k].robin[1] = curves[k].robin[1];
+      if (!std::isfinite(cs[k].robin[0]) || !std::isfinite(cs[k].robin[1]) ||
+          (cs[k].robin[0] == 0.0 && cs[k].robin[1] == 0.0))
+        throw ccg::Error(CCGMG_EINVAL, "Robin coefficients must be finite and not both zero");
+    }
+    cs[k].index = k;
+  }
+  ccg::Options so;
+  so.theta = X->opt.theta;
+  so.w_min = X->opt.w_min;
+  so.coarsest_min_n = std::max(2, X->opt.coarsest_min_n);
+  so.max_levels = std::max(1, X->opt.max_levels);
+  so.threads = threads >= 0 ? threads : X->opt.num_threads;
+  X->H.build(cs, grid->nx, grid->ny, grid->x0, grid->y0, grid->h, a, b, c, so);
+  for (double v : X->H.disc[0].cond) X->plg_max_cond = std::max(X->plg_max_cond, v);
+  X->M = (int)X->H.disc.size() - 1;
+}
+
+// Device part of context creation on the current device: streams and
+// events, the level data, boundary-data buffers, the coarsest inverse, and
+// the measured choices of tile heights, schedule and depth.
+void create_device(ccgmg_ctx* X) {
+  X->stream = (hipStream_t)X->opt.hip_stream;
+  HIP_OK(hipGetDevice(&X->device));
+  X->scratch = scratch_on_current_device();
+  HIP_OK(hipStreamCreateWithFlags(&X->ws, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&X->ev_in, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&X->ev_out, hipEventDisableTiming));
+  for (hipEvent_t& e : X->ev_cyc) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&X->ev_pro, hipEventDisableTiming));
+  HIP_OK(hipEventCreate(&X->ev_t0));
+  HIP_OK(hipEventCreate(&X->ev_t1));
+  const int maxr = X->opt.max_nrhs;
+  X->lv.resize(X->H.disc.size());
+  for (size_t m = 0; m < X->H.disc.size(); ++m) upload_level(X, (int)m, maxr);
+  ccg::Discretization& D0 = X->H.disc[0];
+  X->nfaces = (int)D0.faces.size();
+  X->fptr = upload(D0.fw_ptr, X->owned);
+  X->fface = upload(D0.fw_face, X->owned);
+  X->fval = upload(D0.fw_val, X->owned);
+  std::vector<int32_t> fc(X->nfaces);
+  std::vector<double> fw(X->nfaces, 0.0);
+  for (int k = 0; k < X->nfaces; ++k) fc[k] = D0.faces[k].first;
+  for (size_t k = 0; k < D0.irr.size(); ++k)
+    for (int t = D0.fw_ptr[k]; t < D0.fw_ptr[k + 1]; ++t) fw[D0.fw_face[t]] = D0.fw_val[t];
+  X->fcell = upload(fc, X->owned);
+  X->fweight = upload(fw, X->owned);
+  X->g = dalloc<double>((size_t)std::max(1, X->nfaces) * maxr, X->owned);
+  X->bterm = dalloc<double>((size_t)std::max(1, (int)D0.irr.size()) * maxr, X->owned);
+  if (maxr > 1) X->mrg = dalloc<double>((size_t)MAX_COARSE_UNKNOWNS * maxr, X->owned);
+  for (double** p : {&X->norm_host, &X->norm_host2, &X->norm_host0})
+    HIP_OK(hipHostMalloc((void**)p, sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
+                         hipHostMallocDefault));
+  // the coarsest level must be small enough for the dense inverse
+  while (X->M > 0) {
+    long nu = 0;
+    for (uint8_t v : X->H.disc[X->M].nonempty) nu += v;
+    if (nu <= MAX_COARSE_UNKNOWNS) break;
+    throw ccg::Error(CCGMG_EINVAL, "coarsest level has too many unknowns; allow more levels");
+  }
+  if (X->opt.sweep_tile_rows) {
+    const int ty = X->opt.sweep_tile_rows;
+    if (ty != 8 && ty != 16 && ty != 32) throw ccg::Error(CCGMG_EINVAL, "sweep_tile_rows must be 0, 8, 16 or 32");
+    for (DevLevel& L : X->lv) L.sweep_ty[0] = L.sweep_ty[1] = ty;
+  }
+  std::string key;
+  TuneEntry cached;
+  if (X->opt.tune_cache) {
+    key = tune_key(X);
+    auto fits = [&](int M) {   // the cached depth's coarsest level must suit the dense inverse here too
+      if (M < 0 || M >= (int)X->lv.size()) return false;
+      long nu = 0;
+      for (uint8_t v : X->H.disc[M].nonempty) nu += v;
+      return nu <= MAX_COARSE_UNKNOWNS;
+    };
+    if (tune_cache_get(key, cached) && cached.ty64.size() == X->lv.size() && cached.ty32.size() == X->lv.size() &&
+        fits(cached.M)) {
+      for (size_t m = 0; m < X->lv.size(); ++m) X->lv[m].sweep_ty[0] = cached.ty64[m], X->lv[m].sweep_ty[1] = cached.ty32[m];
+      X->opt.smoother_fused = cached.fused, X->opt.nu1 = cached.nu1, X->opt.nu2 = cached.nu2;
+      X->opt.nu1_coarse = cached.c1, X->opt.nu2_coarse = cached.c2;
+      X->M = cached.M;
+      upload_coarsest(X);
+      return;
+    }
+  }
+  upload_coarsest(X);
+  if (!X->opt.sweep_tile_rows && X->opt.tune_tiles) tune_tiles(X);
+  if (X->opt.auto_depth == 2 && X->M > 1) {
+    tune_schedule_depth(X, nullptr);
+  } else if (X->opt.auto_depth == 1 && X->M > 1) {
+    for (;;) {
+      const double rate = timed_solve(X, nullptr, 0.0, 6, nullptr);
+      if (rate <= X->opt.depth_max_rate || X->M <= 1) break;
+      long next = 0;
+      for (uint8_t v : X->H.disc[X->M - 1].nonempty) next += v;
+      if (next > MAX_COARSE_UNKNOWNS) break;
+      X->M -= 1;
+      upload_coarsest(X);
+    }
+    X->clear_graphs();
+  }
+  if (X->opt.tune_cache) {
+    TuneEntry e;
+    for (const DevLevel& L : X->lv) e.ty64.push_back(L.sweep_ty[0]), e.ty32.push_back(L.sweep_ty[1]);
+    e.fused = X->opt.smoother_fused, e.nu1 = X->opt.nu1, e.nu2 = X->opt.nu2;
+    e.c1 = X->opt.nu1_coarse, e.c2 = X->opt.nu2_coarse, e.M = X->M;
+    tune_cache_put(key, e);
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1676,6 +1917,7 @@ void ccgmg_default_options(ccgmg_options* o) {
   o->inverse_fp32 = 1;
   o->host_only = 0;
   o->cycle = 0;
+  o->tune_cache = 0;
   o->hip_stream = nullptr;
 }
 
@@ -1690,125 +1932,118 @@ int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves,
   g_create_error.clear();
   std::unique_ptr<ccgmg_ctx> X(new ccgmg_ctx());
   try {
-    if (!grid || !curves || ncurves <= 0 || grid->nx <= 0 || grid->ny <= 0 || !(grid->h > 0))
-      throw ccg::Error(CCGMG_EINVAL, "invalid grid or curves");
-    if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
-      throw ccg::Error(CCGMG_EINVAL, "non-finite coefficient");
-    if (b * b - 4.0 * a * c >= 0.0) throw ccg::Error(CCGMG_ENOTELLIPTIC, "b^2 - 4ac >= 0");
-    if (opts)
-      X->opt = *opts;
-    else
-      ccgmg_default_options(&X->opt);
-    if (X->opt.max_nrhs < 1) X->opt.max_nrhs = 1;
-    if (X->opt.smo2_block < 1 || X->opt.smo2_block > 64) throw ccg::Error(CCGMG_EINVAL, "smo2_block must be in 1..64");
-    if (X->opt.nu1 < 0 || X->opt.nu2 < 0 || X->opt.smo2_iters < 1 || X->opt.smo2_overlap < 0 ||
-        X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4 || X->opt.inverse_fp32 < 0 || X->opt.inverse_fp32 > 1 ||
-        X->opt.cycle < 0 || X->opt.cycle > 1)
-      throw ccg::Error(CCGMG_EINVAL, "bad smoothing parameters");
-    X->a = a, X->b = b, X->c = c;
-    X->host_only = X->opt.host_only != 0;
-    std::vector<ccg::Curve> cs(ncurves);
-    for (int k = 0; k < ncurves; ++k) {
-      cs[k].kind = curves[k].kind;
-      for (int t = 0; t < 8; ++t) {
-        cs[k].p[t] = curves[k].p[t];
-        if (!std::isfinite(cs[k].p[t])) throw ccg::Error(CCGMG_EINVAL, "non-finite curve parameter");
-      }
-      cs[k].inside = curves[k].domain_inside;
-      cs[k].bc = curves[k].bc;
-      if (cs[k].bc < 0 || cs[k].bc > 2) throw ccg::Error(CCGMG_EINVAL, "unknown boundary condition");
-      if (cs[k].bc == 2) {
-        cs[k].robin[0] = curves[k].robin[0], cs[k].robin[1] = curves[k].robin[1];
-        if (!std::isfinite(cs[k].robin[0]) || !std::isfinite(cs[k].robin[1]) ||
-            (cs[k].robin[0] == 0.0 && cs[k].robin[1] == 0.0))
-          throw ccg::Error(CCGMG_EINVAL, "Robin coefficients must be finite and not both zero");
-      }
-      cs[k].index = k;
-    }
-    double t0 = now();
-    ccg::Options so;
-    so.theta = X->opt.theta;
-    so.w_min = X->opt.w_min;
-    so.coarsest_min_n = std::max(2, X->opt.coarsest_min_n);
-    so.max_levels = std::max(1, X->opt.max_levels);
-    so.threads = X->opt.num_threads;
-    X->H.build(cs, grid->nx, grid->ny, grid->x0, grid->y0, grid->h, a, b, c, so);
-    for (double v : X->H.disc[0].cond) X->plg_max_cond = std::max(X->plg_max_cond, v);
-    X->M = (int)X->H.disc.size() - 1;
-    if (!X->host_only) {
-      X->stream = (hipStream_t)X->opt.hip_stream;
-      HIP_OK(hipGetDevice(&X->device));
-      X->scratch = scratch_on_current_device();
-      HIP_OK(hipStreamCreateWithFlags(&X->ws, hipStreamNonBlocking));
-      HIP_OK(hipEventCreateWithFlags(&X->ev_in, hipEventDisableTiming));
-      HIP_OK(hipEventCreateWithFlags(&X->ev_out, hipEventDisableTiming));
-      for (hipEvent_t& e : X->ev_cyc) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      HIP_OK(hipEventCreateWithFlags(&X->ev_pro, hipEventDisableTiming));
-      HIP_OK(hipEventCreate(&X->ev_t0));
-      HIP_OK(hipEventCreate(&X->ev_t1));
-      const int maxr = X->opt.max_nrhs;
-      X->lv.resize(X->H.disc.size());
-      for (size_t m = 0; m < X->H.disc.size(); ++m) upload_level(X.get(), (int)m, maxr);
-      ccg::Discretization& D0 = X->H.disc[0];
-      X->nfaces = (int)D0.faces.size();
-      X->fptr = upload(D0.fw_ptr, X->owned);
-      X->fface = upload(D0.fw_face, X->owned);
-      X->fval = upload(D0.fw_val, X->owned);
-      std::vector<int32_t> fc(X->nfaces);
-      std::vector<double> fw(X->nfaces, 0.0);
-      for (int k = 0; k < X->nfaces; ++k) fc[k] = D0.faces[k].first;
-      for (size_t k = 0; k < D0.irr.size(); ++k)
-        for (int t = D0.fw_ptr[k]; t < D0.fw_ptr[k + 1]; ++t) fw[D0.fw_face[t]] = D0.fw_val[t];
-      X->fcell = upload(fc, X->owned);
-      X->fweight = upload(fw, X->owned);
-      X->g = dalloc<double>((size_t)std::max(1, X->nfaces) * maxr, X->owned);
-      X->bterm = dalloc<double>((size_t)std::max(1, (int)D0.irr.size()) * maxr, X->owned);
-      if (maxr > 1) X->mrg = dalloc<double>((size_t)MAX_COARSE_UNKNOWNS * maxr, X->owned);
-      for (double** p : {&X->norm_host, &X->norm_host2, &X->norm_host0})
-        HIP_OK(hipHostMalloc((void**)p, sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
-                             hipHostMallocDefault));
-      // the coarsest level must be small enough for the dense inverse
-      while (X->M > 0) {
-        long nu = 0;
-        for (uint8_t v : X->H.disc[X->M].nonempty) nu += v;
-        if (nu <= MAX_COARSE_UNKNOWNS) break;
-        throw ccg::Error(CCGMG_EINVAL, "coarsest level has too many unknowns; allow more levels");
-      }
-      upload_coarsest(X.get());
-      if (X->opt.sweep_tile_rows) {
-        const int ty = X->opt.sweep_tile_rows;
-        if (ty != 8 && ty != 16 && ty != 32) throw ccg::Error(CCGMG_EINVAL, "sweep_tile_rows must be 0, 8, 16 or 32");
-        for (DevLevel& L : X->lv) L.sweep_ty[0] = L.sweep_ty[1] = ty;
-      } else if (X->opt.tune_tiles) {
-        tune_tiles(X.get());
-      }
-      if (X->opt.auto_depth == 2 && X->M > 1) {
-        tune_schedule_depth(X.get(), nullptr);
-      } else if (X->opt.auto_depth == 1 && X->M > 1) {
-        for (;;) {
-          const double rate = timed_solve(X.get(), nullptr, 0.0, 6, nullptr);
-          if (rate <= X->opt.depth_max_rate || X->M <= 1) break;
-          long next = 0;
-          for (uint8_t v : X->H.disc[X->M - 1].nonempty) next += v;
-          if (next > MAX_COARSE_UNKNOWNS) break;
-          X->M -= 1;
-          upload_coarsest(X.get());
-        }
-        X->clear_graphs();
-      }
-    }
+    const double t0 = now();
+    create_host(X.get(), grid, curves, ncurves, a, b, c, opts, -1);
+    if (!X->host_only) create_device(X.get());
     X->setup_seconds = now() - t0;
   } catch (const ccg::Error& e) {
     g_create_error = e.what();
+    ccgmg_destroy(X.release());
     return e.code;
   } catch (const std::bad_alloc&) {
     g_create_error = "out of host memory";
+    ccgmg_destroy(X.release());
     return CCGMG_ENOMEM;
   } catch (const std::exception& e) {
     g_create_error = e.what();
+    ccgmg_destroy(X.release());
     return CCGMG_EINVAL;
   }
   *out = X.release();
+  return CCGMG_OK;
+}
+
+int ccgmg_create_many(const ccgmg_problem* probs, int n, const ccgmg_options* opts, int host_threads,
+                      ccgmg_ctx** out) {
+  if (!out || !probs || n < 1) return CCGMG_EINVAL;
+  g_create_error.clear();
+  for (int k = 0; k < n; ++k) out[k] = nullptr;
+  std::vector<std::unique_ptr<ccgmg_ctx>> X(n);
+  for (auto& x : X) x.reset(new ccgmg_ctx());
+  // host phase: geometries largest first (cells) onto a pool of workers,
+  // each building with an equal share of the host threads; the calling
+  // thread takes each finished geometry's device phase in that order
+  int T = host_threads > 0 ? host_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  const int W = std::max(1, std::min(n, std::max(1, T / 2)));
+  const int per = std::max(1, T / W);
+  std::vector<int> order(n);
+  for (int k = 0; k < n; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int p, int q) {
+    return (long)probs[p].grid.nx * probs[p].grid.ny > (long)probs[q].grid.nx * probs[q].grid.ny;
+  });
+  std::vector<int> status(n, 1);                // 1 pending, 0 built, < 0 failed
+  std::vector<std::string> msg(n);
+  std::vector<double> host_s(n, 0.0);
+  std::mutex mu;
+  std::condition_variable cv;
+  std::atomic<int> next{0};
+  std::atomic<bool> abort{false};
+  auto worker = [&]() {
+    for (;;) {
+      const int slot = next.fetch_add(1);
+      if (slot >= n) return;
+      const int k = order[slot];
+      int st = CCGMG_OK;
+      std::string m;
+      const double t0 = now();
+      if (!abort.load()) {
+        try {
+          const ccgmg_problem& P = probs[k];
+          create_host(X[k].get(), &P.grid, P.curves, P.ncurves, P.a, P.b, P.c, opts ? &opts[k] : nullptr, per);
+        } catch (const ccg::Error& e) {
+          st = e.code, m = e.what();
+        } catch (const std::bad_alloc&) {
+          st = CCGMG_ENOMEM, m = "out of host memory";
+        } catch (const std::exception& e) {
+          st = CCGMG_EINVAL, m = e.what();
+        }
+      } else {
+        st = CCGMG_EINVAL, m = "not built: an earlier geometry failed";
+      }
+      {
+        std::lock_guard<std::mutex> lock(mu);
+        status[k] = st == CCGMG_OK ? 0 : st;
+        msg[k] = m;
+        host_s[k] = now() - t0;
+      }
+      cv.notify_all();
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 0; w < W; ++w) pool.emplace_back(worker);
+  int code = CCGMG_OK;
+  std::string err;
+  for (int slot = 0; slot < n; ++slot) {
+    const int k = order[slot];
+    {
+      std::unique_lock<std::mutex> lock(mu);
+      cv.wait(lock, [&]() { return status[k] != 1; });
+    }
+    if (code != CCGMG_OK) continue;
+    if (status[k] != 0) {
+      code = status[k];
+      err = "geometry " + std::to_string(k) + ": " + msg[k];
+      abort.store(true);
+      continue;
+    }
+    try {
+      const double t0 = now();
+      if (!X[k]->host_only) create_device(X[k].get());
+      X[k]->setup_seconds = host_s[k] + (now() - t0);
+    } catch (const ccg::Error& e) {
+      code = e.code, err = "geometry " + std::to_string(k) + ": " + e.what();
+    } catch (const std::exception& e) {
+      code = CCGMG_EINVAL, err = "geometry " + std::to_string(k) + ": " + e.what();
+    }
+    if (code != CCGMG_OK) abort.store(true);
+  }
+  for (auto& t : pool) t.join();
+  if (code != CCGMG_OK) {
+    for (auto& x : X) ccgmg_destroy(x.release());
+    g_create_error = err;
+    return code;
+  }
+  for (int k = 0; k < n; ++k) out[k] = X[k].release();
   return CCGMG_OK;
 }
 

@@ -692,7 +692,7 @@ void Geometry::classify_native() {
   comps.clear();
   native_comps.clear();
   std::vector<std::vector<Comp>> traced(cut.size());
-  parallel_for((int)cut.size(), 0, [&](int s, int e) {
+  parallel_for((int)cut.size(), threads, [&](int s, int e) {
     for (int k = s; k < e; ++k) {
       for (auto& lp : loops(cut[k])) traced[k].push_back(trace(cut[k], lp));
     }
@@ -846,10 +846,10 @@ void Geometry::merge() {
 }
 
 void Geometry::build(const std::vector<Curve>& cs, int nx_, int ny_, double x0_, double y0_, double h_,
-                     double theta_) {
+                     double theta_, int threads_) {
   curves = cs;
   for (size_t k = 0; k < curves.size(); ++k) curves[k].index = (int)k;
-  nx = nx_, ny = ny_, x0 = x0_, y0 = y0_, h = h_, theta = theta_;
+  nx = nx_, ny = ny_, x0 = x0_, y0 = y0_, h = h_, theta = theta_, threads = threads_;
   validate();
   intersect();
   classify_native();
@@ -1458,7 +1458,7 @@ void Hierarchy::build(const std::vector<Curve>& curves, int nx, int ny, double x
   geo.clear();
   disc.clear();
   geo.emplace_back();
-  geo.back().build(curves, nx, ny, x0, y0, h, opt.theta);
+  geo.back().build(curves, nx, ny, x0, y0, h, opt.theta, opt.threads);
   disc.emplace_back();
   disc.back().build(geo.back(), a, b, c, opt.w_min, opt.threads);
   int cx = nx, cy = ny;
@@ -1469,7 +1469,7 @@ void Hierarchy::build(const std::vector<Curve>& curves, int nx, int ny, double x
     Geometry G;
     Discretization D;
     try {
-      G.build(curves, cx, cy, x0, y0, ch, opt.theta);
+      G.build(curves, cx, cy, x0, y0, ch, opt.theta, opt.threads);
       D.build(G, a, b, c, opt.w_min, opt.threads);
     } catch (const Error&) {
       break;

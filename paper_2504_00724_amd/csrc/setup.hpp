@@ -78,6 +78,7 @@ struct ControlVolume {        // non-empty cell after merging (not a plain pure 
 struct Geometry {
   int nx = 0, ny = 0;
   double x0 = 0, y0 = 0, h = 0, theta = 0.3;
+  int threads = 0;                  // host threads for the cut-cell pass (0: all)
   int q = 16;                 // Gauss-Legendre nodes per arc piece
   std::vector<Curve> curves;
   int box = -1;               // index of the box curve or -1
@@ -92,7 +93,7 @@ struct Geometry {
   std::unordered_map<int, std::vector<Face>> pure_faces;
 
   void build(const std::vector<Curve>& cs, int nx_, int ny_, double x0_, double y0_, double h_,
-             double theta_);
+             double theta_, int threads_ = 0);
   const Mom& moments(int idx) const;
   const std::vector<Face>& faces(int idx) const;
   bool on_border(int i, int j, int edge) const;

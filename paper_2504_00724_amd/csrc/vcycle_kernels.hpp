@@ -660,7 +660,8 @@ __global__ __launch_bounds__(64 * CMW) void k_coarse_multi(T* __restrict__ u, co
 // the smaller r); swap rows k and pivot in A and B; scale row k by
 // 1 / A[k][k]; copy column k into colk (the multipliers of the elimination).
 __global__ __launch_bounds__(1024) void k_gj_pivot(double* __restrict__ A, double* __restrict__ B, int n, int k,
-                                                   double* __restrict__ colk, int* __restrict__ status) {
+                                                   double* __restrict__ colk, int* __restrict__ status,
+                                                   double tiny) {
   __shared__ double bv[1024];
   __shared__ int bi[1024];
   if (*status) return;
@@ -684,7 +685,9 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(double* __restrict__ A, doubl
   }
   const int piv = bi[0];
   const double pv = bv[0];
-  if (!(pv > 0.0) || !isfinite(pv) || piv >= n) {
+  // a pivot at rounding level of the matrix (tiny = 1e-12 max |A_ij|) means
+  // the matrix is singular (a constant null vector, all-Neumann data)
+  if (!(pv > tiny) || !isfinite(pv) || piv >= n) {
     if (t == 0) *status = 1;
     return;
   }

@@ -159,3 +159,79 @@ def test_batch_follows_boundary_data_changes(nbranches):
     B.close()
     for S in solvers:
         S.close()
+
+
+def test_all_neumann_problem_is_esingular():
+    """Neumann data on every boundary curve: constants are in the null space
+    of L (every row annihilates them), so the coarsest operator is singular
+    and creation fails with ESINGULAR instead of producing a garbage
+    inverse."""
+    from paper_2504_00724_amd.ccgmg import ESINGULAR, CcgmgError
+    _dev()
+    curves = [W.box(bc=W.NEUMANN), W.circle(0.5, 0.5, 0.2, bc=W.NEUMANN)]
+    with pytest.raises(CcgmgError) as e:
+        _solver({"grid": W.grid(64), "curves": curves, "a": 1.0, "b": 0.0, "c": 1.0})
+    assert e.value.code == ESINGULAR, str(e.value)
+
+
+def test_stagnation_below_the_rounding_floor_is_enoconv():
+    """A tolerance below the FP64 rounding floor: the residual stops falling,
+    the solve gives up after three cycles that each reduce it by less than
+    5% (long before max_cycles) and returns ENOCONV with the last iterate,
+    which is the oracle's solution to rounding."""
+    from paper_2504_00724_amd.ccgmg import ENOCONV
+    dev = _dev()
+    cfg, lv = _level(2, 64)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ref = direct_solve(lv, rhs_vector(lv, f, g))
+    S = _solver(cfg, tol=1e-20, max_cycles=150)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    fd = torch.tensor(f, device=dev)
+    u = torch.zeros_like(fd)
+    rep = S.solve(fd, u, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    h = rep["history"]
+    print("stagnation: status %d after %d cycles, last residuals %s" % (
+        rep["status"], rep["cycles"], " ".join("%.2e" % v for v in h[-4:])), flush=True)
+    assert rep["status"] == ENOCONV
+    assert rep["cycles"] < 150
+    assert all(b > 0.95 * a for a, b in zip(h[-4:-1], h[-3:]))
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-10
+    S.close()
+
+
+def test_tune_cache_reuses_the_measured_choices(tmp_path, monkeypatch):
+    """options.tune_cache: a second context with the same level sizes and
+    options reuses the first one's measured tile heights, schedule and depth
+    (recorded in memory and in the CCGMG_TUNE_CACHE file) and still solves to
+    the oracle's direct solution."""
+    dev = _dev()
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("CCGMG_TUNE_CACHE", str(path))
+    cfg_a, _ = _level(4, 128)
+    A = _solver(cfg_a, tol=1e-12, max_cycles=200, tune_cache=1)
+    lines = path.read_text().splitlines()
+    assert len(lines) >= 1 and "\t" in lines[-1]
+    # another three-circle geometry on the same grid
+    curves = [W.box()] + W.random_circles(7, 3, 0.05, 0.15)
+    cfg_b = {"grid": W.grid(128), "curves": curves, "a": 1.0, "b": 0.0, "c": 1.0}
+    B = _solver(cfg_b, tol=1e-12, max_cycles=200, tune_cache=1)
+    keys = ("smoother_fused", "nu1", "nu2", "nu1_coarse", "nu2_coarse", "n_levels")
+    print("tune cache: A %s (%.2f s), B %s (%.2f s)" % ({k: A.info[k] for k in keys}, A.info["setup_seconds"],
+                                                        {k: B.info[k] for k in keys}, B.info["setup_seconds"]),
+          flush=True)
+    if B.info["n_levels"] == A.info["n_levels"] and len(B.kinds(0)[0]) == len(A.kinds(0)[0]):
+        assert all(A.info[k] == B.info[k] for k in keys)
+        assert all(A.tuning(m) == B.tuning(m) for m in range(A.info["n_levels"]))
+    lv = Level(cfg_b["grid"], cfg_b["curves"], 1.0, 0.0, 1.0)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(128 * 128) * lv.nonempty
+    ref = direct_solve(lv, f)
+    u = torch.zeros(128 * 128, dtype=torch.float64, device=dev)
+    B.solve(torch.tensor(f, device=dev), u)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(u.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+    A.close()
+    B.close()

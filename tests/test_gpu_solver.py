@@ -695,3 +695,34 @@ def test_fmg_reduces_the_residual_faster_than_v_cycles():
             cyc, S.info["n_levels"], rates[cyc], " ".join("%.1e" % v for v in h)), flush=True)
         S.close()
     assert rates[1] > rates[0]
+
+
+def test_create_many_batch_matches_oracle():
+    """Contexts made together by ccgmg_create_many (concurrent host set-up,
+    device set-up on the calling thread) solve as a lockstep batch to the
+    oracle's direct solutions."""
+    from paper_2504_00724_amd.ccgmg import Batch, create_many
+    dev = _dev()
+    cases = [(1, 64), (2, 64), (4, 128), (5, 64)]
+    stream = torch.cuda.current_stream().cuda_stream
+    probs, refs, fs = [], [], []
+    for k, n in cases:
+        cfg, lv = _level(k, n)
+        f, g, ref = _reference(k, n)
+        probs.append((cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"]))
+        refs.append((g, ref))
+        fs.append(torch.tensor(f, device=dev))
+    solvers = create_many(probs, [dict(tol=1e-12, max_cycles=200, hip_stream=stream)] * len(probs))
+    for S, (g, _) in zip(solvers, refs):
+        S.set_boundary(torch.tensor(g, device=dev), 1)
+    us = [torch.zeros_like(f) for f in fs]
+    B = Batch(solvers, nbranches=0)
+    reps = B.solve(fs, us)
+    torch.cuda.synchronize()
+    for (k, n), u, (_, ref), rep in zip(cases, us, refs, reps):
+        err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+        print("create_many batch: config %d n=%d cycles %d rel_err %.2e" % (k, n, rep["cycles"], err), flush=True)
+        assert err <= 1e-10
+    B.close()
+    for S in solvers:
+        S.close()

@@ -148,7 +148,7 @@ def test_struct_layouts_match_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
     structs = {"ccgmg_options": ccgmg.OptionsT, "ccgmg_info": ccgmg.InfoT, "ccgmg_report": ccgmg.ReportT,
-               "ccgmg_grid": ccgmg.GridT, "ccgmg_curve": ccgmg.CurveT}
+               "ccgmg_grid": ccgmg.GridT, "ccgmg_curve": ccgmg.CurveT, "ccgmg_problem": ccgmg.ProblemT}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ccgmg.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -213,3 +213,48 @@ def test_get_stencils_matches_get_irregular():
     with pytest.raises(ccgmg.CcgmgError):
         S.stencils(99)
     S.close()
+
+
+def test_create_many_builds_the_same_contexts_concurrently():
+    """ccgmg_create_many (host set-up of several geometries on worker
+    threads, largest first) gives contexts identical to ccgmg_create one by
+    one: kinds, hosts, lattices and weights of every level bit for bit,
+    whatever the thread count."""
+    _lib_or_skip()
+    cfgs = [W.config(1, n=64), W.config(2, n=64), W.config(4, n=128), W.config(5, n=64)] + \
+        W.batch_geometries(count=4, seed0=3100)
+    for c in cfgs[4:]:
+        c["grid"] = W.grid(min(c["grid"]["nx"], 256))
+    probs = [(c["grid"], c["curves"], c["a"], c["b"], c["c"]) for c in cfgs]
+    one = [ccgmg.Solver(*p, host_only=1) for p in probs]
+    for threads in (1, 3, 0):
+        many = ccgmg.create_many(probs, [dict(host_only=1)] * len(probs), host_threads=threads)
+        assert len(many) == len(probs)
+        for A, B in zip(one, many):
+            assert A.info["n_levels"] == B.info["n_levels"]
+            for m in range(A.info["n_levels"]):
+                ka, ha = A.kinds(m)
+                kb, hb = B.kinds(m)
+                assert np.array_equal(ka, kb) and np.array_equal(ha, hb)
+                ra, ca, va = A.stencils(m)
+                rb, cb, vb = B.stencils(m)
+                assert np.array_equal(ra, rb) and np.array_equal(ca, cb)
+                assert np.array_equal(va.view(np.uint64), vb.view(np.uint64))
+        for S in many:
+            S.close()
+    for S in one:
+        S.close()
+
+
+def test_create_many_reports_the_failing_geometry():
+    _lib_or_skip()
+    good = W.config(1, n=32)
+    probs = [(good["grid"], good["curves"], 1.0, 0.0, 1.0),
+             (W.grid(32), [W.box(), W.circle(0.95, 0.5, 0.2)], 1.0, 0.0, 1.0),   # leaves the box
+             (good["grid"], good["curves"], 1.0, 0.0, 1.0)]
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        ccgmg.create_many(probs, [dict(host_only=1)] * 3)
+    assert ei.value.code == ccgmg.EGEOM and "geometry 1" in str(ei.value)
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        ccgmg.create_many([(W.grid(32), [W.box()], 1.0, 3.0, 1.0)], [dict(host_only=1)])
+    assert ei.value.code == ccgmg.ENOTELLIPTIC

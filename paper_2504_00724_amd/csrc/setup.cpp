@@ -1145,17 +1145,18 @@ struct Fitter {
       std::sort(cells.begin(), cells.end());
       ranked.push_back({Key(P[e].sumsq, P[e].maxinf, 0, (int)e), cells});
     }
-    static int ALONG[9];
-    static bool init = false;
-    if (!init) {
+    // offsets along a line, nearest first (ties: negative side first);
+    // initialised once, thread-safely, by the first row to get here
+    static const std::array<int, 9> ALONG = []() {
       std::vector<int> al;
-      for (int v = -R; v <= R; ++v) al.push_back(v);
+      for (int v = -PLG_RADIUS; v <= PLG_RADIUS; ++v) al.push_back(v);
       std::stable_sort(al.begin(), al.end(), [](int x, int y) {
         return std::make_pair(std::abs(x), x) < std::make_pair(std::abs(y), y);
       });
-      for (int k = 0; k < 9; ++k) ALONG[k] = al[k];
-      init = true;
-    }
+      std::array<int, 9> a{};
+      for (int k = 0; k < 9; ++k) a[k] = al[k];
+      return a;
+    }();
     const auto& LA = LINES();
     for (int axis = 0; axis < 2; ++axis) {
       std::vector<std::pair<int, int32_t>> lines[9];  // (along, cell)

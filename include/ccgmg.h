@@ -101,8 +101,11 @@ typedef struct {
   double depth_max_rate; /* contraction bound used by auto_depth, default 0.5            */
   int precision;         /* 0: FP64 sweeps; 1: FP32 sweeps inside FP64 refinement         */
   int prolongation;      /* 0: piecewise constant (Section 4.1); 1: bilinear              */
-  int smo2_every_sweep;  /* 1: SMO-2 after every SMO-1 sweep (Section 4.1); 0: after the
-                            last sweep of each smoothing phase only                        */
+  int smo2_every_sweep;  /* 1: SMO-2 in every smoothing step (Section 4.1); 0: in the last
+                            step of each smoothing phase only; s >= 2: in every s-th step
+                            counted back from the last.  With fused steps the other
+                            steps are plain SMO-1 sweeps (block rows unchanged) and the
+                            step applying the coarse-grid correction is always fused   */
   int smo2_iters;        /* block iterations per SMO-2 application, default 1             */
   int smo2_block;        /* irregular cells per block, default 64                         */
   int smo2_overlap;      /* overlap layers of a block in the matrix graph, default 1      */
@@ -124,7 +127,9 @@ typedef struct {
   int tune_schedule;     /* 1 (default, with auto_depth 2): also time the schedules
                             (smoother_fused, nu1, nu2 / coarse) = (0,3,3), (1,3,3),
                             (1,4,4), (1,5,5), (1,4,4/2,2), (1,5,5/2,2), (1,5,5/3,3),
-                            (1,6,6/3,3), (1,4,4/3,4), (1,4,4/2,5) and keep the fastest;
+                            (1,6,6/3,3), (1,4,4/3,4), (1,4,4/2,5), and with SMO-2 in
+                            every s-th step (1,5,5/2,5; s 2), (1,4,4/2,5; 3),
+                            (1,6,6/3,4; 3), (1,5,5/3,3; 2), and keep the fastest;
                             0: use the fields above                                      */
   int inverse_fp32;      /* storage of the dense inverses (SMO-2 blocks, coarsest level),
                             computed in FP64 and always applied in FP64 arithmetic:
@@ -158,6 +163,7 @@ typedef struct {
   int smoother_fused;    /* smoothing schedule in use (after tuning)                      */
   int nu1, nu2;
   int nu1_coarse, nu2_coarse;
+  int smo2_every_sweep;  /* SMO-2 frequency in use (see the option of that name)          */
 } ccgmg_info;
 
 typedef struct {

@@ -567,9 +567,18 @@ struct Driver {
   template <typename T>
   T* smooth(DevLevel& L, T* cur, T* other, const T* r, const double* bterm, int nsteps, const T* e = nullptr,
             const DevLevel* C = nullptr) {
+    // SMO-2 in step k: every step (smo2_every_sweep = 1), the last step of
+    // the phase only (0), or every s-th step counted back from the last (s)
+    const int every = X->opt.smo2_every_sweep;
+    auto with_smo2 = [&](int k) { return every >= 1 ? (nsteps - 1 - k) % every == 0 : k == nsteps - 1; };
     if (fused(L)) {
       for (int k = 0; k < nsteps; ++k) {
-        fused_step<T>(L, cur, r, other, bterm, k == 0 ? e : nullptr, C);
+        // the step that applies the coarse-grid correction is always fused;
+        // in the other steps without SMO-2 the block rows keep their values
+        if (with_smo2(k) || (k == 0 && e))
+          fused_step<T>(L, cur, r, other, bterm, k == 0 ? e : nullptr, C);
+        else
+          sweep<T>(L, cur, r, other);
         std::swap(cur, other);
       }
       return cur;
@@ -577,7 +586,7 @@ struct Driver {
     for (int k = 0; k < nsteps; ++k) {
       sweep<T>(L, cur, r, other);
       std::swap(cur, other);
-      if (X->opt.smo2_every_sweep || k == nsteps - 1) smo2<T>(L, cur, r, bterm);
+      if (with_smo2(k)) smo2<T>(L, cur, r, bterm);
     }
     return cur;
   }
@@ -593,8 +602,8 @@ struct Driver {
     const double* inv64 = adjoint ? X->mtinv64 : X->minv64;
     const int nm = X->nm;
     if (nrhs == 1) {
-      hipLaunchKernelGGL((k_coarse<T>), dim3((nm + 3) / 4, 1), dim3(BLOCK), nm * sizeof(double), s, u, r, X->mcell,
-                         inv, inv64, nm, L.n);
+      hipLaunchKernelGGL((k_coarse<T>), dim3((nm + COARSE_WAVES - 1) / COARSE_WAVES, 1), dim3(64 * COARSE_WAVES),
+                         nm * sizeof(double), s, u, r, X->mcell, inv, inv64, nm, L.n);
       return;
     }
     // several right-hand sides: gather, then one product reading the inverse once
@@ -1189,22 +1198,28 @@ double timed_solve(ccgmg_ctx* X, const double* f, double tol, int max_cycles, do
 void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
   struct Sched {
     int fused, nu1, nu2, c1, c2;   // c1, c2: coarse-level steps (0: as nu1, nu2)
+    int every;                     // SMO-2 in every step (1) or every s-th step from the last (s)
   };
   std::vector<Sched> cands;
   if (X->opt.tune_schedule)
-    cands = {{0, 3, 3, 0, 0}, {1, 3, 3, 0, 0}, {1, 4, 4, 0, 0}, {1, 5, 5, 0, 0},
-             {1, 4, 4, 2, 2}, {1, 5, 5, 2, 2}, {1, 5, 5, 3, 3}, {1, 6, 6, 3, 3},
-             {1, 4, 4, 3, 4}, {1, 4, 4, 2, 5}};   // fewer pre- than post-steps on the coarse levels
+    cands = {{0, 3, 3, 0, 0, 1}, {1, 3, 3, 0, 0, 1}, {1, 4, 4, 0, 0, 1}, {1, 5, 5, 0, 0, 1},
+             {1, 4, 4, 2, 2, 1}, {1, 5, 5, 2, 2, 1}, {1, 5, 5, 3, 3, 1}, {1, 6, 6, 3, 3, 1},
+             {1, 4, 4, 3, 4, 1}, {1, 4, 4, 2, 5, 1},   // fewer pre- than post-steps on the coarse levels
+             // SMO-2 blocks in every second or third step only (the others are
+             // plain SMO-1 sweeps at the sweep's cost)
+             {1, 5, 5, 2, 5, 2}, {1, 4, 4, 2, 5, 3}, {1, 6, 6, 3, 4, 3}, {1, 5, 5, 3, 3, 2}};
   else
-    cands = {{X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse}};
+    cands = {{X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse,
+              X->opt.smo2_every_sweep}};
   const int Mmax = (int)X->H.disc.size() - 1;
   X->tune_ms.assign(Mmax + 1, -1.0);
   double best = 1e300;
   int bestM = X->M;
-  Sched bestS = {X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse};
+  Sched bestS = {X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse,
+                 X->opt.smo2_every_sweep};
   for (const Sched& sc : cands) {
     X->opt.smoother_fused = sc.fused, X->opt.nu1 = sc.nu1, X->opt.nu2 = sc.nu2;
-    X->opt.nu1_coarse = sc.c1, X->opt.nu2_coarse = sc.c2;
+    X->opt.nu1_coarse = sc.c1, X->opt.nu2_coarse = sc.c2, X->opt.smo2_every_sweep = sc.every;
     for (int Mc = Mmax; Mc >= 1; --Mc) {
       long nu = 0;
       for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
@@ -1221,7 +1236,7 @@ void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
     }
   }
   X->opt.smoother_fused = bestS.fused, X->opt.nu1 = bestS.nu1, X->opt.nu2 = bestS.nu2;
-  X->opt.nu1_coarse = bestS.c1, X->opt.nu2_coarse = bestS.c2;
+  X->opt.nu1_coarse = bestS.c1, X->opt.nu2_coarse = bestS.c2, X->opt.smo2_every_sweep = bestS.every;
   X->M = bestM;
   upload_coarsest(X);
   X->clear_graphs();
@@ -1658,7 +1673,7 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
 // ---------------------------------------------------------------------------
 struct TuneEntry {
   std::vector<int> ty64, ty32;
-  int fused = 0, nu1 = 0, nu2 = 0, c1 = 0, c2 = 0, M = 0;
+  int fused = 0, nu1 = 0, nu2 = 0, c1 = 0, c2 = 0, M = 0, every = 1;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneEntry> g_tune;
@@ -1699,14 +1714,14 @@ void tune_cache_load_locked() {
       v.push_back((int)x);
       q = end;
     }
-    // values: nlev, ty64[nlev], ty32[nlev], fused, nu1, nu2, c1, c2, M
-    if (v.empty() || v[0] < 1 || (int)v.size() != 1 + 2 * v[0] + 6) continue;
+    // values: nlev, ty64[nlev], ty32[nlev], fused, nu1, nu2, c1, c2, M, every
+    if (v.empty() || v[0] < 1 || (int)v.size() != 1 + 2 * v[0] + 7) continue;
     TuneEntry e;
     const int nl = v[0];
     e.ty64.assign(v.begin() + 1, v.begin() + 1 + nl);
     e.ty32.assign(v.begin() + 1 + nl, v.begin() + 1 + 2 * nl);
     const int* t = v.data() + 1 + 2 * nl;
-    e.fused = t[0], e.nu1 = t[1], e.nu2 = t[2], e.c1 = t[3], e.c2 = t[4], e.M = t[5];
+    e.fused = t[0], e.nu1 = t[1], e.nu2 = t[2], e.c1 = t[3], e.c2 = t[4], e.M = t[5], e.every = t[6];
     g_tune[line] = e;
   }
   std::fclose(fp);
@@ -1732,7 +1747,7 @@ void tune_cache_put(const std::string& key, const TuneEntry& e) {
   std::string v = std::to_string(e.ty64.size());
   for (int t : e.ty64) v += " " + std::to_string(t);
   for (int t : e.ty32) v += " " + std::to_string(t);
-  for (int t : {e.fused, e.nu1, e.nu2, e.c1, e.c2, e.M}) v += " " + std::to_string(t);
+  for (int t : {e.fused, e.nu1, e.nu2, e.c1, e.c2, e.M, e.every}) v += " " + std::to_string(t);
   std::fprintf(fp, "%s\t%s\n", key.c_str(), v.c_str());
   std::fclose(fp);
 }
@@ -1849,7 +1864,7 @@ void create_device(ccgmg_ctx* X) {
         fits(cached.M)) {
       for (size_t m = 0; m < X->lv.size(); ++m) X->lv[m].sweep_ty[0] = cached.ty64[m], X->lv[m].sweep_ty[1] = cached.ty32[m];
       X->opt.smoother_fused = cached.fused, X->opt.nu1 = cached.nu1, X->opt.nu2 = cached.nu2;
-      X->opt.nu1_coarse = cached.c1, X->opt.nu2_coarse = cached.c2;
+      X->opt.nu1_coarse = cached.c1, X->opt.nu2_coarse = cached.c2, X->opt.smo2_every_sweep = cached.every;
       X->M = cached.M;
       upload_coarsest(X);
       return;
@@ -1875,7 +1890,7 @@ void create_device(ccgmg_ctx* X) {
     TuneEntry e;
     for (const DevLevel& L : X->lv) e.ty64.push_back(L.sweep_ty[0]), e.ty32.push_back(L.sweep_ty[1]);
     e.fused = X->opt.smoother_fused, e.nu1 = X->opt.nu1, e.nu2 = X->opt.nu2;
-    e.c1 = X->opt.nu1_coarse, e.c2 = X->opt.nu2_coarse, e.M = X->M;
+    e.c1 = X->opt.nu1_coarse, e.c2 = X->opt.nu2_coarse, e.M = X->M, e.every = X->opt.smo2_every_sweep;
     tune_cache_put(key, e);
   }
 }
@@ -2071,6 +2086,7 @@ int ccgmg_query(const ccgmg_ctx* X, ccgmg_info* info) {
   info->nu2 = X->opt.nu2;
   info->nu1_coarse = X->opt.nu1_coarse > 0 ? X->opt.nu1_coarse : X->opt.nu1;
   info->nu2_coarse = X->opt.nu2_coarse > 0 ? X->opt.nu2_coarse : X->opt.nu2;
+  info->smo2_every_sweep = X->opt.smo2_every_sweep;
   return CCGMG_OK;
 }
 

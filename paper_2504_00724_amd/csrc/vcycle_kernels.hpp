@@ -521,15 +521,16 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
 }
 
 // Coarsest level: u[cell_k] = sum_j Inv[k, j] r[cell_j] (FP64), one wavefront
-// per row (4 rows per workgroup), the gathered right-hand side staged in LDS.
-template <typename T>
+// per row (WAVES rows per workgroup), the gathered right-hand side staged in
+// LDS once per workgroup.
+template <typename T, int WAVES = BLOCK / 64>
 __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ u, const T* __restrict__ r,
                                             const int32_t* __restrict__ cell, const float* __restrict__ inv,
                                             const double* __restrict__ inv64, int nm) {
-  for (int k = threadIdx.x; k < nm; k += BLOCK) rv[k] = (double)r[cell[k]];
+  for (int k = threadIdx.x; k < nm; k += WAVES * 64) rv[k] = (double)r[cell[k]];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int row = wg * 4 + (threadIdx.x >> 6);
+  const int row = wg * WAVES + (threadIdx.x >> 6);
   if (row >= nm) return;
   double s0 = 0.0, s1 = 0.0;
   if (inv64) {
@@ -540,25 +541,25 @@ __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ 
   } else {
     // FP32 row read as 16-byte vectors (the stream is latency-bound with
     // 4-byte loads): the 0-3 entries before the first 16-byte boundary, the
-    // aligned body, then the remaining 0-3 entries
+    // aligned body (8 vectors per lane in flight), then the remaining 0-3
+    // entries
     const float* A = inv + (size_t)row * nm;
     const int head = min((int)(((16 - (reinterpret_cast<uintptr_t>(A) & 15)) & 15) >> 2), nm);
     if (lane < head) s0 += (double)A[lane] * rv[lane];
     const int nb = (nm - head) >> 2;
     const float4* A4 = reinterpret_cast<const float4*>(A + head);
     const double* rb = rv + head;
-    int q = lane;
-    for (; q + 64 < nb; q += 128) {
-      const float4 a = A4[q], b = A4[q + 64];
-      const double* x = rb + 4 * q;
-      const double* y = rb + 4 * (q + 64);
-      s0 += (double)a.x * x[0] + (double)a.y * x[1] + (double)a.z * x[2] + (double)a.w * x[3];
-      s1 += (double)b.x * y[0] + (double)b.y * y[1] + (double)b.z * y[2] + (double)b.w * y[3];
-    }
-    if (q < nb) {
+    const int nq = lane < nb ? (nb - lane + 63) / 64 : 0;
+#pragma unroll 8
+    for (int it = 0; it < nq; ++it) {
+      const int q = lane + 64 * it;
       const float4 a = A4[q];
       const double* x = rb + 4 * q;
-      s0 += (double)a.x * x[0] + (double)a.y * x[1] + (double)a.z * x[2] + (double)a.w * x[3];
+      const double t = (double)a.x * x[0] + (double)a.y * x[1] + (double)a.z * x[2] + (double)a.w * x[3];
+      if (it & 1)
+        s1 += t;
+      else
+        s0 += t;
     }
     const int k = head + 4 * nb + lane;
     if (k < nm) s1 += (double)A[k] * rv[k];
@@ -568,18 +569,20 @@ __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ 
   if (lane == 0) u[cell[row]] = (T)s;
 }
 
+// the one-right-hand-side coarsest solve: 16 rows per workgroup
+constexpr int COARSE_WAVES = 16;
+
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
-                                                  const int32_t* __restrict__ cell, const float* __restrict__ inv,
-                                                  const double* __restrict__ inv64, int nm, size_t plane) {
+__global__ __launch_bounds__(64 * COARSE_WAVES) void k_coarse(T* __restrict__ u, const T* __restrict__ r,
+                                                              const int32_t* __restrict__ cell,
+                                                              const float* __restrict__ inv,
+                                                              const double* __restrict__ inv64, int nm,
+                                                              size_t plane) {
   extern __shared__ double rv[];
   const size_t z = blockIdx.y;
-  coarse_rows<T>(rv, blockIdx.x, u + z * plane, r + z * plane, cell, inv, inv64, nm);
+  coarse_rows<T, COARSE_WAVES>(rv, blockIdx.x, u + z * plane, r + z * plane, cell, inv, inv64, nm);
 }
 
-// Coarsest level with several right-hand sides, step 1: gather the
-// right-hand sides of the coarsest unknowns into rg[k][z] (FP64, row k,
-// nrhs contiguous).
 template <typename T>
 __global__ void k_coarse_gather(const T* __restrict__ r, const int32_t* __restrict__ cell, double* __restrict__ rg,
                                 int nm, int nrhs, size_t plane) {

@@ -146,6 +146,31 @@ def cmd_pmc(args):
     print("\n<!-- traffic-record %s -->" % json.dumps(rec))
 
 
+def cmd_counters(args):
+    """Per-kernel mean of every counter in one or more counter-collection
+    files (kernels whose short name contains --match)."""
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    names = []
+    for path in args.paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = short(r["Kernel_Name"])
+                if args.match and args.match not in k:
+                    continue
+                c = r["Counter_Name"]
+                if c not in names:
+                    names.append(c)
+                acc[k][c].append(float(r["Counter_Value"]))
+    print("| kernel | " + " | ".join(names) + " |")
+    print("|---|" + "---|" * len(names))
+    for k in sorted(acc):
+        vals = []
+        for c in names:
+            v = acc[k].get(c)
+            vals.append("%.4g" % (sum(v) / len(v)) if v else "")
+        print("| `%s` | %s |" % (k, " | ".join(vals)))
+
+
 def read_traffic_record(md_path):
     """The record written by ``pmc``, or None if absent or the sources changed."""
     try:
@@ -172,8 +197,11 @@ def main():
     p.add_argument("--cells", type=int, required=True)
     p.add_argument("--kernel", required=True)
     p.add_argument("--calib-kernel", default="k_copy")
+    q = sub.add_parser("counters")
+    q.add_argument("paths", nargs="+")
+    q.add_argument("--match", default="")
     args = ap.parse_args()
-    {"trace": cmd_trace, "cycle": cmd_cycle, "pmc": cmd_pmc}[args.cmd](args)
+    {"trace": cmd_trace, "cycle": cmd_cycle, "pmc": cmd_pmc, "counters": cmd_counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -32,12 +32,14 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=32,
                     help="SMO-1 tile height (the benchmark's tuned choice on the finest level)")
     ap.add_argument("--solves", type=int, default=0)
+    ap.add_argument("--config", type=int, choices=[2, 4, 5], default=4,
+                    help="workload: 4 three circles (b = 0), 5 five ellipses (b = 1.2), 2 flower (b = 0.5)")
     args = ap.parse_args()
     import torch  # noqa: F401  (HIP runtime and device selection)
 
     import workloads as W
     from paper_2504_00724_amd.ccgmg import Solver
-    cfg = W.config(4, n=args.n)
+    cfg = W.config(args.config, n=args.n)
     if args.solves:
         import bench
         dev = torch.device("cuda:0")

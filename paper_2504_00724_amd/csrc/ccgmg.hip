@@ -431,25 +431,28 @@ struct Driver {
     }
   }
 
-  // restriction into rc; also zeroes the coarse iterate uc and the coarse
-  // block rows' compact copy (which becomes the current one)
+  // restriction into rc; also zeroes the coarse block rows' compact copy
+  // (which becomes the current one) and sets the coarse iterate uc to zero,
+  // or (first_sweep) to the result of one plain SMO-1 sweep from zero
   template <typename T>
-  void restrict_(DevLevel& L, DevLevel& C, const T* u, const T* r, T* rc, T* uc) {
+  void restrict_(DevLevel& L, DevLevel& C, const T* u, const T* r, T* rc, T* uc, bool first_sweep = false) {
     CoefT<T> c(L.coef);
     const dim3 g = tiles1d(L.nx, L.ny, nrhs);
     const int nbx = tiles_x(L.nx);
     const bool fin = &L == &X->lv[0];
-    const uint8_t rb = regbit();
+    const uint8_t rb = regbit(), jb = jacbit();
     Smo2Data& CS = rows(C).smo2;
     CS.cur = 0;
     double* cc = CS.cbuf[0];
     const int ncc = CS.ns;
+    const uint8_t* ck = first_sweep ? C.kind : nullptr;
+    const T cw = CoefT<T>(C.coef).omega_invD;
     if (L.cross) {
-      if (fin) hipLaunchKernelGGL((k_restrict<T, T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
-      else hipLaunchKernelGGL((k_restrict<T, T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, true, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb, ck, cw, jb);
+      else hipLaunchKernelGGL((k_restrict<T, T, true, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb, ck, cw, jb);
     } else {
-      if (fin) hipLaunchKernelGGL((k_restrict<T, T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
-      else hipLaunchKernelGGL((k_restrict<T, T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb);
+      if (fin) hipLaunchKernelGGL((k_restrict<T, T, false, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb, ck, cw, jb);
+      else hipLaunchKernelGGL((k_restrict<T, T, false, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, rc, uc, cc, ncc, L.nx, L.ny, nbx, C.nx, C.ny, c, rb, ck, cw, jb);
     }
   }
 
@@ -561,21 +564,42 @@ struct Driver {
 
   bool fused(DevLevel& L) const { return X->opt.smoother_fused && rows(L).smo2.ns > 0; }
 
+  // SMO-2 in step k of a phase of nsteps: every step (smo2_every_sweep =
+  // 1), the last step of the phase only (0), or every s-th step counted
+  // back from the last (s)
+  bool with_smo2(int k, int nsteps) const {
+    const int every = X->opt.smo2_every_sweep;
+    return every >= 1 ? (nsteps - 1 - k) % every == 0 : k == nsteps - 1;
+  }
+
+  int pre_steps(int m) const { return (m > 0 && X->opt.nu1_coarse > 0) ? X->opt.nu1_coarse : X->opt.nu1; }
+
+  // Whether the restriction onto level m (m > 0, starting from a zero
+  // iterate) can also carry out that level's first pre-smoothing step:
+  // true when the step's SMO-1 part is a plain sweep (it then maps the
+  // zero iterate to omega D^-1 r on the SMO-1 cells and leaves the rest at
+  // zero).  In fused mode that step must be one without SMO-2; unfused,
+  // its SMO-2 pass still runs after it.
+  bool fold_first_sweep(int m) {
+    if (m >= X->M) return false;
+    const int n1 = pre_steps(m);
+    if (n1 < 1) return false;
+    return !fused(X->lv[m]) || !with_smo2(0, n1);
+  }
+
   // smooth nsteps times; returns pointer to the buffer holding the result.
   // Fused mode: e (if given) is the pending coarse-grid correction from
-  // level C, applied by the first step.
+  // level C, applied by the first step.  first_done: the SMO-1 sweep of
+  // step 0 has already been carried out (by the restriction; cur holds its
+  // result).
   template <typename T>
   T* smooth(DevLevel& L, T* cur, T* other, const T* r, const double* bterm, int nsteps, const T* e = nullptr,
-            const DevLevel* C = nullptr) {
-    // SMO-2 in step k: every step (smo2_every_sweep = 1), the last step of
-    // the phase only (0), or every s-th step counted back from the last (s)
-    const int every = X->opt.smo2_every_sweep;
-    auto with_smo2 = [&](int k) { return every >= 1 ? (nsteps - 1 - k) % every == 0 : k == nsteps - 1; };
+            const DevLevel* C = nullptr, bool first_done = false) {
     if (fused(L)) {
-      for (int k = 0; k < nsteps; ++k) {
+      for (int k = first_done ? 1 : 0; k < nsteps; ++k) {
         // the step that applies the coarse-grid correction is always fused;
         // in the other steps without SMO-2 the block rows keep their values
-        if (with_smo2(k) || (k == 0 && e))
+        if (with_smo2(k, nsteps) || (k == 0 && e))
           fused_step<T>(L, cur, r, other, bterm, k == 0 ? e : nullptr, C);
         else
           sweep<T>(L, cur, r, other);
@@ -584,9 +608,11 @@ struct Driver {
       return cur;
     }
     for (int k = 0; k < nsteps; ++k) {
-      sweep<T>(L, cur, r, other);
-      std::swap(cur, other);
-      if (with_smo2(k)) smo2<T>(L, cur, r, bterm);
+      if (!(k == 0 && first_done)) {
+        sweep<T>(L, cur, r, other);
+        std::swap(cur, other);
+      }
+      if (with_smo2(k, nsteps)) smo2<T>(L, cur, r, bterm);
     }
     return cur;
   }
@@ -613,9 +639,11 @@ struct Driver {
                        X->mrg, X->mcell, inv, inv64, nm, nrhs, L.n);
   }
 
-  // Alg. 2 on level m with iterate in (u, spare v) and rhs r.
+  // Alg. 2 on level m with iterate in (u, spare v) and rhs r.  first_done:
+  // the restriction onto this level has already carried out the SMO-1
+  // sweep of its first pre-smoothing step (fold_first_sweep).
   template <typename T>
-  T* vcycle(int m, T* u, T* v, const T* r, const double* bterm) {
+  T* vcycle(int m, T* u, T* v, const T* r, const double* bterm, bool first_done = false) {
     DevLevel& L = X->lv[m];
     if (m == X->M) {
       coarse<T>(L, u, r);
@@ -623,14 +651,15 @@ struct Driver {
     }
     // smoothing steps: nu1/nu2 on the finest level, nu1_coarse/nu2_coarse
     // (when positive) on the coarse levels
-    const int n1 = (m > 0 && X->opt.nu1_coarse > 0) ? X->opt.nu1_coarse : X->opt.nu1;
+    const int n1 = pre_steps(m);
     const int n2 = (m > 0 && X->opt.nu2_coarse > 0) ? X->opt.nu2_coarse : X->opt.nu2;
-    T* cur = smooth<T>(L, u, v, r, bterm, n1);
+    T* cur = smooth<T>(L, u, v, r, bterm, n1, nullptr, nullptr, first_done);
     T* oth = cur == u ? v : u;
     DevLevel& C = X->lv[m + 1];
     Buf<T> cb = bufs<T>(C);
-    restrict_<T>(L, C, cur, r, cb.r, cb.u);
-    T* e = vcycle<T>(m + 1, cb.u, cb.v, cb.r, nullptr);
+    const bool fold = fold_first_sweep(m + 1);
+    restrict_<T>(L, C, cur, r, cb.r, cb.u, fold);
+    T* e = vcycle<T>(m + 1, cb.u, cb.v, cb.r, nullptr, fold);
     T* out;
     if (fused(L) && X->opt.prolongation == 0 && n2 > 0) {
       out = smooth<T>(L, cur, oth, r, bterm, n2, e, &C);   // correction applied by the first step

@@ -133,8 +133,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const 
 
 // Residual of the regular cells restricted to the coarse grid:
 // rc_I = 1/4 sum over regular children c of (r - L u)_c  (Section 4.1).
-// The same launch zeroes the coarse iterate uc (the recursion starts from a
-// zero guess, Alg. 2) and the compact copy cc of its block rows.
+// The same launch sets the coarse iterate uc to the recursion's zero guess
+// (Alg. 2) and zeroes the compact copy cc of its block rows.  With ckind
+// set it writes instead the result of one plain SMO-1 sweep of the coarse
+// level from that zero guess: uc_I = cw * rc_I where ckind_I has cregbit
+// (cw = omega / D of the coarse level), 0 elsewhere -- the value the sweep
+// itself computes there (0 + cw * (rc - L 0)), so that sweep can be left
+// out.
 // One tile t of one plane (pointers already offset to the plane); l is the
 // workgroup's index within the plane, which zeroes entries [l * BLOCK,
 // (l + 1) * BLOCK) of the plane's compact copy cc.
@@ -142,7 +147,9 @@ template <typename T, typename TC, bool CROSS>
 __device__ __forceinline__ void restrict_tile(int t, int l, const T* __restrict__ u, const T* __restrict__ r,
                                               const uint8_t* __restrict__ kind, TC* __restrict__ rc,
                                               TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx, int ny,
-                                              int nbx, int ncx, int ncy, const CoefT<T>& c, uint8_t regbit) {
+                                              int nbx, int ncx, int ncy, const CoefT<T>& c, uint8_t regbit,
+                                              const uint8_t* __restrict__ ckind = nullptr, TC cw = (TC)0,
+                                              uint8_t cregbit = 0) {
   __shared__ T tile[LH][LW];
   {
     const int flat = l * BLOCK + threadIdx.x;
@@ -164,24 +171,28 @@ __device__ __forceinline__ void restrict_tile(int t, int l, const T* __restrict_
   __syncthreads();
   const int I = txi * (TX / 2) + cx, J = tyi * (TY / 2) + cy;
   if (I >= ncx || J >= ncy) return;
+  const size_t gc = (size_t)J * ncx + I;
+  const uint8_t ck = ckind ? ckind[gc] : (uint8_t)0;
   T s = (T)0;
 #pragma unroll
   for (int d = 0; d < 4; ++d)
     if (kd[d] & regbit)
       s += rr[d] - apply_regular<T, CROSS>(tile, 2 * cy + (d >> 1) + HALO, 2 * cx + (d & 1) + HALO, c);
-  rc[(size_t)J * ncx + I] = (TC)((T)0.25 * s);
-  uc[(size_t)J * ncx + I] = (TC)0;
+  const TC rv = (TC)((T)0.25 * s);
+  rc[gc] = rv;
+  uc[gc] = (ck & cregbit) ? cw * rv : (TC)0;
 }
 
 template <typename T, typename TC, bool CROSS, bool FINEST>
 __global__ __launch_bounds__(BLOCK) void k_restrict(const T* __restrict__ u, const T* __restrict__ r,
                                                     const uint8_t* __restrict__ kind, TC* __restrict__ rc,
                                                     TC* __restrict__ uc, double* __restrict__ cc, int ncc, int nx,
-                                                    int ny, int nbx, int ncx, int ncy, CoefT<T> c, uint8_t regbit) {
+                                                    int ny, int nbx, int ncx, int ncy, CoefT<T> c, uint8_t regbit,
+                                                    const uint8_t* __restrict__ ckind, TC cw, uint8_t cregbit) {
   const size_t z = blockIdx.z;
   restrict_tile<T, TC, CROSS>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, u + z * nx * ny, r + z * nx * ny, kind,
                               rc + z * ncx * ncy, uc + z * ncx * ncy, cc + z * ncc, ncc, nx, ny, nbx, ncx, ncy, c,
-                              regbit);
+                              regbit, ckind, cw, cregbit);
 }
 
 // Correction u_c += P e on regular fine cells: piecewise constant

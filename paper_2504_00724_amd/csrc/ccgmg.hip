@@ -142,6 +142,12 @@ struct DevLevel {
   double* part = nullptr;         // reduction partials
   int sweep_ty[2] = {16, 16};     // SMO-1 tile height (FP64, FP32), tuned at set-up
   int npart_reg = 0, npart_irr = 0;
+  // level 0: partials of a fused step that also takes the residual norm
+  // (at most npart_fused per plane), and whether the SMO-1 cells and the
+  // SMO-2 block rows together are exactly the non-empty cells (L, L^T)
+  double* fpart = nullptr;
+  int npart_fused = 0;
+  bool norm_cover[2] = {false, false};
 };
 
 }  // namespace
@@ -194,7 +200,7 @@ struct ccgmg_ctx {
   struct GraphEntry {
     const void *u, *f, *bterm, *norm;
     int nrhs, precision, M;
-    bool adjoint;
+    bool adjoint, pipe;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
@@ -489,10 +495,12 @@ struct Driver {
     S.cur = 1 - S.cur;
   }
 
-  // one fused smoothing step (SMO-1 and SMO-2 from the same iterate u)
+  // one fused smoothing step (SMO-1 and SMO-2 from the same iterate u);
+  // part (finest level, FP64, no pending correction): also the residual
+  // norm partials of u, fused_parts(L) per plane
   template <typename T, bool CROSS, bool FIN, bool PRO>
   void fused_t(DevLevel& L, const T* u, const T* r, T* out, const double* bterm, int ty, const T* e,
-               const DevLevel* C) {
+               const DevLevel* C, double* part = nullptr) {
     Smo2Data& S = rows(L).smo2;
     CoefT<T> c(L.coef);
     const int nbx = tiles_x(L.nx);
@@ -502,37 +510,58 @@ struct Driver {
     const Smo2Args a = smo2_args(L, bterm);
     const int ncx = C ? C->nx : 0, ncy = C ? C->ny : 0;
     const uint8_t pb = regbit();
+    if (part) {
+      if constexpr (std::is_same<T, double>::value && FIN && !PRO) {
+        switch (ty) {
+          case 8: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 8, PRO, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb, part); break;
+          case 32: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 32, PRO, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb, part); break;
+          default: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 16, PRO, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb, part); break;
+        }
+        S.cur = 1 - S.cur;
+        return;
+      } else {
+        throw ccg::Error(CCGMG_EINVAL, "residual partials only from the finest FP64 step");
+      }
+    }
     switch (ty) {
-      case 8: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 8, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb); break;
-      case 32: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 32, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb); break;
-      default: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 16, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb); break;
+      case 8: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 8, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb, nullptr); break;
+      case 32: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 32, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb, nullptr); break;
+      default: hipLaunchKernelGGL((k_smooth_fused<T, CROSS, FIN, 16, PRO>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, S.nblk, c, rb, sb, a, e, ncx, ncy, pb, nullptr); break;
     }
     S.cur = 1 - S.cur;
   }
 
+  // partials per plane of a fused step of level L with norm partials
+  int fused_parts(DevLevel& L) {
+    const int ty = L.sweep_ty[0];
+    return tiles_x(L.nx) * ((L.ny + ty - 1) / ty) + rows(L).smo2.nblk;
+  }
+
   template <typename T, bool CROSS, bool FIN>
   void fused_p(DevLevel& L, const T* u, const T* r, T* out, const double* bterm, int ty, const T* e,
-               const DevLevel* C) {
+               const DevLevel* C, double* part) {
     if (e) fused_t<T, CROSS, FIN, true>(L, u, r, out, bterm, ty, e, C);
-    else fused_t<T, CROSS, FIN, false>(L, u, r, out, bterm, ty, nullptr, nullptr);
+    else fused_t<T, CROSS, FIN, false>(L, u, r, out, bterm, ty, nullptr, nullptr, part);
   }
 
   // one fused step; with e, the pending coarse-grid correction P e (coarse
-  // level C) is applied on the fly
+  // level C) is applied on the fly; with part (level 0, FP64, no e), the
+  // residual norm partials of u are written there as well
   template <typename T>
   void fused_step(DevLevel& L, const T* u, const T* r, T* out, const double* bterm, const T* e = nullptr,
-                  const DevLevel* C = nullptr) {
+                  const DevLevel* C = nullptr, double* part = nullptr) {
     // the correction is read at the parent of every in-grid cell
     if (e && (!C || L.nx != 2 * C->nx || L.ny != 2 * C->ny))
       throw ccg::Error(CCGMG_EINVAL, "coarse level is not the fine level halved");
     const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
     const bool fin = &L == &X->lv[0];
+    if (part && (!fin || e)) throw ccg::Error(CCGMG_EINVAL, "residual partials only from the finest FP64 step");
     if (L.cross) {
-      if (fin) fused_p<T, true, true>(L, u, r, out, bterm, ty, e, C);
-      else fused_p<T, true, false>(L, u, r, out, bterm, ty, e, C);
+      if (fin) fused_p<T, true, true>(L, u, r, out, bterm, ty, e, C, part);
+      else fused_p<T, true, false>(L, u, r, out, bterm, ty, e, C, part);
     } else {
-      if (fin) fused_p<T, false, true>(L, u, r, out, bterm, ty, e, C);
-      else fused_p<T, false, false>(L, u, r, out, bterm, ty, e, C);
+      if (fin) fused_p<T, false, true>(L, u, r, out, bterm, ty, e, C, part);
+      else fused_p<T, false, false>(L, u, r, out, bterm, ty, e, C, part);
     }
   }
 
@@ -770,6 +799,13 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
               (jf[k] ? F_JAC : 0) | (jt[k] ? F_JAC_T : 0);
   for (int32_t q : SF.cell) kind[q] |= F_S2;
   for (int32_t q : ST.cell) kind[q] |= F_S2_T;
+  L.norm_cover[0] = L.norm_cover[1] = true;
+  for (size_t k = 0; k < L.n; ++k) {
+    const bool ne = kind[k] & F_NONEMPTY;
+    const bool jf_ = kind[k] & F_JAC, sf_ = kind[k] & F_S2, jt_ = kind[k] & F_JAC_T, st_ = kind[k] & F_S2_T;
+    if (ne ? jf_ == sf_ : (jf_ || sf_)) L.norm_cover[0] = false;
+    if (ne ? jt_ == st_ : (jt_ || st_)) L.norm_cover[1] = false;
+  }
   L.kind = upload(kind, X->owned);
   // coarse parent of every cell that takes the piecewise-constant correction
   // (regular rows of L, resp. of L^T); -1 elsewhere and on the coarsest level
@@ -800,6 +836,10 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
   L.npart_reg = (int)(((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY));
   L.npart_irr = std::max(1, (nrows + BLOCK - 1) / BLOCK);
   L.part = dalloc<double>((size_t)(L.npart_reg + L.npart_irr) * maxr, X->owned);
+  if (m == 0) {
+    L.npart_fused = ((L.nx + TX - 1) / TX) * ((L.ny + 7) / 8) + std::max(L.fwd.smo2.nblk, L.adj.smo2.nblk);
+    L.fpart = dalloc<double>((size_t)L.npart_fused * maxr, X->owned);
+  }
 }
 
 void upload_coarsest(ccgmg_ctx* X) {
@@ -973,10 +1013,33 @@ double norm_of(ccgmg_ctx* X, int nparts, int z, const double* part = nullptr) {
   return m;
 }
 
+// Whether the solve takes each cycle's residual norm from the first
+// smoothing step of the next cycle (norm_in_first_step): FP64 V-cycles
+// whose first finest-level step is a fused one (SMO-1 and SMO-2 from the
+// same iterate), on a level whose SMO-1 cells and SMO-2 block rows are
+// exactly its non-empty cells.  That step computes the residual of the
+// iterate it starts from on every non-empty cell anyway and writes its
+// result to the spare buffer, so the checked iterate stays where it is.
+bool norm_in_first_step(Driver& Dr) {
+  ccgmg_ctx* X = Dr.X;
+  DevLevel& L0 = X->lv[0];
+  return X->opt.precision == 0 && X->opt.cycle == 0 && X->M > 0 && X->opt.nu1 >= 1 && Dr.fused(L0) &&
+         Dr.with_smo2(0, X->opt.nu1) && L0.norm_cover[Dr.adjoint ? 1 : 0];
+}
+
+// The first smoothing step of a cycle with the residual norm partials of
+// its starting iterate u (into L0.fpart): reads u, writes L0.v.
+void first_step_norm(Driver& Dr, const double* u, const double* f, const double* bterm) {
+  DevLevel& L0 = Dr.X->lv[0];
+  Dr.fused_step<double>(L0, u, f, L0.v, bterm, nullptr, nullptr, L0.fpart);
+}
+
 // Start of a solve on stream Dr.s: boundary term, initial iterate, compact
 // copies, and the norm of the initial residual read back (not waited for).
-// Returns the boundary term in use (or nullptr).
-const double* solve_prologue(Driver& Dr, const double* f, double* u) {
+// pipe (norm_in_first_step): also the first step of the first cycle, whose
+// partials give that norm from a zero start.  Returns the boundary term in
+// use (or nullptr).
+const double* solve_prologue(Driver& Dr, const double* f, double* u, bool pipe = false) {
   ccgmg_ctx* X = Dr.X;
   DevLevel& L0 = X->lv[0];
   const int nrhs = Dr.nrhs;
@@ -995,6 +1058,15 @@ const double* solve_prologue(Driver& Dr, const double* f, double* u) {
   // reference norm ||f - N g||; for a zero start it is also the residual
   // the first mixed-precision step needs (stored as FP32)
   const bool zero_start = !X->opt.use_initial_guess;
+  if (pipe) {
+    // from a zero start the step's partials are those of |f - N g|
+    if (!zero_start) Dr.resmax<double>(L0, u, f, bterm, 1, nullptr);
+    first_step_norm(Dr, u, f, bterm);
+    HIP_OK(hipMemcpyAsync(X->norm_host0, zero_start ? L0.fpart : L0.part,
+                          sizeof(double) * (zero_start ? Dr.fused_parts(L0) : Dr.norm_parts(L0)) * nrhs,
+                          hipMemcpyDeviceToHost, Dr.s));
+    return bterm;
+  }
   Dr.resmax<double>(L0, u, f, bterm, 1, (mp && zero_start) ? L0.r32 : nullptr);
   HIP_OK(hipMemcpyAsync(X->norm_host0, L0.part, sizeof(double) * Dr.norm_parts(L0) * nrhs, hipMemcpyDeviceToHost,
                         Dr.s));
@@ -1020,6 +1092,21 @@ void solve_cycle(Driver& Dr, double* u, const double* f, const double* bterm, do
                         hipMemcpyDeviceToHost, Dr.s));
 }
 
+// One FP64 V-cycle whose first step has already run (its result in L0.v,
+// the compact copy advanced), then the first step of the next cycle, which
+// yields the residual norm partials of this cycle's result u, read back
+// into norm_dst (norm_in_first_step; recordable in a graph).
+void solve_cycle_pipe(Driver& Dr, double* u, const double* f, const double* bterm, double* norm_dst) {
+  ccgmg_ctx* X = Dr.X;
+  DevLevel& L0 = X->lv[0];
+  Dr.rows(L0).smo2.cur = 1;   // the state a first step leaves
+  double* res = Dr.vcycle<double>(0, L0.v, u, f, bterm, true);
+  if (res != u) HIP_OK(hipMemcpyAsync(u, res, sizeof(double) * L0.n * Dr.nrhs, hipMemcpyDeviceToDevice, Dr.s));
+  first_step_norm(Dr, u, f, bterm);
+  HIP_OK(hipMemcpyAsync(norm_dst, L0.fpart, sizeof(double) * Dr.fused_parts(L0) * Dr.nrhs, hipMemcpyDeviceToHost,
+                        Dr.s));
+}
+
 // Convergence bookkeeping of one solve (host side, after each read-back).
 struct Monitor {
   std::vector<double> rn;
@@ -1030,13 +1117,14 @@ struct Monitor {
   // from the reference norms ||f - N g|| the prologue read back into
   // X->norm_host0; returns false if one of them is not finite (NaN or Inf
   // in f-hat or g-hat)
-  bool start(ccgmg_ctx* X, int nrhs, int np) {
+  bool start(ccgmg_ctx* X, int nrhs, int np, int np0 = -1) {
+    if (np0 < 0) np0 = np;
     nparts = np;
     rn.assign(nrhs, 1.0);
     rel = 0.0;
     bool finite = true;
     for (int z = 0; z < nrhs; ++z) {
-      const double m = norm_of(X, nparts, z, X->norm_host0);
+      const double m = norm_of(X, np0, z, X->norm_host0);
       finite = finite && std::isfinite(m);
       rn[z] = m > 0 ? m : 1.0;
       if (m > 0) rel = 1.0;
@@ -1083,17 +1171,20 @@ struct Monitor {
 // by its arrays, norm read-back buffer, right-hand-side count, precision,
 // depth and direction); recorded on stream Dr.s, launchable on any stream.
 hipGraphExec_t cycle_graph(Driver& Dr, double* u, const double* f, const double* bterm,
-                           double* norm_dst = nullptr) {
+                           double* norm_dst = nullptr, bool pipe = false) {
   ccgmg_ctx* X = Dr.X;
   if (!norm_dst) norm_dst = X->norm_host;
   for (auto& g : X->graphs)
     if (g.u == u && g.f == f && g.bterm == bterm && g.norm == norm_dst && g.nrhs == Dr.nrhs &&
-        g.precision == X->opt.precision && g.M == X->M && g.adjoint == Dr.adjoint)
+        g.precision == X->opt.precision && g.M == X->M && g.adjoint == Dr.adjoint && g.pipe == pipe)
       return g.exec;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph;
   HIP_OK(hipStreamBeginCapture(Dr.s, hipStreamCaptureModeThreadLocal));
-  solve_cycle(Dr, u, f, bterm, norm_dst);
+  if (pipe)
+    solve_cycle_pipe(Dr, u, f, bterm, norm_dst);
+  else
+    solve_cycle(Dr, u, f, bterm, norm_dst);
   HIP_OK(hipStreamEndCapture(Dr.s, &graph));
   HIP_OK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   (void)hipGraphDestroy(graph);
@@ -1101,7 +1192,7 @@ hipGraphExec_t cycle_graph(Driver& Dr, double* u, const double* f, const double*
     (void)hipGraphExecDestroy(X->graphs.front().exec);
     X->graphs.erase(X->graphs.begin());
   }
-  X->graphs.push_back({u, f, bterm, norm_dst, Dr.nrhs, X->opt.precision, X->M, Dr.adjoint, exec});
+  X->graphs.push_back({u, f, bterm, norm_dst, Dr.nrhs, X->opt.precision, X->M, Dr.adjoint, pipe, exec});
   return exec;
 }
 
@@ -1113,7 +1204,11 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     HIP_OK(hipEventRecord(X->ev_in, X->stream));
     HIP_OK(hipStreamWaitEvent(ws, X->ev_in, 0));
     HIP_OK(hipEventRecord(X->ev_t0, ws));
-    const double* bterm = solve_prologue(Dr, f, u);
+    // pipe: cycle k's residual norm comes from the first step of cycle k + 1
+    // (each recorded cycle ends with the next cycle's first step); a solve
+    // that ends after cycle k returns its result, which that step only read
+    const bool pipe = norm_in_first_step(Dr);
+    const double* bterm = solve_prologue(Dr, f, u, pipe);
     HIP_OK(hipEventRecord(X->ev_pro, ws));
     // cycle k reads its residual back into buffer k mod 2 and records event
     // k mod 2; while the host checks cycle k, cycle k + 1 may already run
@@ -1124,13 +1219,15 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     double* nb[2] = {X->norm_host, X->norm_host2};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     if (X->opt.use_graph)
-      for (int k = 0; k < 2; ++k) exec[k] = cycle_graph(Dr, u, f, bterm, nb[k]);
+      for (int k = 0; k < 2; ++k) exec[k] = cycle_graph(Dr, u, f, bterm, nb[k], pipe);
     if (rep) std::memset(rep, 0, sizeof(*rep));
     int launched = 0, done = 0;
     auto launch = [&]() {
       const int k = launched++ & 1;
       if (exec[k])
         HIP_OK(hipGraphLaunch(exec[k], ws));
+      else if (pipe)
+        solve_cycle_pipe(Dr, u, f, bterm, nb[k]);
       else
         solve_cycle(Dr, u, f, bterm, nb[k]);
       HIP_OK(hipEventRecord(X->ev_cyc[k], ws));
@@ -1138,7 +1235,10 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
     launch();
     HIP_OK(hipEventSynchronize(X->ev_pro));
     Monitor mon;
-    if (!mon.start(X, nrhs, Dr.norm_parts(X->lv[0]))) {
+    DevLevel& L0 = X->lv[0];
+    const int np = pipe ? Dr.fused_parts(L0) : Dr.norm_parts(L0);
+    const int np0 = (pipe && !X->opt.use_initial_guess) ? Dr.fused_parts(L0) : Dr.norm_parts(L0);
+    if (!mon.start(X, nrhs, np, np0)) {
       HIP_OK(hipStreamSynchronize(ws));
       HIP_OK(hipEventRecord(X->ev_out, ws));
       HIP_OK(hipStreamWaitEvent(X->stream, X->ev_out, 0));
@@ -1865,7 +1965,9 @@ void create_device(ccgmg_ctx* X) {
   X->bterm = dalloc<double>((size_t)std::max(1, (int)D0.irr.size()) * maxr, X->owned);
   if (maxr > 1) X->mrg = dalloc<double>((size_t)MAX_COARSE_UNKNOWNS * maxr, X->owned);
   for (double** p : {&X->norm_host, &X->norm_host2, &X->norm_host0})
-    HIP_OK(hipHostMalloc((void**)p, sizeof(double) * (X->lv[0].npart_reg + X->lv[0].npart_irr) * maxr,
+    HIP_OK(hipHostMalloc((void**)p,
+                         sizeof(double) *
+                             std::max(X->lv[0].npart_reg + X->lv[0].npart_irr, X->lv[0].npart_fused) * maxr,
                          hipHostMallocDefault));
   // the coarsest level must be small enough for the dense inverse
   while (X->M > 0) {

@@ -33,11 +33,14 @@ constexpr uint8_t F_S2_T = 64;    // row of an SMO-2 block (L^T)
 template <typename T, int TYS>
 constexpr int sweep_lds_doubles() { return ((TYS + 2 * HALO) * LW * (int)sizeof(T) + 7) / 8; }
 
-template <typename T, bool CROSS, int TYS, bool PRO = false>
-__device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restrict__ u, const T* __restrict__ r,
-                                           const uint8_t* __restrict__ kind, T* __restrict__ out, int nx, int ny,
-                                           int nbx, const CoefT<T>& c, uint8_t regbit, uint8_t skipbit,
-                                           const T* __restrict__ e = nullptr, int ncx = 0, uint8_t probit = 0) {
+// NORM: also returns the thread's maximum of |r - L u| over the cells it
+// updates (the residual of the old iterate the update uses), else 0.
+template <typename T, bool CROSS, int TYS, bool PRO = false, bool NORM = false>
+__device__ __forceinline__ double sweep_tile(double* smem, int t, const T* __restrict__ u, const T* __restrict__ r,
+                                             const uint8_t* __restrict__ kind, T* __restrict__ out, int nx, int ny,
+                                             int nbx, const CoefT<T>& c, uint8_t regbit, uint8_t skipbit,
+                                             const T* __restrict__ e = nullptr, int ncx = 0, uint8_t probit = 0) {
+  double m = 0.0;
   constexpr int RPW = TYS / 4;            // rows per wave
   constexpr int ROWS = TYS + 2 * HALO;
   T (*tile)[LW] = reinterpret_cast<T (*)[LW]>(smem);
@@ -98,13 +101,16 @@ __device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restr
       const int gx = bx + tx, gy = by + r0 + k;
       if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
         T v = win[(k + 2) % 5][2];
-        if (kd[k] & regbit)
-          v += c.omega_invD *
-               (rr[k] - regular_row<T, true>([&](int dy, int dx) { return win[(k + 2 + dy + 5) % 5][dx + 2]; }, c));
+        if (kd[k] & regbit) {
+          const T d =
+              rr[k] - regular_row<T, true>([&](int dy, int dx) { return win[(k + 2 + dy + 5) % 5][dx + 2]; }, c);
+          if (NORM) m = nanmax(m, fabs((double)d));
+          v += c.omega_invD * d;
+        }
         out[(size_t)gy * nx + gx] = v;
       }
     }
-    return;
+    return m;
   }
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
@@ -112,10 +118,15 @@ __device__ __forceinline__ void sweep_tile(double* smem, int t, const T* __restr
     const int gx = bx + tx, gy = by + ry;
     if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
       T v = tile[ry + HALO][tx + HALO];
-      if (kd[k] & regbit) v += c.omega_invD * (rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c));
+      if (kd[k] & regbit) {
+        const T d = rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c);
+        if (NORM) m = nanmax(m, fabs((double)d));
+        v += c.omega_invD * d;
+      }
       out[(size_t)gy * nx + gx] = v;
     }
   }
+  return m;
 }
 
 // SMO-1 sweep launch: one workgroup per tile on a 1-D grid remapped by
@@ -279,10 +290,13 @@ struct Smo2Args {
 // i.e. the block works on u + P e.
 constexpr int SMO2_LDS_DOUBLES = 1024 + 4 * 64 + 64;
 
-template <typename T, bool PRO = false>
-__device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* uin, T* uout,
-                                           const T* __restrict__ r, const Smo2Args& a,
-                                           const T* __restrict__ ecor = nullptr) {
+// NORM: also returns the thread's maximum of |res| over the block's own
+// rows (their residual at the old iterate), else 0.
+template <typename T, bool PRO = false, bool NORM = false>
+__device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T* uin, T* uout,
+                                             const T* __restrict__ r, const Smo2Args& a,
+                                             const T* __restrict__ ecor = nullptr) {
+  double m = 0.0;
   double* res = smem;                                              // [1024]
   double (*part)[64] = reinterpret_cast<double (*)[64]>(smem + 1024);   // [4][64]
   double* uown = smem + 1024 + 4 * 64;                             // [64]
@@ -321,7 +335,9 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc += vv[k] * (uu[k] - uq);
     }
-    res[t] = rhs - acc - a.ersum[e] * uq;
+    const double rt = rhs - acc - a.ersum[e] * uq;
+    res[t] = rt;
+    if (NORM && t < nown) m = nanmax(m, fabs(rt));
   }
   __syncthreads();
   double s = 0.0;
@@ -352,6 +368,7 @@ __device__ __forceinline__ void smo2_block(double* smem, int b, int z, const T* 
     uout[a.ecell[e0 + row]] = v;
     c_out[k] = (double)v;
   }
+  return m;
 }
 
 // SMO-2 by restricted additive Schwarz.  Workgroup = one block of <= 64
@@ -378,23 +395,42 @@ __global__ __launch_bounds__(BLOCK) void k_smo2(T* u, const T* __restrict__ r, S
 // receives every cell.  PRO: the
 // first step after the coarse-grid correction, which it applies on the fly
 // (the iterate is u + P e, P piecewise constant onto the cells flagged
-// probit; the coarse grid is ncx x ncy).
-template <typename T, bool CROSS, bool FINEST, int TYS, bool PRO>
+// probit; the coarse grid is ncx x ncy).  NORM: every workgroup also
+// stores the maximum of |r - bterm - L u| (the old iterate's residual, FP64)
+// over the cells it updates in partial[z * gridDim.x + blockIdx.x]; the
+// SMO-1 cells and the block rows together are every non-empty cell, so the
+// partials carry the residual norm of the incoming iterate.
+template <typename T, bool CROSS, bool FINEST, int TYS, bool PRO, bool NORM = false>
 __global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u, const T* __restrict__ r,
                                                         const uint8_t* __restrict__ kind, T* __restrict__ out,
                                                         int nx, int ny, int nbx, int nblk, CoefT<T> c,
                                                         uint8_t regbit, uint8_t s2bit, Smo2Args a,
-                                                        const T* __restrict__ e, int ncx, int ncy, uint8_t probit) {
+                                                        const T* __restrict__ e, int ncx, int ncy, uint8_t probit,
+                                                        double* __restrict__ partial = nullptr) {
   // one LDS buffer shared by the two kinds of workgroup
   constexpr int NS = sweep_lds_doubles<T, TYS>();
   __shared__ double smem[NS > SMO2_LDS_DOUBLES ? NS : SMO2_LDS_DOUBLES];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   const T* ez = PRO ? e + (size_t)blockIdx.z * ncx * ncy : nullptr;
+  double m;
   if ((int)blockIdx.x < nblk)
-    smo2_block<T, PRO>(smem, blockIdx.x, blockIdx.z, u + zoff, out + zoff, r + zoff, a, ez);
+    m = smo2_block<T, PRO, NORM>(smem, blockIdx.x, blockIdx.z, u + zoff, out + zoff, r + zoff, a, ez);
   else
-    sweep_tile<T, CROSS, TYS, PRO>(smem, xcd_tile(blockIdx.x - nblk, gridDim.x - nblk), u + zoff, r + zoff, kind,
-                                   out + zoff, nx, ny, nbx, c, regbit, s2bit, ez, ncx, probit);
+    m = sweep_tile<T, CROSS, TYS, PRO, NORM>(smem, xcd_tile(blockIdx.x - nblk, gridDim.x - nblk), u + zoff,
+                                             r + zoff, kind, out + zoff, nx, ny, nbx, c, regbit, s2bit, ez, ncx,
+                                             probit);
+  if constexpr (NORM) {
+    __shared__ double red[BLOCK / 64];
+    for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double o = red[0];
+#pragma unroll
+      for (int w = 1; w < BLOCK / 64; ++w) o = nanmax(o, red[w]);
+      partial[(size_t)blockIdx.z * gridDim.x + blockIdx.x] = o;
+    }
+  }
 }
 
 // c[k] = u[cell[k]] for every block row (start of a solve on level 0).

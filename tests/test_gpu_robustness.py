@@ -235,3 +235,46 @@ def test_tune_cache_reuses_the_measured_choices(tmp_path, monkeypatch):
     assert np.max(np.abs(u.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
     A.close()
     B.close()
+
+
+@pytest.mark.parametrize("every", [3, 2])
+def test_stopped_solve_returns_the_iterate_it_reported(every):
+    """Schedules whose first finest-level step carries SMO-2 (smo2_every_sweep
+    = 3 with 4 pre-steps) take each cycle's residual norm from the first
+    step of the next cycle; the others (every second step: the first step is
+    a plain sweep) from a separate residual launch.  Either way a solve cut
+    off after k cycles returns the k-th iterate, whose on-demand residual
+    norm equals the last entry of the reported history, and a converged
+    solve matches the oracle's direct solution."""
+    from paper_2504_00724_amd.ccgmg import ENOCONV
+    dev = _dev()
+    cfg, lv = _level(4, 128)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ref = direct_solve(lv, rhs_vector(lv, f, g))
+    fd = torch.tensor(f, device=dev)
+    gd = torch.tensor(g, device=dev)
+    for k in (1, 2, 5):
+        S = _solver(cfg, tol=1e-14, max_cycles=k, smoother_fused=1, nu1=4, nu2=4, nu1_coarse=2, nu2_coarse=5,
+                    smo2_every_sweep=every, tune_schedule=0)
+        S.set_boundary(gd, 1)
+        u = torch.zeros_like(fd)
+        rep = S.solve(fd, u, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        ri, _ = S.residual_norms(fd, u)
+        print("every %d, max_cycles %d: status %d, history %s, on demand %.6e" % (
+            every, k, rep["status"], " ".join("%.3e" % v for v in rep["history"]), ri[0]), flush=True)
+        assert rep["status"] == ENOCONV and rep["cycles"] == k
+        assert abs(ri[0] - rep["history"][-1]) <= 1e-6 * rep["history"][-1]
+        S.close()
+    S = _solver(cfg, tol=1e-12, max_cycles=100, smoother_fused=1, nu1=4, nu2=4, nu1_coarse=2, nu2_coarse=5,
+                smo2_every_sweep=every, tune_schedule=0)
+    S.set_boundary(gd, 1)
+    u = torch.zeros_like(fd)
+    rep = S.solve(fd, u)
+    torch.cuda.synchronize()
+    ri, _ = S.residual_norms(fd, u)
+    assert ri[0] <= 1e-12 and abs(ri[0] - rep["rel_res_inf"]) <= 1e-4 * rep["rel_res_inf"]
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-10
+    S.close()

@@ -95,10 +95,46 @@ __device__ __forceinline__ T regular_row(const At& at, const CoefT<T>& c) {
   return acc;
 }
 
+// The same row with the y-differences of the cross term given:
+// dy(m) = 8 (u(1, m) - u(-1, m)) - (u(2, m) - u(-2, m)) for m = +-1, +-2,
+// and the axis values uc = u(0, 0), xp1 = u(0, 1), xm1 = u(0, -1), ...,
+// yp1 = u(1, 0), ... (same operations in the same order as regular_row).
+template <typename T, typename Dy>
+__device__ __forceinline__ T regular_row_dy(T uc, T xp1, T xm1, T xp2, T xm2, T yp1, T ym1, T yp2, T ym2,
+                                            const Dy& dy, const CoefT<T>& c) {
+  const T two = (T)2 * uc;
+  T acc = c.ax1 * ((xp1 + xm1) - two) + c.ax2 * ((xp2 + xm2) - two) + c.cy1 * ((yp1 + ym1) - two) +
+          c.cy2 * ((yp2 + ym2) - two);
+  acc += c.bxy * ((T)8 * (dy(1) - dy(-1)) - (dy(2) - dy(-2)));
+  return acc;
+}
+
 // (L u) at tile position (ly, lx) (already offset by HALO), difference form.
 template <typename T, bool CROSS>
 __device__ __forceinline__ T apply_regular(const T (*t)[LW], int ly, int lx, const CoefT<T>& c) {
   return regular_row<T, CROSS>([&](int dy, int dx) { return t[ly + dy][lx + dx]; }, c);
+}
+
+// y-differences of the cross term on the NR x (TX + 4) cells of a tile
+// whose u neighbourhood (NR + 4 rows) is staged in t:
+// dy[y][x] = 8 (t[y+3][x] - t[y+1][x]) - (t[y+4][x] - t[y][x]).
+template <typename T, int NR>
+__device__ __forceinline__ void fill_dy(T (*dy)[LW], const T (*t)[LW]) {
+  for (int k = threadIdx.x; k < NR * LW; k += BLOCK) {
+    const int y = k / LW, x = k - y * LW;
+    dy[y][x] = (T)8 * (t[y + 3][x] - t[y + 1][x]) - (t[y + 4][x] - t[y][x]);
+  }
+}
+
+// (L u) at tile position (ly, lx) (already offset by HALO) with the cross
+// term's y-differences taken from dy (tile rows without the HALO offset).
+template <typename T>
+__device__ __forceinline__ T apply_regular_dy(const T (*t)[LW], const T (*dy)[LW], int ly, int lx,
+                                              const CoefT<T>& c) {
+  const T* row = t[ly] + lx;
+  const T* dr = dy[ly - HALO] + lx;
+  return regular_row_dy<T>(row[0], row[1], row[-1], row[2], row[-2], t[ly + 1][lx], t[ly - 1][lx], t[ly + 2][lx],
+                           t[ly - 2][lx], [&](int dx) { return dr[dx]; }, c);
 }
 
 }  // namespace ccgk

@@ -30,8 +30,12 @@ constexpr uint8_t F_S2_T = 64;    // row of an SMO-2 block (L^T)
 // blocks of a fused step).  Jacobi: reads u, writes a second buffer.  Tiles
 // of TX x TYS cells (TYS = 8, 16 or 32, picked per level by measurement);
 // t is the tile index, nbx the number of tiles per grid row.
-template <typename T, int TYS>
-constexpr int sweep_lds_doubles() { return ((TYS + 2 * HALO) * LW * (int)sizeof(T) + 7) / 8; }
+// LDS of one tile: the (TYS + 4) x (TX + 4) neighbourhood of u, and with the
+// cross-derivative term (CROSS) a TYS x (TX + 4) tile of y-differences.
+template <typename T, int TYS, bool CROSS = false>
+constexpr int sweep_lds_doubles() {
+  return ((TYS + 2 * HALO + (CROSS ? TYS : 0)) * LW * (int)sizeof(T) + 7) / 8;
+}
 
 // NORM: also returns the thread's maximum of |r - L u| over the cells it
 // updates (the residual of the old iterate the update uses), else 0.
@@ -85,30 +89,49 @@ __device__ __forceinline__ double sweep_tile(double* smem, int t, const T* __res
   }
   __syncthreads();
   if (CROSS) {
-    // the 5 x 5 neighbourhood of the current cell in registers: ring of 5
-    // tile rows (x-2..x+2); each new cell loads one new row (5 LDS reads
-    // instead of 25)
-    T win[5][5];
+    // the cross-derivative term is a difference in x of the y-differences
+    // Dy(y, x) = 8 (u(y+1) - u(y-1)) - (u(y+2) - u(y-2)): they are formed
+    // once per tile column into a second LDS tile (each wave's own columns
+    // from a vertical window of 5 values, then the 4 halo columns), so a
+    // cell reads 4 of them instead of the 16 values they come from
+    T (*dyt)[LW] = tile + ROWS;
     const int r0 = w * RPW;   // tile row of the wave's first cell (before HALO offset)
+    {
+      T c0 = tile[r0][tx + HALO], c1 = tile[r0 + 1][tx + HALO], c2 = tile[r0 + 2][tx + HALO],
+        c3 = tile[r0 + 3][tx + HALO];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int dx = 0; dx < 5; ++dx) win[a][dx] = tile[r0 + a][tx + dx];
+      for (int k = 0; k < RPW; ++k) {
+        const T c4 = tile[r0 + k + 4][tx + HALO];
+        dyt[r0 + k][tx + HALO] = (T)8 * (c3 - c1) - (c4 - c0);
+        c0 = c1, c1 = c2, c2 = c3, c3 = c4;
+      }
+      for (int h = threadIdx.x; h < TYS * 2 * HALO; h += BLOCK) {
+        const int y = h / (2 * HALO), q = h - y * (2 * HALO);
+        const int lx = q < HALO ? q : TX + q;
+        dyt[y][lx] = (T)8 * (tile[y + 3][lx] - tile[y + 1][lx]) - (tile[y + 4][lx] - tile[y][lx]);
+      }
+    }
+    __syncthreads();
+    T c0 = tile[r0][tx + HALO], c1 = tile[r0 + 1][tx + HALO], c2 = tile[r0 + 2][tx + HALO],
+      c3 = tile[r0 + 3][tx + HALO];
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
-#pragma unroll
-      for (int dx = 0; dx < 5; ++dx) win[(k + 4) % 5][dx] = tile[r0 + k + 4][tx + dx];
+      const T c4 = tile[r0 + k + 4][tx + HALO];
       const int gx = bx + tx, gy = by + r0 + k;
       if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
-        T v = win[(k + 2) % 5][2];
+        T v = c2;
         if (kd[k] & regbit) {
-          const T d =
-              rr[k] - regular_row<T, true>([&](int dy, int dx) { return win[(k + 2 + dy + 5) % 5][dx + 2]; }, c);
+          const T* row = tile[r0 + k + HALO] + tx + HALO;
+          const T* dyr = dyt[r0 + k] + tx + HALO;
+          const T d = rr[k] - regular_row_dy<T>(
+                                  c2, row[1], row[-1], row[2], row[-2], c3, c1, c4, c0,
+                                  [&](int dx) { return dyr[dx]; }, c);
           if (NORM) m = nanmax(m, fabs((double)d));
           v += c.omega_invD * d;
         }
         out[(size_t)gy * nx + gx] = v;
       }
+      c0 = c1, c1 = c2, c2 = c3, c3 = c4;
     }
     return m;
   }
@@ -136,7 +159,7 @@ template <typename T, bool CROSS, bool FINEST, int TYS>
 __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const T* __restrict__ r,
                                                  const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
                                                  int ny, int nbx, CoefT<T> c, uint8_t regbit) {
-  __shared__ double smem[sweep_lds_doubles<T, TYS>()];
+  __shared__ double smem[sweep_lds_doubles<T, TYS, CROSS>()];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   sweep_tile<T, CROSS, TYS>(smem, xcd_tile(blockIdx.x, gridDim.x), u + zoff, r + zoff, kind, out + zoff, nx, ny,
                             nbx, c, regbit, 0);
@@ -162,6 +185,7 @@ __device__ __forceinline__ void restrict_tile(int t, int l, const T* __restrict_
                                               const uint8_t* __restrict__ ckind = nullptr, TC cw = (TC)0,
                                               uint8_t cregbit = 0) {
   __shared__ T tile[LH][LW];
+  __shared__ T dyt[CROSS ? TY : 1][LW];   // y-differences of the cross term
   {
     const int flat = l * BLOCK + threadIdx.x;
     if (flat < ncc) cc[flat] = 0.0;
@@ -180,6 +204,10 @@ __device__ __forceinline__ void restrict_tile(int t, int l, const T* __restrict_
   }
   load_tile(tile, u, nx, ny, bx, by);
   __syncthreads();
+  if (CROSS) {
+    fill_dy<T, TY>(dyt, tile);
+    __syncthreads();
+  }
   const int I = txi * (TX / 2) + cx, J = tyi * (TY / 2) + cy;
   if (I >= ncx || J >= ncy) return;
   const size_t gc = (size_t)J * ncx + I;
@@ -187,8 +215,10 @@ __device__ __forceinline__ void restrict_tile(int t, int l, const T* __restrict_
   T s = (T)0;
 #pragma unroll
   for (int d = 0; d < 4; ++d)
-    if (kd[d] & regbit)
-      s += rr[d] - apply_regular<T, CROSS>(tile, 2 * cy + (d >> 1) + HALO, 2 * cx + (d & 1) + HALO, c);
+    if (kd[d] & regbit) {
+      const int ly = 2 * cy + (d >> 1) + HALO, lx = 2 * cx + (d & 1) + HALO;
+      s += rr[d] - (CROSS ? apply_regular_dy<T>(tile, dyt, ly, lx, c) : apply_regular<T, false>(tile, ly, lx, c));
+    }
   const TC rv = (TC)((T)0.25 * s);
   rc[gc] = rv;
   uc[gc] = (ck & cregbit) ? cw * rv : (TC)0;
@@ -408,7 +438,7 @@ __global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u,
                                                         const T* __restrict__ e, int ncx, int ncy, uint8_t probit,
                                                         double* __restrict__ partial = nullptr) {
   // one LDS buffer shared by the two kinds of workgroup
-  constexpr int NS = sweep_lds_doubles<T, TYS>();
+  constexpr int NS = sweep_lds_doubles<T, TYS, CROSS>();
   __shared__ double smem[NS > SMO2_LDS_DOUBLES ? NS : SMO2_LDS_DOUBLES];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   const T* ez = PRO ? e + (size_t)blockIdx.z * ncx * ncy : nullptr;
@@ -496,6 +526,7 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
                                                 const double* __restrict__ vals, const double* __restrict__ rowsum,
                                                 int nrows, float* __restrict__ res_out) {
   __shared__ T tile[LH][LW];
+  __shared__ T dyt[CROSS ? TY : 1][LW];   // y-differences of the cross term
   __shared__ double red[BLOCK / 64];
   double m = 0.0;
   if (l >= nrb) {
@@ -514,12 +545,18 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
     }
     load_tile(tile, u, nx, ny, bx, by);
     __syncthreads();
+    if (CROSS && !zero_u) {
+      fill_dy<T, TY>(dyt, tile);
+      __syncthreads();
+    }
 #pragma unroll
     for (int k = 0; k < TY / 4; ++k) {
       const int gx = bx + tx, gy = by + w + 4 * k;
       if (kd[k] & regbit) {
         T v = rr[k];
-        if (!zero_u) v -= apply_regular<T, CROSS>(tile, w + 4 * k + HALO, tx + HALO, c);
+        if (!zero_u)
+          v -= CROSS ? apply_regular_dy<T>(tile, dyt, w + 4 * k + HALO, tx + HALO, c)
+                     : apply_regular<T, false>(tile, w + 4 * k + HALO, tx + HALO, c);
         m = nanmax(m, fabs((double)v));
         if (res_out) res_out[(size_t)gy * nx + gx] = (float)v;
       } else if (res_out && gx < nx && gy < ny && !(kd[k] & F_NONEMPTY)) {
@@ -891,7 +928,7 @@ struct BFused {                    // fused smoothing step of one geometry on on
 template <typename T, bool CROSS, bool PRO, int TYS>
 __global__ __launch_bounds__(BLOCK) void k_fused_batched(const BFused* __restrict__ descs, BStarts st,
                                                          const int* __restrict__ active) {
-  constexpr int NS = sweep_lds_doubles<T, TYS>();
+  constexpr int NS = sweep_lds_doubles<T, TYS, CROSS>();
   __shared__ double smem[NS > SMO2_LDS_DOUBLES ? NS : SMO2_LDS_DOUBLES];
   const int di = bfind(st, blockIdx.x);
   const BFused& d = descs[di];

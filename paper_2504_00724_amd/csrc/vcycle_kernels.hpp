@@ -335,17 +335,25 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
   const int e0 = a.ext_ptr[b], ne = a.ext_ptr[b + 1] - e0, nown = a.own_cnt[b];
   const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int64_t ioff = a.inv_off[b] + row;
-  for (int t = threadIdx.x; t < ne; t += BLOCK) {
-    const int e = e0 + t;
+  // G lanes per overlapped row (4, 2 or 1: as many as the block's rows
+  // leave), each summing a contiguous slice of the row's ELL entries in
+  // rounds of 8 loads; the slices' sums are added by lane shuffles (every
+  // lane of the group gets the same sum: fp addition commutes)
+  const int G = ne <= BLOCK / 4 ? 4 : (ne <= BLOCK / 2 ? 2 : 1);
+  const int sub = threadIdx.x & (G - 1);
+  const int per = (a.ew + G - 1) / G;
+  for (int t0 = 0; t0 < ne; t0 += BLOCK / G) {
+    const int t = t0 + (int)threadIdx.x / G;
+    const bool live = t < ne;
+    const int e = e0 + (live ? t : 0);
     double uq = c_in[a.eidx[e]];
     if (PRO) {
       const int pq = a.eqpar[e];
       if (pq >= 0) uq += (double)ecor[pq];
     }
-    if (t < 64) uown[t] = uq;
     double rhs = (double)r[a.ecell[e]];
     if (a.bterm && a.ebt[e] >= 0) rhs -= a.bterm[(size_t)z * a.nbt + a.ebt[e]];
-    const int p0 = e * a.ew, p1 = p0 + a.ew;
+    const int p0 = e * a.ew + sub * per, p1 = min(p0 + per, (e + 1) * a.ew);
     double acc = 0.0;
     for (int p = p0; p < p1; p += 8) {
       int cc[8], pp[8];
@@ -365,9 +373,14 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc += vv[k] * (uu[k] - uq);
     }
-    const double rt = rhs - acc - a.ersum[e] * uq;
-    res[t] = rt;
-    if (NORM && t < nown) m = nanmax(m, fabs(rt));
+    if (G >= 2) acc += __shfl_xor(acc, 1, 64);
+    if (G >= 4) acc += __shfl_xor(acc, 2, 64);
+    if (live && sub == 0) {
+      if (t < 64) uown[t] = uq;
+      const double rt = rhs - acc - a.ersum[e] * uq;
+      res[t] = rt;
+      if (NORM && t < nown) m = nanmax(m, fabs(rt));
+    }
   }
   __syncthreads();
   double s = 0.0;

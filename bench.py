@@ -474,7 +474,7 @@ def main():
     cells = args.n * args.n
     block_bytes = 0
     if info["smoother_fused"]:
-        kname = "k_smooth_fused<double, %s, true, %d, false>" % ("true" if cfg["b"] != 0 else "false", ty)
+        kname = "k_smooth_fused<double, %s, true, %d, false, false>" % ("true" if cfg["b"] != 0 else "false", ty)
         kdesc = "finest-level fused SMO-1 + SMO-2 step"
         dom_us = S.profile_kernel(7, 0, 50)
         dom_bytes = method_step_bytes(cells, info["n_irregular"])

@@ -73,6 +73,30 @@ def cmd_trace(args):
         print("| `%s` | %d | %.2f | %.2f | %.3f | %.1f%% |" % (k, n, a / 1e3, m / 1e3, t / 1e6, 100 * t / tot))
 
 
+def template_args(name):
+    """['double', 'false', ...] of a demangled kernel name (empty if none)."""
+    if "<" not in name:
+        return []
+    return [t.strip() for t in name[name.index("<") + 1:name.rindex(">")].split(",")]
+
+
+def is_norm_launch(name):
+    """A launch that yields a residual norm: the norm kernel, or a fused
+    smoothing step instantiated with the norm flag (sixth template argument),
+    which takes the norm of the iterate it starts from."""
+    if name.startswith("k_resnorm"):
+        return True
+    ta = template_args(name)
+    return name.startswith("k_smooth_fused") and len(ta) >= 6 and ta[5] == "true"
+
+
+def is_correction_step(name):
+    """The fused step that applies the coarse-grid correction (fifth
+    template argument)."""
+    ta = template_args(name)
+    return name.startswith("k_smooth_fused") and len(ta) >= 5 and ta[4] == "true"
+
+
 def cmd_cycle(args):
     with open(args.path) as f:
         rows = list(csv.DictReader(f))
@@ -85,14 +109,14 @@ def cmd_cycle(args):
     for i in range(1, len(rows)):
         if st[i] - en[i - 1] > 300000:
             first = i
-    norms = [i for i in range(first, len(rows)) if names[i].startswith("k_resnorm")]
+    norms = [i for i in range(first, len(rows)) if is_norm_launch(names[i])]
     if len(norms) < 3:
         raise SystemExit("fewer than two complete cycles in the last solve")
     i0, i1 = norms[-3], norms[-2]
     level, lv_ns, lv_n, other = 0, collections.defaultdict(float), collections.defaultdict(int), []
     for i in range(i0 + 1, i1 + 1):
         nm, d = names[i], en[i] - st[i]
-        if nm.startswith("k_smooth_fused") and nm.endswith("true>"):
+        if is_correction_step(nm):
             level -= 1                      # ascent: the step that applies P e
         if nm.startswith(("k_smooth_fused", "k_restrict", "k_sweep", "k_smo2", "k_prolong")):
             lv_ns[level] += d
@@ -105,6 +129,8 @@ def cmd_cycle(args):
     busy = sum(en[i] - st[i] for i in range(i0 + 1, i1 + 1)) / 1e3
     print("one V-cycle of the last solve: %.1f us from norm to norm, %.1f us in kernels, %d launches\n"
           % (span, busy, i1 - i0))
+    print("(a cycle runs from one launch that yields a residual norm to the next: the norm kernel, or\n"
+          "the next cycle's first fused step when that step takes the norm)\n")
     print("| level | launches | kernel time us | share of cycle |")
     print("|---|---|---|---|")
     for m in sorted(lv_ns):

@@ -19,31 +19,40 @@ def _trace(path, launches, gap0=1000000):
             t += d
 
 
-def _cycle(levels, nu=2):
+def _fused(fin, pro, norm=False):
+    return "void k_smooth_fused<double, false, %s, 16, %s, %s>(...)" % (
+        "true" if fin else "false", "true" if pro else "false", "true" if norm else "false")
+
+
+def _cycle(levels, nu=2, pipe=False):
     """A V-cycle on `levels` levels (0 finest): nu fused steps and a
     restriction per level going down, the coarsest solve, then nu fused
-    steps per level going up (the first applying the correction), the norm."""
+    steps per level going up (the first applying the correction), then the
+    norm: a norm launch, or (pipe) the next cycle's first fused step, which
+    takes it (that cycle then has one finest-level pre-step less)."""
     out = []
     for m in range(levels - 1):
-        out += [("void k_smooth_fused<double, false, %s, 16, false>(...)" % ("true" if m == 0 else "false"),
-                 1000 * (levels - m), 0)] * nu
+        steps = nu - 1 if (pipe and m == 0) else nu
+        out += [(_fused(m == 0, False), 1000 * (levels - m), 0)] * steps
         out.append(("void k_restrict<double, double, false, false>(...)", 500, 0))
     out.append(("void k_coarse<double>(...)", 700, 0))
     for m in range(levels - 2, -1, -1):
-        fin = "true" if m == 0 else "false"
-        out.append(("void k_smooth_fused<double, false, %s, 16, true>(...)" % fin, 1000 * (levels - m), 0))
-        out += [("void k_smooth_fused<double, false, %s, 16, false>(...)" % fin, 1000 * (levels - m), 0)] * (nu - 1)
-    out.append(("void k_resnorm<double, false>(...)", 300, 0))
+        out.append((_fused(m == 0, True), 1000 * (levels - m), 0))
+        out += [(_fused(m == 0, False), 1000 * (levels - m), 0)] * (nu - 1)
+    if pipe:
+        out.append((_fused(True, False, norm=True), 1000 * levels, 0))
+    else:
+        out.append(("void k_resnorm<double, false>(...)", 300, 0))
     out.append(("__amd_rocclr_copyBuffer", 100, 50000))
     return out
 
 
-def test_cycle_split_by_level(tmp_path, capsys):
+def _split(tmp_path, capsys, pipe):
     path = tmp_path / "t_kernel_trace.csv"
     launches = [("k_gj_elim", 100, 0)] * 5                      # set-up, then an idle gap
-    solve = []
+    solve = [(_fused(True, False, norm=True), 4000, 0)] if pipe else []
     for _ in range(3):
-        solve += _cycle(4)
+        solve += _cycle(4, pipe=pipe)
     launches += [(n, d, g) for n, d, g in solve]
     launches[5] = (launches[5][0], launches[5][1], 400000)      # the solve starts after a long gap
     _trace(path, launches)
@@ -54,13 +63,28 @@ def test_cycle_split_by_level(tmp_path, capsys):
     a.path = str(path)
     P.cmd_cycle(a)
     out = capsys.readouterr().out
-    rows = {l.split("|")[1].strip(): l for l in out.splitlines() if l.startswith("| ")}
+    return {l.split("|")[1].strip(): l for l in out.splitlines() if l.startswith("| ")}
+
+
+def test_cycle_split_by_level(tmp_path, capsys):
+    rows = _split(tmp_path, capsys, False)
     # per level: 2 down + 2 up fused steps + 1 restriction (levels 0..2); level 3 is the coarsest
     for m in range(3):
         cells = [c.strip() for c in rows[str(m)].split("|")]
         assert cells[2] == "5"
         assert abs(float(cells[3]) - (4 * (4 - m) + 0.5)) < 1e-9
     assert "`k_coarse<double>`" in rows and "`k_resnorm<double, false>`" in rows
+
+
+def test_cycle_split_when_the_first_step_takes_the_norm(tmp_path, capsys):
+    """Cycles delimited by the norm-taking first fused step (no norm
+    launch): the step counts on level 0 (it closes the cycle there)."""
+    rows = _split(tmp_path, capsys, True)
+    for m in range(3):
+        cells = [c.strip() for c in rows[str(m)].split("|")]
+        assert cells[2] == "5"
+        assert abs(float(cells[3]) - (4 * (4 - m) + 0.5)) < 1e-9
+    assert "`k_coarse<double>`" in rows and not any("k_resnorm" in k for k in rows)
 
 
 def test_traffic_record_scaling(tmp_path, capsys):

@@ -39,18 +39,48 @@ struct CoefT {
       : ax1((T)c.ax1), ax2((T)c.ax2), cy1((T)c.cy1), cy2((T)c.cy2), bxy((T)c.bxy), omega_invD((T)c.omega_invD) {}
 };
 
+// Fill a ROWS x (TX+4) LDS tile: entry k (row-major) is ld(ly, lx),
+// computed by thread k mod BLOCK.  The loads of CH of a thread's entries
+// are issued together, with no wait between them, and only then written
+// to LDS: a loop that waits for each load before issuing the next one
+// serializes the memory latency (6-10 round trips per workgroup).
+template <typename T, int ROWS, int CH = 5, typename Ld>
+__device__ __forceinline__ void stage_tile(T (*tile)[LW], const Ld& ld) {
+  constexpr int N = ROWS * LW, NIT = (N + BLOCK - 1) / BLOCK;
+#pragma unroll
+  for (int i0 = 0; i0 < NIT; i0 += CH) {
+    T v[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      if (i0 + i < NIT) {
+        const int k = (int)threadIdx.x + (i0 + i) * BLOCK;
+        const int kk = k < N ? k : 0;
+        const int ly = kk / LW, lx = kk - ly * LW;
+        v[i] = ld(ly, lx);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int k = (int)threadIdx.x + (i0 + i) * BLOCK;
+      if (i0 + i < NIT && k < N) {
+        const int ly = k / LW, lx = k - ly * LW;
+        tile[ly][lx] = v[i];
+      }
+    }
+  }
+}
+
 // Stage the (ROWS) x (TX+4) neighbourhood of a tile (ROWS = tile height + 4)
 // in LDS; outside the grid the value is 0 (never read by a regular cell).
+// Branch-free: an outside entry loads u[0] and discards it.
 template <typename T, int ROWS = LH>
 __device__ __forceinline__ void load_tile(T (*tile)[LW], const T* __restrict__ u, int nx, int ny, int bx, int by) {
-  const int tid = threadIdx.x;
-  for (int k = tid; k < ROWS * LW; k += BLOCK) {
-    const int ly = k / LW, lx = k - ly * LW;
+  stage_tile<T, ROWS>(tile, [&](int ly, int lx) {
     const int gx = bx + lx - HALO, gy = by + ly - HALO;
-    T v = (T)0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = u[(size_t)gy * nx + gx];
-    tile[ly][lx] = v;
-  }
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const T x = u[in ? (size_t)gy * nx + gx : 0];
+    return in ? x : (T)0;
+  });
 }
 
 // Workgroups of a launch are handed to the 8 XCDs round-robin (workgroup id
@@ -67,6 +97,13 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   int start = x * per;
   if (rem != 0 && x > rem) start -= x - rem;
   return start + k;
+}
+
+// x if keep, else +0.0, as a bit mask: a select between a loaded value and
+// a constant can be compiled into a branch around the load that waits for
+// it inside, which serializes the loads of a gather.
+__device__ __forceinline__ double keep_or_zero(double x, bool keep) {
+  return __longlong_as_double(__double_as_longlong(x) & (keep ? ~0LL : 0LL));
 }
 
 // Maximum that keeps a NaN (fmax drops it): a non-finite residual must

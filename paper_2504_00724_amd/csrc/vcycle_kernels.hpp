@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 // private header of ccgmg.hip (included once); kernels keep global names
@@ -71,18 +73,37 @@ __device__ __forceinline__ double sweep_tile(double* smem, int t, const T* __res
     // with a coarser one has even sides, so the parent (gy/2, gx/2) of an
     // in-grid cell is a coarse cell: its value is loaded alongside u and
     // kind (no load waits for the flag) and selected by the flag
-    for (int k = threadIdx.x; k < ROWS * LW; k += BLOCK) {
-      const int ly = k / LW, lx = k - ly * LW;
-      const int gx = bx + lx - HALO, gy = by + ly - HALO;
-      T v = (T)0;
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        const size_t g = (size_t)gy * nx + gx;
-        const T uv = u[g];
-        const uint8_t kb = kind[g];
-        const T ev = e[(size_t)(gy >> 1) * ncx + (gx >> 1)];
-        v = (kb & probit) ? uv + ev : uv;
+    // (the loads of 5 entries per thread first, then their combination:
+    // no load waits behind another)
+    constexpr int N = ROWS * LW, NIT = (N + BLOCK - 1) / BLOCK, CH = 5;
+#pragma unroll
+    for (int i0 = 0; i0 < NIT; i0 += CH) {
+      T uv[CH], ev[CH];
+      uint8_t kb[CH];
+      bool inn[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        if (i0 + i < NIT) {
+          const int k = (int)threadIdx.x + (i0 + i) * BLOCK;
+          const int kk = k < N ? k : 0;
+          const int ly = kk / LW, lx = kk - ly * LW;
+          const int gx = bx + lx - HALO, gy = by + ly - HALO;
+          inn[i] = k < N && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+          const size_t g = inn[i] ? (size_t)gy * nx + gx : 0;
+          uv[i] = u[g];
+          kb[i] = kind[g];
+          ev[i] = e[inn[i] ? (size_t)(gy >> 1) * ncx + (gx >> 1) : 0];
+        }
       }
-      tile[ly][lx] = v;
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int k = (int)threadIdx.x + (i0 + i) * BLOCK;
+        if (i0 + i < NIT && k < N) {
+          const int ly = k / LW, lx = k - ly * LW;
+          const T w = (kb[i] & probit) ? uv[i] + ev[i] : uv[i];
+          tile[ly][lx] = inn[i] ? w : (T)0;
+        }
+      }
     }
   } else {
     load_tile<T, ROWS>(tile, u, nx, ny, bx, by);
@@ -346,13 +367,19 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
     const int t = t0 + (int)threadIdx.x / G;
     const bool live = t < ne;
     const int e = e0 + (live ? t : 0);
+    // every conditional value below is loaded from a valid address and
+    // selected afterwards (no load sits behind a branch that waits for it)
     double uq = c_in[a.eidx[e]];
     if (PRO) {
       const int pq = a.eqpar[e];
-      if (pq >= 0) uq += (double)ecor[pq];
+      uq += keep_or_zero((double)ecor[pq >= 0 ? pq : 0], pq >= 0);
     }
-    double rhs = (double)r[a.ecell[e]];
-    if (a.bterm && a.ebt[e] >= 0) rhs -= a.bterm[(size_t)z * a.nbt + a.ebt[e]];
+    // boundary term: loaded from a valid address either way (the row sums
+    // stand in when there is none) and masked
+    const int bi = a.ebt[e];
+    const bool hasbt = a.bterm != nullptr && bi >= 0;
+    const double* btp = a.bterm ? a.bterm + (size_t)z * a.nbt : a.ersum;
+    const double rhs = (double)r[a.ecell[e]] - keep_or_zero(btp[hasbt ? bi : 0], hasbt);
     const int p0 = e * a.ew + sub * per, p1 = min(p0 + per, (e + 1) * a.ew);
     double acc = 0.0;
     for (int p = p0; p < p1; p += 8) {
@@ -367,8 +394,15 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        uu[k] = cc[k] >= 0 ? (double)uin[cc[k]] : c_in[-cc[k] - 1];
-        if (PRO && pp[k] >= 0) uu[k] += (double)ecor[pp[k]];
+        const bool blk = cc[k] < 0;   // a block row: its value is in the compact copy
+        if constexpr (std::is_same<T, double>::value) {
+          uu[k] = *(blk ? c_in + (-cc[k] - 1) : uin + cc[k]);
+        } else {
+          const double xc = c_in[blk ? -cc[k] - 1 : 0];
+          const double xu = (double)uin[blk ? 0 : cc[k]];
+          uu[k] = blk ? xc : xu;
+        }
+        if (PRO) uu[k] += keep_or_zero((double)ecor[pp[k] >= 0 ? pp[k] : 0], pp[k] >= 0);
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc += vv[k] * (uu[k] - uq);
@@ -624,7 +658,19 @@ template <typename T, int WAVES = BLOCK / 64>
 __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ u, const T* __restrict__ r,
                                             const int32_t* __restrict__ cell, const float* __restrict__ inv,
                                             const double* __restrict__ inv64, int nm) {
-  for (int k = threadIdx.x; k < nm; k += WAVES * 64) rv[k] = (double)r[cell[k]];
+  // gathered in chunks of 4 entries per thread: the cell indices of a
+  // chunk, then their values, are each loaded together
+  for (int k0 = threadIdx.x; k0 < nm; k0 += 4 * WAVES * 64) {
+    int ci[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ci[i] = cell[min(k0 + i * WAVES * 64, nm - 1)];
+    double x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = (double)r[ci[i]];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (k0 + i * WAVES * 64 < nm) rv[k0 + i * WAVES * 64] = x[i];
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = wg * WAVES + (threadIdx.x >> 6);

@@ -304,17 +304,31 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(T* __restrict__ u, const T* _
 
 // Residual of one explicit row (FP64, difference form):
 //   r_q - bterm - sum_s beta_s (u_s - u_q) - S u_q,  S = sum_s beta_s.
+// The entries are taken 8 at a time: their columns and weights, then the 8
+// gathers, each group of loads issued together (two accumulators, even and
+// odd entries).
 template <typename T>
 __device__ __forceinline__ double row_residual(const T* __restrict__ u, double rhs, int q, const int32_t* cols,
                                                const double* vals, int len, double rowsum) {
   const double uq = (double)u[q];
   double a0 = 0.0, a1 = 0.0;
-  int s = 0;
-  for (; s + 1 < len; s += 2) {
-    a0 += vals[s] * ((double)u[cols[s]] - uq);
-    a1 += vals[s + 1] * ((double)u[cols[s + 1]] - uq);
+  for (int s = 0; s < len; s += 8) {
+    int c[8];
+    double w[8], x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool in = s + k < len;
+      c[k] = cols[in ? s + k : 0];
+      w[k] = in ? vals[s + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = (double)u[c[k]];
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      a0 += w[k] * (x[k] - uq);
+      a1 += w[k + 1] * (x[k + 1] - uq);
+    }
   }
-  if (s < len) a0 += vals[s] * ((double)u[cols[s]] - uq);
   return rhs - (a0 + a1) - rowsum * uq;
 }
 
@@ -417,6 +431,9 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
     }
   }
   __syncthreads();
+  // indices of this thread's own row for the final write, loaded ahead
+  const int wr = grp == 0 && row < nown ? e0 + row : e0;
+  const int widx = a.eidx[wr], wcell = a.ecell[wr];
   double s = 0.0;
   // the own rows' inverse (column-major) times the residual; the storage
   // precision is uniform per launch
@@ -440,10 +457,9 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
   part[grp][row] = s;
   __syncthreads();
   if (grp == 0 && row < nown) {
-    const int k = a.eidx[e0 + row];
     const T v = (T)(uown[row] + (part[0][row] + part[1][row] + part[2][row] + part[3][row]));
-    uout[a.ecell[e0 + row]] = v;
-    c_out[k] = (double)v;
+    uout[wcell] = v;
+    c_out[widx] = (double)v;
   }
   return m;
 }

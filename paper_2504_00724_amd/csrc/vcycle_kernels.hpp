@@ -709,8 +709,25 @@ __device__ __forceinline__ void coarse_rows(double* rv, int wg, T* __restrict__ 
     const float4* A4 = reinterpret_cast<const float4*>(A + head);
     const double* rb = rv + head;
     const int nq = lane < nb ? (nb - lane + 63) / 64 : 0;
+    // full chunks of 8 vectors per lane, all 8 loaded before any is used,
+    // then the remaining vectors one at a time
+    int it = 0;
+    for (; it + 8 <= nq; it += 8) {
+      float4 a[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[i] = A4[lane + 64 * (it + i)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double* x = rb + 4 * (lane + 64 * (it + i));
+        const double t = (double)a[i].x * x[0] + (double)a[i].y * x[1] + (double)a[i].z * x[2] + (double)a[i].w * x[3];
+        if (i & 1)
+          s1 += t;
+        else
+          s0 += t;
+      }
+    }
 #pragma unroll 8
-    for (int it = 0; it < nq; ++it) {
+    for (; it < nq; ++it) {
       const int q = lane + 64 * it;
       const float4 a = A4[q];
       const double* x = rb + 4 * q;

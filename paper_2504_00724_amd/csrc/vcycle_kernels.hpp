@@ -437,16 +437,27 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
   double s = 0.0;
   // the own rows' inverse (column-major) times the residual; the storage
   // precision is uniform per launch
+  // (rounds of 8 loads; in the last round the columns past ne reload the
+  // first one and add +0, so the sum keeps its column order)
   auto matvec = [&](const auto* A) {
-    int col = grp;
-    for (; col + 28 < ne; col += 32) {
+    int c0 = grp;
+    for (; c0 + 28 < ne; c0 += 32) {
       double v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = (double)A[(size_t)(col + 4 * k) * nown];
+      for (int k = 0; k < 8; ++k) v[k] = (double)A[(size_t)(c0 + 4 * k) * nown];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s += v[k] * res[col + 4 * k];
+      for (int k = 0; k < 8; ++k) s += v[k] * res[c0 + 4 * k];
     }
-    for (; col < ne; col += 4) s += (double)A[(size_t)col * nown] * res[col];
+    if (c0 < ne) {
+      double v[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) v[k] = (double)A[(size_t)(c0 + 4 * k < ne ? c0 + 4 * k : grp) * nown];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const bool in = c0 + 4 * k < ne;
+        s += keep_or_zero(v[k] * res[in ? c0 + 4 * k : grp], in);
+      }
+    }
   };
   if (row < nown) {
     if (a.inv64)

@@ -494,7 +494,7 @@ def main():
     # HBM bytes per launch of the same kernel from the committed counter runs
     # (FETCH_SIZE, WRITE_SIZE, copy-calibrated); null once the kernel sources
     # differ from those the counters were taken on
-    rec = read_traffic_record(os.path.join(ROOT, "profiles", "smoothing_step_fp64_2048_pmc.md"))
+    rec = read_traffic_record(os.path.join(ROOT, "profiles", "smoothing_step_fp64_2048_pmc.md"), kname)
     traffic = None
     if rec and rec["cells"] == cells and rec["kernel"] == kname:
         traffic = rec["traffic_bytes_per_launch"]

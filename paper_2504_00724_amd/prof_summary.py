@@ -155,8 +155,6 @@ def cmd_pmc(args):
     known_kib = 8.0 * args.cells / 1024.0
     cf, cw = fetch[args.calib_kernel][0], write[args.calib_kernel][0]
     sf, sw = known_kib / cf, known_kib / cw
-    kf, kw = fetch[args.kernel][0], write[args.kernel][0]
-    traffic = (kf * sf + kw * sw) * 1024.0
     print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |")
     print("|---|---|---|---|")
     for k in sorted(set(fetch) | set(write)):
@@ -164,12 +162,16 @@ def cmd_pmc(args):
                                                write.get(k, (0, 0))[0]))
     print("\ncalibration: `%s` over %d cells moves %.1f KiB each way; counter scale fetch %.4f, write %.4f"
           % (args.calib_kernel, args.cells, known_kib, sf, sw))
-    print("\n`%s`: HBM traffic %.1f MB per launch (fetch %.1f MB, write %.1f MB, scaled)"
-          % (args.kernel, traffic / 1e6, kf * sf * 1024 / 1e6, kw * sw * 1024 / 1e6))
-    rec = {"kernel": args.kernel, "cells": args.cells, "traffic_bytes_per_launch": traffic,
-           "fetch_kib": kf, "write_kib": kw, "scale_fetch": sf, "scale_write": sw,
-           "sources_sha256": source_hash()}
-    print("\n<!-- traffic-record %s -->" % json.dumps(rec))
+    # one record per --kernel
+    for kern in args.kernel:
+        kf, kw = fetch[kern][0], write[kern][0]
+        traffic = (kf * sf + kw * sw) * 1024.0
+        print("\n`%s`: HBM traffic %.1f MB per launch (fetch %.1f MB, write %.1f MB, scaled)"
+              % (kern, traffic / 1e6, kf * sf * 1024 / 1e6, kw * sw * 1024 / 1e6))
+        rec = {"kernel": kern, "cells": args.cells, "traffic_bytes_per_launch": traffic,
+               "fetch_kib": kf, "write_kib": kw, "scale_fetch": sf, "scale_write": sw,
+               "sources_sha256": source_hash()}
+        print("\n<!-- traffic-record %s -->" % json.dumps(rec))
 
 
 def cmd_counters(args):
@@ -197,13 +199,16 @@ def cmd_counters(args):
         print("| `%s` | %s |" % (k, " | ".join(vals)))
 
 
-def read_traffic_record(md_path):
-    """The record written by ``pmc``, or None if absent or the sources changed."""
+def read_traffic_record(md_path, kernel=None):
+    """The record ``pmc`` wrote for kernel (the first one if kernel is None),
+    or None if absent or the sources changed since."""
     try:
         with open(md_path) as f:
             for line in f:
                 if line.startswith("<!-- traffic-record "):
                     rec = json.loads(line[len("<!-- traffic-record "):].rsplit("-->", 1)[0])
+                    if kernel is not None and rec.get("kernel") != kernel:
+                        continue
                     return rec if rec.get("sources_sha256") == source_hash() else None
     except OSError:
         return None
@@ -221,7 +226,8 @@ def main():
     p.add_argument("fetch")
     p.add_argument("write")
     p.add_argument("--cells", type=int, required=True)
-    p.add_argument("--kernel", required=True)
+    p.add_argument("--kernel", required=True, action="append",
+                   help="kernel whose traffic record is written (repeatable)")
     p.add_argument("--calib-kernel", default="k_copy")
     q = sub.add_parser("counters")
     q.add_argument("paths", nargs="+")

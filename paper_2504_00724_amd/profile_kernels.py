@@ -29,8 +29,9 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--kernels", default="sweep,copy")
-    ap.add_argument("--tile-rows", type=int, default=32,
-                    help="SMO-1 tile height (the benchmark's tuned choice on the finest level)")
+    ap.add_argument("--tile-rows", default="32",
+                    help="SMO-1 tile heights, comma-separated (8, 16, 32): the kernels are launched "
+                         "for each (the benchmark tunes its finest level among them)")
     ap.add_argument("--solves", type=int, default=0)
     ap.add_argument("--config", type=int, choices=[2, 4, 5], default=4,
                     help="workload: 4 three circles (b = 0), 5 five ellipses (b = 1.2), 2 flower (b = 0.5)")
@@ -57,14 +58,14 @@ def main():
             print("solve %d: %d cycles, %.3f ms" % (k, rep["cycles"], 1e3 * rep["seconds"]), flush=True)
         S.close()
         return
-    S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], auto_depth=0,
-               sweep_tile_rows=args.tile_rows)
-    out = {"n": args.n, "cells": args.n * args.n}
-    for name in args.kernels.split(","):
-        out[name + "_us"] = S.profile_kernel(KERNELS[name], 0, args.reps)
-        print(name, "done", flush=True)
-    print(json.dumps(out), flush=True)
-    S.close()
+    for ty in [int(t) for t in args.tile_rows.split(",")]:
+        S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], auto_depth=0, sweep_tile_rows=ty)
+        out = {"n": args.n, "cells": args.n * args.n, "tile_rows": ty}
+        for name in args.kernels.split(","):
+            out[name + "_us"] = S.profile_kernel(KERNELS[name], 0, args.reps)
+            print(name, "done", flush=True)
+        print(json.dumps(out), flush=True)
+        S.close()
 
 
 if __name__ == "__main__":

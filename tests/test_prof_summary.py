@@ -96,16 +96,23 @@ def test_traffic_record_scaling(tmp_path, capsys):
                 w.writerow({"Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
     cells = 1024
     known = 8.0 * cells / 1024.0                                  # KiB the copy reads and writes
-    counters(tmp_path / "f.csv", "FETCH_SIZE", [("k_copy", known / 2), ("k_x", 10.0)])
-    counters(tmp_path / "w.csv", "WRITE_SIZE", [("k_copy", known), ("k_x", 3.0)])
+    counters(tmp_path / "f.csv", "FETCH_SIZE", [("k_copy", known / 2), ("k_x", 10.0), ("k_y", 4.0)])
+    counters(tmp_path / "w.csv", "WRITE_SIZE", [("k_copy", known), ("k_x", 3.0), ("k_y", 1.0)])
 
     class A:
         pass
     a = A()
     a.fetch, a.write, a.cells, a.kernel, a.calib_kernel = str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), cells, \
-        "k_x", "k_copy"
+        ["k_x", "k_y"], "k_copy"
     P.cmd_pmc(a)
     out = capsys.readouterr().out
     rec = json.loads(out.split("<!-- traffic-record ")[1].rsplit("-->", 1)[0])
+    assert rec["kernel"] == "k_x"
     assert abs(rec["scale_fetch"] - 2.0) < 1e-12 and abs(rec["scale_write"] - 1.0) < 1e-12
     assert abs(rec["traffic_bytes_per_launch"] - (10.0 * 2.0 + 3.0) * 1024.0) < 1e-9
+    # one record per kernel; the lookup picks the named one
+    md = tmp_path / "p.md"
+    md.write_text(out)
+    ry = P.read_traffic_record(str(md), "k_y")
+    assert ry["kernel"] == "k_y" and abs(ry["traffic_bytes_per_launch"] - (4.0 * 2.0 + 1.0) * 1024.0) < 1e-9
+    assert P.read_traffic_record(str(md), "k_z") is None

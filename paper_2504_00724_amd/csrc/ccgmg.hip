@@ -437,6 +437,34 @@ struct Driver {
     }
   }
 
+  // two consecutive plain SMO-1 sweeps in one launch (b = 0 stencil only;
+  // returns false, launching nothing, when the level has the cross term)
+  template <typename T>
+  bool sweep2(DevLevel& L, const T* u, const T* r, T* out) {
+    if (L.cross) return false;
+    const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
+    CoefT<T> c(L.coef);
+    const dim3 g = tiles1d(L.nx, L.ny, nrhs, ty);
+    const int nbx = tiles_x(L.nx);
+    const uint8_t rb = jacbit();
+    const bool fin = &L == &X->lv[0];
+    switch (ty) {
+      case 8:
+        if (fin) hipLaunchKernelGGL((k_sweep2<T, true, 8>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
+        else hipLaunchKernelGGL((k_sweep2<T, false, 8>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
+        break;
+      case 32:
+        if (fin) hipLaunchKernelGGL((k_sweep2<T, true, 32>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
+        else hipLaunchKernelGGL((k_sweep2<T, false, 32>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
+        break;
+      default:
+        if (fin) hipLaunchKernelGGL((k_sweep2<T, true, 16>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
+        else hipLaunchKernelGGL((k_sweep2<T, false, 16>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
+        break;
+    }
+    return true;
+  }
+
   // restriction into rc; also zeroes the coarse block rows' compact copy
   // (which becomes the current one) and sets the coarse iterate uc to zero,
   // or (first_sweep) to the result of one plain SMO-1 sweep from zero
@@ -621,6 +649,9 @@ struct Driver {
   // level C, applied by the first step.  first_done: the SMO-1 sweep of
   // step 0 has already been carried out (by the restriction; cur holds its
   // result).
+  // Two steps k, k + 1 whose SMO-1 sweeps follow each other with no SMO-2
+  // pass between them run as one two-sweep launch (sweep2) where the level
+  // allows it.
   template <typename T>
   T* smooth(DevLevel& L, T* cur, T* other, const T* r, const double* bterm, int nsteps, const T* e = nullptr,
             const DevLevel* C = nullptr, bool first_done = false) {
@@ -630,6 +661,8 @@ struct Driver {
         // in the other steps without SMO-2 the block rows keep their values
         if (with_smo2(k, nsteps) || (k == 0 && e))
           fused_step<T>(L, cur, r, other, bterm, k == 0 ? e : nullptr, C);
+        else if (k + 1 < nsteps && !with_smo2(k + 1, nsteps) && sweep2<T>(L, cur, r, other))
+          ++k;
         else
           sweep<T>(L, cur, r, other);
         std::swap(cur, other);
@@ -638,7 +671,10 @@ struct Driver {
     }
     for (int k = 0; k < nsteps; ++k) {
       if (!(k == 0 && first_done)) {
-        sweep<T>(L, cur, r, other);
+        if (!with_smo2(k, nsteps) && k + 1 < nsteps && sweep2<T>(L, cur, r, other))
+          ++k;   // steps k and k + 1 swept; step k has no SMO-2 pass
+        else
+          sweep<T>(L, cur, r, other);
         std::swap(cur, other);
       }
       if (with_smo2(k, nsteps)) smo2<T>(L, cur, r, bterm);
@@ -2709,7 +2745,7 @@ int ccgmg_apply_NT(ccgmg_ctx* X, const double* lam, double* out, int nrhs) {
 
 int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* avg_us) {
   return guard(X, [&]() {
-    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 7)
+    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 8)
       throw ccg::Error(CCGMG_EINVAL, "bad profile arguments");
     Driver Dr{X, X->stream, 1, false};
     DevLevel& L = X->lv[level];
@@ -2732,6 +2768,9 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
         case 4: Dr.coarse<double>(L, L.u, L.r); break;
         case 7:
           Dr.fused_step<double>(L, L.u, L.r, L.v, nullptr);
+          break;
+        case 8:
+          if (!Dr.sweep2<double>(L, L.u, L.r, L.v)) throw ccg::Error(CCGMG_EINVAL, "no two-sweep kernel with b != 0");
           break;
         case 6:
           hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(8192, (L.n + 255) / 256)), dim3(256), 0, X->stream, L.v,

@@ -39,14 +39,14 @@ struct CoefT {
       : ax1((T)c.ax1), ax2((T)c.ax2), cy1((T)c.cy1), cy2((T)c.cy2), bxy((T)c.bxy), omega_invD((T)c.omega_invD) {}
 };
 
-// Fill a ROWS x (TX+4) LDS tile: entry k (row-major) is ld(ly, lx),
+// Fill a ROWS x W LDS tile (W = TX + 4 by default): entry k (row-major) is ld(ly, lx),
 // computed by thread k mod BLOCK.  The loads of CH of a thread's entries
 // are issued together, with no wait between them, and only then written
 // to LDS: a loop that waits for each load before issuing the next one
 // serializes the memory latency (6-10 round trips per workgroup).
-template <typename T, int ROWS, int CH = 5, typename Ld>
-__device__ __forceinline__ void stage_tile(T (*tile)[LW], const Ld& ld) {
-  constexpr int N = ROWS * LW, NIT = (N + BLOCK - 1) / BLOCK;
+template <typename T, int ROWS, int W = LW, int CH = 5, typename Ld>
+__device__ __forceinline__ void stage_tile(T (*tile)[W], const Ld& ld) {
+  constexpr int N = ROWS * W, NIT = (N + BLOCK - 1) / BLOCK;
 #pragma unroll
   for (int i0 = 0; i0 < NIT; i0 += CH) {
     T v[CH];
@@ -55,7 +55,7 @@ __device__ __forceinline__ void stage_tile(T (*tile)[LW], const Ld& ld) {
       if (i0 + i < NIT) {
         const int k = (int)threadIdx.x + (i0 + i) * BLOCK;
         const int kk = k < N ? k : 0;
-        const int ly = kk / LW, lx = kk - ly * LW;
+        const int ly = kk / W, lx = kk - ly * W;
         v[i] = ld(ly, lx);
       }
     }
@@ -63,7 +63,7 @@ __device__ __forceinline__ void stage_tile(T (*tile)[LW], const Ld& ld) {
     for (int i = 0; i < CH; ++i) {
       const int k = (int)threadIdx.x + (i0 + i) * BLOCK;
       if (i0 + i < NIT && k < N) {
-        const int ly = k / LW, lx = k - ly * LW;
+        const int ly = k / W, lx = k - ly * W;
         tile[ly][lx] = v[i];
       }
     }

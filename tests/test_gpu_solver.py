@@ -614,6 +614,39 @@ def test_solve_parity_every_tile_height(k, n, fused, ty):
     S.close()
 
 
+@pytest.mark.parametrize("k,n", [(4, 128), (5, 128), (2, 64)])
+@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("ty", [8, 16, 32])
+def test_two_sweep_launches_parity(k, n, fused, ty):
+    """A schedule with SMO-2 in every third step (4 + 4 finest, 2 + 5
+    coarse steps) has consecutive plain SMO-1 steps on every level; with
+    b = 0 each such pair runs as one two-sweep launch (temporal blocking,
+    every tile height), with b != 0 as two sweeps.  Either way the solve
+    converges to the oracle's direct solution."""
+    from paper_2504_00724_amd.ccgmg import EINVAL, CcgmgError
+    dev = _dev()
+    cfg, lv = _level(k, n)
+    f, g, ref = _reference(k, n)
+    print("two-sweep parity config %d n=%d fused %d rows %d" % (k, n, fused, ty), flush=True)
+    S = _solver(cfg, tol=1e-12, max_cycles=300, sweep_tile_rows=ty, tune_schedule=0, smoother_fused=fused,
+                nu1=4, nu2=4, nu1_coarse=2, nu2_coarse=5, smo2_every_sweep=3)
+    fd = torch.tensor(f, device=dev)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    u = torch.zeros_like(fd)
+    rep = S.solve(fd, u)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    print("   cycles %d rel_res %.2e rel_err %.2e" % (rep["cycles"], rep["rel_res_inf"], err), flush=True)
+    assert err <= 1e-10
+    if cfg["b"] != 0:
+        with pytest.raises(CcgmgError) as e:
+            S.profile_kernel(8, 0, 1)
+        assert e.value.code == EINVAL
+    else:
+        assert S.profile_kernel(8, 0, 2) > 0
+    S.close()
+
+
 @pytest.fixture(scope="module")
 def large_refs():
     """Oracle direct solutions of the three-circle (b = 0) and five-ellipse

@@ -5,7 +5,8 @@ hardware-counter collection under a profiler, e.g.
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- \
         python3 -m paper_2504_00724_amd.profile_kernels --n 2048
 
-Kernel 0 is the FP64 SMO-1 sweep, kernel 6 a plain FP64 copy of the same
+Kernel 0 is the FP64 SMO-1 sweep, kernel 8 two sweeps in one launch, kernel
+6 a plain FP64 copy of the same
 cell array (16 bytes per cell), which calibrates the byte counters.
 
 With --solves K it instead builds the context as the benchmark does (tuned
@@ -21,7 +22,7 @@ import time
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-KERNELS = {"sweep": 0, "restrict": 1, "prolong": 2, "smo2": 3, "sweep_f32": 5, "copy": 6, "fused": 7}
+KERNELS = {"sweep": 0, "restrict": 1, "prolong": 2, "smo2": 3, "sweep_f32": 5, "copy": 6, "fused": 7, "sweep2": 8}
 
 
 def main():

@@ -783,7 +783,9 @@ struct Driver {
   }
 
   template <typename T>
-  void resmax(DevLevel& L, const T* u, const T* r, const double* bterm, int zero_u, float* res_out) {
+  void resmax(DevLevel& L, const T* u, const T* r, const double* bterm, int zero_u, float* res_out,
+              double* part = nullptr) {
+    if (!part) part = L.part;
     const int nbx = tiles_x(L.nx);
     const int ntiles = nbx * ((L.ny + TY - 1) / TY);
     DevRows& R = rows(L);
@@ -793,10 +795,10 @@ struct Driver {
     const uint8_t rb = regbit();
     if (L.cross)
       hipLaunchKernelGGL((k_resnorm<T, true>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.nx, L.ny, nbx, ntiles, c, zero_u,
-                         rb, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, res_out, L.part);
+                         rb, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, res_out, part);
     else
       hipLaunchKernelGGL((k_resnorm<T, false>), g, dim3(BLOCK), 0, s, u, r, L.kind, L.nx, L.ny, nbx, ntiles, c,
-                         zero_u, rb, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, res_out, L.part);
+                         zero_u, rb, bterm, R.cell, R.rp, R.cols, R.vals, R.rowsum, R.n, res_out, part);
   }
 };
 
@@ -1064,10 +1066,13 @@ bool norm_in_first_step(Driver& Dr) {
 }
 
 // The first smoothing step of a cycle with the residual norm partials of
-// its starting iterate u (into L0.fpart): reads u, writes L0.v.
-void first_step_norm(Driver& Dr, const double* u, const double* f, const double* bterm) {
+// its starting iterate u: reads u, writes L0.v; the partials go to part,
+// which may be the pinned host buffer the solve loop reads (the kernel
+// writes it directly: the host reads it after the event that follows the
+// launch, when the writes are visible), else to L0.fpart.
+void first_step_norm(Driver& Dr, const double* u, const double* f, const double* bterm, double* part = nullptr) {
   DevLevel& L0 = Dr.X->lv[0];
-  Dr.fused_step<double>(L0, u, f, L0.v, bterm, nullptr, nullptr, L0.fpart);
+  Dr.fused_step<double>(L0, u, f, L0.v, bterm, nullptr, nullptr, part ? part : L0.fpart);
 }
 
 // Start of a solve on stream Dr.s: boundary term, initial iterate, compact
@@ -1095,24 +1100,25 @@ const double* solve_prologue(Driver& Dr, const double* f, double* u, bool pipe =
   // the first mixed-precision step needs (stored as FP32)
   const bool zero_start = !X->opt.use_initial_guess;
   if (pipe) {
-    // from a zero start the step's partials are those of |f - N g|
-    if (!zero_start) Dr.resmax<double>(L0, u, f, bterm, 1, nullptr);
-    first_step_norm(Dr, u, f, bterm);
-    HIP_OK(hipMemcpyAsync(X->norm_host0, zero_start ? L0.fpart : L0.part,
-                          sizeof(double) * (zero_start ? Dr.fused_parts(L0) : Dr.norm_parts(L0)) * nrhs,
-                          hipMemcpyDeviceToHost, Dr.s));
+    // from a zero start the step's partials are those of |f - N g|,
+    // written straight into the pinned buffer
+    if (zero_start) {
+      first_step_norm(Dr, u, f, bterm, X->norm_host0);
+    } else {
+      Dr.resmax<double>(L0, u, f, bterm, 1, nullptr, X->norm_host0);
+      first_step_norm(Dr, u, f, bterm);
+    }
     return bterm;
   }
-  Dr.resmax<double>(L0, u, f, bterm, 1, (mp && zero_start) ? L0.r32 : nullptr);
-  HIP_OK(hipMemcpyAsync(X->norm_host0, L0.part, sizeof(double) * Dr.norm_parts(L0) * nrhs, hipMemcpyDeviceToHost,
-                        Dr.s));
+  Dr.resmax<double>(L0, u, f, bterm, 1, (mp && zero_start) ? L0.r32 : nullptr, X->norm_host0);
   if (mp && !zero_start) Dr.resmax<double>(L0, u, f, bterm, 0, L0.r32);   // residual of the initial guess
   return bterm;
 }
 
-// One V-cycle (FP64, or FP32 inside one FP64 refinement step), the FP64
-// residual check and its read-back into norm_dst (pinned; default
-// norm_host), on stream Dr.s (recordable in a graph).
+// One V-cycle (FP64, or FP32 inside one FP64 refinement step) and the FP64
+// residual check, whose partial maxima the kernel writes straight into
+// norm_dst (pinned; default norm_host), on stream Dr.s (recordable in a
+// graph).
 void solve_cycle(Driver& Dr, double* u, const double* f, const double* bterm, double* norm_dst = nullptr) {
   ccgmg_ctx* X = Dr.X;
   DevLevel& L0 = X->lv[0];
@@ -1123,24 +1129,20 @@ void solve_cycle(Driver& Dr, double* u, const double* f, const double* bterm, do
     fp64_cycle(Dr, u, f, bterm);
   // the residual check; in mixed precision it also leaves the FP32 residual
   // for the next refinement step
-  Dr.resmax<double>(L0, u, f, bterm, 0, mp ? L0.r32 : nullptr);
-  HIP_OK(hipMemcpyAsync(norm_dst ? norm_dst : X->norm_host, L0.part, sizeof(double) * Dr.norm_parts(L0) * Dr.nrhs,
-                        hipMemcpyDeviceToHost, Dr.s));
+  Dr.resmax<double>(L0, u, f, bterm, 0, mp ? L0.r32 : nullptr, norm_dst ? norm_dst : X->norm_host);
 }
 
 // One FP64 V-cycle whose first step has already run (its result in L0.v,
 // the compact copy advanced), then the first step of the next cycle, which
-// yields the residual norm partials of this cycle's result u, read back
-// into norm_dst (norm_in_first_step; recordable in a graph).
+// writes the residual norm partials of this cycle's result u into the
+// pinned buffer norm_dst (norm_in_first_step; recordable in a graph).
 void solve_cycle_pipe(Driver& Dr, double* u, const double* f, const double* bterm, double* norm_dst) {
   ccgmg_ctx* X = Dr.X;
   DevLevel& L0 = X->lv[0];
   Dr.rows(L0).smo2.cur = 1;   // the state a first step leaves
   double* res = Dr.vcycle<double>(0, L0.v, u, f, bterm, true);
   if (res != u) HIP_OK(hipMemcpyAsync(u, res, sizeof(double) * L0.n * Dr.nrhs, hipMemcpyDeviceToDevice, Dr.s));
-  first_step_norm(Dr, u, f, bterm);
-  HIP_OK(hipMemcpyAsync(norm_dst, L0.fpart, sizeof(double) * Dr.fused_parts(L0) * Dr.nrhs, hipMemcpyDeviceToHost,
-                        Dr.s));
+  first_step_norm(Dr, u, f, bterm, norm_dst);
 }
 
 // Convergence bookkeeping of one solve (host side, after each read-back).

@@ -170,6 +170,8 @@ typedef struct {
   int cycles;            /* V-cycles run (all outer iterations together)                  */
   int outer_iters;       /* FP64 refinement steps (precision 1)                           */
   double rel_res_inf;    /* final relative L-infinity residual (FP64, difference form)    */
+  double rel_res_2;      /* final relative L2 residual ||f - N g - L u||_2 / ||f - N g||_2
+                            (the same checks' sums of squares; max over right-hand sides) */
   double seconds;        /* device time of the solve                                      */
   double history[64];    /* relative residual after each check                            */
 } ccgmg_report;
@@ -228,12 +230,9 @@ int ccgmg_get_level_shape(const ccgmg_ctx* ctx, int level, int* nx, int* ny);
 /* Cut-cell volumes in units of h^2 (host, nx_m * ny_m). */
 int ccgmg_get_volumes(const ccgmg_ctx* ctx, int level, double* vol);
 
-/* Irregular rows of L on level m (Section 3.3): for the k-th irregular cell
- * (increasing linear index) rows[k] is its index, cols[15k..15k+14] its
- * lattice in increasing linear index, vals the weights (1/h^2 units) and
- * cond[k] the 2-norm condition number of the lattice's cell-average sample
- * matrix.  Host arrays sized by ccgmg_info.n_irregular for level 0 (query
- * other levels with ccgmg_get_counts).  Any pointer may be NULL. */
+/* Counts of level m: *n_irregular irregular cells (the rows of
+ * ccgmg_get_irregular) and *n_faces boundary faces (Section 3.1); either
+ * pointer may be NULL.  CCGMG_EINVAL for a bad level. */
 int ccgmg_get_counts(const ccgmg_ctx* ctx, int level, long* n_irregular, long* n_faces);
 
 /* SMO-1 tile height (64-wide tiles of 8, 16 or 32 rows) chosen for level m

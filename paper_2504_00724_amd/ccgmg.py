@@ -65,7 +65,7 @@ class InfoT(C.Structure):
 
 class ReportT(C.Structure):
     _fields_ = [("cycles", C.c_int), ("outer_iters", C.c_int), ("rel_res_inf", C.c_double),
-                ("seconds", C.c_double), ("history", C.c_double * 64)]
+                ("rel_res_2", C.c_double), ("seconds", C.c_double), ("history", C.c_double * 64)]
 
 
 _LIB = None
@@ -422,6 +422,7 @@ def create_many(problems, options=None, host_threads=0):
 
 def _report(rep, st):
     return {"status": st, "cycles": rep.cycles, "outer_iters": rep.outer_iters, "rel_res_inf": rep.rel_res_inf,
+            "rel_res_2": rep.rel_res_2,
             "seconds": rep.seconds, "history": list(rep.history[:min(64, max(rep.cycles, 0))])}
 
 

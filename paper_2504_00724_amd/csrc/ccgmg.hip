@@ -873,10 +873,11 @@ void upload_level(ccgmg_ctx* X, int m, int maxr) {
   L.du = dalloc<double>((size_t)nrows * maxr, X->owned);
   L.npart_reg = (int)(((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY));
   L.npart_irr = std::max(1, (nrows + BLOCK - 1) / BLOCK);
-  L.part = dalloc<double>((size_t)(L.npart_reg + L.npart_irr) * maxr, X->owned);
+  // norm partials: a (maximum, sum of squares) pair per workgroup
+  L.part = dalloc<double>((size_t)2 * (L.npart_reg + L.npart_irr) * maxr, X->owned);
   if (m == 0) {
     L.npart_fused = ((L.nx + TX - 1) / TX) * ((L.ny + 7) / 8) + std::max(L.fwd.smo2.nblk, L.adj.smo2.nblk);
-    L.fpart = dalloc<double>((size_t)L.npart_fused * maxr, X->owned);
+    L.fpart = dalloc<double>((size_t)2 * L.npart_fused * maxr, X->owned);
   }
 }
 
@@ -1044,11 +1045,20 @@ double norm_of(ccgmg_ctx* X, int nparts, int z, const double* part = nullptr) {
   const double* p = part ? part : X->norm_host;
   double m = 0.0;
   for (int k = 0; k < nparts; ++k) {
-    const double v = p[(size_t)z * nparts + k];
+    const double v = p[2 * ((size_t)z * nparts + k)];
     if (std::isnan(v)) return v;   // a NaN partial is the result
     m = std::max(m, v);
   }
   return m;
+}
+
+// The L2 norm from the same partials (their sums of squares, in workgroup
+// order).
+double l2_of(ccgmg_ctx* X, int nparts, int z, const double* part = nullptr) {
+  const double* p = part ? part : X->norm_host;
+  double s = 0.0;
+  for (int k = 0; k < nparts; ++k) s += p[2 * ((size_t)z * nparts + k) + 1];
+  return std::sqrt(s);
 }
 
 // Whether the solve takes each cycle's residual norm from the first
@@ -1147,9 +1157,9 @@ void solve_cycle_pipe(Driver& Dr, double* u, const double* f, const double* bter
 
 // Convergence bookkeeping of one solve (host side, after each read-back).
 struct Monitor {
-  std::vector<double> rn;
+  std::vector<double> rn, rn2;   // reference norms ||f - N g|| (L-infinity, L2)
   int nparts = 0, cycles = 0, hist = 0, slow = 0;
-  double prev = 1e300, rel = 1.0;
+  double prev = 1e300, rel = 1.0, rel2 = 1.0;
   bool converged = false, stopped = false;
   bool guess = false;   // the solve starts from the caller's iterate
   // from the reference norms ||f - N g|| the prologue read back into
@@ -1159,13 +1169,15 @@ struct Monitor {
     if (np0 < 0) np0 = np;
     nparts = np;
     rn.assign(nrhs, 1.0);
-    rel = 0.0;
+    rn2.assign(nrhs, 1.0);
+    rel = rel2 = 0.0;
     bool finite = true;
     for (int z = 0; z < nrhs; ++z) {
-      const double m = norm_of(X, np0, z, X->norm_host0);
+      const double m = norm_of(X, np0, z, X->norm_host0), m2 = l2_of(X, np0, z, X->norm_host0);
       finite = finite && std::isfinite(m);
       rn[z] = m > 0 ? m : 1.0;
-      if (m > 0) rel = 1.0;
+      rn2[z] = m2 > 0 ? m2 : 1.0;
+      if (m > 0) rel = rel2 = 1.0;
     }
     guess = X->opt.use_initial_guess != 0;
     return finite;
@@ -1176,8 +1188,11 @@ struct Monitor {
     converged = stopped = false;
     ++cycles;
     const double before = cycles > 1 ? prev : 1.0;
-    rel = 0;
-    for (size_t z = 0; z < rn.size(); ++z) rel = std::max(rel, norm_of(X, nparts, (int)z, part) / rn[z]);
+    rel = rel2 = 0;
+    for (size_t z = 0; z < rn.size(); ++z) {
+      rel = std::max(rel, norm_of(X, nparts, (int)z, part) / rn[z]);
+      rel2 = std::max(rel2, l2_of(X, nparts, (int)z, part) / rn2[z]);
+    }
     if (rep && hist < 64) rep->history[hist++] = rel;
     if (!std::isfinite(rel)) return stopped = true;
     if (rel <= X->opt.tol) return converged = stopped = true;
@@ -1301,6 +1316,7 @@ int solve_impl(ccgmg_ctx* X, const double* f, double* u, int nrhs, ccgmg_report*
       rep->cycles = mon.cycles;
       rep->outer_iters = X->opt.precision == 1 ? mon.cycles : 0;
       rep->rel_res_inf = mon.rel;
+      rep->rel_res_2 = mon.rel2;
       rep->seconds = ms * 1e-3;
     }
     if (!mon.converged) throw ccg::Error(CCGMG_ENOCONV, "tolerance not reached");
@@ -1824,6 +1840,7 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
       reps[g].cycles = mon[g].cycles;
       reps[g].outer_iters = mp ? mon[g].cycles : 0;
       reps[g].rel_res_inf = mon[g].rel;
+      reps[g].rel_res_2 = mon[g].rel2;
       reps[g].seconds = ms * 1e-3;
     }
     ok = ok && mon[g].converged;
@@ -2004,7 +2021,7 @@ void create_device(ccgmg_ctx* X) {
   if (maxr > 1) X->mrg = dalloc<double>((size_t)MAX_COARSE_UNKNOWNS * maxr, X->owned);
   for (double** p : {&X->norm_host, &X->norm_host2, &X->norm_host0})
     HIP_OK(hipHostMalloc((void**)p,
-                         sizeof(double) *
+                         2 * sizeof(double) *
                              std::max(X->lv[0].npart_reg + X->lv[0].npart_irr, X->lv[0].npart_fused) * maxr,
                          hipHostMallocDefault));
   // the coarsest level must be small enough for the dense inverse
@@ -2557,7 +2574,7 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
       size_t total = 0;
       for (int g = 0; g < n; ++g) {
         B->part_off[g] = total;
-        total += (size_t)lockstep_parts(ctxs[g]) * ctxs[g]->opt.max_nrhs;
+        total += (size_t)2 * lockstep_parts(ctxs[g]) * ctxs[g]->opt.max_nrhs;
       }
       HIP_OK(hipMalloc((void**)&B->part_d, sizeof(double) * total));
       HIP_OK(hipHostMalloc((void**)&B->part_h, sizeof(double) * total, hipHostMallocDefault));
@@ -2704,6 +2721,7 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
         reps[g].cycles = mon[g].cycles;
         reps[g].outer_iters = B->ctx[g]->opt.precision == 1 ? mon[g].cycles : 0;
         reps[g].rel_res_inf = mon[g].rel;
+        reps[g].rel_res_2 = mon[g].rel2;
         reps[g].seconds = ms * 1e-3;
       }
       ok = ok && mon[g].converged;

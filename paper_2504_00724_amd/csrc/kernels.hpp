@@ -110,6 +110,34 @@ __device__ __forceinline__ double keep_or_zero(double x, bool keep) {
 // survive the norm reductions so that the host sees it.
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
+// Residual-norm accumulators of a thread, then of a workgroup: the maximum
+// of |r| (NaN kept) and the sum of r^2.  Every norm-taking launch stores
+// one pair per workgroup, (max, sum of squares), at 2 * (z * G + b); the
+// host reduces the pairs of a plane in workgroup order.
+struct NormAcc {
+  double m = 0.0, s = 0.0;
+  __device__ __forceinline__ void add(double r) {
+    m = nanmax(m, fabs(r));
+    s += r * r;
+  }
+};
+
+// The workgroup's pair (valid in thread 0): shuffle reduction within each
+// wavefront, then the wavefronts in order through red (2 * BLOCK / 64
+// doubles of LDS).  Every thread must call it.
+__device__ __forceinline__ NormAcc block_norm(NormAcc a, double* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a.m = nanmax(a.m, __shfl_xor(a.m, off, 64));
+    a.s += __shfl_xor(a.s, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) red[2 * (threadIdx.x >> 6)] = a.m, red[2 * (threadIdx.x >> 6) + 1] = a.s;
+  __syncthreads();
+  NormAcc o;
+  o.m = red[0], o.s = red[1];
+  for (int w = 1; w < BLOCK / 64; ++w) o.m = nanmax(o.m, red[2 * w]), o.s += red[2 * w + 1];
+  return o;
+}
+
 // (L u) at a cell from a value accessor at(dy, dx) (neighbour offsets in
 // -2..2), difference form.  The one arithmetic sequence shared by the LDS
 // tile form and the register-window form below.

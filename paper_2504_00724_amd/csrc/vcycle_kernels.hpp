@@ -39,14 +39,14 @@ constexpr int sweep_lds_doubles() {
   return ((TYS + 2 * HALO + (CROSS ? TYS : 0)) * LW * (int)sizeof(T) + 7) / 8;
 }
 
-// NORM: also returns the thread's maximum of |r - L u| over the cells it
-// updates (the residual of the old iterate the update uses), else 0.
+// NORM: also returns the thread's norm accumulators of r - L u over the
+// cells it updates (the residual of the old iterate the update uses).
 template <typename T, bool CROSS, int TYS, bool PRO = false, bool NORM = false>
-__device__ __forceinline__ double sweep_tile(double* smem, int t, const T* __restrict__ u, const T* __restrict__ r,
+__device__ __forceinline__ NormAcc sweep_tile(double* smem, int t, const T* __restrict__ u, const T* __restrict__ r,
                                              const uint8_t* __restrict__ kind, T* __restrict__ out, int nx, int ny,
                                              int nbx, const CoefT<T>& c, uint8_t regbit, uint8_t skipbit,
                                              const T* __restrict__ e = nullptr, int ncx = 0, uint8_t probit = 0) {
-  double m = 0.0;
+  NormAcc m;
   constexpr int RPW = TYS / 4;            // rows per wave
   constexpr int ROWS = TYS + 2 * HALO;
   T (*tile)[LW] = reinterpret_cast<T (*)[LW]>(smem);
@@ -147,7 +147,7 @@ __device__ __forceinline__ double sweep_tile(double* smem, int t, const T* __res
           const T d = rr[k] - regular_row_dy<T>(
                                   c2, row[1], row[-1], row[2], row[-2], c3, c1, c4, c0,
                                   [&](int dx) { return dyr[dx]; }, c);
-          if (NORM) m = nanmax(m, fabs((double)d));
+          if (NORM) m.add((double)d);
           v += c.omega_invD * d;
         }
         out[(size_t)gy * nx + gx] = v;
@@ -164,7 +164,7 @@ __device__ __forceinline__ double sweep_tile(double* smem, int t, const T* __res
       T v = tile[ry + HALO][tx + HALO];
       if (kd[k] & regbit) {
         const T d = rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c);
-        if (NORM) m = nanmax(m, fabs((double)d));
+        if (NORM) m.add((double)d);
         v += c.omega_invD * d;
       }
       out[(size_t)gy * nx + gx] = v;
@@ -446,13 +446,13 @@ struct Smo2Args {
 // i.e. the block works on u + P e.
 constexpr int SMO2_LDS_DOUBLES = 1024 + 4 * 64 + 64;
 
-// NORM: also returns the thread's maximum of |res| over the block's own
-// rows (their residual at the old iterate), else 0.
+// NORM: also returns the thread's norm accumulators of res over the
+// block's own rows (their residual at the old iterate).
 template <typename T, bool PRO = false, bool NORM = false>
-__device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T* uin, T* uout,
-                                             const T* __restrict__ r, const Smo2Args& a,
-                                             const T* __restrict__ ecor = nullptr) {
-  double m = 0.0;
+__device__ __forceinline__ NormAcc smo2_block(double* smem, int b, int z, const T* uin, T* uout,
+                                              const T* __restrict__ r, const Smo2Args& a,
+                                              const T* __restrict__ ecor = nullptr) {
+  NormAcc m;
   double* res = smem;                                              // [1024]
   double (*part)[64] = reinterpret_cast<double (*)[64]>(smem + 1024);   // [4][64]
   double* uown = smem + 1024 + 4 * 64;                             // [64]
@@ -518,7 +518,7 @@ __device__ __forceinline__ double smo2_block(double* smem, int b, int z, const T
       if (t < 64) uown[t] = uq;
       const double rt = rhs - acc - a.ersum[e] * uq;
       res[t] = rt;
-      if (NORM && t < nown) m = nanmax(m, fabs(rt));
+      if (NORM && t < nown) m.add(rt);
     }
   }
   __syncthreads();
@@ -594,7 +594,9 @@ __global__ __launch_bounds__(BLOCK) void k_smo2(T* u, const T* __restrict__ r, S
 // stores the maximum of |r - bterm - L u| (the old iterate's residual, FP64)
 // over the cells it updates in partial[z * gridDim.x + blockIdx.x]; the
 // SMO-1 cells and the block rows together are every non-empty cell, so the
-// partials carry the residual norm of the incoming iterate.
+// partials carry the residual norm of the incoming iterate.  With the
+// maximum goes the sum of squares: partial[2 q], partial[2 q + 1] for
+// q = z * gridDim.x + blockIdx.x.
 template <typename T, bool CROSS, bool FINEST, int TYS, bool PRO, bool NORM = false>
 __global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u, const T* __restrict__ r,
                                                         const uint8_t* __restrict__ kind, T* __restrict__ out,
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u,
   __shared__ double smem[NS > SMO2_LDS_DOUBLES ? NS : SMO2_LDS_DOUBLES];
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   const T* ez = PRO ? e + (size_t)blockIdx.z * ncx * ncy : nullptr;
-  double m;
+  NormAcc m;
   if ((int)blockIdx.x < nblk)
     m = smo2_block<T, PRO, NORM>(smem, blockIdx.x, blockIdx.z, u + zoff, out + zoff, r + zoff, a, ez);
   else
@@ -615,15 +617,11 @@ __global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u,
                                              r + zoff, kind, out + zoff, nx, ny, nbx, c, regbit, s2bit, ez, ncx,
                                              probit);
   if constexpr (NORM) {
-    __shared__ double red[BLOCK / 64];
-    for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
+    __shared__ double red[2 * BLOCK / 64];
+    const NormAcc o = block_norm(m, red);
     if (threadIdx.x == 0) {
-      double o = red[0];
-#pragma unroll
-      for (int w = 1; w < BLOCK / 64; ++w) o = nanmax(o, red[w]);
-      partial[(size_t)blockIdx.z * gridDim.x + blockIdx.x] = o;
+      const size_t q = 2 * ((size_t)blockIdx.z * gridDim.x + blockIdx.x);
+      partial[q] = o.m, partial[q + 1] = o.s;
     }
   }
 }
@@ -675,15 +673,15 @@ __global__ __launch_bounds__(BLOCK) void k_apply(const double* __restrict__ u, c
 // cell is also stored there as FP32 (0 on empty cells) for the refinement
 // loop: stencil cells by the tile workgroups, explicit rows by the row
 // workgroups, so no cell is written twice.  Every workgroup stores its
-// partial maximum in partial[z * gridDim.x + b]; the host, which reads the
-// norm back anyway, takes the maximum of the partials (no second launch and
-// no device-wide fence).
+// partial maximum and sum of squares in partial[2 q], partial[2 q + 1],
+// q = z * gridDim.x + b; the host, which reads the norms back anyway,
+// reduces the partials (no second launch and no device-wide fence).
 // Workgroup l of one plane (pointers offset to the plane; bterm and res_out
 // too): workgroups [0, nrb) take BLOCK explicit rows each, the others one
-// tile (remapped by xcd_tile over ntiles).  Returns the workgroup's maximum
-// (valid in thread 0).
+// tile (remapped by xcd_tile over ntiles).  Returns the workgroup's
+// accumulators (valid in thread 0).
 template <typename T, bool CROSS>
-__device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, const T* __restrict__ u,
+__device__ __forceinline__ NormAcc resnorm_block(int l, int nrb, int ntiles, const T* __restrict__ u,
                                                 const T* __restrict__ r, const uint8_t* __restrict__ kind, int nx,
                                                 int ny, int nbx, const CoefT<T>& c, int zero_u, uint8_t regbit,
                                                 const double* __restrict__ bterm, const int32_t* __restrict__ cell,
@@ -692,8 +690,8 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
                                                 int nrows, float* __restrict__ res_out) {
   __shared__ T tile[LH][LW];
   __shared__ T dyt[CROSS ? TY : 1][LW];   // y-differences of the cross term
-  __shared__ double red[BLOCK / 64];
-  double m = 0.0;
+  __shared__ double red[2 * BLOCK / 64];
+  NormAcc m;
   if (l >= nrb) {
     const int t = xcd_tile(l - nrb, ntiles);
     const int tyi = t / nbx;
@@ -722,7 +720,7 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
         if (!zero_u)
           v -= CROSS ? apply_regular_dy<T>(tile, dyt, w + 4 * k + HALO, tx + HALO, c)
                      : apply_regular<T, false>(tile, w + 4 * k + HALO, tx + HALO, c);
-        m = nanmax(m, fabs((double)v));
+        m.add((double)v);
         if (res_out) res_out[(size_t)gy * nx + gx] = (float)v;
       } else if (res_out && gx < nx && gy < ny && !(kd[k] & F_NONEMPTY)) {
         res_out[(size_t)gy * nx + gx] = 0.0f;   // explicit rows: written by the row workgroups
@@ -736,17 +734,10 @@ __device__ __forceinline__ double resnorm_block(int l, int nrb, int ntiles, cons
       if (bterm) rhs -= bterm[k];
       if (!zero_u) rhs = row_residual(u, rhs, q, cols + rp[k], vals + rp[k], rp[k + 1] - rp[k], rowsum[k]);
       if (res_out) res_out[q] = (float)rhs;
-      m = fabs(rhs);
+      m.add(rhs);
     }
   }
-  // maximum within each wavefront, then over the workgroup's wavefronts
-  for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  double out = red[0];
-#pragma unroll
-  for (int w = 1; w < BLOCK / 64; ++w) out = nanmax(out, red[w]);
-  return out;
+  return block_norm(m, red);
 }
 
 template <typename T, bool CROSS>
@@ -762,11 +753,14 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm(const T* __restrict__ u, cons
   const size_t plane = (size_t)nx * ny;
   // the row workgroups (chains of dependent loads) come first in the grid so
   // that their latency overlaps the streaming tiles
-  const double m = resnorm_block<T, CROSS>(blockIdx.x, (int)gridDim.x - ntiles, ntiles, u + z * plane,
-                                           r + z * plane, kind, nx, ny, nbx, c, zero_u, regbit,
-                                           bterm ? bterm + (size_t)z * nrows : nullptr, cell, rp, cols, vals, rowsum,
-                                           nrows, res_out ? res_out + z * plane : nullptr);
-  if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = m;
+  const NormAcc m = resnorm_block<T, CROSS>(blockIdx.x, (int)gridDim.x - ntiles, ntiles, u + z * plane,
+                                            r + z * plane, kind, nx, ny, nbx, c, zero_u, regbit,
+                                            bterm ? bterm + (size_t)z * nrows : nullptr, cell, rp, cols, vals,
+                                            rowsum, nrows, res_out ? res_out + z * plane : nullptr);
+  if (threadIdx.x == 0) {
+    const size_t q = 2 * ((size_t)z * gridDim.x + blockIdx.x);
+    partial[q] = m.m, partial[q + 1] = m.s;
+  }
 }
 
 // Coarsest level: u[cell_k] = sum_j Inv[k, j] r[cell_j] (FP64), one wavefront
@@ -1203,7 +1197,7 @@ struct BNorm {                     // residual check of one geometry (level 0, F
   const double *vals, *rowsum;
   int nrows;
   float* res_out;
-  double* partial;                 // [plane][nrb + ntiles]
+  double* partial;                 // [plane][nrb + ntiles][max, sum of squares]
   uint8_t regbit;
   int geo;
 };
@@ -1218,12 +1212,12 @@ __global__ __launch_bounds__(BLOCK) void k_resnorm_batched(const BNorm* __restri
   const int per = d.nrb + d.ntiles;
   const int z = local / per, l = local - z * per;
   const CoefT<double> c(d.c);
-  const double m = resnorm_block<double, CROSS>(l, d.nrb, d.ntiles, d.u + z * d.plane, d.r + z * d.plane, d.kind,
-                                                d.nx, d.ny, d.nbx, c, 0, d.regbit,
-                                                d.bterm ? d.bterm + (size_t)z * d.nrows : nullptr, d.cell, d.rp,
-                                                d.cols, d.vals, d.rowsum, d.nrows,
-                                                d.res_out ? d.res_out + z * d.plane : nullptr);
-  if (threadIdx.x == 0) d.partial[local] = m;
+  const NormAcc m = resnorm_block<double, CROSS>(l, d.nrb, d.ntiles, d.u + z * d.plane, d.r + z * d.plane,
+                                                 d.kind, d.nx, d.ny, d.nbx, c, 0, d.regbit,
+                                                 d.bterm ? d.bterm + (size_t)z * d.nrows : nullptr, d.cell, d.rp,
+                                                 d.cols, d.vals, d.rowsum, d.nrows,
+                                                 d.res_out ? d.res_out + z * d.plane : nullptr);
+  if (threadIdx.x == 0) d.partial[2 * local] = m.m, d.partial[2 * local + 1] = m.s;
 }
 
 struct BAux {                      // mixed precision, level 0: zero start / correction

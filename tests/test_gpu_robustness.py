@@ -261,11 +261,13 @@ def test_stopped_solve_returns_the_iterate_it_reported(every):
         u = torch.zeros_like(fd)
         rep = S.solve(fd, u, raise_on_noconv=False)
         torch.cuda.synchronize()
-        ri, _ = S.residual_norms(fd, u)
-        print("every %d, max_cycles %d: status %d, history %s, on demand %.6e" % (
-            every, k, rep["status"], " ".join("%.3e" % v for v in rep["history"]), ri[0]), flush=True)
+        ri, r2 = S.residual_norms(fd, u)
+        print("every %d, max_cycles %d: status %d, history %s, on demand %.6e (L2 %.6e, reported %.6e)" % (
+            every, k, rep["status"], " ".join("%.3e" % v for v in rep["history"]), ri[0], r2[0], rep["rel_res_2"]),
+              flush=True)
         assert rep["status"] == ENOCONV and rep["cycles"] == k
         assert abs(ri[0] - rep["history"][-1]) <= 1e-6 * rep["history"][-1]
+        assert abs(r2[0] - rep["rel_res_2"]) <= 1e-6 * rep["rel_res_2"]
         S.close()
     S = _solver(cfg, tol=1e-12, max_cycles=100, smoother_fused=1, nu1=4, nu2=4, nu1_coarse=2, nu2_coarse=5,
                 smo2_every_sweep=every, tune_schedule=0)

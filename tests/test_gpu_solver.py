@@ -377,6 +377,10 @@ def test_lockstep_batch_matches_oracle(precision):
                 k, n, z, reps[i]["cycles"], reps[i]["rel_res_inf"], err), flush=True)
             assert err <= 1e-10
         assert reps[i]["rel_res_inf"] <= 1e-12
+        # the reported L2 residual: the worst right-hand side's, as the
+        # on-demand norms give it
+        _, r2 = solvers[i].residual_norms(fs[i], us[i], nr[i])
+        assert abs(max(r2) - reps[i]["rel_res_2"]) <= 1e-4 * max(r2)
     for u in us:
         u.zero_()
     reps2 = B.solve(fs, us, nr)
@@ -565,11 +569,13 @@ def test_residual_norms_match_oracle():
     u = torch.zeros(lv.nx * lv.ny, dtype=torch.float64, device=dev)
     rep = S.solve(Ft[0], u)
     ri, r2 = S.residual_norms(Ft[0], u)
-    print("   converged: inf %.3e (solve %.3e), l2 %.3e" % (ri[0], rep["rel_res_inf"], r2[0]), flush=True)
+    print("   converged: inf %.3e (solve %.3e), l2 %.3e (solve %.3e)" % (ri[0], rep["rel_res_inf"], r2[0],
+                                                                      rep["rel_res_2"]), flush=True)
     # same per-cell arithmetic as the solve's check; the compiler may still
     # contract the last product differently (an ulp of |L u| in a residual
-    # 1e10 times smaller)
+    # 1e10 times smaller), and the sums of squares are taken in another order
     assert abs(ri[0] - rep["rel_res_inf"]) <= 1e-4 * rep["rel_res_inf"]
+    assert abs(r2[0] - rep["rel_res_2"]) <= 1e-4 * rep["rel_res_2"]
     assert ri[0] <= 1e-10 and r2[0] <= 1e-10
     S.close()
 

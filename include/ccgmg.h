@@ -353,8 +353,7 @@ int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out, int nrhs);
  * pass (FP64), 4 coarsest solve, 5 SMO-1 sweep (FP32), 6 plain FP64 copy of
  * the level's cell array (16 bytes per cell; calibrates byte counters),
  * 7 fused smoothing step (FP64, smoother_fused), 8 two consecutive plain
- * SMO-1 sweeps in one launch (FP64; CCGMG_EINVAL when b != 0, which has
- * no such kernel).  Leaves the work
+ * SMO-1 sweeps in one launch (FP64).  Leaves the work
  * buffers of that level undefined; no user buffer is touched. */
 int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double* avg_us);
 

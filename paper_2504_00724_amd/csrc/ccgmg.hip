@@ -437,30 +437,31 @@ struct Driver {
     }
   }
 
-  // two consecutive plain SMO-1 sweeps in one launch (b = 0 stencil only;
-  // returns false, launching nothing, when the level has the cross term)
-  template <typename T>
-  bool sweep2(DevLevel& L, const T* u, const T* r, T* out) {
-    if (L.cross) return false;
-    const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
+  // two consecutive plain SMO-1 sweeps in one launch
+  template <typename T, bool CROSS, bool FIN>
+  void sweep2_t(DevLevel& L, const T* u, const T* r, T* out, int ty) {
     CoefT<T> c(L.coef);
     const dim3 g = tiles1d(L.nx, L.ny, nrhs, ty);
     const int nbx = tiles_x(L.nx);
     const uint8_t rb = jacbit();
-    const bool fin = &L == &X->lv[0];
     switch (ty) {
-      case 8:
-        if (fin) hipLaunchKernelGGL((k_sweep2<T, true, 8>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
-        else hipLaunchKernelGGL((k_sweep2<T, false, 8>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
-        break;
-      case 32:
-        if (fin) hipLaunchKernelGGL((k_sweep2<T, true, 32>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
-        else hipLaunchKernelGGL((k_sweep2<T, false, 32>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
-        break;
-      default:
-        if (fin) hipLaunchKernelGGL((k_sweep2<T, true, 16>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
-        else hipLaunchKernelGGL((k_sweep2<T, false, 16>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb);
-        break;
+      case 8: hipLaunchKernelGGL((k_sweep2<T, CROSS, FIN, 8>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb); break;
+      case 32: hipLaunchKernelGGL((k_sweep2<T, CROSS, FIN, 32>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb); break;
+      default: hipLaunchKernelGGL((k_sweep2<T, CROSS, FIN, 16>), g, dim3(BLOCK), 0, s, u, r, L.kind, out, L.nx, L.ny, nbx, c, rb); break;
+    }
+  }
+
+  // returns true: it always applies (a caller may fall back to two sweeps)
+  template <typename T>
+  bool sweep2(DevLevel& L, const T* u, const T* r, T* out) {
+    const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
+    const bool fin = &L == &X->lv[0];
+    if (L.cross) {
+      if (fin) sweep2_t<T, true, true>(L, u, r, out, ty);
+      else sweep2_t<T, true, false>(L, u, r, out, ty);
+    } else {
+      if (fin) sweep2_t<T, false, true>(L, u, r, out, ty);
+      else sweep2_t<T, false, false>(L, u, r, out, ty);
     }
     return true;
   }
@@ -2789,9 +2790,7 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
         case 7:
           Dr.fused_step<double>(L, L.u, L.r, L.v, nullptr);
           break;
-        case 8:
-          if (!Dr.sweep2<double>(L, L.u, L.r, L.v)) throw ccg::Error(CCGMG_EINVAL, "no two-sweep kernel with b != 0");
-          break;
+        case 8: Dr.sweep2<double>(L, L.u, L.r, L.v); break;
         case 6:
           hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(8192, (L.n + 255) / 256)), dim3(256), 0, X->stream, L.v,
                              L.u, L.n);

@@ -186,22 +186,32 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const T* __restrict__ u, const 
                             nbx, c, regbit, 0);
 }
 
-// Two SMO-1 sweeps in one launch (b = 0 stencil): two consecutive plain
-// sweeps (no SMO-2 between them, so the block rows keep their values) by
-// temporal blocking.  A workgroup stages u on its tile plus a halo of 4,
-// sweeps the tile plus a halo of 2 into a second LDS tile, then sweeps its
-// tile from that into out: the same operations per cell as two k_sweep
-// launches, but u', the intermediate iterate, never leaves LDS (25 instead
-// of 50 bytes per cell for the pair, one launch instead of two).
-template <typename T, bool FINEST, int TYS>
+// Two SMO-1 sweeps in one launch: two consecutive plain sweeps (no SMO-2
+// between them, so the block rows keep their values) by temporal blocking.
+// A workgroup stages u on its tile plus a halo of 4, sweeps the tile plus a
+// halo of 2 into a second LDS tile, then sweeps its tile from that into
+// out: the same operations per cell as two k_sweep launches, but u', the
+// intermediate iterate, never leaves LDS (25 instead of 50 bytes per cell
+// for the pair, one launch instead of two).  With the cross-derivative term
+// (CROSS) each sweep first forms the y-differences of its input in LDS (as
+// sweep_tile does), the second sweep's in the first one's space.
+template <typename T, int TYS, bool CROSS>
+constexpr int sweep2_lds_doubles() {
+  constexpr int W0 = TX + 4 * HALO, R0 = TYS + 4 * HALO, R1 = TYS + 2 * HALO;
+  return ((R0 * W0 + R1 * LW + (CROSS ? R1 * W0 : 0)) * (int)sizeof(T) + 7) / 8;
+}
+
+template <typename T, bool CROSS, bool FINEST, int TYS>
 __global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const T* __restrict__ r,
                                                   const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
                                                   int ny, int nbx, CoefT<T> c, uint8_t regbit) {
   constexpr int H2 = 2 * HALO;
   constexpr int W0 = TX + 2 * H2, R0 = TYS + 2 * H2;    // u on the tile plus 4
   constexpr int R1 = TYS + 2 * HALO;                    // u' on the tile plus 2 (LW columns)
-  __shared__ T t0[R0][W0];
-  __shared__ T t1[R1][LW];
+  __shared__ double smem[sweep2_lds_doubles<T, TYS, CROSS>()];
+  T (*t0)[W0] = reinterpret_cast<T (*)[W0]>(smem);
+  T (*t1)[LW] = reinterpret_cast<T (*)[LW]>(smem + (R0 * W0 * (int)sizeof(T) + 7) / 8);
+  T (*dy)[W0] = reinterpret_cast<T (*)[W0]>(smem + ((R0 * W0 + R1 * LW) * (int)sizeof(T) + 7) / 8);
   const size_t zoff = (size_t)blockIdx.z * nx * ny;
   u += zoff, r += zoff, out += zoff;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -244,6 +254,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const
     k1[i] = in ? kb : (uint8_t)0;
   }
   __syncthreads();
+  if (CROSS) {
+    // y-differences of u on the first sweep's rows, every staged column
+    for (int k = threadIdx.x; k < R1 * W0; k += BLOCK) {
+      const int y = k / W0, x = k - y * W0;
+      dy[y][x] = (T)8 * (t0[y + HALO + 1][x] - t0[y + HALO - 1][x]) - (t0[y + HALO + 2][x] - t0[y + HALO - 2][x]);
+    }
+    __syncthreads();
+  }
   // first sweep: u' on the tile plus 2 (0 outside the grid, never read by a
   // regular cell)
 #pragma unroll
@@ -251,25 +269,52 @@ __global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const
     const int k = (int)threadIdx.x + i * BLOCK;
     if (k < N1) {
       const int ly = k / LW, lx = k - ly * LW;
-      T v = t0[ly + HALO][lx + HALO];
+      const int cy = ly + HALO, cx = lx + HALO;   // in t0
+      T v = t0[cy][cx];
       if (k1[i] & regbit) {
-        const T d = r1[i] - regular_row<T, false>(
-                                [&](int dy, int dx) { return t0[ly + HALO + dy][lx + HALO + dx]; }, c);
+        T lu;
+        if (CROSS) {
+          const T* dr = dy[ly] + cx;
+          lu = regular_row_dy<T>(t0[cy][cx], t0[cy][cx + 1], t0[cy][cx - 1], t0[cy][cx + 2], t0[cy][cx - 2],
+                                 t0[cy + 1][cx], t0[cy - 1][cx], t0[cy + 2][cx], t0[cy - 2][cx],
+                                 [&](int dx) { return dr[dx]; }, c);
+        } else {
+          lu = regular_row<T, false>([&](int ddy, int ddx) { return t0[cy + ddy][cx + ddx]; }, c);
+        }
+        const T d = r1[i] - lu;
         v += c.omega_invD * d;
       }
       t1[ly][lx] = v;
     }
   }
   __syncthreads();
+  if (CROSS) {
+    // y-differences of u' on the tile rows (in the first ones' space)
+    for (int k = threadIdx.x; k < TYS * LW; k += BLOCK) {
+      const int y = k / LW, x = k - y * LW;
+      dy[y][x] = (T)8 * (t1[y + HALO + 1][x] - t1[y + HALO - 1][x]) - (t1[y + HALO + 2][x] - t1[y + HALO - 2][x]);
+    }
+    __syncthreads();
+  }
   // second sweep on the tile
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int ry = w + 4 * k;
     const int gx = bx + tx, gy = by + ry;
     if (gx < nx && gy < ny) {
-      T v = t1[ry + HALO][tx + HALO];
+      const int cy = ry + HALO, cx = tx + HALO;
+      T v = t1[cy][cx];
       if (kd[k] & regbit) {
-        const T d = rr[k] - apply_regular<T, false>(t1, ry + HALO, tx + HALO, c);
+        T lu;
+        if (CROSS) {
+          const T* dr = dy[ry] + cx;
+          lu = regular_row_dy<T>(t1[cy][cx], t1[cy][cx + 1], t1[cy][cx - 1], t1[cy][cx + 2], t1[cy][cx - 2],
+                                 t1[cy + 1][cx], t1[cy - 1][cx], t1[cy + 2][cx], t1[cy - 2][cx],
+                                 [&](int dx) { return dr[dx]; }, c);
+        } else {
+          lu = apply_regular<T, false>(t1, cy, cx, c);
+        }
+        const T d = rr[k] - lu;
         v += c.omega_invD * d;
       }
       out[(size_t)gy * nx + gx] = v;

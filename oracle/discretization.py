@@ -135,11 +135,19 @@ def regular_coefficients(a, b, c, h):
 class Discretization:
     """L and N of one grid level."""
 
-    def __init__(self, cg, a, b, c, w_min=0.5, cond_max=COND_MAX, need_plg_parity=True, eager=True):
+    def __init__(self, cg, a, b, c, w_min=0.5, cond_max=COND_MAX, need_plg_parity=True, eager=True,
+                 lattice_rule="min_norm"):
         """eager=False skips fitting the irregular rows; ``row(q)`` then fits
-        one on demand (large grids sampled cell by cell)."""
+        one on demand (large grids sampled cell by cell).  lattice_rule:
+        which acceptable lattice R-PLG keeps, "min_norm" (the smallest
+        W^-1-norm of the weights; the library's rule) or "min_cond" (the
+        smallest condition number of the cell sample matrix; a measured
+        alternative, not used by the library)."""
         if b * b - 4.0 * a * c >= 0.0:
             raise ValueError("operator is not elliptic")
+        if lattice_rule not in ("min_norm", "min_cond"):
+            raise ValueError("unknown lattice rule %r" % lattice_rule)
+        self.lattice_rule = lattice_rule
         self.cg = cg
         self.a, self.b, self.c = float(a), float(b), float(c)
         self.w_min = w_min
@@ -370,7 +378,7 @@ class Discretization:
             cond, beta, fkeys, w = self.fit(q, cells)
             if cond > self.cond_max or beta[cells.index(q)] > bound:
                 continue
-            nrm = float(np.sum(w * beta * beta))
+            nrm = float(np.sum(w * beta * beta)) if self.lattice_rule == "min_norm" else cond
             if best is None or nrm < best[0] * (1.0 - NORM_TIE):
                 best = (nrm, cells, cond, beta, fkeys)
         if best is None:

@@ -32,9 +32,9 @@ from .geometry import CutGrid, GeometryError
 
 
 class Level:
-    def __init__(self, grid, curves, a, b, c, theta=0.3):
+    def __init__(self, grid, curves, a, b, c, theta=0.3, lattice_rule="min_norm"):
         self.cg = CutGrid(grid, curves, theta=theta)
-        self.disc = Discretization(self.cg, a, b, c)
+        self.disc = Discretization(self.cg, a, b, c, lattice_rule=lattice_rule)
         d = self.disc
         self.nx, self.ny = d.nx, d.ny
         self.L, self.N = d.matrices()
@@ -163,9 +163,10 @@ def cyclic_bandwidth(level):
 class Hierarchy:
     """Grid levels 0..M (Section 4) with the bottom LU."""
 
-    def __init__(self, grid, curves, a, b, c, theta=0.3, coarsest_min_n=16, max_levels=20):
+    def __init__(self, grid, curves, a, b, c, theta=0.3, coarsest_min_n=16, max_levels=20, lattice_rule="min_norm"):
         self.a, self.b, self.c = a, b, c
-        self.levels = [Level(grid, curves, a, b, c, theta)]
+        self.lattice_rule = lattice_rule
+        self.levels = [Level(grid, curves, a, b, c, theta, lattice_rule)]
         g = dict(grid)
         while len(self.levels) < max_levels:
             nx, ny = g["nx"], g["ny"]
@@ -173,7 +174,7 @@ class Hierarchy:
                 break
             g = {"x0": g["x0"], "y0": g["y0"], "h": 2.0 * g["h"], "nx": nx // 2, "ny": ny // 2}
             try:
-                self.levels.append(Level(g, curves, a, b, c, theta))
+                self.levels.append(Level(g, curves, a, b, c, theta, lattice_rule))
             except (GeometryError, PLGError):
                 break
         self._factor_bottom()

@@ -59,6 +59,37 @@ def direct_reference(case, n):
     return f, g, ref, np.asarray(lv.nonempty, dtype=bool)
 
 
+def lattice_rule_p2n_error(rule, n):
+    """L-infinity error of Problem 2 (Neumann data on the ellipse) at n^2
+    with the given lattice rule of the oracle."""
+    import workloads as W
+    from oracle.discretization import boundary_data
+    from oracle.geometry import cell_averages
+    from oracle.multigrid import Level, direct_solve, rhs_vector
+    from oracle.norms import norms
+    cfg = W.problem2(n, hole_bc=W.NEUMANN)
+    lv = Level(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], lattice_rule=rule)
+    f = cell_averages(lv.cg, cfg["f"])
+    g = boundary_data(lv.disc, cfg["solution"])
+    u = direct_solve(lv, rhs_vector(lv, f, g))
+    return norms(u - cell_averages(lv.cg, cfg["solution"].u).ravel(), lv.cg.vol)[2]
+
+
+def lattice_rule_vcycle_history(rule, k, n, cycles):
+    """Relative residuals of the oracle's two-level V-cycles (zero start,
+    seeded random right-hand side) on workload k at n^2 with the given
+    lattice rule."""
+    import numpy as np
+    import workloads as W
+    from oracle.multigrid import Hierarchy
+    cfg = W.config(k, n=n)
+    H = Hierarchy(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], lattice_rule=rule, max_levels=2)
+    r = np.random.default_rng(5).standard_normal(n * n) * H.levels[0].nonempty
+    hist = []
+    H.solve(r, tol=1e-10, max_cycles=cycles, history=hist)
+    return hist
+
+
 def pool(workers=None):
     """A process pool of fresh interpreters, sized to the host's CPU share
     (at most 8 workers)."""

@@ -49,6 +49,37 @@ def test_problem2_neumann_fourth_order():
         assert 3.5 < np.log2(a / b) < 5.0
 
 
+@pytest.mark.slow
+def test_smallest_condition_lattice_pick_measured():
+    """The measured alternative to R-PLG's lattice pick (the paper gives no
+    algorithm, Section 2.2): keeping the acceptable lattice with the smallest
+    condition number instead of the smallest W^-1-norm.  On Problem 2 with
+    Neumann data on the ellipse (Table tab:errorsOfEllipseDN) its L-infinity
+    error at h = 1/128 is within 2x of the paper's and below the min-norm
+    pick's (3.6x the paper's there), but on the five-ellipse b = 1.2 workload
+    at 128^2 the oracle's two-level V-cycle with it does not converge (the
+    residual grows), which the min-norm pick avoids: the library keeps the
+    latter.  The divergence is grid-specific (the same workload at 64^2 and
+    96^2 converges with either pick); the test pins the grid where it shows."""
+    import oracle_jobs
+    gold = json.load(open(os.path.join(GOLDEN, "problem2_errors.json")))["neumann_ellipse"]
+    rules = ("min_norm", "min_cond")
+    with oracle_jobs.pool(4) as ex:
+        errs = ex.map(oracle_jobs.lattice_rule_p2n_error, rules, [128] * 2)
+        hists = ex.map(oracle_jobs.lattice_rule_vcycle_history, rules, [5] * 2, [128] * 2, [8] * 2)
+        li = dict(zip(rules, errs))
+        hist = dict(zip(rules, hists))
+    print("P2N h=1/128 Linf: min-norm %.3e, min-cond %.3e, paper %.3e" % (li["min_norm"], li["min_cond"],
+                                                                        gold["Linf"][1]))
+    assert li["min_cond"] < li["min_norm"]
+    assert gold["Linf"][1] / 2 < li["min_cond"] < 2 * gold["Linf"][1]
+    assert li["min_norm"] > 2 * gold["Linf"][1]
+    print("five ellipses 128^2, 2 levels: min-norm %s, min-cond %s" % (
+        " ".join("%.1e" % v for v in hist["min_norm"][-3:]), " ".join("%.1e" % v for v in hist["min_cond"][-3:])))
+    assert hist["min_norm"][-1] < hist["min_norm"][0]
+    assert not (hist["min_cond"][-1] < hist["min_cond"][0])
+
+
 def test_exact_recovery_of_quartic():
     """u in Pi_4 is reproduced to rounding (the discretization is exact on Pi_4)."""
     cfg = W.config(2, n=32)

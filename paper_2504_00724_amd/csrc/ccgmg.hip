@@ -451,9 +451,12 @@ struct Driver {
     }
   }
 
-  // returns true: it always applies (a caller may fall back to two sweeps)
+  // false (nothing launched) where it does not apply: the two-sweep kernel
+  // addresses a plane through 32-bit buffer offsets, which needs planes
+  // below 2^31 bytes; the caller then runs two sweeps
   template <typename T>
   bool sweep2(DevLevel& L, const T* u, const T* r, T* out) {
+    if ((uint64_t)L.nx * (uint64_t)L.ny * sizeof(T) >= (1ull << 31)) return false;
     const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
     const bool fin = &L == &X->lv[0];
     if (L.cross) {

@@ -99,6 +99,40 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return start + k;
 }
 
+// Raw buffer views of one array (gfx9 buffer descriptor: base address, size
+// in bytes, word 3 = 0x00020000, i.e. 32-bit data format, no swizzle).  The
+// hardware checks every access against the size: a load at a byte offset
+// outside [0, size) returns 0 and a store there is dropped.  Offsets are
+// 32-bit; callers keep arrays below 2^31 bytes and give a cell outside the
+// grid an offset of at least 2^31 (as unsigned), so it reads 0 and writes
+// nothing without a select or a branch.
+using bufrsrc = __amdgpu_buffer_rsrc_t;
+constexpr int BUF_OUT = (int)0x80000000u;   // an offset no array reaches
+__device__ __forceinline__ bufrsrc make_buf(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int bufu2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T buf_ld(bufrsrc r, int off);
+template <>
+__device__ __forceinline__ double buf_ld<double>(bufrsrc r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_ld<float>(bufrsrc r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ uint8_t buf_ld<uint8_t>(bufrsrc r, int off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(bufrsrc r, int off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bufu2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(bufrsrc r, int off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
 // x if keep, else +0.0, as a bit mask: a select between a loaded value and
 // a constant can be compiled into a branch around the load that waits for
 // it inside, which serializes the loads of a gather.

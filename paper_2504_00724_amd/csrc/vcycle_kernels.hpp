@@ -208,6 +208,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const
   constexpr int H2 = 2 * HALO;
   constexpr int W0 = TX + 2 * H2, R0 = TYS + 2 * H2;    // u on the tile plus 4
   constexpr int R1 = TYS + 2 * HALO;                    // u' on the tile plus 2 (LW columns)
+  constexpr int RPW = TYS / 4, M0 = R0 / 4, M1 = R1 / 4;
   __shared__ double smem[sweep2_lds_doubles<T, TYS, CROSS>()];
   T (*t0)[W0] = reinterpret_cast<T (*)[W0]>(smem);
   T (*t1)[LW] = reinterpret_cast<T (*)[LW]>(smem + (R0 * W0 * (int)sizeof(T) + 7) / 8);
@@ -217,94 +218,137 @@ __global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int tyi = t / nbx;
   const int bx = (t - tyi * nbx) * TX, by = tyi * TYS;
-  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
-  constexpr int RPW = TYS / 4;
-  // the second sweep's flags and right-hand side (this thread's tile cells)
-  uint8_t kd[RPW];
-  T rr[RPW];
+  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6, q = threadIdx.x;
+  const unsigned unx = nx, uny = ny;
+  // Work split: thread (w, tx) owns tile column tx (grid column gx) and the
+  // rows w, w + 4, ... of each region; the columns left and right of the
+  // tile's 64 are taken by threads q = 0, 1, ... in a pass of their own.
+  // Loads and stores go through buffer views of the plane (the launcher
+  // keeps planes below 2^31 bytes): an offset outside the plane reads 0 and
+  // writes nothing, so a cell outside the grid (a row above or below it, or
+  // the whole column when gx >= nx) stages value 0 and flags 0 with no select.
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const bufrsrc bu = make_buf(u, plane * (uint32_t)sizeof(T)), br = make_buf(r, plane * (uint32_t)sizeof(T)),
+                bk = make_buf(kind, plane), bo = make_buf(out, plane * (uint32_t)sizeof(T));
+  constexpr int SZ = (int)sizeof(T);
+  const int gx = bx + tx;
+  const bool xin = (unsigned)gx < unx;
+  // cell index of row gyy of this thread's column (BUF_OUT off the grid's
+  // columns; rows above the grid give negative, rows below it too large
+  // indices, both outside the plane)
+  auto col_idx = [&](int gyy) { return xin ? gyy * nx + gx : BUF_OUT; };
+  auto col_off = [&](int gyy) { return xin ? (gyy * nx + gx) * SZ : BUF_OUT; };
+  // index of cell (gyy, gxx), BUF_OUT outside the grid
+  auto cell_idx = [&](int gyy, int gxx) {
+    return (unsigned)gxx < unx && (unsigned)gyy < uny ? gyy * nx + gxx : BUF_OUT;
+  };
+  // (1) every load before the barrier.  u on t0: main columns, rows w + 4 i
+  T v0[M0];
+  {
+    const int o0 = col_off(by - H2 + w);
+#pragma unroll
+    for (int i = 0; i < M0; ++i) v0[i] = buf_ld<T>(bu, o0 + 4 * i * nx * SZ);
+  }
+  // u on t0: the 2 x H2 side columns (8 R0 entries)
+  constexpr int NS0 = 2 * H2 * R0, NIS0 = (NS0 + BLOCK - 1) / BLOCK;
+  T vs[NIS0];
+#pragma unroll
+  for (int i = 0; i < NIS0; ++i) {
+    const int qq = q + i * BLOCK, cc = qq & (2 * H2 - 1), ly = qq / (2 * H2);
+    const int lx = cc < H2 ? cc : TX + cc;
+    const int g = qq < NS0 ? cell_idx(by - H2 + ly, bx - H2 + lx) : BUF_OUT;
+    vs[i] = buf_ld<T>(bu, g == BUF_OUT ? BUF_OUT : g * SZ);
+  }
+  // flags and right-hand side of the first sweep's cells.  (A) the tile's
+  // own cells, rows w + 4 k (the same cell in the second sweep: one load
+  // serves both); (B) the two rows above and below the tile, wave w taking
+  // row {0, 1, R1 - 2, R1 - 1}[w]; (C) the 2 x HALO side columns, all R1
+  // rows (4 R1 entries)
+  uint8_t ka[RPW], kb1, kc1;
+  T ra[RPW], rb1, rc1;
+  const int ia = col_idx(by + w), oa = col_off(by + w);
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
-    const int gx = bx + tx, gy = by + w + 4 * k;
-    const bool in = gx < nx && gy < ny;
-    const size_t g = in ? (size_t)gy * nx + gx : 0;
-    kd[k] = in ? kind[g] : (uint8_t)0;
-    rr[k] = r[g];
+    ka[k] = buf_ld<uint8_t>(bk, ia + 4 * k * nx);
+    ra[k] = buf_ld<T>(br, oa + 4 * k * nx * SZ);
   }
-  stage_tile<T, R0, W0>(t0, [&](int ly, int lx) {
-    const int gx = bx + lx - H2, gy = by + ly - H2;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const T x = u[in ? (size_t)gy * nx + gx : 0];
-    return in ? x : (T)0;
-  });
-  // the first sweep's flags and right-hand side on the tile plus 2, loaded
-  // together in chunks before the barrier
-  constexpr int N1 = R1 * LW, NIT1 = (N1 + BLOCK - 1) / BLOCK;
-  uint8_t k1[NIT1];
-  T r1[NIT1];
+  const int lyb = w < 2 ? w : R1 - 4 + w;
+  kb1 = buf_ld<uint8_t>(bk, col_idx(by - HALO + lyb));
+  rb1 = buf_ld<T>(br, col_off(by - HALO + lyb));
+  constexpr int NC = 2 * HALO * R1;
+  const int cc1 = q & (2 * HALO - 1), lyc = q / (2 * HALO);
+  const int lxc = cc1 < HALO ? cc1 : TX + cc1;     // t1 column 0, 1, 66, 67
+  {
+    const int g = q < NC ? cell_idx(by - HALO + lyc, bx - HALO + lxc) : BUF_OUT;
+    kc1 = buf_ld<uint8_t>(bk, g);
+    rc1 = buf_ld<T>(br, g == BUF_OUT ? BUF_OUT : g * SZ);
+  }
 #pragma unroll
-  for (int i = 0; i < NIT1; ++i) {
-    const int k = (int)threadIdx.x + i * BLOCK;
-    const int kk = k < N1 ? k : 0;
-    const int ly = kk / LW, lx = kk - ly * LW;
-    const int gx = bx + lx - HALO, gy = by + ly - HALO;
-    const bool in = k < N1 && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const size_t g = in ? (size_t)gy * nx + gx : 0;
-    const uint8_t kb = kind[g];
-    r1[i] = r[g];
-    k1[i] = in ? kb : (uint8_t)0;
+  for (int i = 0; i < M0; ++i) t0[w + 4 * i][tx + H2] = v0[i];
+#pragma unroll
+  for (int i = 0; i < NIS0; ++i) {
+    const int qq = q + i * BLOCK, cc = qq & (2 * H2 - 1), ly = qq / (2 * H2);
+    if (qq < NS0) t0[ly][cc < H2 ? cc : TX + cc] = vs[i];
   }
   __syncthreads();
   if (CROSS) {
     // y-differences of u on the first sweep's rows, every staged column
-    for (int k = threadIdx.x; k < R1 * W0; k += BLOCK) {
-      const int y = k / W0, x = k - y * W0;
+    auto dyu = [&](int y, int x) {
       dy[y][x] = (T)8 * (t0[y + HALO + 1][x] - t0[y + HALO - 1][x]) - (t0[y + HALO + 2][x] - t0[y + HALO - 2][x]);
+    };
+#pragma unroll
+    for (int i = 0; i < M1; ++i) dyu(w + 4 * i, tx + H2);
+    for (int qq = q; qq < 2 * H2 * R1; qq += BLOCK) {
+      const int cc = qq & (2 * H2 - 1);
+      dyu(qq / (2 * H2), cc < H2 ? cc : TX + cc);
     }
     __syncthreads();
   }
-  // first sweep: u' on the tile plus 2 (0 outside the grid, never read by a
-  // regular cell)
-#pragma unroll
-  for (int i = 0; i < NIT1; ++i) {
-    const int k = (int)threadIdx.x + i * BLOCK;
-    if (k < N1) {
-      const int ly = k / LW, lx = k - ly * LW;
-      const int cy = ly + HALO, cx = lx + HALO;   // in t0
-      T v = t0[cy][cx];
-      if (k1[i] & regbit) {
-        T lu;
-        if (CROSS) {
-          const T* dr = dy[ly] + cx;
-          lu = regular_row_dy<T>(t0[cy][cx], t0[cy][cx + 1], t0[cy][cx - 1], t0[cy][cx + 2], t0[cy][cx - 2],
-                                 t0[cy + 1][cx], t0[cy - 1][cx], t0[cy + 2][cx], t0[cy - 2][cx],
-                                 [&](int dx) { return dr[dx]; }, c);
-        } else {
-          lu = regular_row<T, false>([&](int ddy, int ddx) { return t0[cy + ddy][cx + ddx]; }, c);
-        }
-        const T d = r1[i] - lu;
-        v += c.omega_invD * d;
+  // (2) first sweep: u' on the tile plus 2 (cells outside the grid copy
+  // their staged value; no regular cell reads it)
+  auto sweep1 = [&](int ly, int lx, uint8_t kf, T rv) {
+    const int cy = ly + HALO, cx = lx + HALO;   // in t0
+    T v = t0[cy][cx];
+    if (kf & regbit) {
+      T lu;
+      if (CROSS) {
+        const T* dr = dy[ly] + cx;
+        lu = regular_row_dy<T>(t0[cy][cx], t0[cy][cx + 1], t0[cy][cx - 1], t0[cy][cx + 2], t0[cy][cx - 2],
+                               t0[cy + 1][cx], t0[cy - 1][cx], t0[cy + 2][cx], t0[cy - 2][cx],
+                               [&](int dx) { return dr[dx]; }, c);
+      } else {
+        lu = regular_row<T, false>([&](int ddy, int ddx) { return t0[cy + ddy][cx + ddx]; }, c);
       }
-      t1[ly][lx] = v;
+      v += c.omega_invD * (rv - lu);
     }
-  }
+    t1[ly][lx] = v;
+  };
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) sweep1(HALO + w + 4 * k, tx + HALO, ka[k], ra[k]);
+  sweep1(lyb, tx + HALO, kb1, rb1);
+  if (q < NC) sweep1(lyc, lxc, kc1, rc1);
   __syncthreads();
   if (CROSS) {
     // y-differences of u' on the tile rows (in the first ones' space)
-    for (int k = threadIdx.x; k < TYS * LW; k += BLOCK) {
-      const int y = k / LW, x = k - y * LW;
+    auto dyu1 = [&](int y, int x) {
       dy[y][x] = (T)8 * (t1[y + HALO + 1][x] - t1[y + HALO - 1][x]) - (t1[y + HALO + 2][x] - t1[y + HALO - 2][x]);
+    };
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) dyu1(w + 4 * k, tx + HALO);
+    for (int qq = q; qq < 2 * HALO * TYS; qq += BLOCK) {
+      const int cc = qq & (2 * HALO - 1);
+      dyu1(qq / (2 * HALO), cc < HALO ? cc : TX + cc);
     }
     __syncthreads();
   }
-  // second sweep on the tile
+  // (3) second sweep on the tile (a store outside the grid is dropped)
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int ry = w + 4 * k;
-    const int gx = bx + tx, gy = by + ry;
-    if (gx < nx && gy < ny) {
+    {
       const int cy = ry + HALO, cx = tx + HALO;
       T v = t1[cy][cx];
-      if (kd[k] & regbit) {
+      if (ka[k] & regbit) {
         T lu;
         if (CROSS) {
           const T* dr = dy[ry] + cx;
@@ -314,10 +358,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const
         } else {
           lu = apply_regular<T, false>(t1, cy, cx, c);
         }
-        const T d = rr[k] - lu;
-        v += c.omega_invD * d;
+        v += c.omega_invD * (ra[k] - lu);
       }
-      out[(size_t)gy * nx + gx] = v;
+      buf_st(bo, oa + 4 * k * nx * SZ, v);
     }
   }
 }

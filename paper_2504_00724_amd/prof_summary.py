@@ -113,7 +113,7 @@ def cmd_cycle(args):
     if len(norms) < 3:
         raise SystemExit("fewer than two complete cycles in the last solve")
     i0, i1 = norms[-3], norms[-2]
-    level, lv_ns, lv_n, other = 0, collections.defaultdict(float), collections.defaultdict(int), []
+    level, lv_ns, lv_n, other, seq = 0, collections.defaultdict(float), collections.defaultdict(int), [], []
     for i in range(i0 + 1, i1 + 1):
         nm, d = names[i], en[i] - st[i]
         if is_correction_step(nm):
@@ -121,8 +121,10 @@ def cmd_cycle(args):
         if nm.startswith(("k_smooth_fused", "k_restrict", "k_sweep", "k_smo2", "k_prolong")):
             lv_ns[level] += d
             lv_n[level] += 1
+            seq.append((level, nm, d, st[i] - en[i - 1]))
         else:
             other.append((nm, d))
+            seq.append(("", nm, d, st[i] - en[i - 1]))
         if nm.startswith("k_restrict"):
             level += 1                      # descent
     span = (en[i1] - en[i0]) / 1e3
@@ -138,6 +140,11 @@ def cmd_cycle(args):
     for nm, d in other:
         print("| `%s` | 1 | %.1f | %.1f%% |" % (nm, d / 1e3, 100 * d / 1e3 / span))
     print("| between launches | | %.1f | %.1f%% |" % (span - busy, 100 * (span - busy) / span))
+    print("\nThe launches of that cycle in order (gap: from the previous launch's end to this one's start):\n")
+    print("| # | level | kernel | us | gap us |")
+    print("|---|---|---|---|---|")
+    for k, (lv, nm, d, gap) in enumerate(seq):
+        print("| %d | %s | `%s` | %.1f | %.1f |" % (k + 1, lv, nm, d / 1e3, gap / 1e3))
 
 
 def counter_means(path, counter):

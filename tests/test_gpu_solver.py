@@ -620,7 +620,7 @@ def test_solve_parity_every_tile_height(k, n, fused, ty):
     S.close()
 
 
-@pytest.mark.parametrize("k,n", [(4, 128), (5, 128), (2, 64)])
+@pytest.mark.parametrize("k,n", [(4, 128), (5, 128), (2, 64), (1, 72), (5, 96)])
 @pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("ty", [8, 16, 32])
 def test_two_sweep_launches_parity(k, n, fused, ty):
@@ -628,7 +628,9 @@ def test_two_sweep_launches_parity(k, n, fused, ty):
     coarse steps) has consecutive plain SMO-1 steps on every level; each
     such pair runs as one two-sweep launch (temporal blocking, every tile
     height; with b != 0 through the y-difference tiles).  The solve
-    converges to the oracle's direct solution."""
+    converges to the oracle's direct solution.  72^2 and 96^2 give ragged
+    tiles (grid sides not multiples of 64 or of the tile height) on every
+    level."""
     dev = _dev()
     cfg, lv = _level(k, n)
     f, g, ref = _reference(k, n)

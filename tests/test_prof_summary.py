@@ -63,7 +63,11 @@ def _split(tmp_path, capsys, pipe):
     a.path = str(path)
     P.cmd_cycle(a)
     out = capsys.readouterr().out
-    return {l.split("|")[1].strip(): l for l in out.splitlines() if l.startswith("| ")}
+    head, seq = out.split("The launches of that cycle in order")
+    rows = {l.split("|")[1].strip(): l for l in head.splitlines() if l.startswith("| ")}
+    rows["_seq"] = [[c.strip() for c in l.split("|")[1:-1]] for l in seq.splitlines() if l.startswith("| ") and
+                    not l.startswith("| #") and not l.startswith("|---")]
+    return rows
 
 
 def test_cycle_split_by_level(tmp_path, capsys):
@@ -85,6 +89,23 @@ def test_cycle_split_when_the_first_step_takes_the_norm(tmp_path, capsys):
         assert cells[2] == "5"
         assert abs(float(cells[3]) - (4 * (4 - m) + 0.5)) < 1e-9
     assert "`k_coarse<double>`" in rows and not any("k_resnorm" in k for k in rows)
+
+
+def test_cycle_launch_sequence(tmp_path, capsys):
+    """The per-launch table lists every launch of the cycle once, in order,
+    with the level the descent and ascent assign to it."""
+    rows = _split(tmp_path, capsys, True)
+    seq = rows["_seq"]
+    other = [k for k in rows if k.startswith("`")]                              # coarsest solve, copies
+    nlaunch = sum(int(rows[str(m)].split("|")[2]) for m in range(3)) + len(other)
+    assert len(seq) == nlaunch
+    assert [int(r[0]) for r in seq] == list(range(1, nlaunch + 1))
+    levels = [r[1] for r in seq]
+    assert levels[-1] == "0"
+    ic = [r[2] for r in seq].index("`k_coarse<double>`")
+    assert levels[ic] == ""
+    down = [v for v in levels[:ic] if v]
+    assert down == sorted(down, key=int)                                         # the descent only goes down
 
 
 def test_traffic_record_scaling(tmp_path, capsys):

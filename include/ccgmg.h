@@ -185,7 +185,9 @@ void ccgmg_default_options(ccgmg_options* opts);
  * least-squares weights (Section 3.3, eq. derivedCoefAgain) on every level,
  * the SMO-2 block data (Section 4.1, ordered by Alg. 3) and the inverse of
  * the coarsest operator; uploads everything to the current HIP device.
- * grid, curves, opts: host, read only.  *out receives the new context. */
+ * grid, curves, opts: host, read only.  *out receives the new context.
+ * CCGMG_EINVAL also for a grid of 2^28 cells or more (nx * ny * 8 bytes
+ * must stay below 2^31: the kernels address a plane with 32-bit offsets). */
 int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves, double a, double b,
                  double c, const ccgmg_options* opts, ccgmg_ctx** out);
 

@@ -141,6 +141,7 @@ struct DevLevel {
   double* du = nullptr;
   double* part = nullptr;         // reduction partials
   int sweep_ty[2] = {16, 16};     // SMO-1 tile height (FP64, FP32), tuned at set-up
+  int sweep2_ty[2] = {8, 8};      // the same for the two-sweep launch, tuned separately
   int npart_reg = 0, npart_irr = 0;
   // level 0: partials of a fused step that also takes the residual norm
   // (at most npart_fused per plane), and whether the SMO-1 cells and the
@@ -455,9 +456,13 @@ struct Driver {
   // addresses a plane through 32-bit buffer offsets, which needs planes
   // below 2^31 bytes; the caller then runs two sweeps
   template <typename T>
-  bool sweep2(DevLevel& L, const T* u, const T* r, T* out) {
-    if ((uint64_t)L.nx * (uint64_t)L.ny * sizeof(T) >= (1ull << 31)) return false;
-    const int ty = L.sweep_ty[sizeof(T) == 8 ? 0 : 1];
+  static bool sweep2_fits(const DevLevel& L) {
+    return (uint64_t)L.nx * (uint64_t)L.ny * sizeof(T) < (1ull << 31);
+  }
+  template <typename T>
+  bool sweep2(DevLevel& L, const T* u, const T* r, T* out, int ty = 0) {
+    if (!sweep2_fits<T>(L)) return false;
+    if (ty == 0) ty = L.sweep2_ty[sizeof(T) == 8 ? 0 : 1];
     const bool fin = &L == &X->lv[0];
     if (L.cross) {
       if (fin) sweep2_t<T, true, true>(L, u, r, out, ty);
@@ -964,9 +969,12 @@ void upload_coarsest(ccgmg_ctx* X) {
   X->coarse_cache[X->M] = {n, X->mcell, X->minv, X->mtinv, X->minv64, X->mtinv64};
 }
 
-// Tile-height autotuning of the SMO-1 sweep: on every level and in both
-// precisions, time each admissible tile height (HIP events, private stream,
-// work buffers of that level) and keep the fastest.
+// Tile-height autotuning of the SMO-1 sweep and of the two-sweep launch: on
+// every level and in both precisions, time each admissible tile height (HIP
+// events, private stream, work buffers of that level; best of two
+// interleaved rounds) and keep the lowest one within 3% of the fastest:
+// on small levels the candidates time alike within noise, and the lowest
+// height gives the most workgroups.
 void tune_tiles(ccgmg_ctx* X) {
   static const int cand[] = {8, 16, 32};
   Driver Dr{X, X->ws, 1, false};
@@ -979,13 +987,22 @@ void tune_tiles(ccgmg_ctx* X) {
     Dr.fill<double>(L.r, L.n, 0.5);
     Dr.fill<float>(L.u32, L.n, 1.0f);
     Dr.fill<float>(L.r32, L.n, 0.5f);
+    for (int kern = 0; kern < 2; ++kern)
     for (int prec = 0; prec < 2; ++prec) {
-      float best = 1e30f;
+      if (kern == 1 && !(prec == 0 ? Dr.sweep2_fits<double>(L) : Dr.sweep2_fits<float>(L))) continue;
+      float best[3] = {1e30f, 1e30f, 1e30f};
+      int* pick = kern == 0 ? &L.sweep_ty[prec] : &L.sweep2_ty[prec];
       for (int round = 0; round < 2; ++round)
-      for (int ty : cand) {
+      for (int ci = 0; ci < 3; ++ci) {
+        const int ty = cand[ci];
         auto launch = [&]() {
-          if (prec == 0) Dr.sweep<double>(L, L.u, L.r, L.v, ty);
-          else Dr.sweep<float>(L, L.u32, L.r32, L.v32, ty);
+          if (kern == 0) {
+            if (prec == 0) Dr.sweep<double>(L, L.u, L.r, L.v, ty);
+            else Dr.sweep<float>(L, L.u32, L.r32, L.v32, ty);
+          } else {
+            if (prec == 0) Dr.sweep2<double>(L, L.u, L.r, L.v, ty);
+            else Dr.sweep2<float>(L, L.u32, L.r32, L.v32, ty);
+          }
         };
         launch();
         launch();
@@ -995,8 +1012,11 @@ void tune_tiles(ccgmg_ctx* X) {
         HIP_OK(hipEventSynchronize(e1));
         float ms = 0;
         HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) best = ms, L.sweep_ty[prec] = ty;
+        best[ci] = std::min(best[ci], ms);
       }
+      const float fastest = std::min(best[0], std::min(best[1], best[2]));
+      for (int ci = 2; ci >= 0; --ci)
+        if (best[ci] <= 1.03f * fastest) *pick = cand[ci];
     }
   }
   (void)hipEventDestroy(e0);
@@ -1860,7 +1880,7 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
 // in that file (one "key<TAB>values" line per entry, read once, appended).
 // ---------------------------------------------------------------------------
 struct TuneEntry {
-  std::vector<int> ty64, ty32;
+  std::vector<int> ty64, ty32, ty2_64, ty2_32;   // SMO-1 and two-sweep tile heights per level
   int fused = 0, nu1 = 0, nu2 = 0, c1 = 0, c2 = 0, M = 0, every = 1;
 };
 std::mutex g_tune_mu;
@@ -1902,14 +1922,17 @@ void tune_cache_load_locked() {
       v.push_back((int)x);
       q = end;
     }
-    // values: nlev, ty64[nlev], ty32[nlev], fused, nu1, nu2, c1, c2, M, every
-    if (v.empty() || v[0] < 1 || (int)v.size() != 1 + 2 * v[0] + 7) continue;
+    // values: nlev, ty64[nlev], ty32[nlev], fused, nu1, nu2, c1, c2, M, every,
+    // ty2_64[nlev], ty2_32[nlev] (lines of another layout are skipped)
+    if (v.empty() || v[0] < 1 || (int)v.size() != 1 + 4 * v[0] + 7) continue;
     TuneEntry e;
     const int nl = v[0];
     e.ty64.assign(v.begin() + 1, v.begin() + 1 + nl);
     e.ty32.assign(v.begin() + 1 + nl, v.begin() + 1 + 2 * nl);
     const int* t = v.data() + 1 + 2 * nl;
     e.fused = t[0], e.nu1 = t[1], e.nu2 = t[2], e.c1 = t[3], e.c2 = t[4], e.M = t[5], e.every = t[6];
+    e.ty2_64.assign(v.begin() + 8 + 2 * nl, v.begin() + 8 + 3 * nl);
+    e.ty2_32.assign(v.begin() + 8 + 3 * nl, v.begin() + 8 + 4 * nl);
     g_tune[line] = e;
   }
   std::fclose(fp);
@@ -1936,6 +1959,8 @@ void tune_cache_put(const std::string& key, const TuneEntry& e) {
   for (int t : e.ty64) v += " " + std::to_string(t);
   for (int t : e.ty32) v += " " + std::to_string(t);
   for (int t : {e.fused, e.nu1, e.nu2, e.c1, e.c2, e.M, e.every}) v += " " + std::to_string(t);
+  for (int t : e.ty2_64) v += " " + std::to_string(t);
+  for (int t : e.ty2_32) v += " " + std::to_string(t);
   std::fprintf(fp, "%s\t%s\n", key.c_str(), v.c_str());
   std::fclose(fp);
 }
@@ -1947,6 +1972,9 @@ void create_host(ccgmg_ctx* X, const ccgmg_grid* grid, const ccgmg_curve* curves
                double c, const ccgmg_options* opts, int threads) {
   if (!grid || !curves || ncurves <= 0 || grid->nx <= 0 || grid->ny <= 0 || !(grid->h > 0))
     throw ccg::Error(CCGMG_EINVAL, "invalid grid or curves");
+  // the kernels address one plane of a level with 32-bit offsets
+  if ((uint64_t)grid->nx * (uint64_t)grid->ny * sizeof(double) >= (1ull << 31))
+    throw ccg::Error(CCGMG_EINVAL, "grid too large: a plane of FP64 cell values must stay below 2^31 bytes");
   if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
     throw ccg::Error(CCGMG_EINVAL, "non-finite coefficient");
   if (b * b - 4.0 * a * c >= 0.0) throw ccg::Error(CCGMG_ENOTELLIPTIC, "b^2 - 4ac >= 0");
@@ -2038,7 +2066,7 @@ void create_device(ccgmg_ctx* X) {
   if (X->opt.sweep_tile_rows) {
     const int ty = X->opt.sweep_tile_rows;
     if (ty != 8 && ty != 16 && ty != 32) throw ccg::Error(CCGMG_EINVAL, "sweep_tile_rows must be 0, 8, 16 or 32");
-    for (DevLevel& L : X->lv) L.sweep_ty[0] = L.sweep_ty[1] = ty;
+    for (DevLevel& L : X->lv) L.sweep_ty[0] = L.sweep_ty[1] = L.sweep2_ty[0] = L.sweep2_ty[1] = ty;
   }
   std::string key;
   TuneEntry cached;
@@ -2051,8 +2079,11 @@ void create_device(ccgmg_ctx* X) {
       return nu <= MAX_COARSE_UNKNOWNS;
     };
     if (tune_cache_get(key, cached) && cached.ty64.size() == X->lv.size() && cached.ty32.size() == X->lv.size() &&
-        fits(cached.M)) {
-      for (size_t m = 0; m < X->lv.size(); ++m) X->lv[m].sweep_ty[0] = cached.ty64[m], X->lv[m].sweep_ty[1] = cached.ty32[m];
+        cached.ty2_64.size() == X->lv.size() && cached.ty2_32.size() == X->lv.size() && fits(cached.M)) {
+      for (size_t m = 0; m < X->lv.size(); ++m) {
+        X->lv[m].sweep_ty[0] = cached.ty64[m], X->lv[m].sweep_ty[1] = cached.ty32[m];
+        X->lv[m].sweep2_ty[0] = cached.ty2_64[m], X->lv[m].sweep2_ty[1] = cached.ty2_32[m];
+      }
       X->opt.smoother_fused = cached.fused, X->opt.nu1 = cached.nu1, X->opt.nu2 = cached.nu2;
       X->opt.nu1_coarse = cached.c1, X->opt.nu2_coarse = cached.c2, X->opt.smo2_every_sweep = cached.every;
       X->M = cached.M;
@@ -2078,7 +2109,10 @@ void create_device(ccgmg_ctx* X) {
   }
   if (X->opt.tune_cache) {
     TuneEntry e;
-    for (const DevLevel& L : X->lv) e.ty64.push_back(L.sweep_ty[0]), e.ty32.push_back(L.sweep_ty[1]);
+    for (const DevLevel& L : X->lv) {
+      e.ty64.push_back(L.sweep_ty[0]), e.ty32.push_back(L.sweep_ty[1]);
+      e.ty2_64.push_back(L.sweep2_ty[0]), e.ty2_32.push_back(L.sweep2_ty[1]);
+    }
     e.fused = X->opt.smoother_fused, e.nu1 = X->opt.nu1, e.nu2 = X->opt.nu2;
     e.c1 = X->opt.nu1_coarse, e.c2 = X->opt.nu2_coarse, e.M = X->M, e.every = X->opt.smo2_every_sweep;
     tune_cache_put(key, e);

@@ -133,6 +133,39 @@ __device__ __forceinline__ void buf_st(bufrsrc r, int off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
 }
 
+// Stage the ROWS x (TX + 2 H) neighbourhood of a tile in LDS: rows
+// by - H .. by - H + ROWS - 1, columns bx - H .. bx + TX + H - 1 of the
+// nx x ny plane viewed by bu, 0 outside the grid (ROWS a multiple of 4).
+// Thread (w, tx) loads tile column tx in rows w, w + 4, ... (32-bit
+// offsets stepping by 4 rows; a column past nx reads from BUF_OUT), threads
+// q < 2 H ROWS load the side columns; every load is issued before the
+// first LDS write.
+template <typename T, int ROWS, int H>
+__device__ __forceinline__ void stage_cols(T (*tile)[TX + 2 * H], bufrsrc bu, int nx, int ny, int bx, int by) {
+  static_assert(ROWS % 4 == 0, "rows in steps of 4");
+  constexpr int SZ = (int)sizeof(T), M = ROWS / 4, NS = 2 * H * ROWS, NIS = (NS + BLOCK - 1) / BLOCK;
+  const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6, q = threadIdx.x;
+  const int gx = bx + tx;
+  const int o0 = (unsigned)gx < (unsigned)nx ? ((by - H + w) * nx + gx) * SZ : BUF_OUT;
+  T v[M], vs[NIS];
+#pragma unroll
+  for (int i = 0; i < M; ++i) v[i] = buf_ld<T>(bu, o0 + 4 * i * nx * SZ);
+#pragma unroll
+  for (int i = 0; i < NIS; ++i) {
+    const int qq = q + i * BLOCK, cc = qq & (2 * H - 1), ly = qq / (2 * H);
+    const int gxs = bx - H + (cc < H ? cc : TX + cc), gys = by - H + ly;
+    const bool in = qq < NS && (unsigned)gxs < (unsigned)nx && (unsigned)gys < (unsigned)ny;
+    vs[i] = buf_ld<T>(bu, in ? (gys * nx + gxs) * SZ : BUF_OUT);
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) tile[w + 4 * i][tx + H] = v[i];
+#pragma unroll
+  for (int i = 0; i < NIS; ++i) {
+    const int qq = q + i * BLOCK, cc = qq & (2 * H - 1), ly = qq / (2 * H);
+    if (qq < NS) tile[ly][cc < H ? cc : TX + cc] = vs[i];
+  }
+}
+
 // x if keep, else +0.0, as a bit mask: a select between a loaded value and
 // a constant can be compiled into a branch around the load that waits for
 // it inside, which serializes the loads of a gather.

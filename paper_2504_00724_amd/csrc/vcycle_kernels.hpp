@@ -57,15 +57,23 @@ __device__ __forceinline__ NormAcc sweep_tile(double* smem, int t, const T* __re
   // (cross-derivative stencil) RPW contiguous rows per wave, swept with a
   // register window
   auto row_of = [&](int k) { return CROSS ? w * RPW + k : w + 4 * k; };
+  // the plane through buffer views (planes stay below 2^31 bytes): a cell
+  // outside the grid reads flags 0 and value 0, and a store there (or to a
+  // cell left to the SMO-2 blocks, given offset BUF_OUT) is dropped
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const bufrsrc br = make_buf(r, plane * (uint32_t)sizeof(T)), bk = make_buf(kind, plane),
+                bo = make_buf(out, plane * (uint32_t)sizeof(T));
+  const int gx = bx + tx;
+  const int g0 = (unsigned)gx < (unsigned)nx ? by * nx + gx : BUF_OUT;   // this thread's column, tile row 0
+  auto gcell = [&](int k) { return g0 == BUF_OUT ? BUF_OUT : g0 + row_of(k) * nx; };
   // issue the kind and right-hand-side loads before the tile barrier
   uint8_t kd[RPW];
   T rr[RPW];
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
-    const int gx = bx + tx, gy = by + row_of(k);
-    const bool in = gx < nx && gy < ny;
-    kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
-    rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
+    const int g = gcell(k);
+    kd[k] = buf_ld<uint8_t>(bk, g);
+    rr[k] = buf_ld<T>(br, g == BUF_OUT ? BUF_OUT : g * (int)sizeof(T));
   }
   if (PRO) {
     // tile of u + P e: the pending coarse-grid correction (piecewise
@@ -106,7 +114,7 @@ __device__ __forceinline__ NormAcc sweep_tile(double* smem, int t, const T* __re
       }
     }
   } else {
-    load_tile<T, ROWS>(tile, u, nx, ny, bx, by);
+    stage_cols<T, ROWS, HALO>(tile, make_buf(u, plane * (uint32_t)sizeof(T)), nx, ny, bx, by);
   }
   __syncthreads();
   if (CROSS) {
@@ -138,20 +146,18 @@ __device__ __forceinline__ NormAcc sweep_tile(double* smem, int t, const T* __re
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
       const T c4 = tile[r0 + k + 4][tx + HALO];
-      const int gx = bx + tx, gy = by + r0 + k;
-      if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
-        T v = c2;
-        if (kd[k] & regbit) {
-          const T* row = tile[r0 + k + HALO] + tx + HALO;
-          const T* dyr = dyt[r0 + k] + tx + HALO;
-          const T d = rr[k] - regular_row_dy<T>(
-                                  c2, row[1], row[-1], row[2], row[-2], c3, c1, c4, c0,
-                                  [&](int dx) { return dyr[dx]; }, c);
-          if (NORM) m.add((double)d);
-          v += c.omega_invD * d;
-        }
-        out[(size_t)gy * nx + gx] = v;
+      const int g = gcell(k);
+      T v = c2;
+      if ((kd[k] & regbit) && !(kd[k] & skipbit)) {
+        const T* row = tile[r0 + k + HALO] + tx + HALO;
+        const T* dyr = dyt[r0 + k] + tx + HALO;
+        const T d = rr[k] - regular_row_dy<T>(
+                                c2, row[1], row[-1], row[2], row[-2], c3, c1, c4, c0,
+                                [&](int dx) { return dyr[dx]; }, c);
+        if (NORM) m.add((double)d);
+        v += c.omega_invD * d;
       }
+      buf_st(bo, (kd[k] & skipbit) || g == BUF_OUT ? BUF_OUT : g * (int)sizeof(T), v);
       c0 = c1, c1 = c2, c2 = c3, c3 = c4;
     }
     return m;
@@ -159,16 +165,14 @@ __device__ __forceinline__ NormAcc sweep_tile(double* smem, int t, const T* __re
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int ry = w + 4 * k;
-    const int gx = bx + tx, gy = by + ry;
-    if (gx < nx && gy < ny && !(kd[k] & skipbit)) {
-      T v = tile[ry + HALO][tx + HALO];
-      if (kd[k] & regbit) {
-        const T d = rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c);
-        if (NORM) m.add((double)d);
-        v += c.omega_invD * d;
-      }
-      out[(size_t)gy * nx + gx] = v;
+    const int g = gcell(k);
+    T v = tile[ry + HALO][tx + HALO];
+    if ((kd[k] & regbit) && !(kd[k] & skipbit)) {
+      const T d = rr[k] - apply_regular<T, CROSS>(tile, ry + HALO, tx + HALO, c);
+      if (NORM) m.add((double)d);
+      v += c.omega_invD * d;
     }
+    buf_st(bo, (kd[k] & skipbit) || g == BUF_OUT ? BUF_OUT : g * (int)sizeof(T), v);
   }
   return m;
 }
@@ -393,16 +397,21 @@ __device__ __forceinline__ void restrict_tile(int t, int l, const T* __restrict_
   const int tyi = t / nbx, txi = t - tyi * nbx;
   const int bx = txi * TX, by = tyi * TY;
   const int cx = threadIdx.x & 31, cy = threadIdx.x >> 5;  // 32 x 8 coarse cells
+  // fine cells through buffer views of the plane (cells outside the grid
+  // read value 0 and flags 0; planes stay below 2^31 bytes)
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const bufrsrc bu = make_buf(u, plane * (uint32_t)sizeof(T)), br = make_buf(r, plane * (uint32_t)sizeof(T)),
+                bk = make_buf(kind, plane);
   uint8_t kd[4];
   T rr[4];
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     const int gx = bx + 2 * cx + (d & 1), gy = by + 2 * cy + (d >> 1);
-    const bool in = gx < nx && gy < ny;
-    kd[d] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
-    rr[d] = in ? r[(size_t)gy * nx + gx] : (T)0;
+    const int g = (unsigned)gx < (unsigned)nx ? gy * nx + gx : BUF_OUT;   // gy >= 0; gy >= ny is outside the plane
+    kd[d] = buf_ld<uint8_t>(bk, g);
+    rr[d] = buf_ld<T>(br, g == BUF_OUT ? BUF_OUT : g * (int)sizeof(T));
   }
-  load_tile(tile, u, nx, ny, bx, by);
+  stage_cols<T, LH, HALO>(tile, bu, nx, ny, bx, by);
   __syncthreads();
   if (CROSS) {
     fill_dy<T, TY>(dyt, tile);

@@ -120,6 +120,18 @@ def test_error_codes(curves, abc, code):
     assert ei.value.code == code
 
 
+def test_grid_too_large_for_32_bit_plane_offsets():
+    """A grid of 2^28 cells (one FP64 plane = 2^31 bytes) is refused before
+    any set-up work: the kernels address a plane with 32-bit offsets."""
+    _lib_or_skip()
+    g = dict(W.grid(32))
+    g["nx"] = g["ny"] = 16384
+    g["h"] = 1.0 / 16384
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        ccgmg.Solver(g, [W.box()], 1.0, 0.0, 1.0, host_only=1)
+    assert ei.value.code == ccgmg.EINVAL and "2^31" in str(ei.value)
+
+
 def test_host_only_context_refuses_device_calls():
     """The library refuses device calls on a host-only context (called
     through ctypes directly: the binding itself refuses host arrays before

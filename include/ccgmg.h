@@ -355,8 +355,11 @@ int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out, int nrhs);
  * pass (FP64), 4 coarsest solve, 5 SMO-1 sweep (FP32), 6 plain FP64 copy of
  * the level's cell array (16 bytes per cell; calibrates byte counters),
  * 7 fused smoothing step (FP64, smoother_fused), 8 two consecutive plain
- * SMO-1 sweeps in one launch (FP64).  Leaves the work
- * buffers of that level undefined; no user buffer is touched. */
+ * SMO-1 sweeps in one launch (FP64), 9 the fused step that also applies a
+ * pending coarse-grid correction (FP64; needs a coarser level, whose work
+ * iterate serves as the correction).  Leaves the work buffers of that level
+ * (and for 9 the coarser level's iterate) undefined; no user buffer is
+ * touched. */
 int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double* avg_us);
 
 /* ---- Many geometries in one launch (batching) -------------------------

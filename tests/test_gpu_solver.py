@@ -646,6 +646,7 @@ def test_two_sweep_launches_parity(k, n, fused, ty):
     print("   cycles %d rel_res %.2e rel_err %.2e" % (rep["cycles"], rep["rel_res_inf"], err), flush=True)
     assert err <= 1e-10
     assert S.profile_kernel(8, 0, 2) > 0
+    assert S.profile_kernel(9, 0, 2) > 0          # the correction-applying fused step
     S.close()
 
 

@@ -694,8 +694,15 @@ __global__ __launch_bounds__(BLOCK) void k_smo2(T* u, const T* __restrict__ r, S
 // partials carry the residual norm of the incoming iterate.  With the
 // maximum goes the sum of squares: partial[2 q], partial[2 q + 1] for
 // q = z * gridDim.x + blockIdx.x.
+// Occupancy floor of the fused step's variants (waves per SIMD the
+// register allocation must allow): the norm-taking variant needs a few
+// registers more than the plain one and would drop from 7 to 6 waves (it
+// fits in 70 without spills).  The correction-applying one is left alone
+// (held at 6 waves it spills).
+constexpr int fused_min_waves(bool pro, bool norm) { return norm && !pro ? 7 : 1; }
+
 template <typename T, bool CROSS, bool FINEST, int TYS, bool PRO, bool NORM = false>
-__global__ __launch_bounds__(BLOCK) void k_smooth_fused(const T* __restrict__ u, const T* __restrict__ r,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(fused_min_waves(PRO, NORM)))) void k_smooth_fused(const T* __restrict__ u, const T* __restrict__ r,
                                                         const uint8_t* __restrict__ kind, T* __restrict__ out,
                                                         int nx, int ny, int nbx, int nblk, CoefT<T> c,
                                                         uint8_t regbit, uint8_t s2bit, Smo2Args a,

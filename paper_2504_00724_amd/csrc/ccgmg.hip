@@ -1469,6 +1469,8 @@ struct ccgmg_batch {
   // for all geometries
   bool lockstep = false;
   int nu = 4;
+  int every = 1;                    // SMO-2 in every every-th step counted back from the last
+  bool pair = false;                // consecutive plain steps as one two-sweep launch
   int* active_d = nullptr;          // per geometry: 1 while it still cycles
   int* active_h = nullptr;          // pinned copy
   double* part_d = nullptr;         // residual-norm partials of all geometries
@@ -1501,7 +1503,8 @@ namespace {
 // geometry taking part.
 // ---------------------------------------------------------------------------
 struct LRec {
-  int kind;                       // 0 fused, 1 restrict, 2 coarse, 3 coarse (many RHS), 4 norm, 5 aux
+  int kind;                       // 0 fused, 1 restrict, 2 coarse, 3 coarse (many RHS), 4 norm, 5 aux,
+                                  // 6 two plain sweeps
   bool pro = false;
   int mode = 0;                   // aux mode
   BStarts st{};
@@ -1560,6 +1563,12 @@ Smo2Args lock_smo2_args(DevLevel& L, int cur, const double* bterm) {
 
 constexpr int LOCK_TY = 16;   // SMO-1 tile height of batched fused steps
 
+// Whether step k (of nu, in a phase) of a lockstep batch has its SMO-2 part
+// (the same rule as a single solve's with_smo2).
+bool lock_smo2_step(const ccgmg_batch* B, int k) {
+  return B->every >= 1 ? (B->nu - 1 - k) % B->every == 0 : k == B->nu - 1;
+}
+
 // One V-cycle in precision T on level-0 arrays (u0, v0, r0, bterm0) of every
 // geometry; the result ends in u0 (an even number of steps per level).
 template <typename T>
@@ -1581,7 +1590,10 @@ void plan_vcycle(ccgmg_batch* B, Planner& P, const std::vector<void*>& u0, const
       rr[g][m] = m == 0 ? r0[g] : (const void*)lvbuf<T>(X->lv[m], 2);
     }
   }
-  auto fused = [&](int m, bool pro) {
+  // one step (blocks: with its SMO-2 part; a step without it writes the
+  // block rows unchanged, s2bit = 0) or, sweeps2, two plain steps in one
+  // two-sweep launch
+  auto fused = [&](int m, bool pro, bool blocks, bool sweeps2) {
     std::vector<BFused> ds;
     std::vector<int> wg;
     for (int g = 0; g < G; ++g) {
@@ -1592,8 +1604,8 @@ void plan_vcycle(ccgmg_batch* B, Planner& P, const std::vector<void*>& u0, const
       d.u = cur[g][m], d.r = rr[g][m], d.out = oth[g][m], d.kind = L.kind, d.c = L.coef;
       d.plane = L.n;
       d.nx = L.nx, d.ny = L.ny, d.nbx = tiles_x(L.nx), d.ntiles = d.nbx * ((L.ny + LOCK_TY - 1) / LOCK_TY);
-      d.nblk = L.fwd.smo2.nblk;
-      d.regbit = F_JAC, d.s2bit = F_S2, d.probit = F_REG;
+      d.nblk = blocks ? L.fwd.smo2.nblk : 0;
+      d.regbit = F_JAC, d.s2bit = blocks ? F_S2 : 0, d.probit = F_REG;
       d.geo = g;
       d.a = lock_smo2_args(L, cc[g][m], m == 0 ? bterm0[g] : nullptr);
       if (pro) {
@@ -1603,14 +1615,28 @@ void plan_vcycle(ccgmg_batch* B, Planner& P, const std::vector<void*>& u0, const
       ds.push_back(d);
       wg.push_back((d.nblk + d.ntiles) * planes[g]);
       std::swap(cur[g][m], oth[g][m]);
-      if (L.fwd.smo2.ns > 0) cc[g][m] ^= 1;
+      if (blocks && L.fwd.smo2.ns > 0) cc[g][m] ^= 1;
     }
     LRec rec{};
-    rec.kind = 0, rec.pro = pro;
+    rec.kind = sweeps2 ? 6 : 0, rec.pro = pro;
     P.add(rec, ds, wg);
   };
+  // the nu steps of one phase on level m (up: the first applies the
+  // coarse-grid correction and always has its SMO-2 part)
+  auto phase = [&](int m, bool up) {
+    for (int k = 0; k < B->nu; ++k) {
+      const bool pro = up && k == 0;
+      const bool blk = pro || lock_smo2_step(B, k);
+      if (!blk && B->pair && k + 1 < B->nu && !lock_smo2_step(B, k + 1)) {
+        fused(m, false, false, true);
+        ++k;
+      } else {
+        fused(m, pro, blk, false);
+      }
+    }
+  };
   for (int m = 0; m <= Mmax; ++m) {
-    for (int k = 0; k < B->nu; ++k) fused(m, false);
+    phase(m, false);
     std::vector<BRestrict> rs;
     std::vector<int> rw;
     std::vector<BCoarse> cs;
@@ -1654,8 +1680,7 @@ void plan_vcycle(ccgmg_batch* B, Planner& P, const std::vector<void*>& u0, const
     for (auto& d : cs) r2.smem = std::max(r2.smem, sizeof(double) * (size_t)d.nm);
     P.add(r2, cs, cw);
   }
-  for (int m = Mmax - 1; m >= 0; --m)
-    for (int k = 0; k < B->nu; ++k) fused(m, k == 0);
+  for (int m = Mmax - 1; m >= 0; --m) phase(m, true);
 }
 
 template <typename T, bool CROSS>
@@ -1674,6 +1699,9 @@ void launch_recs(ccgmg_batch* B, const std::vector<LRec>& recs, const char* dblo
         break;
       case 1:
         hipLaunchKernelGGL((k_restrict_batched<T, CROSS>), g, b, 0, s, (const BRestrict*)d, r.st, B->active_d);
+        break;
+      case 6:
+        hipLaunchKernelGGL((k_sweep2_batched<T, CROSS, LOCK_TY>), g, b, 0, s, (const BFused*)d, r.st, B->active_d);
         break;
       case 2:
         hipLaunchKernelGGL((k_coarse_batched<T>), g, b, r.smem, s, (const BCoarse*)d, r.st, B->active_d);
@@ -2598,6 +2626,21 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
       B->lockstep = true;
       const ccgmg_options& o0 = ctxs[0]->opt;
       B->nu = (o0.smoother_fused && o0.nu1 == o0.nu2 && o0.nu1 > 0) ? o0.nu1 : 4;
+      // the first context's SMO-2 schedule, where it keeps the cycle's
+      // bookkeeping simple: an even number of SMO-2 passes per level (the
+      // finest level's compact copy returns to where it started) and, for
+      // two-sweep launches, as many of them going down as coming up (the
+      // result returns to the first buffer); else SMO-2 in every step
+      B->every = o0.smo2_every_sweep;
+      int blk = 0, pd = 0, pu = 0;
+      for (int up = 0; up < 2; ++up)
+        for (int k = 0; k < B->nu; ++k) {
+          const bool b1 = (up && k == 0) || lock_smo2_step(B.get(), k);
+          blk += b1;
+          if (!b1 && k + 1 < B->nu && !lock_smo2_step(B.get(), k + 1)) ++(up ? pu : pd), ++k;
+        }
+      if (blk % 2) B->every = 1;
+      B->pair = B->every != 1 && pd == pu;
       for (int g = 0; g < n; ++g) {
         ccgmg_ctx* X = ctxs[g];
         if (X->opt.precision != o0.precision) throw ccg::Error(CCGMG_EINVAL, "lockstep batch needs one precision");

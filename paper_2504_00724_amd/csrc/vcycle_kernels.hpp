@@ -205,21 +205,19 @@ constexpr int sweep2_lds_doubles() {
   return ((R0 * W0 + R1 * LW + (CROSS ? R1 * W0 : 0)) * (int)sizeof(T) + 7) / 8;
 }
 
-template <typename T, bool CROSS, bool FINEST, int TYS>
-__global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const T* __restrict__ r,
-                                                  const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
-                                                  int ny, int nbx, CoefT<T> c, uint8_t regbit) {
+// One tile t of one plane (pointers already offset to the plane); smem
+// holds sweep2_lds_doubles<T, TYS, CROSS>() doubles.
+template <typename T, bool CROSS, int TYS>
+__device__ __forceinline__ void sweep2_tile(double* smem, int t, const T* __restrict__ u, const T* __restrict__ r,
+                                            const uint8_t* __restrict__ kind, T* __restrict__ out, int nx, int ny,
+                                            int nbx, const CoefT<T>& c, uint8_t regbit) {
   constexpr int H2 = 2 * HALO;
   constexpr int W0 = TX + 2 * H2, R0 = TYS + 2 * H2;    // u on the tile plus 4
   constexpr int R1 = TYS + 2 * HALO;                    // u' on the tile plus 2 (LW columns)
   constexpr int RPW = TYS / 4, M0 = R0 / 4, M1 = R1 / 4;
-  __shared__ double smem[sweep2_lds_doubles<T, TYS, CROSS>()];
   T (*t0)[W0] = reinterpret_cast<T (*)[W0]>(smem);
   T (*t1)[LW] = reinterpret_cast<T (*)[LW]>(smem + (R0 * W0 * (int)sizeof(T) + 7) / 8);
   T (*dy)[W0] = reinterpret_cast<T (*)[W0]>(smem + ((R0 * W0 + R1 * LW) * (int)sizeof(T) + 7) / 8);
-  const size_t zoff = (size_t)blockIdx.z * nx * ny;
-  u += zoff, r += zoff, out += zoff;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int tyi = t / nbx;
   const int bx = (t - tyi * nbx) * TX, by = tyi * TYS;
   const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6, q = threadIdx.x;
@@ -367,6 +365,16 @@ __global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const
       buf_st(bo, oa + 4 * k * nx * SZ, v);
     }
   }
+}
+
+template <typename T, bool CROSS, bool FINEST, int TYS>
+__global__ __launch_bounds__(BLOCK) void k_sweep2(const T* __restrict__ u, const T* __restrict__ r,
+                                                  const uint8_t* __restrict__ kind, T* __restrict__ out, int nx,
+                                                  int ny, int nbx, CoefT<T> c, uint8_t regbit) {
+  __shared__ double smem[sweep2_lds_doubles<T, TYS, CROSS>()];
+  const size_t zoff = (size_t)blockIdx.z * nx * ny;
+  sweep2_tile<T, CROSS, TYS>(smem, xcd_tile(blockIdx.x, gridDim.x), u + zoff, r + zoff, kind, out + zoff, nx, ny,
+                             nbx, c, regbit);
 }
 
 // Residual of the regular cells restricted to the coarse grid:
@@ -1239,6 +1247,22 @@ __global__ __launch_bounds__(BLOCK) void k_fused_batched(const BFused* __restric
     sweep_tile<T, CROSS, TYS, PRO>(smem, xcd_tile(l - d.nblk, d.ntiles), u, r, d.kind, out, d.nx, d.ny, d.nbx, c,
                                    d.regbit, d.s2bit, e, d.ncx, d.probit);
   }
+}
+
+// Two plain SMO-1 sweeps of one geometry on one level per descriptor (the
+// fused step's descriptor, nblk = 0): sweep2_tile on tiles of TYS rows.
+template <typename T, bool CROSS, int TYS>
+__global__ __launch_bounds__(BLOCK) void k_sweep2_batched(const BFused* __restrict__ descs, BStarts st,
+                                                          const int* __restrict__ active) {
+  __shared__ double smem[sweep2_lds_doubles<T, TYS, CROSS>()];
+  const int di = bfind(st, blockIdx.x);
+  const BFused& d = descs[di];
+  if (!active[d.geo]) return;
+  const int local = blockIdx.x - st.start[di];
+  const int z = local / d.ntiles, l = local - z * d.ntiles;
+  const CoefT<T> c(d.c);
+  sweep2_tile<T, CROSS, TYS>(smem, xcd_tile(l, d.ntiles), (const T*)d.u + z * d.plane, (const T*)d.r + z * d.plane,
+                             d.kind, (T*)d.out + z * d.plane, d.nx, d.ny, d.nbx, c, d.regbit);
 }
 
 struct BRestrict {                 // residual + restriction of one geometry from one level

@@ -342,13 +342,16 @@ def test_tune_on_callers_problem_keeps_parity():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_lockstep_batch_matches_oracle(precision):
+@pytest.mark.parametrize("every", [0, 1, 3])
+def test_lockstep_batch_matches_oracle(precision, every):
     """Lockstep batch (one launch per V-cycle step for all geometries):
     geometries with different sizes, depths, coefficients (b = 0 and b != 0)
     and boundary conditions, one with 6 right-hand sides (coarsest solve by
     the many-RHS product), in FP64 and in mixed precision, each against the
     oracle's direct solve; converged geometries are masked while others
-    continue."""
+    continue.  every: the tuned schedule (0), or 4 + 4 fused steps with
+    SMO-2 in every step (1) or in every third (3: steps without it, and
+    pairs of them as two-sweep launches)."""
     from paper_2504_00724_amd.ccgmg import Batch
     dev = _dev()
     cases = [((1, 64), 1), ((2, 64), 6), ((4, 128), 1), ((5, 64), 2), ((1, 72), 1)]
@@ -357,7 +360,8 @@ def test_lockstep_batch_matches_oracle(precision):
         cfg, lv = _level(k, n)
         f = cell_averages(lv.cg, cfg["f"]).ravel()
         g = boundary_data(lv.disc, cfg["solution"])
-        S = _solver(cfg, tol=1e-12, max_cycles=200, max_nrhs=m, precision=precision)
+        sched = {} if every == 0 else dict(tune_schedule=0, smoother_fused=1, nu1=4, nu2=4, smo2_every_sweep=every)
+        S = _solver(cfg, tol=1e-12, max_cycles=200, max_nrhs=m, precision=precision, **sched)
         F = np.stack([f * (1 + 0.5 * z) for z in range(m)])
         S.set_boundary(torch.tensor(np.tile(g, (m, 1)), device=dev), m)
         refs.append([direct_solve(lv, rhs_vector(lv, F[z], g)) for z in range(m)])
@@ -365,7 +369,8 @@ def test_lockstep_batch_matches_oracle(precision):
         fs.append(torch.tensor(F, device=dev))
         us.append(torch.zeros(m, n * n, dtype=torch.float64, device=dev))
         nr.append(m)
-    print("lockstep batch of %d geometries, precision %d" % (len(cases), precision), flush=True)
+    print("lockstep batch of %d geometries, precision %d, SMO-2 schedule %d" % (len(cases), precision, every),
+          flush=True)
     B = Batch(solvers, nbranches=0)
     reps = B.solve(fs, us, nr)
     torch.cuda.synchronize()

@@ -357,9 +357,11 @@ int ccgmg_apply_NT(ccgmg_ctx* ctx, const double* lambda, double* out, int nrhs);
  * 7 fused smoothing step (FP64, smoother_fused), 8 two consecutive plain
  * SMO-1 sweeps in one launch (FP64), 9 the fused step that also applies a
  * pending coarse-grid correction (FP64; needs a coarser level, whose work
- * iterate serves as the correction).  Leaves the work buffers of that level
- * (and for 9 the coarser level's iterate) undefined; no user buffer is
- * touched. */
+ * iterate serves as the correction), 10 and 11 the fused step that also
+ * writes the residual norm partials (level 0 only), into
+ * the solve's pinned host buffer (10, as solves do) or into device memory
+ * (11).  Leaves the work buffers of that level (and for 9 the coarser
+ * level's iterate) undefined; no user buffer is touched. */
 int ccgmg_profile_kernel(ccgmg_ctx* ctx, int kernel, int level, int reps, double* avg_us);
 
 /* ---- Many geometries in one launch (batching) -------------------------

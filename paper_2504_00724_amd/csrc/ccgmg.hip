@@ -2846,7 +2846,7 @@ int ccgmg_apply_NT(ccgmg_ctx* X, const double* lam, double* out, int nrhs) {
 
 int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* avg_us) {
   return guard(X, [&]() {
-    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 9)
+    if (!avg_us || reps < 1 || level < 0 || level > X->M || kernel < 0 || kernel > 11)
       throw ccg::Error(CCGMG_EINVAL, "bad profile arguments");
     Driver Dr{X, X->stream, 1, false};
     DevLevel& L = X->lv[level];
@@ -2858,6 +2858,8 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
     DevLevel* C = level < X->M ? &X->lv[level + 1] : nullptr;
     if ((kernel == 1 || kernel == 2 || kernel == 9) && !C) throw ccg::Error(CCGMG_EINVAL, "no coarser level");
     if (kernel == 9) Dr.fill<double>(C->u, C->n, 0.25);
+    if ((kernel == 10 || kernel == 11) && level != 0)
+      throw ccg::Error(CCGMG_EINVAL, "the norm-taking step is a fused step of level 0");
     if (kernel == 4 && level != X->M) throw ccg::Error(CCGMG_EINVAL, "coarsest solve only on the coarsest level");
     auto launch = [&]() {
       switch (kernel) {
@@ -2874,6 +2876,12 @@ int ccgmg_profile_kernel(ccgmg_ctx* X, int kernel, int level, int reps, double* 
         case 8: Dr.sweep2<double>(L, L.u, L.r, L.v); break;
         case 9:
           Dr.fused_step<double>(L, L.u, L.r, L.v, nullptr, C->u, C);
+          break;
+        case 10:
+          Dr.fused_step<double>(L, L.u, L.r, L.v, nullptr, nullptr, nullptr, X->norm_host);
+          break;
+        case 11:
+          Dr.fused_step<double>(L, L.u, L.r, L.v, nullptr, nullptr, nullptr, L.fpart);
           break;
         case 6:
           hipLaunchKernelGGL(k_copy, dim3(std::min<size_t>(8192, (L.n + 255) / 256)), dim3(256), 0, X->stream, L.v,

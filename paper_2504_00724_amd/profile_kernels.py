@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 KERNELS = {"sweep": 0, "restrict": 1, "prolong": 2, "smo2": 3, "sweep_f32": 5, "copy": 6, "fused": 7, "sweep2": 8,
-           "fused_pro": 9}
+           "fused_pro": 9, "fused_norm_host": 10, "fused_norm_dev": 11}
 
 
 def main():

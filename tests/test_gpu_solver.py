@@ -652,6 +652,8 @@ def test_two_sweep_launches_parity(k, n, fused, ty):
     assert err <= 1e-10
     assert S.profile_kernel(8, 0, 2) > 0
     assert S.profile_kernel(9, 0, 2) > 0          # the correction-applying fused step
+    if fused:
+        assert S.profile_kernel(10, 0, 2) > 0 and S.profile_kernel(11, 0, 2) > 0   # the norm-taking step
     S.close()
 
 

@@ -809,16 +809,23 @@ __device__ __forceinline__ NormAcc resnorm_block(int l, int nrb, int ntiles, con
     const int tyi = t / nbx;
     const int bx = (t - tyi * nbx) * TX, by = tyi * TY;
     const int tx = threadIdx.x & (TX - 1), w = threadIdx.x >> 6;
+    // the plane through buffer views (planes stay below 2^31 bytes): cells
+    // outside the grid read flags 0 and value 0, stores there are dropped
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const bufrsrc bk = make_buf(kind, plane), br = make_buf(r, plane * (uint32_t)sizeof(T)),
+                  bro = make_buf(res_out, plane * (uint32_t)sizeof(float));
+    const int gx = bx + tx;
+    const int g0 = (unsigned)gx < (unsigned)nx ? by * nx + gx : BUF_OUT;
+    auto gcell = [&](int k) { return g0 == BUF_OUT ? BUF_OUT : g0 + (w + 4 * k) * nx; };
     uint8_t kd[TY / 4];
     T rr[TY / 4];
 #pragma unroll
     for (int k = 0; k < TY / 4; ++k) {
-      const int gx = bx + tx, gy = by + w + 4 * k;
-      const bool in = gx < nx && gy < ny;
-      kd[k] = in ? kind[(size_t)gy * nx + gx] : (uint8_t)0;
-      rr[k] = in ? r[(size_t)gy * nx + gx] : (T)0;
+      const int g = gcell(k);
+      kd[k] = buf_ld<uint8_t>(bk, g);
+      rr[k] = buf_ld<T>(br, g == BUF_OUT ? BUF_OUT : g * (int)sizeof(T));
     }
-    load_tile(tile, u, nx, ny, bx, by);
+    stage_cols<T, LH, HALO>(tile, make_buf(u, plane * (uint32_t)sizeof(T)), nx, ny, bx, by);
     __syncthreads();
     if (CROSS && !zero_u) {
       fill_dy<T, TY>(dyt, tile);
@@ -826,16 +833,19 @@ __device__ __forceinline__ NormAcc resnorm_block(int l, int nrb, int ntiles, con
     }
 #pragma unroll
     for (int k = 0; k < TY / 4; ++k) {
-      const int gx = bx + tx, gy = by + w + 4 * k;
+      const int g = gcell(k);
+      T v = rr[k];
       if (kd[k] & regbit) {
-        T v = rr[k];
         if (!zero_u)
           v -= CROSS ? apply_regular_dy<T>(tile, dyt, w + 4 * k + HALO, tx + HALO, c)
                      : apply_regular<T, false>(tile, w + 4 * k + HALO, tx + HALO, c);
         m.add((double)v);
-        if (res_out) res_out[(size_t)gy * nx + gx] = (float)v;
-      } else if (res_out && gx < nx && gy < ny && !(kd[k] & F_NONEMPTY)) {
-        res_out[(size_t)gy * nx + gx] = 0.0f;   // explicit rows: written by the row workgroups
+      }
+      // the FP32 residual: regular cells and empty ones (0); the explicit
+      // rows are written by the row workgroups
+      if (res_out) {
+        const bool reg = kd[k] & regbit, wr = reg || !(kd[k] & F_NONEMPTY);
+        buf_st(bro, wr && g != BUF_OUT ? g * (int)sizeof(float) : BUF_OUT, reg ? (float)v : 0.0f);
       }
     }
   } else {

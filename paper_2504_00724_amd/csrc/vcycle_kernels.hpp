@@ -564,8 +564,11 @@ __device__ __forceinline__ NormAcc smo2_block(double* smem, int b, int z, const 
   const double* c_in = a.c_in + (size_t)z * a.ns;
   double* c_out = a.c_out + (size_t)z * a.ns;
   const int e0 = a.ext_ptr[b], ne = a.ext_ptr[b + 1] - e0, nown = a.own_cnt[b];
-  const int row = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int64_t ioff = a.inv_off[b] + row;
+  // grp (the wavefront) is uniform across a wavefront: taken through
+  // readfirstlane, the product's column offsets (grp + 4 k) * nown stay in
+  // scalar registers and only the row varies per lane
+  const int row = threadIdx.x & 63, grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t iblk = a.inv_off[b];   // the block's inverse (column-major, nown rows)
   // G lanes per overlapped row (4, 2 or 1: as many as the block's rows
   // leave), each summing a contiguous slice of the row's ELL entries in
   // rounds of 8 loads; the slices' sums are added by lane shuffles (every
@@ -634,20 +637,21 @@ __device__ __forceinline__ NormAcc smo2_block(double* smem, int b, int z, const 
   // the own rows' inverse (column-major) times the residual; the storage
   // precision is uniform per launch
   // (rounds of 8 loads; in the last round the columns past ne reload the
-  // first one and add +0, so the sum keeps its column order)
+  // first one and add +0, so the sum keeps its column order).  A is the
+  // block's inverse; entry (row, col) at col * nown + row.
   auto matvec = [&](const auto* A) {
     int c0 = grp;
     for (; c0 + 28 < ne; c0 += 32) {
       double v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = (double)A[(size_t)(c0 + 4 * k) * nown];
+      for (int k = 0; k < 8; ++k) v[k] = (double)A[(c0 + 4 * k) * nown + row];
 #pragma unroll
       for (int k = 0; k < 8; ++k) s += v[k] * res[c0 + 4 * k];
     }
     if (c0 < ne) {
       double v[7];
 #pragma unroll
-      for (int k = 0; k < 7; ++k) v[k] = (double)A[(size_t)(c0 + 4 * k < ne ? c0 + 4 * k : grp) * nown];
+      for (int k = 0; k < 7; ++k) v[k] = (double)A[(c0 + 4 * k < ne ? c0 + 4 * k : grp) * nown + row];
 #pragma unroll
       for (int k = 0; k < 7; ++k) {
         const bool in = c0 + 4 * k < ne;
@@ -657,9 +661,9 @@ __device__ __forceinline__ NormAcc smo2_block(double* smem, int b, int z, const 
   };
   if (row < nown) {
     if (a.inv64)
-      matvec(a.inv64 + ioff);
+      matvec(a.inv64 + iblk);
     else
-      matvec(a.inv + ioff);
+      matvec(a.inv + iblk);
   }
   part[grp][row] = s;
   __syncthreads();

@@ -525,7 +525,8 @@ def main():
         fp64_inv = {"value": nu / (m64 * 1e-3), "ms_per_step": m64, "cycles": r64[-1]["cycles"],
                     "rel_res_inf": r64[-1]["rel_res_inf"],
                     "device_ms_median": 1e3 * float(np.median([r["seconds"] for r in r64])),
-                    "schedule": {k: S64.info[k] for k in ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "smo2_every_sweep")}}
+                    "schedule": {k: S64.info[k] for k in ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "smo2_every_sweep",
+                                                                   "omega")}}
         S64.close()
         del u2
 
@@ -569,7 +570,8 @@ def main():
         fmg = {"value": nu / (mf * 1e-3), "ms_per_step": mf, "cycles": rf[-1]["cycles"],
                "rel_res_inf": rf[-1]["rel_res_inf"],
                "rel_diff_vs_fp64": float(np.max(np.abs(uf.cpu().numpy() - u64)[ne]) / np.max(np.abs(u64[ne]))),
-               "schedule": {k: Sf.info[k] for k in ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "smo2_every_sweep", "n_levels")}}
+               "schedule": {k: Sf.info[k] for k in ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "smo2_every_sweep", "n_levels",
+                                                     "omega")}}
         Sf.close()
 
     cpu = cpu_job.result() if cpu_job else None
@@ -593,7 +595,7 @@ def main():
                    "coarsest": info["nx_coarsest"], "nrhs": 1,
                    "schedule": {"smoother_fused": info["smoother_fused"], "nu1": info["nu1"], "nu2": info["nu2"],
                                 "nu1_coarse": info["nu1_coarse"], "nu2_coarse": info["nu2_coarse"],
-                                "smo2_every_sweep": info["smo2_every_sweep"]},
+                                "smo2_every_sweep": info["smo2_every_sweep"], "omega": info["omega"]},
                    "sweep_tile_rows": tiles,
                    # dense inverses are computed in FP64 and applied in FP64
                    # arithmetic; this is their storage (fp64_inverses below:

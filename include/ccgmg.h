@@ -130,7 +130,10 @@ typedef struct {
                             (1,6,6/3,3), (1,4,4/3,4), (1,4,4/2,5), and with SMO-2 in
                             every s-th step (1,5,5/2,5; s 2), (1,4,4/2,5; 3),
                             (1,6,6/3,4; 3), (1,5,5/3,3; 2), and keep the fastest;
-                            0: use the fields above                                      */
+                            then the SMO-1 weight omega in {0.5, 0.6, 0.7, 0.77,
+                            0.85} at that schedule and depth, and, if another weight
+                            wins, the schedules again at that weight;
+                            0: use the fields above (omega included)                     */
   int inverse_fp32;      /* storage of the dense inverses (SMO-2 blocks, coarsest level),
                             computed in FP64 and always applied in FP64 arithmetic:
                             1 (default) FP32, 0 FP64                                      */
@@ -164,6 +167,7 @@ typedef struct {
   int nu1, nu2;
   int nu1_coarse, nu2_coarse;
   int smo2_every_sweep;  /* SMO-2 frequency in use (see the option of that name)          */
+  double omega;          /* SMO-1 weight in use (after tuning)                            */
 } ccgmg_info;
 
 typedef struct {

@@ -60,7 +60,8 @@ class InfoT(C.Structure):
                 ("n_bdry_faces", C.c_long), ("n_levels", C.c_int), ("nx_coarsest", C.c_int),
                 ("ny_coarsest", C.c_int), ("coarse_unknowns", C.c_long), ("setup_seconds", C.c_double),
                 ("plg_max_cond", C.c_double), ("smoother_fused", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
-                ("nu1_coarse", C.c_int), ("nu2_coarse", C.c_int), ("smo2_every_sweep", C.c_int)]
+                ("nu1_coarse", C.c_int), ("nu2_coarse", C.c_int), ("smo2_every_sweep", C.c_int),
+                ("omega", C.c_double)]
 
 
 class ReportT(C.Structure):

@@ -1402,6 +1402,18 @@ double timed_solve(ccgmg_ctx* X, const double* f, double tol, int max_cycles, do
 // (set-up) the seeded random right-hand side is used and candidates are
 // ranked by the asymptotic-rate estimate; with the caller's f they are
 // ranked by the measured time of the solve itself.
+// The SMO-1 weight omega of every level (omega / D of the regular rows; the
+// graphs captured with the former value are dropped).
+void set_omega(ccgmg_ctx* X, double omega) {
+  X->opt.omega = omega;
+  for (DevLevel& L : X->lv) {
+    if (L.n == 0) continue;
+    const double h2 = L.h * L.h;
+    L.coef.omega_invD = omega / (-30.0 * (X->a + X->c) / (12.0 * h2));
+  }
+  X->clear_graphs();
+}
+
 void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
   struct Sched {
     int fused, nu1, nu2, c1, c2;   // c1, c2: coarse-level steps (0: as nu1, nu2)
@@ -1424,26 +1436,51 @@ void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
   int bestM = X->M;
   Sched bestS = {X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse,
                  X->opt.smo2_every_sweep};
-  for (const Sched& sc : cands) {
-    X->opt.smoother_fused = sc.fused, X->opt.nu1 = sc.nu1, X->opt.nu2 = sc.nu2;
-    X->opt.nu1_coarse = sc.c1, X->opt.nu2_coarse = sc.c2, X->opt.smo2_every_sweep = sc.every;
-    for (int Mc = Mmax; Mc >= 1; --Mc) {
-      long nu = 0;
-      for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
-      if (nu > MAX_COARSE_UNKNOWNS) break;
-      X->M = Mc;
-      upload_coarsest(X);
-      double sec = 0, score = 0;
-      timed_solve(X, f, 1e-10, 60, &sec, true);   // captures the graph
-      const double rate = timed_solve(X, f, 1e-10, 60, &sec, false, &score);
-      const double cost = f ? sec : score;
-      const bool ok = rate <= X->opt.depth_max_rate;
-      if (ok && (X->tune_ms[Mc] < 0 || 1e3 * cost < X->tune_ms[Mc])) X->tune_ms[Mc] = 1e3 * cost;
-      if (ok && cost < best) best = cost, bestM = Mc, bestS = sc;
+  // one timed solve of the current schedule at depth Mc (capture, then a
+  // timed replay); false if it does not converge fast enough
+  auto measure = [&](int Mc, double& cost) {
+    X->M = Mc;
+    upload_coarsest(X);
+    double sec = 0, score = 0;
+    timed_solve(X, f, 1e-10, 60, &sec, true);   // captures the graph
+    const double rate = timed_solve(X, f, 1e-10, 60, &sec, false, &score);
+    cost = f ? sec : score;
+    return rate <= X->opt.depth_max_rate;
+  };
+  auto search = [&]() {
+    for (const Sched& sc : cands) {
+      X->opt.smoother_fused = sc.fused, X->opt.nu1 = sc.nu1, X->opt.nu2 = sc.nu2;
+      X->opt.nu1_coarse = sc.c1, X->opt.nu2_coarse = sc.c2, X->opt.smo2_every_sweep = sc.every;
+      for (int Mc = Mmax; Mc >= 1; --Mc) {
+        long nu = 0;
+        for (uint8_t v : X->H.disc[Mc].nonempty) nu += v;
+        if (nu > MAX_COARSE_UNKNOWNS) break;
+        double cost = 0;
+        const bool ok = measure(Mc, cost);
+        if (ok && (X->tune_ms[Mc] < 0 || 1e3 * cost < X->tune_ms[Mc])) X->tune_ms[Mc] = 1e3 * cost;
+        if (ok && cost < best) best = cost, bestM = Mc, bestS = sc;
+      }
     }
+    X->opt.smoother_fused = bestS.fused, X->opt.nu1 = bestS.nu1, X->opt.nu2 = bestS.nu2;
+    X->opt.nu1_coarse = bestS.c1, X->opt.nu2_coarse = bestS.c2, X->opt.smo2_every_sweep = bestS.every;
+  };
+  search();
+  if (X->opt.tune_schedule) {
+    // the SMO-1 weight at the chosen schedule and depth (the paper's
+    // experiments use 0.5; for the fourth-order stencil a Fourier analysis
+    // of weighted Jacobi puts the best high-frequency damping near 0.77),
+    // then the schedules again at the chosen weight
+    const double om0 = X->opt.omega;
+    double bestOm = om0;
+    for (double om : {0.5, 0.6, 0.7, 0.77, 0.85}) {
+      if (om == om0) continue;
+      set_omega(X, om);
+      double cost = 0;
+      if (measure(bestM, cost) && cost < best) best = cost, bestOm = om;
+    }
+    set_omega(X, bestOm);
+    if (bestOm != om0) search();
   }
-  X->opt.smoother_fused = bestS.fused, X->opt.nu1 = bestS.nu1, X->opt.nu2 = bestS.nu2;
-  X->opt.nu1_coarse = bestS.c1, X->opt.nu2_coarse = bestS.c2, X->opt.smo2_every_sweep = bestS.every;
   X->M = bestM;
   upload_coarsest(X);
   X->clear_graphs();
@@ -1910,6 +1947,7 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
 struct TuneEntry {
   std::vector<int> ty64, ty32, ty2_64, ty2_32;   // SMO-1 and two-sweep tile heights per level
   int fused = 0, nu1 = 0, nu2 = 0, c1 = 0, c2 = 0, M = 0, every = 1;
+  int omega_milli = 500;                         // SMO-1 weight x 1000
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneEntry> g_tune;
@@ -1951,8 +1989,9 @@ void tune_cache_load_locked() {
       q = end;
     }
     // values: nlev, ty64[nlev], ty32[nlev], fused, nu1, nu2, c1, c2, M, every,
-    // ty2_64[nlev], ty2_32[nlev] (lines of another layout are skipped)
-    if (v.empty() || v[0] < 1 || (int)v.size() != 1 + 4 * v[0] + 7) continue;
+    // ty2_64[nlev], ty2_32[nlev], omega x 1000 (lines of another layout are
+    // skipped)
+    if (v.empty() || v[0] < 1 || (int)v.size() != 1 + 4 * v[0] + 8) continue;
     TuneEntry e;
     const int nl = v[0];
     e.ty64.assign(v.begin() + 1, v.begin() + 1 + nl);
@@ -1961,6 +2000,7 @@ void tune_cache_load_locked() {
     e.fused = t[0], e.nu1 = t[1], e.nu2 = t[2], e.c1 = t[3], e.c2 = t[4], e.M = t[5], e.every = t[6];
     e.ty2_64.assign(v.begin() + 8 + 2 * nl, v.begin() + 8 + 3 * nl);
     e.ty2_32.assign(v.begin() + 8 + 3 * nl, v.begin() + 8 + 4 * nl);
+    e.omega_milli = v[8 + 4 * nl];
     g_tune[line] = e;
   }
   std::fclose(fp);
@@ -1989,6 +2029,7 @@ void tune_cache_put(const std::string& key, const TuneEntry& e) {
   for (int t : {e.fused, e.nu1, e.nu2, e.c1, e.c2, e.M, e.every}) v += " " + std::to_string(t);
   for (int t : e.ty2_64) v += " " + std::to_string(t);
   for (int t : e.ty2_32) v += " " + std::to_string(t);
+  v += " " + std::to_string(e.omega_milli);
   std::fprintf(fp, "%s\t%s\n", key.c_str(), v.c_str());
   std::fclose(fp);
 }
@@ -2114,6 +2155,7 @@ void create_device(ccgmg_ctx* X) {
       }
       X->opt.smoother_fused = cached.fused, X->opt.nu1 = cached.nu1, X->opt.nu2 = cached.nu2;
       X->opt.nu1_coarse = cached.c1, X->opt.nu2_coarse = cached.c2, X->opt.smo2_every_sweep = cached.every;
+      set_omega(X, cached.omega_milli / 1000.0);
       X->M = cached.M;
       upload_coarsest(X);
       return;
@@ -2143,6 +2185,7 @@ void create_device(ccgmg_ctx* X) {
     }
     e.fused = X->opt.smoother_fused, e.nu1 = X->opt.nu1, e.nu2 = X->opt.nu2;
     e.c1 = X->opt.nu1_coarse, e.c2 = X->opt.nu2_coarse, e.M = X->M, e.every = X->opt.smo2_every_sweep;
+    e.omega_milli = (int)std::lround(1000.0 * X->opt.omega);
     tune_cache_put(key, e);
   }
 }
@@ -2339,6 +2382,7 @@ int ccgmg_query(const ccgmg_ctx* X, ccgmg_info* info) {
   info->nu1_coarse = X->opt.nu1_coarse > 0 ? X->opt.nu1_coarse : X->opt.nu1;
   info->nu2_coarse = X->opt.nu2_coarse > 0 ? X->opt.nu2_coarse : X->opt.nu2;
   info->smo2_every_sweep = X->opt.smo2_every_sweep;
+  info->omega = X->opt.omega;
   return CCGMG_OK;
 }
 

@@ -657,6 +657,32 @@ def test_two_sweep_launches_parity(k, n, fused, ty):
     S.close()
 
 
+@pytest.mark.parametrize("k,n", [(4, 128), (5, 128), (2, 64)])
+@pytest.mark.parametrize("omega", [0.6, 0.77, 0.85])
+def test_smo1_weight_parity(k, n, omega):
+    """SMO-1 weights other than the paper's 0.5 (the tuner's candidates,
+    here fixed with tune_schedule = 0; fused 4 + 4 / 2 + 5 steps with SMO-2
+    in every third, where the restriction also carries out the first coarse
+    sweep with omega / D): the converged solution is the oracle's direct
+    solution, and the context reports the weight it uses."""
+    dev = _dev()
+    cfg, lv = _level(k, n)
+    f, g, ref = _reference(k, n)
+    print("SMO-1 weight %.2f config %d n=%d" % (omega, k, n), flush=True)
+    S = _solver(cfg, tol=1e-12, max_cycles=300, tune_schedule=0, smoother_fused=1, nu1=4, nu2=4, nu1_coarse=2,
+                nu2_coarse=5, smo2_every_sweep=3, omega=omega)
+    assert S.info["omega"] == omega
+    fd = torch.tensor(f, device=dev)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    u = torch.zeros_like(fd)
+    rep = S.solve(fd, u)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    print("   cycles %d rel_res %.2e rel_err %.2e" % (rep["cycles"], rep["rel_res_inf"], err), flush=True)
+    assert err <= 1e-10
+    S.close()
+
+
 @pytest.fixture(scope="module")
 def large_refs():
     """Oracle direct solutions of the three-circle (b = 0) and five-ellipse
@@ -685,9 +711,10 @@ def test_solve_matches_oracle_elementwise_at_256_and_512(large_refs, k, n):
     torch.cuda.synchronize()
     got = u.cpu().numpy()
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
-    print("config %d n=%d: cycles %d rel_res %.2e rel_err %.2e tiles %s" % (
-        k, n, rep["cycles"], rep["rel_res_inf"], err, [S.tuning(m)[0] for m in range(S.info["n_levels"])]),
-        flush=True)
+    print("config %d n=%d: cycles %d rel_res %.2e rel_err %.2e tiles %s omega %.2f" % (
+        k, n, rep["cycles"], rep["rel_res_inf"], err, [S.tuning(m)[0] for m in range(S.info["n_levels"])],
+        S.info["omega"]), flush=True)
+    assert S.info["omega"] in (0.5, 0.6, 0.7, 0.77, 0.85)     # the tuner's SMO-1 weights
     assert err <= 1e-10
     assert np.all(got[~ne] == 0.0)
     S.close()

@@ -198,7 +198,7 @@ def run_batch(args):
     t0 = time.perf_counter()
     probs = [W.config(3, n=512)] + W.batch_geometries(args.batch_geometries)
     sched = {} if args.batch_tune else dict(tune_schedule=0, smoother_fused=1, nu1=4, nu2=4,
-                                            smo2_every_sweep=args.batch_smo2_every)
+                                            smo2_every_sweep=args.batch_smo2_every, omega=args.batch_omega)
     opts = [dict(tol=1e-10, max_cycles=200, hip_stream=stream, max_nrhs=(args.batch_rhs if i == 0 else 1),
                  precision=prec, **sched) for i in range(len(probs))]
     problems = [(c["grid"], c["curves"], c["a"], c["b"], c["c"]) for c in probs]
@@ -248,7 +248,8 @@ def run_batch(args):
                                % (args.batch_rhs, args.batch_geometries),
                    "unknowns_x_rhs": nu, "branches": args.batch_branches,
                    "schedule": "tuned per context" if args.batch_tune else
-                               "4 + 4 fused steps, SMO-2 in every %d. step" % args.batch_smo2_every,
+                               "4 + 4 fused steps, SMO-2 in every %d. step, SMO-1 weight %.2f"
+                               % (args.batch_smo2_every, args.batch_omega),
                    "precision": "FP32 V-cycles in FP64 refinement" if prec else "FP64"},
         "max_cycles": max(r["cycles"] for r in reps), "worst_rel_res": max(r["rel_res_inf"] for r in reps),
         "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms, "setup_s": setup_s,
@@ -395,6 +396,8 @@ def main():
     ap.add_argument("--batch-fp64", action="store_true")
     ap.add_argument("--batch-smo2-every", type=int, default=3,
                     help="batched workload: SMO-2 in every s-th of the 4 + 4 fused steps (1: every step)")
+    ap.add_argument("--batch-omega", type=float, default=0.7,
+                    help="batched workload: SMO-1 weight (the paper's experiments use 0.5)")
     ap.add_argument("--batch-setup", choices=["many", "one"], default="many",
                     help="many: ccgmg_create_many (concurrent host set-up); one: ccgmg_create per geometry")
     ap.add_argument("--batch-tune", type=int, default=0,

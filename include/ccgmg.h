@@ -131,7 +131,7 @@ typedef struct {
                             every s-th step (1,5,5/2,5; s 2), (1,4,4/2,5; 3),
                             (1,6,6/3,4; 3), (1,5,5/3,3; 2), and keep the fastest;
                             then the SMO-1 weight omega in {0.5, 0.6, 0.7, 0.77,
-                            0.85} at that schedule and depth, and, if another weight
+                            0.85, 0.92, 1.0} at that schedule and depth, and, if another weight
                             wins, the schedules again at that weight;
                             0: use the fields above (omega included)                     */
   int inverse_fp32;      /* storage of the dense inverses (SMO-2 blocks, coarsest level),

@@ -1467,12 +1467,14 @@ void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
   search();
   if (X->opt.tune_schedule) {
     // the SMO-1 weight at the chosen schedule and depth (the paper's
-    // experiments use 0.5; for the fourth-order stencil a Fourier analysis
-    // of weighted Jacobi puts the best high-frequency damping near 0.77),
-    // then the schedules again at the chosen weight
+    // experiments use 0.5; for the fourth-order stencil with b = 0 a Fourier
+    // analysis of weighted Jacobi puts the best high-frequency damping near
+    // 0.77, and above 2/2.13 = 0.94 the highest frequency grows, so such a
+    // weight fails the rate check there), then the schedules again at the
+    // chosen weight
     const double om0 = X->opt.omega;
     double bestOm = om0;
-    for (double om : {0.5, 0.6, 0.7, 0.77, 0.85}) {
+    for (double om : {0.5, 0.6, 0.7, 0.77, 0.85, 0.92, 1.0}) {
       if (om == om0) continue;
       set_omega(X, om);
       double cost = 0;

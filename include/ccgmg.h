@@ -130,7 +130,8 @@ typedef struct {
                             (1,6,6/3,3), (1,4,4/3,4), (1,4,4/2,5), and with SMO-2 in
                             every s-th step (1,5,5/2,5; s 2), (1,4,4/2,5; 3),
                             (1,6,6/3,4; 3), (1,5,5/3,3; 2), (1,3,3/2,3),
-                            (1,3,3/2,4; 3), (1,4,4/2,4; 3), and keep the fastest;
+                            (1,3,3/2,4; 3), (1,4,4/2,4; 3), (1,3,3/2,2), (1,2,3/2,3),
+                            (1,3,3/1,3), and keep the fastest;
                             then the SMO-1 weight omega in {0.5, 0.6, 0.7, 0.77,
                             0.85, 0.92, 1.0} at that schedule and depth, and, if another weight
                             wins, the schedules again at that weight;

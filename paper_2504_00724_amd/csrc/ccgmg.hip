@@ -1428,7 +1428,8 @@ void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
              // plain SMO-1 sweeps at the sweep's cost)
              {1, 5, 5, 2, 5, 2}, {1, 4, 4, 2, 5, 3}, {1, 6, 6, 3, 4, 3}, {1, 5, 5, 3, 3, 2},
              // lighter schedules (with a tuned SMO-1 weight fewer steps may do)
-             {1, 3, 3, 2, 3, 1}, {1, 3, 3, 2, 4, 3}, {1, 4, 4, 2, 4, 3}};
+             {1, 3, 3, 2, 3, 1}, {1, 3, 3, 2, 4, 3}, {1, 4, 4, 2, 4, 3}, {1, 3, 3, 2, 2, 1},
+             {1, 2, 3, 2, 3, 1}, {1, 3, 3, 1, 3, 1}};
   else
     cands = {{X->opt.smoother_fused, X->opt.nu1, X->opt.nu2, X->opt.nu1_coarse, X->opt.nu2_coarse,
               X->opt.smo2_every_sweep}};

@@ -192,8 +192,9 @@ void ccgmg_default_options(ccgmg_options* opts);
  * the SMO-2 block data (Section 4.1, ordered by Alg. 3) and the inverse of
  * the coarsest operator; uploads everything to the current HIP device.
  * grid, curves, opts: host, read only.  *out receives the new context.
- * CCGMG_EINVAL also for a grid of 2^28 cells or more (nx * ny * 8 bytes
- * must stay below 2^31: the kernels address a plane with 32-bit offsets). */
+ * CCGMG_EINVAL also for a grid with (ny + 64) * nx * 8 >= 2^31 bytes (about
+ * 2^28 cells: the kernels address a plane, its tile halos included, with
+ * signed 32-bit byte offsets). */
 int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves, double a, double b,
                  double c, const ccgmg_options* opts, ccgmg_ctx** out);
 

@@ -2046,9 +2046,11 @@ void create_host(ccgmg_ctx* X, const ccgmg_grid* grid, const ccgmg_curve* curves
                double c, const ccgmg_options* opts, int threads) {
   if (!grid || !curves || ncurves <= 0 || grid->nx <= 0 || grid->ny <= 0 || !(grid->h > 0))
     throw ccg::Error(CCGMG_EINVAL, "invalid grid or curves");
-  // the kernels address one plane of a level with 32-bit offsets
-  if ((uint64_t)grid->nx * (uint64_t)grid->ny * sizeof(double) >= (1ull << 31))
-    throw ccg::Error(CCGMG_EINVAL, "grid too large: a plane of FP64 cell values must stay below 2^31 bytes");
+  // the kernels address one plane of a level with signed 32-bit byte
+  // offsets, including rows up to 40 beyond the grid (tile halos): keep
+  // (ny + 64) * nx FP64 values below 2^31 bytes
+  if ((uint64_t)grid->nx * ((uint64_t)grid->ny + 64) * sizeof(double) >= (1ull << 31))
+    throw ccg::Error(CCGMG_EINVAL, "grid too large: (ny + 64) * nx FP64 cell values must stay below 2^31 bytes");
   if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
     throw ccg::Error(CCGMG_EINVAL, "non-finite coefficient");
   if (b * b - 4.0 * a * c >= 0.0) throw ccg::Error(CCGMG_ENOTELLIPTIC, "b^2 - 4ac >= 0");

@@ -121,15 +121,18 @@ def test_error_codes(curves, abc, code):
 
 
 def test_grid_too_large_for_32_bit_plane_offsets():
-    """A grid of 2^28 cells (one FP64 plane = 2^31 bytes) is refused before
-    any set-up work: the kernels address a plane with 32-bit offsets."""
+    """Grids whose FP64 plane, with 64 rows of tile halo, reaches 2^31 bytes
+    are refused before any set-up work (the kernels address a plane with
+    signed 32-bit byte offsets): 16384^2 (exactly 2^31 bytes without halo)
+    and 16383^2 (below 2^31 bytes, but not with the halo rows)."""
     _lib_or_skip()
-    g = dict(W.grid(32))
-    g["nx"] = g["ny"] = 16384
-    g["h"] = 1.0 / 16384
-    with pytest.raises(ccgmg.CcgmgError) as ei:
-        ccgmg.Solver(g, [W.box()], 1.0, 0.0, 1.0, host_only=1)
-    assert ei.value.code == ccgmg.EINVAL and "2^31" in str(ei.value)
+    for n in (16384, 16383):
+        g = dict(W.grid(32))
+        g["nx"] = g["ny"] = n
+        g["h"] = 1.0 / n
+        with pytest.raises(ccgmg.CcgmgError) as ei:
+            ccgmg.Solver(g, [W.box()], 1.0, 0.0, 1.0, host_only=1)
+        assert ei.value.code == ccgmg.EINVAL and "2^31" in str(ei.value)
 
 
 def test_host_only_context_refuses_device_calls():

@@ -197,7 +197,7 @@ def run_batch(args):
     from paper_2504_00724_amd.ccgmg import create_many
     t0 = time.perf_counter()
     probs = [W.config(3, n=512)] + W.batch_geometries(args.batch_geometries)
-    sched = {} if args.batch_tune else dict(tune_schedule=0, smoother_fused=1, nu1=4, nu2=4,
+    sched = {} if args.batch_tune else dict(tune_schedule=0, smoother_fused=1, nu1=args.batch_nu, nu2=args.batch_nu,
                                             smo2_every_sweep=args.batch_smo2_every, omega=args.batch_omega)
     opts = [dict(tol=1e-10, max_cycles=200, hip_stream=stream, max_nrhs=(args.batch_rhs if i == 0 else 1),
                  precision=prec, **sched) for i in range(len(probs))]
@@ -248,8 +248,8 @@ def run_batch(args):
                                % (args.batch_rhs, args.batch_geometries),
                    "unknowns_x_rhs": nu, "branches": args.batch_branches,
                    "schedule": "tuned per context" if args.batch_tune else
-                               "4 + 4 fused steps, SMO-2 in every %d. step, SMO-1 weight %.2f"
-                               % (args.batch_smo2_every, args.batch_omega),
+                               "%d + %d fused steps, SMO-2 in every %d. step, SMO-1 weight %.2f"
+                               % (args.batch_nu, args.batch_nu, args.batch_smo2_every, args.batch_omega),
                    "precision": "FP32 V-cycles in FP64 refinement" if prec else "FP64"},
         "max_cycles": max(r["cycles"] for r in reps), "worst_rel_res": max(r["rel_res_inf"] for r in reps),
         "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms, "setup_s": setup_s,
@@ -394,8 +394,10 @@ def main():
     ap.add_argument("--batch-geometries", type=int, default=32)
     ap.add_argument("--batch-branches", type=int, default=4)
     ap.add_argument("--batch-fp64", action="store_true")
+    ap.add_argument("--batch-nu", type=int, default=4,
+                    help="batched workload: fused smoothing steps before and after the coarse correction")
     ap.add_argument("--batch-smo2-every", type=int, default=3,
-                    help="batched workload: SMO-2 in every s-th of the 4 + 4 fused steps (1: every step)")
+                    help="batched workload: SMO-2 in every s-th of the fused steps (1: every step)")
     ap.add_argument("--batch-omega", type=float, default=0.7,
                     help="batched workload: SMO-1 weight (the paper's experiments use 0.5)")
     ap.add_argument("--batch-setup", choices=["many", "one"], default="many",

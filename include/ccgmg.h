@@ -88,7 +88,7 @@ typedef struct {
 typedef struct {
   double theta;          /* small-cell merge threshold (Alg. 1), default 0.3              */
   double w_min;          /* least-squares weight floor (eq. weightDef), default 0.5       */
-  double omega;          /* weighted-Jacobi factor of SMO-1, default 0.5                  */
+  double omega;          /* weighted-Jacobi factor of SMO-1, default 0.5; in (0, 2)      */
   int nu1, nu2;          /* pre/post smoothing steps, default 3, 3                        */
   int nu1_coarse, nu2_coarse; /* steps on the coarse levels when > 0 (default 0: nu1, nu2) */
   int coarsest_min_n;    /* smallest coarse grid side considered, default 16              */

@@ -2009,6 +2009,18 @@ void tune_cache_load_locked() {
     e.ty2_64.assign(v.begin() + 8 + 2 * nl, v.begin() + 8 + 3 * nl);
     e.ty2_32.assign(v.begin() + 8 + 3 * nl, v.begin() + 8 + 4 * nl);
     e.omega_milli = v[8 + 4 * nl];
+    // a line whose values the launches could not take (a tile height the
+    // kernels are not built for, a weight outside (0, 2), negative step
+    // counts) is skipped like one of another layout: set-up then tunes anew
+    auto tile_ok = [](const std::vector<int>& t) {
+      for (int x : t)
+        if (x != 8 && x != 16 && x != 32) return false;
+      return true;
+    };
+    if (!tile_ok(e.ty64) || !tile_ok(e.ty32) || !tile_ok(e.ty2_64) || !tile_ok(e.ty2_32) || e.fused < 0 ||
+        e.fused > 1 || e.nu1 < 0 || e.nu2 < 0 || e.c1 < 0 || e.c2 < 0 || e.every < 0 ||
+        e.M < 0 || e.omega_milli <= 0 || e.omega_milli >= 2000)
+      continue;
     g_tune[line] = e;
   }
   std::fclose(fp);
@@ -2063,6 +2075,10 @@ void create_host(ccgmg_ctx* X, const ccgmg_grid* grid, const ccgmg_curve* curves
     ccgmg_default_options(&X->opt);
   if (X->opt.max_nrhs < 1) X->opt.max_nrhs = 1;
   if (X->opt.smo2_block < 1 || X->opt.smo2_block > 64) throw ccg::Error(CCGMG_EINVAL, "smo2_block must be in 1..64");
+  // weighted Jacobi reduces no error at omega <= 0, and from omega = 2 on
+  // |1 - omega lambda/D| exceeds 1 at every mode with lambda/D > 1 (the
+  // highest frequencies of the stencil)
+  if (!(X->opt.omega > 0.0 && X->opt.omega < 2.0)) throw ccg::Error(CCGMG_EINVAL, "omega must be in (0, 2)");
   if (X->opt.nu1 < 0 || X->opt.nu2 < 0 || X->opt.smo2_iters < 1 || X->opt.smo2_overlap < 0 ||
       X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4 || X->opt.inverse_fp32 < 0 || X->opt.inverse_fp32 > 1 ||
       X->opt.cycle < 0 || X->opt.cycle > 1)

@@ -237,6 +237,72 @@ def test_tune_cache_reuses_the_measured_choices(tmp_path, monkeypatch):
     B.close()
 
 
+_CACHE_CHILD = r"""
+import sys
+import numpy as np
+import torch
+import workloads as W
+from paper_2504_00724_amd.ccgmg import Solver
+d, tag = sys.argv[1], sys.argv[2]
+print("tune cache child", tag, flush=True)
+cfg = W.config(1, n=128)
+S = Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], tol=1e-12, max_cycles=200, tune_cache=1)
+f = torch.tensor(np.load(d + "/f.npy"), device="cuda:0")
+u = torch.zeros_like(f)
+S.solve(f, u)
+torch.cuda.synchronize()
+np.save(d + "/u_%s.npy" % tag, u.cpu().numpy())
+print("RESULT", S.info["omega"], " ".join("%d,%d" % S.tuning(m) for m in range(S.info["n_levels"])), flush=True)
+S.close()
+"""
+
+
+def test_tune_cache_skips_lines_it_cannot_use(tmp_path):
+    """A CCGMG_TUNE_CACHE line whose values the launches cannot take (tile
+    heights other than 8, 16 and 32, an SMO-1 weight outside (0, 2)) is
+    skipped when the file is read: a fresh process given such a line for its
+    own key tunes anew, keeps valid tile heights and weight, and solves to the
+    oracle's direct solution.  The file is read once per process, so each
+    context is made in a process of its own."""
+    import os
+    import subprocess
+    import sys
+    _dev()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = tmp_path / "tune.txt"
+    cfg, lv = _level(1, 128)
+    f = np.random.default_rng(11).standard_normal(128 * 128) * lv.nonempty
+    np.save(tmp_path / "f.npy", f)
+    ref = direct_solve(lv, f)
+    env = dict(os.environ, CCGMG_TUNE_CACHE=str(path),
+               PYTHONPATH=os.pathsep.join([root, os.path.join(root, "tests")]))
+
+    def run(tag):
+        out = subprocess.run([sys.executable, "-c", _CACHE_CHILD, str(tmp_path), tag], env=env, cwd=root,
+                             capture_output=True, text=True, timeout=100)
+        print(out.stdout[-1500:], out.stderr[-1500:], flush=True)
+        assert out.returncode == 0
+        res = [ln for ln in out.stdout.splitlines() if ln.startswith("RESULT")][-1].split()
+        return float(res[1]), [tuple(int(t) for t in x.split(",")) for x in res[2:]]
+
+    run("a")
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    key, vals = lines[0].split("\t")
+    v = [int(x) for x in vals.split()]
+    nl = v[0]
+    assert len(v) == 1 + 4 * nl + 8
+    for i in list(range(1, 1 + 2 * nl)) + list(range(8 + 2 * nl, 8 + 4 * nl)):
+        v[i] = 7
+    v[-1] = 2500
+    path.write_text(key + "\t" + " ".join(str(x) for x in v) + "\n")
+    omega, tiles = run("b")
+    assert 0.0 < omega < 2.0
+    assert tiles and all(t in (8, 16, 32) for tt in tiles for t in tt)
+    u = np.load(tmp_path / "u_b.npy")
+    assert np.max(np.abs(u - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("every", [3, 2])
 def test_stopped_solve_returns_the_iterate_it_reported(every):
     """Schedules whose first finest-level step carries SMO-2 (smo2_every_sweep

@@ -120,6 +120,17 @@ def test_error_codes(curves, abc, code):
     assert ei.value.code == code
 
 
+@pytest.mark.parametrize("omega", [0.0, -0.5, 2.0, float("nan")])
+def test_smo1_weight_out_of_range_refused(omega):
+    """options.omega outside (0, 2) (weighted Jacobi then damps nothing or
+    amplifies every mode) is refused at creation with EINVAL."""
+    _lib_or_skip()
+    cfg = W.config(1, n=32)
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        ccgmg.Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], host_only=1, omega=omega)
+    assert ei.value.code == ccgmg.EINVAL and "omega" in str(ei.value)
+
+
 def test_grid_too_large_for_32_bit_plane_offsets():
     """Grids whose FP64 plane, with 64 rows of tile halo, reaches 2^31 bytes
     are refused before any set-up work (the kernels address a plane with

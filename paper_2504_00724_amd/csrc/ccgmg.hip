@@ -2083,6 +2083,15 @@ void create_host(ccgmg_ctx* X, const ccgmg_grid* grid, const ccgmg_curve* curves
       X->opt.smo2_widen < 0 || X->opt.smo2_widen > 4 || X->opt.inverse_fp32 < 0 || X->opt.inverse_fp32 > 1 ||
       X->opt.cycle < 0 || X->opt.cycle > 1)
     throw ccg::Error(CCGMG_EINVAL, "bad smoothing parameters");
+  // Alg. 1 merges interface cells of volume <= theta h^2, a fraction of a
+  // full cell; the weights of eq. weightDef are at least w_min, so the
+  // centre row of a least-squares problem keeps a positive weight
+  if (!(X->opt.theta >= 0.0 && X->opt.theta < 1.0)) throw ccg::Error(CCGMG_EINVAL, "theta must be in [0, 1)");
+  if (!(X->opt.w_min > 0.0 && std::isfinite(X->opt.w_min))) throw ccg::Error(CCGMG_EINVAL, "w_min must be positive");
+  if (X->opt.precision < 0 || X->opt.precision > 1 || X->opt.prolongation < 0 || X->opt.prolongation > 1 ||
+      X->opt.smoother_fused < 0 || X->opt.smoother_fused > 1 || X->opt.auto_depth < 0 || X->opt.auto_depth > 2 ||
+      X->opt.smo2_every_sweep < 0)
+    throw ccg::Error(CCGMG_EINVAL, "precision, prolongation, smoother_fused, auto_depth or smo2_every_sweep out of range");
   X->a = a, X->b = b, X->c = c;
   X->host_only = X->opt.host_only != 0;
   std::vector<ccg::Curve> cs(ncurves);

@@ -131,6 +131,19 @@ def test_smo1_weight_out_of_range_refused(omega):
     assert ei.value.code == ccgmg.EINVAL and "omega" in str(ei.value)
 
 
+@pytest.mark.parametrize("opt", [dict(theta=-0.1), dict(theta=1.0), dict(theta=float("nan")), dict(w_min=0.0),
+                                 dict(w_min=float("inf")), dict(precision=2), dict(prolongation=-1),
+                                 dict(smoother_fused=2), dict(auto_depth=3), dict(smo2_every_sweep=-1)])
+def test_options_out_of_range_refused(opt):
+    """Options outside their documented ranges are refused at creation with
+    EINVAL, before any set-up work."""
+    _lib_or_skip()
+    cfg = W.config(1, n=32)
+    with pytest.raises(ccgmg.CcgmgError) as ei:
+        ccgmg.Solver(cfg["grid"], cfg["curves"], cfg["a"], cfg["b"], cfg["c"], host_only=1, **opt)
+    assert ei.value.code == ccgmg.EINVAL
+
+
 def test_grid_too_large_for_32_bit_plane_offsets():
     """Grids whose FP64 plane, with 64 rows of tile halo, reaches 2^31 bytes
     are refused before any set-up work (the kernels address a plane with

@@ -1785,6 +1785,19 @@ int batch_guard(ccgmg_batch* B, const std::function<void()>& body) {
 }
 
 // Residual-norm partials of one geometry's plane in a lockstep batch.
+// Appends the SMO-1 weight of a context and, with schedule, its smoothing
+// schedule to a graph-cache key (batch graphs capture both; ccgmg_tune may
+// change them).
+void push_tuning_key(std::vector<const void*>& key, const ccgmg_ctx* X, bool schedule) {
+  uint64_t w;
+  std::memcpy(&w, &X->opt.omega, sizeof(w));
+  key.push_back((const void*)(uintptr_t)w);
+  if (!schedule) return;
+  const ccgmg_options& o = X->opt;
+  for (int v : {o.smoother_fused, o.nu1, o.nu2, o.nu1_coarse, o.nu2_coarse, o.smo2_every_sweep})
+    key.push_back((const void*)(intptr_t)v);
+}
+
 int lockstep_parts(ccgmg_ctx* X) {
   DevLevel& L0 = X->lv[0];
   return (L0.fwd.n + BLOCK - 1) / BLOCK + tiles_x(L0.nx) * ((L0.ny + TY - 1) / TY);
@@ -1815,14 +1828,17 @@ void lockstep_solve(ccgmg_batch* B, const double* const* f, double* const* u, co
   for (int g = 0; g < n; ++g)
     if (!mon[g].start(B->ctx[g], nrhs[g], nparts[g]))
       throw ccg::Error(CCGMG_EINVAL, "non-finite right-hand side or boundary data for geometry " + std::to_string(g));
-  // the captured cycle fixes the arrays, the right-hand-side counts and
-  // whether each geometry has a boundary term
+  // the captured cycle fixes the arrays, the right-hand-side counts,
+  // whether each geometry has a boundary term, and each geometry's depth and
+  // SMO-1 weight (ccgmg_tune may change both after a first batch solve)
   std::vector<const void*> key;
   for (int g = 0; g < n; ++g) {
     key.push_back(f[g]);
     key.push_back(u[g]);
     key.push_back((const void*)(intptr_t)nrhs[g]);
     key.push_back(bterm[g]);
+    key.push_back((const void*)(intptr_t)B->ctx[g]->M);
+    push_tuning_key(key, B->ctx[g], false);
   }
   hipGraphExec_t exec = nullptr;
   for (auto& gr : B->graphs)
@@ -2808,6 +2824,7 @@ int ccgmg_batch_solve(ccgmg_batch* B, const double* const* f, double* const* u, 
       key.push_back((const void*)(intptr_t)nrhs[g]);
       key.push_back((const void*)(intptr_t)(B->ctx[g]->opt.precision * 64 + B->ctx[g]->M));
       key.push_back(bterm[g]);
+      push_tuning_key(key, B->ctx[g], true);
     }
     hipGraphExec_t exec = nullptr;
     for (auto& gr : B->graphs)

@@ -341,6 +341,50 @@ def test_tune_on_callers_problem_keeps_parity():
     S.close()
 
 
+@pytest.mark.parametrize("nbranches,sched", [(4, {}),
+                                             (0, dict(tune_schedule=0, smoother_fused=1, nu1=4, nu2=4))])
+def test_batch_follows_a_retuned_context(nbranches, sched):
+    """A batch that has solved with a context before ccgmg_tune re-chose the
+    context's depth, SMO-1 weight or schedule captures a new cycle
+    afterwards: its solve then equals, bit for bit and in cycles, that of a
+    batch made after the tuning, and matches the oracle's direct solve.
+    Branch mode: all three may change.  Lockstep mode fixes its steps from
+    the first context's schedule when the batch is made, so there the
+    schedule is held (fused 4 + 4, not tuned) and the tuning re-chooses the
+    depth only."""
+    from paper_2504_00724_amd.ccgmg import Batch
+    dev = _dev()
+    cfg, lv = _level(2, 64)
+    f = cell_averages(lv.cg, cfg["f"]).ravel()
+    g = boundary_data(lv.disc, cfg["solution"])
+    ref = direct_solve(lv, rhs_vector(lv, f, g))
+    # untuned at creation: deepest level, omega 0.5, the default schedule
+    S = _solver(cfg, tol=1e-12, max_cycles=200, auto_depth=0, **sched)
+    fd = torch.tensor(f, device=dev)
+    S.set_boundary(torch.tensor(g, device=dev), 1)
+    keys = ("n_levels", "omega", "smoother_fused", "nu1", "nu2", "nu1_coarse", "nu2_coarse", "smo2_every_sweep")
+    B1 = Batch([S], nbranches=nbranches)
+    u0 = torch.zeros_like(fd)
+    r0 = B1.solve([fd], [u0], [1])[0]
+    before = {k: S.info[k] for k in keys}
+    S.tune(fd)
+    after = {k: S.info[k] for k in keys}
+    u1 = torch.zeros_like(fd)
+    r1 = B1.solve([fd], [u1], [1])[0]
+    B2 = Batch([S], nbranches=nbranches)
+    u2 = torch.zeros_like(fd)
+    r2 = B2.solve([fd], [u2], [1])[0]
+    torch.cuda.synchronize()
+    print("batch (%d branches) before tuning %s: %d cycles; after %s: old batch %d, new batch %d cycles" % (
+        nbranches, before, r0["cycles"], after, r1["cycles"], r2["cycles"]), flush=True)
+    assert r1["cycles"] == r2["cycles"] and torch.equal(u1, u2)
+    err = np.max(np.abs(u1.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-10
+    B1.close()
+    B2.close()
+    S.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("every", [0, 1, 3])
 def test_lockstep_batch_matches_oracle(precision, every):

@@ -407,8 +407,10 @@ int ccgmg_batch_create(ccgmg_ctx* const* ctxs, int n, int nbranches, ccgmg_batch
  * CCGMG_ENOCONV if any geometry did not reach its tolerance, CCGMG_EINVAL
  * for non-finite data (as ccgmg_solve).  The residual buffers are
  * allocated by ccgmg_batch_create; the first solve with a new set of arrays
- * (or a change of boundary data between none and some) records a new
- * graph, and in lockstep mode allocates its descriptor table. */
+ * (or a change of boundary data between none and some, or of a context's
+ * depth or SMO-1 weight -- with branches also its schedule -- by
+ * ccgmg_tune) records a new graph, and in lockstep mode allocates its
+ * descriptor table. */
 int ccgmg_batch_solve(ccgmg_batch* batch, const double* const* f, double* const* u, const int* nrhs,
                       ccgmg_report* reps);
 /* Error text of the batch's last failed call (owned by the batch). */
@@ -417,13 +419,14 @@ const char* ccgmg_batch_last_error(const ccgmg_batch* batch);
  * contexts stay the caller's. */
 void ccgmg_batch_destroy(ccgmg_batch* batch);
 
-/* Re-choose the smoothing schedule and the depth (as auto_depth 2 /
- * tune_schedule do at set-up) by timing solves of the caller's own problem:
- * f is one right-hand side (device, ny x nx) representative of the solves to
- * come, with the boundary data last given to ccgmg_set_boundary.  Each
- * candidate is solved from zero to 1e-10 twice (capture, timed replay) and
- * the fastest that converges is kept.  Not a paper construct (the paper
- * fixes its cycle parameters); a measured autotuner of this library. */
+/* Re-choose the smoothing schedule, the depth and (with tune_schedule) the
+ * SMO-1 weight, as auto_depth 2 / tune_schedule do at set-up, by timing
+ * solves of the caller's own problem: f is one right-hand side (device,
+ * ny x nx) representative of the solves to come, with the boundary data
+ * last given to ccgmg_set_boundary.  Each candidate is solved from zero to
+ * 1e-10 three times (capture, then two timed replays, the faster counting)
+ * and the fastest that converges is kept.  Not a paper construct (the
+ * paper fixes its cycle parameters); a measured autotuner of this library. */
 int ccgmg_tune(ccgmg_ctx* ctx, const double* f);
 
 /* Error text of the context's last failed call (owned by the context,

@@ -355,8 +355,9 @@ class Solver:
         return _report(rep, st)
 
     def tune(self, f):
-        """Re-choose schedule and depth by timing solves of this right-hand
-        side (with the boundary data last set); refreshes ``info``."""
+        """Re-choose schedule, depth and (with tune_schedule) the SMO-1
+        weight by timing solves of this right-hand side (with the boundary
+        data last set); refreshes ``info``."""
         self._check(lib().ccgmg_tune(self.ctx, _dev(f, self.n_cells, "f")))
         self.info = self.query()
 

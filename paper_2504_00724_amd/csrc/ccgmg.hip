@@ -1396,12 +1396,6 @@ double timed_solve(ccgmg_ctx* X, const double* f, double tol, int max_cycles, do
   return (std::isfinite(last) && rep.cycles > 0) ? std::pow(last, 1.0 / rep.cycles) : 1e300;
 }
 
-// Measured choice of smoothing schedule and depth: every candidate schedule
-// (with tune_schedule) at every admissible coarsest level (<= the dense
-// inverse limit), solved twice (capture, then timed replay).  With f == 0
-// (set-up) the seeded random right-hand side is used and candidates are
-// ranked by the asymptotic-rate estimate; with the caller's f they are
-// ranked by the measured time of the solve itself.
 // The SMO-1 weight omega of every level (omega / D of the regular rows; the
 // graphs captured with the former value are dropped).
 void set_omega(ccgmg_ctx* X, double omega) {
@@ -1414,6 +1408,13 @@ void set_omega(ccgmg_ctx* X, double omega) {
   X->clear_graphs();
 }
 
+// Measured choice of smoothing schedule and depth: every candidate schedule
+// (with tune_schedule) at every admissible coarsest level (<= the dense
+// inverse limit), solved three times (capture, then two timed replays, the
+// faster counting), then the SMO-1 weight (see below).  With f == 0
+// (set-up) the seeded random right-hand side is used and candidates are
+// ranked by the asymptotic-rate estimate; with the caller's f they are
+// ranked by the measured time of the solve itself.
 void tune_schedule_depth(ccgmg_ctx* X, const double* f) {
   struct Sched {
     int fused, nu1, nu2, c1, c2;   // c1, c2: coarse-level steps (0: as nu1, nu2)

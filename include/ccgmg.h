@@ -193,8 +193,8 @@ void ccgmg_default_options(ccgmg_options* opts);
  * the coarsest operator; uploads everything to the current HIP device.
  * grid, curves, opts: host, read only.  *out receives the new context.
  * CCGMG_EINVAL for options out of their ranges (theta outside [0, 1),
- * w_min <= 0, omega outside (0, 2), an enumeration field outside the values
- * listed with it), and also for a grid with (ny + 64) * nx * 8 >= 2^31 bytes (about
+ * w_min <= 0, omega outside (0, 2), max_cycles < 1, tol < 0 or NaN, an
+ * enumeration field outside the values listed with it), and also for a grid with (ny + 64) * nx * 8 >= 2^31 bytes (about
  * 2^28 cells: the kernels address a plane, its tile halos included, with
  * signed 32-bit byte offsets). */
 int ccgmg_create(const ccgmg_grid* grid, const ccgmg_curve* curves, int ncurves, double a, double b,

@@ -2105,6 +2105,7 @@ void create_host(ccgmg_ctx* X, const ccgmg_grid* grid, const ccgmg_curve* curves
   // centre row of a least-squares problem keeps a positive weight
   if (!(X->opt.theta >= 0.0 && X->opt.theta < 1.0)) throw ccg::Error(CCGMG_EINVAL, "theta must be in [0, 1)");
   if (!(X->opt.w_min > 0.0 && std::isfinite(X->opt.w_min))) throw ccg::Error(CCGMG_EINVAL, "w_min must be positive");
+  if (X->opt.max_cycles < 1 || !(X->opt.tol >= 0.0)) throw ccg::Error(CCGMG_EINVAL, "max_cycles must be >= 1 and tol >= 0");
   if (X->opt.precision < 0 || X->opt.precision > 1 || X->opt.prolongation < 0 || X->opt.prolongation > 1 ||
       X->opt.smoother_fused < 0 || X->opt.smoother_fused > 1 || X->opt.auto_depth < 0 || X->opt.auto_depth > 2 ||
       X->opt.smo2_every_sweep < 0)

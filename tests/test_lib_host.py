@@ -133,7 +133,8 @@ def test_smo1_weight_out_of_range_refused(omega):
 
 @pytest.mark.parametrize("opt", [dict(theta=-0.1), dict(theta=1.0), dict(theta=float("nan")), dict(w_min=0.0),
                                  dict(w_min=float("inf")), dict(precision=2), dict(prolongation=-1),
-                                 dict(smoother_fused=2), dict(auto_depth=3), dict(smo2_every_sweep=-1)])
+                                 dict(smoother_fused=2), dict(auto_depth=3), dict(smo2_every_sweep=-1),
+                                 dict(max_cycles=0), dict(tol=-1e-10), dict(tol=float("nan"))])
 def test_options_out_of_range_refused(opt):
     """Options outside their documented ranges are refused at creation with
     EINVAL, before any set-up work."""
